@@ -1,0 +1,710 @@
+/*
+ * coil_oracle.c -- plain, slow, FP64 CPU oracle of the coil quench hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the CPU
+ * baseline leg of the benchmark, never by the product path.  It shares no
+ * code with the HIP library.
+ *
+ * Method (paper, Methods: "Numerical Algorithm", the heat-diffusion paragraph,
+ * the E-J paragraph; Fig. 1(b), Fig. 2(a,b)):
+ *   The solenoid is rotationally symmetric, so its (r,z) cross-section is
+ *   modelled.  Wires sit on a square array; each wire is split into square
+ *   current elements, each element a coaxial ring carrying current I_e.
+ *   Per time step k -> k+1:
+ *     1. field: B_e = B_a(t_k) z + sum_{j != e} G_B(e,j) I_j (coaxial-ring
+ *        Green's function with complete elliptic integrals);
+ *     2. local law: Jc(B,T,eps), E = Ec (|J|/Jc)^n sgn J and dE/dJ, evaluated
+ *        at step k (the paper evaluates the resistivity from J^k);
+ *     3. per wire A-V solve: one loop voltage per wire enforces the transport
+ *        current; the other wires drive the wire through the flux of their
+ *        transport current (first iteration of the paper's scheme);
+ *     4. heat: c dT/dt = div(k grad T) + E.J, Robin h (T - T0) on the four
+ *        borders, explicit finite volumes on the enthalpy, sub-cycled;
+ *     5. accumulate Joule heat Q, per-wire Q_w, peak temperature.
+ *
+ * Readings where the paper is silent (its constitutive laws, A-V details and
+ * GPU algorithm are in the Supplementary Information, which is not available):
+ *   R1 geometry: contiguous square wires, ne x ne square elements per wire.
+ *   R2 self terms: the B self term of an element at its own centre is 0;
+ *      ring self inductance mu0 r (ln(8r/g) - 2) with g the geometric mean
+ *      distance of a square section, g = 0.4470491559036625 d.
+ *   R3 inter-wire coupling in Faraday's law: transport current of the other
+ *      wires only (static pattern Psi_u times dI_t); the all-pairs B from
+ *      every element current enters through Jc(B).
+ *   R4 A-V: 2 pi r_e E_e + U_w = -dPhi_e/dt, sum_{e in w} I_e = I_t.
+ *   R5 time integrator: linearised backward Euler per wire.
+ *   R6 order: field -> local -> wire solve -> heat; Jc, E from (B^k, T^k).
+ *   R8 Joule source: q = (E + E' dI/d^2) J^{k+1}.
+ *   R9 heat substeps n_sub = max(1, ceil(dt / (0.9 h_max))) (1e-9 relative
+ *      tolerance on the quotient), h_max the explicit stability limit at T_bath.
+ *   R10 axisymmetric finite volumes, half-cell series resistance at borders.
+ *   R11 constant k and h, C = C0 (T/T_ref)^p, enthalpy form.
+ * Every reading is listed with its justification in the design notes.
+ *
+ * Elliptic integrals: Carlson's symmetric forms R_F, R_D by the duplication
+ * algorithm (B. C. Carlson, "Numerical computation of real or complex elliptic
+ * integrals", Numer. Algorithms 10 (1995)).  Sums over sources use Neumaier's
+ * compensated summation.  OpenMP parallelises over independent targets and
+ * wires only; every sum is evaluated in a fixed order.
+ */
+#include "coil_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_MU0 (4.0e-7 * ORC_PI)
+/* geometric mean distance of a unit square from itself:
+   exp( integral over the square x square of ln|p - q| ) */
+#define ORC_GMD_SQUARE 0.4470491559036625
+
+/* ------------------------------------------------------------------ */
+/* compensated summation                                               */
+/* ------------------------------------------------------------------ */
+typedef struct { double s, c; } nsum;
+static void ns_add(nsum *a, double x) {
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+    else                       a->c += (x - t) + a->s;
+    a->s = t;
+}
+static double ns_val(const nsum *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------ */
+/* Carlson symmetric elliptic integrals                                */
+/* ------------------------------------------------------------------ */
+double orc_carlson_rf(double x, double y, double z) {
+    const double r = 1.0e-16;
+    const double x0 = x, y0 = y, z0 = z;
+    const double A0 = (x + y + z) / 3.0;
+    double A = A0;
+    const double Q = pow(3.0 * r, -1.0 / 6.0) *
+                     fmax(fabs(A0 - x0), fmax(fabs(A0 - y0), fabs(A0 - z0)));
+    double p4 = 1.0;
+    while (p4 * fabs(A) <= Q) {
+        const double sx = sqrt(x), sy = sqrt(y), sz = sqrt(z);
+        const double lam = sx * sy + sx * sz + sy * sz;
+        A = 0.25 * (A + lam);
+        x = 0.25 * (x + lam);
+        y = 0.25 * (y + lam);
+        z = 0.25 * (z + lam);
+        p4 *= 4.0;
+    }
+    const double X = (A0 - x0) / (p4 * A);
+    const double Y = (A0 - y0) / (p4 * A);
+    const double Z = -(X + Y);
+    const double E2 = X * Y - Z * Z;
+    const double E3 = X * Y * Z;
+    return (1.0 - E2 / 10.0 + E3 / 14.0 + E2 * E2 / 24.0 - 3.0 * E2 * E3 / 44.0) / sqrt(A);
+}
+
+double orc_carlson_rd(double x, double y, double z) {
+    const double r = 1.0e-16;
+    const double x0 = x, y0 = y, z0 = z;
+    const double A0 = (x + y + 3.0 * z) / 5.0;
+    double A = A0;
+    const double Q = pow(0.25 * r, -1.0 / 6.0) *
+                     fmax(fabs(A0 - x0), fmax(fabs(A0 - y0), fabs(A0 - z0)));
+    double p4 = 1.0, sum = 0.0;
+    while (p4 * fabs(A) <= Q) {
+        const double sx = sqrt(x), sy = sqrt(y), sz = sqrt(z);
+        const double lam = sx * sy + sx * sz + sy * sz;
+        sum += 1.0 / (p4 * sz * (z + lam));
+        A = 0.25 * (A + lam);
+        x = 0.25 * (x + lam);
+        y = 0.25 * (y + lam);
+        z = 0.25 * (z + lam);
+        p4 *= 4.0;
+    }
+    const double X = (A0 - x0) / (p4 * A);
+    const double Y = (A0 - y0) / (p4 * A);
+    const double Z = -(X + Y) / 3.0;
+    const double XY = X * Y, Z2 = Z * Z;
+    const double E2 = XY - 6.0 * Z2;
+    const double E3 = (3.0 * XY - 8.0 * Z2) * Z;
+    const double E4 = 3.0 * (XY - Z2) * Z2;
+    const double E5 = XY * Z2 * Z;
+    const double ser = 1.0 - 3.0 * E2 / 14.0 + E3 / 6.0 + 9.0 * E2 * E2 / 88.0
+                     - 3.0 * E4 / 22.0 - 9.0 * E2 * E3 / 52.0 + 3.0 * E5 / 26.0;
+    return ser / (p4 * A * sqrt(A)) + 3.0 * sum;
+}
+
+/* K(m) = R_F(0, 1-m, 1), E(m) = R_F(0, 1-m, 1) - (m/3) R_D(0, 1-m, 1) */
+void orc_ellip(double m1, double *K, double *E) {
+    if (m1 <= 0.0) { *K = INFINITY; *E = 1.0; return; }
+    const double m = 1.0 - m1;
+    const double rf = orc_carlson_rf(0.0, m1, 1.0);
+    const double rd = orc_carlson_rd(0.0, m1, 1.0);
+    *K = rf;
+    *E = rf - (m / 3.0) * rd;
+}
+
+/* ------------------------------------------------------------------ */
+/* ring Green's functions (coaxial filament loop; textbook closed forms) */
+/* ------------------------------------------------------------------ */
+void orc_ring_B(double a, double zs, double r, double z, double I, double *Br, double *Bz) {
+    const double dz = z - zs;
+    const double al2 = (r - a) * (r - a) + dz * dz;
+    const double be2 = (r + a) * (r + a) + dz * dz;
+    const double be = sqrt(be2);
+    double K, E;
+    orc_ellip(al2 / be2, &K, &E);
+    const double pre = ORC_MU0 * I / (2.0 * ORC_PI * al2 * be);
+    *Bz = pre * ((a * a - r * r - dz * dz) * E + al2 * K);
+    *Br = (r > 0.0) ? pre * (dz / r) * ((a * a + r * r + dz * dz) * E - al2 * K) : 0.0;
+}
+
+double orc_ring_M(double a, double zs, double r, double z) {
+    const double dz = z - zs;
+    const double al2 = (r - a) * (r - a) + dz * dz;
+    const double be2 = (r + a) * (r + a) + dz * dz;
+    const double m1 = al2 / be2;
+    double K, E;
+    orc_ellip(m1, &K, &E);
+    return ORC_MU0 * sqrt(be2) * (0.5 * (1.0 + m1) * K - E);
+}
+
+double orc_self_L(double r, double d) {
+    return ORC_MU0 * r * (log(8.0 * r / (ORC_GMD_SQUARE * d)) - 2.0);
+}
+
+/* ------------------------------------------------------------------ */
+/* simulation state                                                    */
+/* ------------------------------------------------------------------ */
+struct orc_sim {
+    orc_cfg cfg;
+    long N, Nw;
+    int n_sub;
+    /* geometry, public order */
+    double *r, *z, *d, *V;
+    int *coil, *wire;
+    long *coil_off, *wire_off;   /* first element of coil c; first slot of wire w in welem */
+    long *welem;                 /* elements of each wire, local order a*ne + b */
+    int  *wn;                    /* elements per wire */
+    int  *wcoil;                 /* coil of wire */
+    /* static material */
+    double *jcs;                 /* Jc0 * mu_e * (1 - eps_coef |eps|^eps_pow) */
+    double *cw;                  /* per-wire multiplier */
+    /* precompute */
+    double **Mww;                /* per wire, wn x wn row-major */
+    double *psi;                 /* transport flux pattern per element */
+    long *nb;                    /* 4 neighbours per element, -1 = border */
+    double *G;                   /* 4 face conductances */
+    double *Gb;                  /* border conductance (sum over border faces) */
+    /* state */
+    double *I, *u, *T, *Phi, *Br, *Bz, *E, *Ep, *Jc, *dI, *q, *Qw, *U;
+    double Q, Tpeak, Qout, maxx, sumU;
+    long step, Tpeak_e, Tpeak_k;
+};
+
+long orc_n_elem(const orc_sim *s) { return s->N; }
+long orc_n_wire(const orc_sim *s) { return s->Nw; }
+int  orc_n_sub(const orc_sim *s) { return s->n_sub; }
+
+static double *dalloc(long n) { return (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double)); }
+
+static int cfg_valid(const orc_cfg *c) {
+    if (c->n_coils < 1 || c->n_coils > ORC_MAXC) return 0;
+    for (int i = 0; i < c->n_coils; ++i) {
+        if (c->layers[i] < 1 || c->turns[i] < 1 || c->ne[i] < 1) return 0;
+        if (!(c->wire_side[i] > 0) || !(c->r_inner[i] > 0)) return 0;
+    }
+    if (!(c->dt > 0) || !(c->Ec > 0) || !(c->n >= 1) || !(c->Jc0 > 0)) return 0;
+    if (!(c->Tc > 0) || !(c->B0 > 0) || !(c->C0 > 0) || !(c->T_ref > 0)) return 0;
+    if (!(c->k0 > 0) || !(c->h0 >= 0) || !(c->T_bath > 0)) return 0;
+    for (int i = 0; i < c->n_coils; ++i)
+        if (c->I0[i] != 0.0) return 0; /* runs start from zero current */
+    return 1;
+}
+
+/* enthalpy per volume relative to the bath and its inverse:
+   u(T) = C0 T_ref/(p+1) [ (T/T_ref)^(p+1) - (T_bath/T_ref)^(p+1) ] */
+static double u_of_T(const orc_cfg *c, double T) {
+    const double p1 = c->cp_exp + 1.0;
+    return c->C0 * c->T_ref / p1 * (pow(T / c->T_ref, p1) - pow(c->T_bath / c->T_ref, p1));
+}
+static double T_of_u(const orc_cfg *c, double u) {
+    const double p1 = c->cp_exp + 1.0;
+    const double x = p1 * u / (c->C0 * c->T_ref) + pow(c->T_bath / c->T_ref, p1);
+    return c->T_ref * pow(x, 1.0 / p1);
+}
+
+/* heat conductances of element e (public index inside its coil grid) */
+static void build_heat(orc_sim *s) {
+    const orc_cfg *c = &s->cfg;
+    for (int ci = 0; ci < c->n_coils; ++ci) {
+        const int ne = c->ne[ci];
+        const long nr = (long)c->layers[ci] * ne, nz = (long)c->turns[ci] * ne;
+        const double d = c->wire_side[ci] / ne;
+        const double rin = c->r_inner[ci];
+        for (long ir = 0; ir < nr; ++ir)
+            for (long iz = 0; iz < nz; ++iz) {
+                const long e = s->coil_off[ci] + ir * nz + iz;
+                const double re = s->r[e];
+                /* faces: 0 = inner radial (ir-1), 1 = outer radial (ir+1),
+                          2 = lower axial (iz-1), 3 = upper axial (iz+1) */
+                const double rf_in = rin + (double)ir * d;
+                const double rf_out = rin + (double)(ir + 1) * d;
+                double area[4], gface[4];
+                if (c->planar) {
+                    area[0] = area[1] = area[2] = area[3] = d;
+                } else {
+                    area[0] = 2.0 * ORC_PI * rf_in * d;
+                    area[1] = 2.0 * ORC_PI * rf_out * d;
+                    area[2] = area[3] = 2.0 * ORC_PI * re * d;
+                }
+                long nbr[4];
+                nbr[0] = (ir > 0) ? e - nz : -1;
+                nbr[1] = (ir < nr - 1) ? e + nz : -1;
+                nbr[2] = (iz > 0) ? e - 1 : -1;
+                nbr[3] = (iz < nz - 1) ? e + 1 : -1;
+                double gb = 0.0;
+                for (int f = 0; f < 4; ++f) {
+                    gface[f] = c->k0 * area[f] / d; /* centre-to-centre distance d */
+                    s->nb[4 * e + f] = nbr[f];
+                    if (nbr[f] >= 0) {
+                        s->G[4 * e + f] = gface[f];
+                    } else {
+                        s->G[4 * e + f] = 0.0;
+                        gb += (c->h0 > 0.0) ? area[f] / (1.0 / c->h0 + d / (2.0 * c->k0)) : 0.0;
+                    }
+                }
+                s->Gb[e] = gb;
+            }
+    }
+    /* explicit stability limit at the bath temperature */
+    const double Cb = c->C0 * pow(c->T_bath / c->T_ref, c->cp_exp);
+    double hmax = INFINITY;
+    for (long e = 0; e < s->N; ++e) {
+        double g = s->Gb[e];
+        for (int f = 0; f < 4; ++f) g += s->G[4 * e + f];
+        if (g > 0.0) {
+            const double h = s->V[e] * Cb / g;
+            if (h < hmax) hmax = h;
+        }
+    }
+    if (c->n_sub > 0) {
+        s->n_sub = c->n_sub;
+    } else {
+        const double qt = c->dt / (0.9 * hmax);
+        long ns = (long)ceil(qt * (1.0 - 1.0e-9));
+        s->n_sub = (int)(ns < 1 ? 1 : ns);
+    }
+}
+
+orc_sim *orc_create(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
+                    const double *c_wire) {
+    if (!cfg || !cfg_valid(cfg)) return NULL;
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    s->cfg = *cfg;
+    const orc_cfg *c = &s->cfg;
+    long N = 0, Nw = 0, nwe = 0;
+    s->coil_off = (long *)calloc((size_t)c->n_coils + 1, sizeof(long));
+    for (int ci = 0; ci < c->n_coils; ++ci) {
+        s->coil_off[ci] = N;
+        const long ne = c->ne[ci];
+        N += (long)c->layers[ci] * c->turns[ci] * ne * ne;
+        Nw += (long)c->layers[ci] * c->turns[ci];
+        nwe += (long)c->layers[ci] * c->turns[ci] * ne * ne;
+    }
+    s->coil_off[c->n_coils] = N;
+    s->N = N;
+    s->Nw = Nw;
+    s->r = dalloc(N); s->z = dalloc(N); s->d = dalloc(N); s->V = dalloc(N);
+    s->coil = (int *)calloc((size_t)N, sizeof(int));
+    s->wire = (int *)calloc((size_t)N, sizeof(int));
+    s->wire_off = (long *)calloc((size_t)Nw + 1, sizeof(long));
+    s->welem = (long *)calloc((size_t)nwe, sizeof(long));
+    s->wn = (int *)calloc((size_t)Nw, sizeof(int));
+    s->wcoil = (int *)calloc((size_t)Nw, sizeof(int));
+    /* geometry (R1) */
+    long w0 = 0, slot = 0;
+    for (int ci = 0; ci < c->n_coils; ++ci) {
+        const int ne = c->ne[ci], L = c->layers[ci], Tn = c->turns[ci];
+        const long nz = (long)Tn * ne;
+        const double ws = c->wire_side[ci], d = ws / ne;
+        const double zbot = c->z_center[ci] - 0.5 * Tn * ws;
+        for (int li = 0; li < L; ++li)
+            for (int ti = 0; ti < Tn; ++ti) {
+                const long w = w0 + (long)li * Tn + ti;
+                s->wire_off[w] = slot;
+                s->wn[w] = ne * ne;
+                s->wcoil[w] = ci;
+                for (int a = 0; a < ne; ++a)
+                    for (int b = 0; b < ne; ++b) {
+                        const long ir = (long)li * ne + a, iz = (long)ti * ne + b;
+                        const long e = s->coil_off[ci] + ir * nz + iz;
+                        s->welem[slot++] = e;
+                        s->r[e] = c->r_inner[ci] + ((double)ir + 0.5) * d;
+                        s->z[e] = zbot + ((double)iz + 0.5) * d;
+                        s->d[e] = d;
+                        s->V[e] = c->planar ? d * d : 2.0 * ORC_PI * s->r[e] * d * d;
+                        s->coil[e] = ci;
+                        s->wire[e] = (int)w;
+                    }
+            }
+        w0 += (long)L * Tn;
+    }
+    s->wire_off[Nw] = slot;
+    /* static part of Jc */
+    s->jcs = dalloc(N);
+    s->cw = dalloc(Nw);
+    for (long e = 0; e < N; ++e) {
+        const double mu = jc0_mult ? jc0_mult[e] : 1.0;
+        const double ep = strain ? strain[e] : 0.0;
+        s->jcs[e] = c->Jc0 * mu * (1.0 - c->eps_coef * pow(fabs(ep), c->eps_pow));
+    }
+    for (long w = 0; w < Nw; ++w) s->cw[w] = c_wire ? c_wire[w] : 1.0;
+    /* per-wire inductance blocks (R2) */
+    s->Mww = (double **)calloc((size_t)Nw, sizeof(double *));
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (long w = 0; w < Nw; ++w) {
+        const int n = s->wn[w];
+        const long *el = s->welem + s->wire_off[w];
+        double *M = dalloc((long)n * n);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const long ei = el[i], ej = el[j];
+                M[i * n + j] = (i == j) ? orc_self_L(s->r[ei], s->d[ei])
+                                        : orc_ring_M(s->r[ej], s->z[ej], s->r[ei], s->z[ei]);
+            }
+        s->Mww[w] = M;
+    }
+    /* transport flux pattern (R3): flux through ring e per ampere of transport
+       current carried uniformly by every other wire of the same coil */
+    s->psi = dalloc(N);
+    #pragma omp parallel for schedule(dynamic, 64)
+    for (long e = 0; e < N; ++e) {
+        const int ci = s->coil[e];
+        nsum acc = {0.0, 0.0};
+        for (long j = s->coil_off[ci]; j < s->coil_off[ci + 1]; ++j) {
+            if (s->wire[j] == s->wire[e]) continue;
+            ns_add(&acc, orc_ring_M(s->r[j], s->z[j], s->r[e], s->z[e]) / (double)s->wn[s->wire[j]]);
+        }
+        s->psi[e] = ns_val(&acc);
+    }
+    /* heat */
+    s->nb = (long *)calloc((size_t)4 * N, sizeof(long));
+    s->G = dalloc(4 * N);
+    s->Gb = dalloc(N);
+    build_heat(s);
+    /* state */
+    s->I = dalloc(N); s->u = dalloc(N); s->T = dalloc(N); s->Phi = dalloc(N);
+    s->Br = dalloc(N); s->Bz = dalloc(N); s->E = dalloc(N); s->Ep = dalloc(N);
+    s->Jc = dalloc(N); s->dI = dalloc(N); s->q = dalloc(N);
+    s->Qw = dalloc(Nw); s->U = dalloc(Nw);
+    for (long e = 0; e < N; ++e) s->T[e] = c->T_bath;
+    s->Tpeak = c->T_bath;
+    s->Tpeak_e = -1;
+    s->Tpeak_k = -1;
+    return s;
+}
+
+void orc_destroy(orc_sim *s) {
+    if (!s) return;
+    if (s->Mww) for (long w = 0; w < s->Nw; ++w) free(s->Mww[w]);
+    free(s->Mww);
+    void *p[] = {s->r, s->z, s->d, s->V, s->coil, s->wire, s->coil_off, s->wire_off, s->welem,
+                 s->wn, s->wcoil, s->jcs, s->cw, s->psi, s->nb, s->G, s->Gb, s->I, s->u, s->T,
+                 s->Phi, s->Br, s->Bz, s->E, s->Ep, s->Jc, s->dI, s->q, s->Qw, s->U};
+    for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
+    free(s);
+}
+
+/* ------------------------------------------------------------------ */
+/* field sum                                                           */
+/* ------------------------------------------------------------------ */
+static void field_at_element(const orc_sim *s, const double *I, long e, double *Br, double *Bz) {
+    const int ci = s->coil[e];
+    nsum ar = {0.0, 0.0}, az = {0.0, 0.0};
+    for (long j = s->coil_off[ci]; j < s->coil_off[ci + 1]; ++j) {
+        if (j == e || I[j] == 0.0) continue;
+        double br, bz;
+        orc_ring_B(s->r[j], s->z[j], s->r[e], s->z[e], I[j], &br, &bz);
+        ns_add(&ar, br);
+        ns_add(&az, bz);
+    }
+    *Br = ns_val(&ar);
+    *Bz = ns_val(&az);
+}
+
+void orc_field_targets(const orc_sim *s, const double *I, long nt, const long *tgt,
+                       double *Br, double *Bz) {
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < nt; ++i) field_at_element(s, I, tgt[i], &Br[i], &Bz[i]);
+}
+
+void orc_field_points(const orc_sim *s, const double *I, long np, const double *r,
+                      const double *z, double *Br, double *Bz) {
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (long i = 0; i < np; ++i) {
+        nsum ar = {0.0, 0.0}, az = {0.0, 0.0};
+        for (long j = 0; j < s->N; ++j) {
+            if (I[j] == 0.0) continue;
+            double br, bz;
+            orc_ring_B(s->r[j], s->z[j], r[i], z[i], I[j], &br, &bz);
+            ns_add(&ar, br);
+            ns_add(&az, bz);
+        }
+        Br[i] = ns_val(&ar);
+        Bz[i] = ns_val(&az);
+    }
+}
+
+int orc_wire_elems(const orc_sim *s, long w, long *dst) {
+    if (w < 0 || w >= s->Nw) return 0;
+    const int n = s->wn[w];
+    for (int i = 0; i < n; ++i) dst[i] = s->welem[s->wire_off[w] + i];
+    return n;
+}
+
+/* ------------------------------------------------------------------ */
+/* dense Cholesky and triangular solves                                */
+/* ------------------------------------------------------------------ */
+static int cholesky(double *A, int n) { /* lower factor in place, row-major */
+    for (int j = 0; j < n; ++j) {
+        double dsum = A[j * n + j];
+        for (int k = 0; k < j; ++k) dsum -= A[j * n + k] * A[j * n + k];
+        if (!(dsum > 0.0)) return -1;
+        const double ljj = sqrt(dsum);
+        A[j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = v / ljj;
+        }
+    }
+    return 0;
+}
+static void chol_solve(const double *L, int n, double *x) { /* L L^T x = b in place */
+    for (int i = 0; i < n; ++i) {
+        double v = x[i];
+        for (int k = 0; k < i; ++k) v -= L[i * n + k] * x[k];
+        x[i] = v / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = x[i];
+        for (int k = i + 1; k < n; ++k) v -= L[k * n + i] * x[k];
+        x[i] = v / L[i * n + i];
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* one time step                                                       */
+/* ------------------------------------------------------------------ */
+int orc_step(orc_sim *s) {
+    const orc_cfg *c = &s->cfg;
+    const long N = s->N, Nw = s->Nw;
+    const double dt = c->dt;
+    const double tk = (double)s->step * dt;
+    const double Ba = c->dBa_dt * tk;
+    const double dBa = c->dBa_dt * dt;
+    int bad = 0;
+
+    /* 1. field from the element currents at step k */
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (long e = 0; e < N; ++e) {
+        double br, bz;
+        field_at_element(s, s->I, e, &br, &bz);
+        s->Br[e] = br;
+        s->Bz[e] = bz + Ba;
+    }
+
+    /* 2. local law at step k */
+    double maxx = 0.0;
+    for (long e = 0; e < N; ++e) {
+        const double d2 = s->d[e] * s->d[e];
+        const double J = s->I[e] / d2;
+        const double Bm = sqrt(s->Br[e] * s->Br[e] + s->Bz[e] * s->Bz[e]);
+        const double fT = fmax(0.0, 1.0 - s->T[e] / c->Tc);
+        const double Jc = s->cw[s->wire[e]] * s->jcs[e] * fT * c->B0 / (c->B0 + Bm);
+        s->Jc[e] = Jc;
+        if (J == 0.0) {
+            s->E[e] = 0.0;
+            s->Ep[e] = 0.0;
+            continue;
+        }
+        if (!(Jc > 0.0)) { bad = 1; s->E[e] = NAN; s->Ep[e] = NAN; continue; }
+        const double x = fabs(J) / Jc;
+        if (x > maxx) maxx = x;
+        s->E[e] = c->Ec * pow(x, c->n) * (J > 0.0 ? 1.0 : -1.0);
+        s->Ep[e] = c->n * c->Ec / Jc * pow(x, c->n - 1.0);
+    }
+
+    /* 3. per-wire A-V solve, linearised backward Euler */
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (long w = 0; w < Nw; ++w) {
+        const int n = s->wn[w];
+        const int ci = s->wcoil[w];
+        const double dIt = c->ramp[ci] * dt;
+        const long *el = s->welem + s->wire_off[w];
+        double *A = dalloc((long)n * n), *x = dalloc(n), *y = dalloc(n), *MdI = dalloc(n);
+        memcpy(A, s->Mww[w], sizeof(double) * (size_t)n * n);
+        for (int i = 0; i < n; ++i) {
+            const long e = el[i];
+            const double d2 = s->d[e] * s->d[e];
+            A[i * n + i] += dt * 2.0 * ORC_PI * s->r[e] * s->Ep[e] / d2;
+            x[i] = -dIt * s->psi[e] - ORC_PI * s->r[e] * s->r[e] * dBa
+                   - dt * 2.0 * ORC_PI * s->r[e] * s->E[e];
+            y[i] = 1.0;
+        }
+        if (cholesky(A, n) != 0) {
+            #pragma omp atomic write
+            bad = 1;
+        } else {
+            chol_solve(A, n, x);
+            chol_solve(A, n, y);
+            double sx = 0.0, sy = 0.0;
+            for (int i = 0; i < n; ++i) { sx += x[i]; sy += y[i]; }
+            const double U = (sx - dIt) / (dt * sy);
+            s->U[w] = U;
+            for (int i = 0; i < n; ++i) s->dI[el[i]] = x[i] - dt * U * y[i];
+            /* flux update Phi += M_ww dI + dI_t Psi_u + pi r^2 dB_a */
+            for (int i = 0; i < n; ++i) {
+                double v = 0.0;
+                for (int j = 0; j < n; ++j) v += s->Mww[w][i * n + j] * s->dI[el[j]];
+                MdI[i] = v;
+            }
+            for (int i = 0; i < n; ++i) {
+                const long e = el[i];
+                s->Phi[e] += MdI[i] + dIt * s->psi[e] + ORC_PI * s->r[e] * s->r[e] * dBa;
+            }
+        }
+        free(A); free(x); free(y); free(MdI);
+    }
+    if (bad) return -4;
+
+    /* currents, Joule source q = E_lin J^{k+1} (R8), Q accumulation */
+    nsum qsum = {0.0, 0.0};
+    for (long w = 0; w < Nw; ++w) {
+        const long *el = s->welem + s->wire_off[w];
+        nsum qw = {0.0, 0.0};
+        for (int i = 0; i < s->wn[w]; ++i) {
+            const long e = el[i];
+            const double d2 = s->d[e] * s->d[e];
+            s->I[e] += s->dI[e];
+            const double Elin = s->E[e] + s->Ep[e] * s->dI[e] / d2;
+            s->q[e] = Elin * (s->I[e] / d2);
+            ns_add(&qw, dt * s->V[e] * s->q[e]);
+        }
+        s->Qw[w] += ns_val(&qw);
+        ns_add(&qsum, ns_val(&qw));
+    }
+    s->Q += ns_val(&qsum);
+    {
+        nsum us = {0.0, 0.0};
+        for (long w = 0; w < Nw; ++w) ns_add(&us, s->U[w]);
+        s->sumU = ns_val(&us);
+    }
+    s->maxx = maxx;
+
+    /* 4. explicit heat, n_sub substeps with q held fixed */
+    const double hs = dt / (double)s->n_sub;
+    double *un = dalloc(N);
+    for (int sub = 0; sub < s->n_sub; ++sub) {
+        nsum out = {0.0, 0.0};
+        for (long e = 0; e < N; ++e) {
+            double flux = s->Gb[e] * (c->T_bath - s->T[e]);
+            for (int f = 0; f < 4; ++f) {
+                const long nbr = s->nb[4 * e + f];
+                if (nbr >= 0) flux += s->G[4 * e + f] * (s->T[nbr] - s->T[e]);
+            }
+            un[e] = s->u[e] + hs / s->V[e] * flux + hs * s->q[e];
+            ns_add(&out, hs * s->Gb[e] * (s->T[e] - c->T_bath));
+        }
+        s->Qout += ns_val(&out);
+        for (long e = 0; e < N; ++e) {
+            s->u[e] = un[e];
+            s->T[e] = T_of_u(c, un[e]);
+        }
+    }
+    free(un);
+
+    /* 5. peak temperature, lowest (step, element) on ties */
+    for (long e = 0; e < N; ++e) {
+        if (!isfinite(s->T[e]) || !isfinite(s->I[e])) bad = 1;
+        if (s->T[e] > s->Tpeak) {
+            s->Tpeak = s->T[e];
+            s->Tpeak_e = e;
+            s->Tpeak_k = s->step + 1;
+        }
+    }
+    s->step += 1;
+    return bad ? -4 : 0;
+}
+
+int orc_run(orc_sim *s, long nsteps) {
+    for (long k = 0; k < nsteps; ++k) {
+        const int rc = orc_step(s);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+int orc_get(const orc_sim *s, int field, double *dst, long count) {
+    const long N = s->N, Nw = s->Nw;
+    const double *src = NULL;
+    long n = N;
+    switch (field) {
+        case ORC_I: src = s->I; break;
+        case ORC_BR: src = s->Br; break;
+        case ORC_BZ: src = s->Bz; break;
+        case ORC_T: src = s->T; break;
+        case ORC_PHI: src = s->Phi; break;
+        case ORC_QW: src = s->Qw; n = Nw; break;
+        case ORC_UW: src = s->U; n = Nw; break;
+        case ORC_E: src = s->E; break;
+        case ORC_EP: src = s->Ep; break;
+        case ORC_U: src = s->u; break;
+        case ORC_Q: src = s->q; break;
+        case ORC_PSI: src = s->psi; break;
+        case ORC_R: src = s->r; break;
+        case ORC_Z: src = s->z; break;
+        case ORC_V: src = s->V; break;
+        case ORC_JC: src = s->Jc; break;
+        case ORC_DI: src = s->dI; break;
+        case ORC_J:
+            if (count < N) return -1;
+            for (long e = 0; e < N; ++e) dst[e] = s->I[e] / (s->d[e] * s->d[e]);
+            return 0;
+        default: return -1;
+    }
+    if (count < n) return -1;
+    memcpy(dst, src, sizeof(double) * (size_t)n);
+    return 0;
+}
+
+int orc_set(orc_sim *s, int field, const double *src, long count) {
+    const long N = s->N;
+    if (count < N) return -1;
+    switch (field) {
+        case ORC_I: memcpy(s->I, src, sizeof(double) * (size_t)N); return 0;
+        case ORC_T:
+            for (long e = 0; e < N; ++e) { s->T[e] = src[e]; s->u[e] = u_of_T(&s->cfg, src[e]); }
+            return 0;
+        default: return -1;
+    }
+}
+
+int orc_scalars(const orc_sim *s, double *dst, int n) {
+    double v[12];
+    v[0] = (double)s->step * s->cfg.dt;
+    v[1] = (double)s->step;
+    v[2] = s->Q;
+    v[3] = s->Tpeak;
+    v[4] = s->sumU;
+    v[5] = s->maxx;
+    v[6] = s->Qout;
+    {
+        nsum st = {0.0, 0.0};
+        for (long e = 0; e < s->N; ++e) ns_add(&st, s->V[e] * s->u[e]);
+        v[7] = ns_val(&st);
+    }
+    v[8] = s->cfg.I0[0] + s->cfg.ramp[0] * v[0];
+    v[9] = (double)s->Tpeak_e;
+    v[10] = (double)s->Tpeak_k;
+    v[11] = (double)s->n_sub;
+    for (int i = 0; i < n && i < 12; ++i) dst[i] = v[i];
+    return 0;
+}

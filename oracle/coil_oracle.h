@@ -1,0 +1,95 @@
+/*
+ * coil_oracle.h -- plain, slow FP64 CPU oracle of the coil quench hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load or call this library.  It shares no
+ * code, header, table or helper with the HIP library.
+ *
+ * What it computes (paper: Methods, "Numerical Algorithm" and the heat
+ * paragraph that follows the figures; Fig. 2(b) flow chart):
+ *   - each current element is a coaxial ring (axisymmetric cross-section);
+ *   - per time step: the all-pairs ring field B from every element current,
+ *     the local power law E-J with Jc(B,T,eps), a per-wire A-V solve that
+ *     enforces the wire's transport current, then the explicit heat step
+ *     c dT/dt = div(k grad T) + E.J with a Robin condition on the four
+ *     borders of the cross-section.
+ * Readings where the paper is silent are listed at the top of coil_oracle.c.
+ *
+ * Element order ("public order"): coils concatenated, inside a coil the
+ * (r,z) grid row-major, e = i_r * n_z + i_z.  Wire order w = layer*turns+turn.
+ */
+#ifndef COIL_ORACLE_H
+#define COIL_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAXC 64
+
+typedef struct {
+    int n_coils;
+    int layers[ORC_MAXC], turns[ORC_MAXC], ne[ORC_MAXC];
+    double r_inner[ORC_MAXC], z_center[ORC_MAXC], wire_side[ORC_MAXC];
+    double ramp[ORC_MAXC], I0[ORC_MAXC];
+    double dBa_dt;
+    double Ec, n, Jc0, Tc, B0, eps_coef, eps_pow;
+    double C0, T_ref, cp_exp, k0, h0, T_bath;
+    double dt;
+    int n_sub;   /* heat substeps per step; 0 = automatic stability rule */
+    int planar;  /* 1: heat in planar (Cartesian) geometry, test use only */
+} orc_cfg;
+
+typedef struct orc_sim orc_sim;
+
+/* ---- pure functions (pinned by the unit tests) ---- */
+/* complete elliptic integrals K(m), E(m) with the complementary parameter
+   m1 = 1 - m passed directly (Carlson symmetric forms). */
+void   orc_ellip(double m1, double *K, double *E);
+double orc_carlson_rf(double x, double y, double z);
+double orc_carlson_rd(double x, double y, double z);
+/* field at (r,z) of a coaxial filament ring of radius a at height zs, current I */
+void   orc_ring_B(double a, double zs, double r, double z, double I, double *Br, double *Bz);
+/* mutual inductance of two coaxial filament rings (Maxwell) */
+double orc_ring_M(double a, double zs, double r, double z);
+/* self inductance of a ring of radius r with a square d x d section */
+double orc_self_L(double r, double d);
+
+/* ---- simulation ---- */
+/* inputs in public order: jc0_mult[N], strain[N], c_wire[Nw].  Returns NULL
+   on invalid configuration. */
+orc_sim *orc_create(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
+                    const double *c_wire);
+void   orc_destroy(orc_sim *s);
+long   orc_n_elem(const orc_sim *s);
+long   orc_n_wire(const orc_sim *s);
+int    orc_n_sub(const orc_sim *s);
+/* one time step; returns 0, or -4 when a non-finite value appeared */
+int    orc_step(orc_sim *s);
+int    orc_run(orc_sim *s, long nsteps);
+
+/* field names for orc_get / orc_set */
+enum { ORC_I = 0, ORC_J = 1, ORC_BR = 2, ORC_BZ = 3, ORC_T = 4, ORC_PHI = 5,
+       ORC_QW = 6, ORC_UW = 7, ORC_E = 8, ORC_EP = 9, ORC_U = 10, ORC_Q = 11,
+       ORC_PSI = 12, ORC_R = 13, ORC_Z = 14, ORC_V = 15, ORC_JC = 16, ORC_DI = 17 };
+int    orc_get(const orc_sim *s, int field, double *dst, long count);
+int    orc_set(orc_sim *s, int field, const double *src, long count);
+/* scalars: [0]=t, [1]=step, [2]=Q, [3]=T_peak, [4]=sum U_w, [5]=max |J|/Jc,
+   [6]=heat out through the borders, [7]=stored heat sum V u, [8]=I_t,
+   [9]=argmax element of T_peak, [10]=argmax step of T_peak, [11]=n_sub */
+int    orc_scalars(const orc_sim *s, double *dst, int n);
+
+/* field sum B = sum_j G_B(e,j) I_j at the listed target elements, for an
+   arbitrary current vector I[N] (public order); background field excluded. */
+void   orc_field_targets(const orc_sim *s, const double *I, long nt, const long *tgt,
+                         double *Br, double *Bz);
+/* the same sum at arbitrary points (r,z) of coil `coil` */
+void   orc_field_points(const orc_sim *s, const double *I, long np, const double *r,
+                        const double *z, double *Br, double *Bz);
+/* elements of wire w (public indices), returns count */
+int    orc_wire_elems(const orc_sim *s, long w, long *dst);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
