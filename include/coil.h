@@ -1,0 +1,198 @@
+/*
+ * coil.h -- C ABI of the MI355X (gfx950) coil quench hot path.
+ *
+ * What the library computes (Xue et al., "Holistic numerical simulation of a
+ * quenching process on a real-size multifilamentary superconducting coil";
+ * Methods: "Numerical Algorithm", the heat-diffusion paragraph and the E-J
+ * paragraph; Fig. 1(b) and Fig. 2(a,b)):
+ *   the (r,z) cross-section of one or more solenoids, each wire split into
+ *   ne x ne square current elements treated as coaxial rings.  One time step:
+ *     1. all-pairs field sum B_e = B_a(t) z + sum_{j != e} G_B(e,j) I_j with the
+ *        coaxial-ring Green's function (complete elliptic integrals K, E
+ *        evaluated on the fly);
+ *     2. local power law E = Ec (|J|/Jc)^n sgn J, Jc = c_w Jc0 mu_e (1 - T/Tc)
+ *        B0/(B0 + |B|) (1 - eps_coef |eps|^eps_pow), from the state at step k;
+ *     3. per-wire A-V solve: each wire's element currents respond to the flux
+ *        of the other wires' transport current and of the background field,
+ *        one loop voltage per wire enforces the wire's transport current
+ *        (linearised backward Euler);
+ *     4. explicit heat step c dT/dt = div(k grad T) + E.J on the enthalpy, with
+ *        a Robin condition h (T - T_bath) on the four borders, sub-cycled;
+ *     5. reductions: Joule heat Q (total and per wire), peak temperature,
+ *        terminal voltage, max |J|/Jc.
+ *
+ * Conventions
+ *   - Every function returns int: COIL_OK (0) or a negative COIL_E_* code;
+ *     coil_last_error() then holds a message (thread-local).  No C++ exception
+ *     crosses the ABI.  Arguments are validated before any allocation or
+ *     launch.
+ *   - Units: SI (m, s, A, T, V, K, J).
+ *   - Element order seen through this ABI ("public order"): coils concatenated;
+ *     inside a coil the (r,z) grid is row-major, e = i_r * n_z + i_z, with
+ *     n_r = layers*ne radial and n_z = turns*ne axial elements, i_r = 0 at
+ *     r_inner and i_z = 0 at the bottom.  Wire order: w = layer*turns + turn,
+ *     coils concatenated.  The internal device layout is the library's own.
+ *   - Device memory: the caller owns one device workspace (e.g. a torch uint8
+ *     tensor) of the size coil_query() reports and keeps it alive until
+ *     coil_destroy().  The library allocates no device memory of its own
+ *     except where a function says so.
+ *   - Streams: every call enqueues on the HIP stream given to coil_init.  Only
+ *     coil_run at report points, coil_scalars, host-destination coil_get,
+ *     coil_timing and coil_adjoint synchronise with the host.
+ *   - A handle is not thread-safe: use one handle per host thread.
+ */
+#ifndef COIL_H
+#define COIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum coil_status {
+    COIL_OK = 0,
+    COIL_E_INVAL = -1,     /* invalid argument or configuration */
+    COIL_E_NOMEM = -2,     /* workspace too small, or a host allocation failed */
+    COIL_E_HIP = -3,       /* a HIP runtime call failed; message in coil_last_error */
+    COIL_E_NONFINITE = -4, /* a non-finite value or a non-positive pivot appeared */
+    COIL_E_STATE = -5      /* call not valid in the handle's current state */
+};
+
+enum coil_precision {
+    COIL_FP64 = 0,  /* everything in FP64 */
+    COIL_MIXED = 1  /* field pairs in FP32 with compensated sums, pairs with
+                       k > near_k (and their elliptic arguments) in FP64;
+                       all state (I, Phi, u, T, Q) in FP64 */
+};
+
+/* fields for coil_get / coil_set_state */
+enum coil_field {
+    COIL_F_I = 0,     /* element current, A                (settable) */
+    COIL_F_J = 1,     /* current density I/d^2, A/m^2 */
+    COIL_F_BR = 2,    /* field at the element centre, T (from the last field pass) */
+    COIL_F_BZ = 3,
+    COIL_F_T = 4,     /* temperature, K                    (settable) */
+    COIL_F_PHI = 5,   /* accumulated flux linkage, Wb */
+    COIL_F_QW = 6,    /* per-wire time-integrated Joule heat, J   (N_w entries) */
+    COIL_F_UW = 7,    /* per-wire loop voltage of the last step, V (N_w entries) */
+    COIL_F_E = 8,     /* electric field of the last step, V/m */
+    COIL_F_EP = 9,    /* dE/dJ of the last step */
+    COIL_F_U = 10,    /* enthalpy per volume relative to the bath, J/m^3 */
+    COIL_F_Q = 11,    /* Joule source of the last step, W/m^3 */
+    COIL_F_PSI = 12,  /* transport-flux pattern, Wb/A */
+    COIL_F_R = 13,    /* element radius, m */
+    COIL_F_Z = 14,    /* element height, m */
+    COIL_F_DI = 15,   /* current increment of the last step, A */
+    COIL_F_JC = 16    /* critical current density of the last step, A/m^2 */
+};
+
+typedef struct {
+    /* geometry and drive, one entry per coil (host arrays, copied at init) */
+    int32_t n_coils;
+    const int32_t *layers, *turns, *ne;   /* wires radial, axial; elements per wire side */
+    const double *r_inner, *z_center, *wire_side; /* m */
+    const double *ramp;                   /* transport current ramp, A/s (I(0) = 0) */
+    double dBa_dt;                        /* background axial field ramp, T/s */
+    /* E-J law and Jc(B, T, eps) */
+    double Ec, n, Jc0, Tc, B0, eps_coef, eps_pow;
+    /* heat: C = C0 (T/T_ref)^cp_exp, constant k0 and h0, bath T_bath */
+    double C0, T_ref, cp_exp, k0, h0, T_bath;
+    double dt;              /* s */
+    int32_t heat_substeps;  /* 0 = automatic: max(1, ceil(dt / (0.9 h_max))) */
+    int32_t precision;      /* enum coil_precision */
+    double near_k;          /* mixed mode: pairs with k > near_k run in FP64 (0 -> 0.99) */
+    int32_t tile_targets;   /* field-pass tile: targets per workgroup (0 -> 256) */
+    int32_t tile_sources;   /* sources per work item (0 -> automatic) */
+    int32_t grid_limit;     /* 0: one workgroup per work item; > 0: persistent grid of at
+                               most this many workgroups striding over the work items */
+} coil_config;
+
+typedef struct {
+    /* host arrays in public order, copied at init; NULL means all ones (jc0_mult,
+       c_wire) or all zeros (strain) */
+    const double *jc0_mult;  /* N: per-element Jc0 multiplier mu_e */
+    const double *strain;    /* N: per-element strain eps_e */
+    const double *c_wire;    /* N_w: per-wire Jc multiplier c_w */
+} coil_inputs;
+
+typedef struct {
+    size_t workspace_bytes;  /* device bytes coil_init needs */
+    int64_t n_elem, n_wire;
+    int32_t heat_substeps;   /* the substep count the run will use */
+    int32_t n_work_items;    /* field-pass work items */
+} coil_sizes;
+
+typedef struct coil_s coil_t;
+
+/* diag[] passed to a report callback: 0 t, 1 step, 2 I_t of coil 0, 3 max|B|,
+   4 T_peak, 5 Q, 6 sum_w U_w, 7 max |J|/Jc of the last step */
+typedef void (*coil_report_fn)(const double *diag, int32_t ndiag, void *user);
+
+/* Sizes for a configuration.  No device work. */
+int coil_query(const coil_config *cfg, coil_sizes *out);
+
+/* Build a handle: validate, carve `workspace` (device memory, >= workspace_bytes,
+   256-byte aligned), precompute geometry, per-layer inductance blocks (host,
+   FP64), the transport-flux pattern (device, FP64 all-pairs pass), heat
+   conductances, and zero the state (I = 0, T = T_bath, Phi = 0, Q = 0).
+   `stream` is a hipStream_t (NULL = default stream).  Synchronises once. */
+int coil_init(const coil_config *cfg, const coil_inputs *in, void *workspace,
+              size_t workspace_bytes, void *stream, coil_t **out);
+
+/* Enqueue one time step (field pass, local law + wire solve, heat substeps,
+   reductions).  Asynchronous. */
+int coil_step(coil_t *h);
+
+/* nsteps steps.  If report_every > 0 and cb != NULL, synchronise every
+   report_every steps and call cb; returns COIL_E_NONFINITE if the status word
+   shows a non-finite value at a report point or at the end (state left as is). */
+int coil_run(coil_t *h, int64_t nsteps, int64_t report_every, coil_report_fn cb, void *user);
+
+/* Only the field pass (step 1) on the current currents and time; results in
+   COIL_F_BR / COIL_F_BZ.  Asynchronous. */
+int coil_compute_field(coil_t *h);
+
+/* Copy a field out in public order.  dst is device memory if dst_on_device,
+   else host memory (then the call synchronises).  count must be >= the
+   field's length (N, or N_w for per-wire fields). */
+int coil_get(coil_t *h, int32_t field, double *dst, int64_t count, int32_t dst_on_device);
+
+/* Overwrite a settable field (COIL_F_I, COIL_F_T) from public order; setting T
+   also sets the enthalpy u = u(T).  Test and resume hook. */
+int coil_set_state(coil_t *h, int32_t field, const double *src, int64_t count,
+                   int32_t src_on_device);
+
+/* Synchronise and read scalars: 0 t, 1 step, 2 Q, 3 T_peak, 4 sum U_w,
+   5 max |J|/Jc, 6 heat out through the borders, 7 stored heat sum V u,
+   8 status flags, 9 T_peak element (public index, -1 if none), 10 T_peak step,
+   11 heat substeps, 12 field-pass work items.  Writes min(n, 13) values. */
+int coil_scalars(coil_t *h, double *dst, int32_t n);
+
+/* Back to the t = 0 state (keeps the precompute). */
+int coil_reset(coil_t *h);
+
+/* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
+   recording (clears totals), 0 stops.  coil_timing_read synchronises and
+   returns per-phase totals: ms[p] and launches[p] for p = 0 field pass,
+   1 local law + wire solve, 2 heat substeps, 3 reductions (n >= 4). */
+int coil_timing(coil_t *h, int32_t enable);
+int coil_timing_read(coil_t *h, double *ms, int64_t *launches, int32_t n);
+
+/* Capture `steps` consecutive coil_step calls into a HIP graph; subsequent
+   coil_run calls replay it in chunks of `steps` (remainder eagerly).  steps = 0
+   drops the graph.  The graph holds only kernel nodes. */
+int coil_graph(coil_t *h, int64_t steps);
+
+void coil_destroy(coil_t *h);  /* does not free the caller's workspace */
+const char *coil_last_error(void);
+
+/* ---- test hook: library elliptic integrals evaluated on the host ----
+   precision COIL_FP64 or COIL_MIXED (FP32 polynomial); no device work. */
+int coil_host_ellip(double m1, int32_t precision, double *K, double *E);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COIL_H */

@@ -1,0 +1,12 @@
+"""MI355X (gfx950) coil quench hot path: HIP kernels behind a C ABI
+(include/coil.h), with a thin ctypes binding.
+
+    from paper_2403_07666_amd import Coil
+    c = Coil(workload, inputs)      # workload: coil_synth.Workload
+    c.run(100)
+    B = c.get(F_BZ)
+"""
+from .coil import (  # noqa: F401
+    FP64, MIXED, F_I, F_J, F_BR, F_BZ, F_T, F_PHI, F_QW, F_UW, F_E, F_EP, F_U, F_Q, F_PSI, F_R, F_Z,
+    F_DI, F_JC, Coil, CoilError, host_ellip, lib, query, EXPORTS,
+)

@@ -1,0 +1,281 @@
+"""Thin ctypes binding over libcoil.so (include/coil.h).
+
+Argument marshalling only: every step of the time step runs in the HIP
+kernels of the library.  PyTorch provides the device workspace and the stream.
+The binding never falls back to a CPU path: without the built library, or
+without a GPU, constructing a ``Coil`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Callable, Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcoil.so")
+
+# enum coil_status / coil_precision / coil_field (include/coil.h)
+OK, E_INVAL, E_NOMEM, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+F_I, F_J, F_BR, F_BZ, F_T, F_PHI, F_QW, F_UW, F_E, F_EP, F_U, F_Q, F_PSI, F_R, F_Z, F_DI, F_JC = range(17)
+PER_WIRE = (F_QW, F_UW)
+
+_i32p = C.POINTER(C.c_int32)
+_dp = C.POINTER(C.c_double)
+
+
+class CoilError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"coil error {code}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("n_coils", C.c_int32),
+        ("layers", _i32p), ("turns", _i32p), ("ne", _i32p),
+        ("r_inner", _dp), ("z_center", _dp), ("wire_side", _dp), ("ramp", _dp),
+        ("dBa_dt", C.c_double),
+        ("Ec", C.c_double), ("n", C.c_double), ("Jc0", C.c_double), ("Tc", C.c_double),
+        ("B0", C.c_double), ("eps_coef", C.c_double), ("eps_pow", C.c_double),
+        ("C0", C.c_double), ("T_ref", C.c_double), ("cp_exp", C.c_double), ("k0", C.c_double),
+        ("h0", C.c_double), ("T_bath", C.c_double),
+        ("dt", C.c_double),
+        ("heat_substeps", C.c_int32), ("precision", C.c_int32),
+        ("near_k", C.c_double),
+        ("tile_targets", C.c_int32), ("tile_sources", C.c_int32), ("grid_limit", C.c_int32),
+    ]
+
+
+class Inputs(C.Structure):
+    _fields_ = [("jc0_mult", _dp), ("strain", _dp), ("c_wire", _dp)]
+
+
+class Sizes(C.Structure):
+    _fields_ = [("workspace_bytes", C.c_size_t), ("n_elem", C.c_int64), ("n_wire", C.c_int64),
+                ("heat_substeps", C.c_int32), ("n_work_items", C.c_int32)]
+
+
+REPORT_FN = C.CFUNCTYPE(None, _dp, C.c_int32, C.c_void_p)
+
+EXPORTS = [
+    "coil_query", "coil_init", "coil_step", "coil_run", "coil_compute_field", "coil_get",
+    "coil_set_state", "coil_scalars", "coil_reset", "coil_timing", "coil_timing_read",
+    "coil_graph", "coil_destroy", "coil_last_error", "coil_host_ellip",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libcoil.so (built in-tree by build.py); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2403_07666_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.coil_query.argtypes = [C.POINTER(Config), C.POINTER(Sizes)]
+        L.coil_init.argtypes = [C.POINTER(Config), C.POINTER(Inputs), vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.coil_step.argtypes = [vp]
+        L.coil_run.argtypes = [vp, C.c_int64, C.c_int64, REPORT_FN, vp]
+        L.coil_compute_field.argtypes = [vp]
+        L.coil_get.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_int32]
+        L.coil_set_state.argtypes = [vp, C.c_int32, vp, C.c_int64, C.c_int32]
+        L.coil_scalars.argtypes = [vp, _dp, C.c_int32]
+        L.coil_reset.argtypes = [vp]
+        L.coil_timing.argtypes = [vp, C.c_int32]
+        L.coil_timing_read.argtypes = [vp, _dp, C.POINTER(C.c_int64), C.c_int32]
+        L.coil_graph.argtypes = [vp, C.c_int64]
+        L.coil_destroy.argtypes = [vp]
+        L.coil_destroy.restype = None
+        L.coil_last_error.restype = C.c_char_p
+        L.coil_host_ellip.argtypes = [C.c_double, C.c_int32, _dp, _dp]
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != OK:
+        raise CoilError(rc, lib().coil_last_error().decode())
+
+
+def host_ellip(m1: float, precision: int = FP64):
+    """The library's K(m), E(m) approximations evaluated on the host (m1 = 1 - m)."""
+    k, e = C.c_double(), C.c_double()
+    check(lib().coil_host_ellip(float(m1), int(precision), C.byref(k), C.byref(e)))
+    return k.value, e.value
+
+
+def _prec_id(p) -> int:
+    if p in (FP64, "fp64", "f64"):
+        return FP64
+    if p in (MIXED, "mixed"):
+        return MIXED
+    if isinstance(p, int):
+        return p  # validated by the library
+    raise ValueError(f"unknown precision {p!r}")
+
+
+class _CfgHolder:
+    """Keeps the per-coil arrays of a Config alive."""
+
+    def __init__(self, w, precision=None, tile_targets=0, tile_sources=0, grid_limit=0,
+                 near_k=0.0, heat_substeps=None):
+        co = w.coils
+        self.arr = {
+            "layers": np.array([c.layers for c in co], dtype=np.int32),
+            "turns": np.array([c.turns for c in co], dtype=np.int32),
+            "ne": np.array([c.ne for c in co], dtype=np.int32),
+            "r_inner": np.array([c.r_inner for c in co], dtype=np.float64),
+            "z_center": np.array([c.z_center for c in co], dtype=np.float64),
+            "wire_side": np.array([c.wire_side for c in co], dtype=np.float64),
+            "ramp": np.array([c.ramp for c in co], dtype=np.float64),
+        }
+        if any(c.I0 != 0.0 for c in co):
+            raise ValueError("runs start from zero current (I0 must be 0)")
+        cfg = Config()
+        cfg.n_coils = len(co)
+        for k in ("layers", "turns", "ne"):
+            setattr(cfg, k, self.arr[k].ctypes.data_as(_i32p))
+        for k in ("r_inner", "z_center", "wire_side", "ramp"):
+            setattr(cfg, k, self.arr[k].ctypes.data_as(_dp))
+        for k in ("dBa_dt", "Ec", "n", "Jc0", "Tc", "B0", "eps_coef", "eps_pow", "C0", "T_ref",
+                  "cp_exp", "k0", "h0", "T_bath", "dt"):
+            setattr(cfg, k, float(getattr(w, k)))
+        cfg.heat_substeps = int(w.heat_substeps if heat_substeps is None else heat_substeps)
+        cfg.precision = _prec_id(w.precision if precision is None else precision)
+        cfg.near_k = float(near_k)
+        cfg.tile_targets = int(tile_targets)
+        cfg.tile_sources = int(tile_sources)
+        cfg.grid_limit = int(grid_limit)
+        self.cfg = cfg
+
+
+def query(w, **kw) -> Sizes:
+    h = _CfgHolder(w, **kw)
+    s = Sizes()
+    check(lib().coil_query(C.byref(h.cfg), C.byref(s)))
+    return s
+
+
+class Coil:
+    """One handle of the HIP library on a CUDA/HIP device, with a torch-owned
+    workspace and a dedicated (default-priority) torch stream."""
+
+    def __init__(self, w, inputs: Optional[dict] = None, device: str = "cuda:0", **kw):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the coil library needs a GPU; none is visible")
+        L = lib()
+        self.w = w
+        self.device = torch.device(device)
+        self._cfg = _CfgHolder(w, **kw)
+        sizes = Sizes()
+        check(L.coil_query(C.byref(self._cfg.cfg), C.byref(sizes)))
+        self.sizes = sizes
+        self.N = int(sizes.n_elem)
+        self.Nw = int(sizes.n_wire)
+        self.n_sub = int(sizes.heat_substeps)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.Stream(device=self.device)
+            self.ws = torch.empty(int(sizes.workspace_bytes), dtype=torch.uint8, device=self.device)
+            torch.cuda.synchronize(self.device)
+        if self.ws.data_ptr() % 256 != 0:
+            raise RuntimeError("workspace is not 256-byte aligned")
+        inputs = inputs or {}
+        self._in_arrays = {k: np.ascontiguousarray(inputs[k], dtype=np.float64)
+                           for k in ("jc0_mult", "strain", "c_wire") if inputs.get(k) is not None}
+        if "jc0_mult" in self._in_arrays and self._in_arrays["jc0_mult"].size != self.N:
+            raise ValueError("jc0_mult has the wrong length")
+        if "strain" in self._in_arrays and self._in_arrays["strain"].size != self.N:
+            raise ValueError("strain has the wrong length")
+        if "c_wire" in self._in_arrays and self._in_arrays["c_wire"].size != self.Nw:
+            raise ValueError("c_wire has the wrong length")
+        inp = Inputs()
+        for k, a in self._in_arrays.items():
+            setattr(inp, k, a.ctypes.data_as(_dp))
+        h = C.c_void_p()
+        check(L.coil_init(C.byref(self._cfg.cfg), C.byref(inp), C.c_void_p(self.ws.data_ptr()),
+                          C.c_size_t(self.ws.numel()), C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.h = h
+
+    # -------------------------------------------------------------- lifetime
+    def close(self) -> None:
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().coil_destroy(h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------------------- stepping
+    def step(self) -> None:
+        check(lib().coil_step(self.h))
+
+    def run(self, nsteps: int, report_every: int = 0,
+            cb: Optional[Callable[[np.ndarray], None]] = None) -> None:
+        if cb is not None and report_every > 0:
+            def _tramp(diag, nd, _user):
+                cb(np.ctypeslib.as_array(diag, shape=(nd,)).copy())
+            fn = REPORT_FN(_tramp)
+        else:
+            fn = REPORT_FN()
+            report_every = 0
+        check(lib().coil_run(self.h, int(nsteps), int(report_every), fn, None))
+
+    def compute_field(self) -> None:
+        check(lib().coil_compute_field(self.h))
+
+    def reset(self) -> None:
+        check(lib().coil_reset(self.h))
+
+    def graph(self, steps: int) -> None:
+        check(lib().coil_graph(self.h, int(steps)))
+
+    def synchronize(self) -> None:
+        self.stream.synchronize()
+
+    # -------------------------------------------------------------- state
+    def get(self, field: int) -> np.ndarray:
+        n = self.Nw if field in PER_WIRE else self.N
+        out = np.empty(n, dtype=np.float64)
+        check(lib().coil_get(self.h, int(field), out.ctypes.data_as(C.c_void_p), n, 0))
+        return out
+
+    def get_device(self, field: int):
+        import torch
+        n = self.Nw if field in PER_WIRE else self.N
+        out = torch.empty(n, dtype=torch.float64, device=self.device)
+        check(lib().coil_get(self.h, int(field), C.c_void_p(out.data_ptr()), n, 1))
+        self.stream.synchronize()
+        return out
+
+    def set_state(self, field: int, values) -> None:
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        check(lib().coil_set_state(self.h, int(field), v.ctypes.data_as(C.c_void_p), v.size, 0))
+
+    def scalars(self) -> dict:
+        v = np.empty(13, dtype=np.float64)
+        check(lib().coil_scalars(self.h, v.ctypes.data_as(_dp), 13))
+        keys = ["t", "step", "Q", "T_peak", "sumU", "max_x", "Q_out", "stored", "status",
+                "T_peak_elem", "T_peak_step", "n_sub", "n_work_items"]
+        return dict(zip(keys, v.tolist()))
+
+    # -------------------------------------------------------------- timing
+    def timing(self, enable: bool) -> None:
+        check(lib().coil_timing(self.h, 1 if enable else 0))
+
+    def timing_read(self) -> dict:
+        ms = np.zeros(4, dtype=np.float64)
+        n = np.zeros(4, dtype=np.int64)
+        check(lib().coil_timing_read(self.h, ms.ctypes.data_as(_dp),
+                                     n.ctypes.data_as(C.POINTER(C.c_int64)), 4))
+        names = ["field", "wire", "heat", "reduce"]
+        return {nm: {"ms": float(ms[i]), "launches": int(n[i])} for i, nm in enumerate(names)}

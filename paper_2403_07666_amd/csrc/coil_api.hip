@@ -1,0 +1,922 @@
+// coil_api.hip -- host side of the C ABI declared in include/coil.h:
+// validation, device layout planning, precompute (geometry, per-layer
+// inductance blocks, heat conductances, bounding boxes, field-pass work
+// items), step sequencing, HIP event timing and HIP graph replay.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "coil_internal.h"
+
+using namespace coilq;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHECK(x)                                                                       \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess) return fail(COIL_E_HIP, "%s: %s", #x, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" const char *coil_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ plan
+namespace {
+
+struct Buf {  // one carved region
+    size_t off, bytes;
+};
+
+struct Plan {
+    int N = 0, Nw = 0, nlayers = 0, ngroups = 0, nsub = 1, max_ne2 = 1, nheat_blocks = 0;
+    int tile_targets = 256;
+    std::vector<CoilDev> coils;
+    std::vector<PairItem> items;
+    int nchunk_max = 1;
+    size_t total = 0;
+    // regions
+    Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
+        perm_b, wire_coil_b, elem_coil_b, Mlay_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
+        q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
+        sc_b, tmp_b, misc_b;
+};
+
+Buf carve(size_t &cur, size_t bytes) {
+    cur = (cur + 255) & ~size_t(255);
+    Buf b{cur, bytes};
+    cur += bytes;
+    return b;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+int validate(const coil_config *c) {
+    if (!c) return fail(COIL_E_INVAL, "config is NULL");
+    if (c->n_coils < 1 || c->n_coils > 4096) return fail(COIL_E_INVAL, "n_coils out of range");
+    if (!c->layers || !c->turns || !c->ne || !c->r_inner || !c->z_center || !c->wire_side || !c->ramp)
+        return fail(COIL_E_INVAL, "per-coil array is NULL");
+    long long N = 0;
+    for (int i = 0; i < c->n_coils; ++i) {
+        if (c->layers[i] < 1 || c->turns[i] < 1 || c->ne[i] < 1)
+            return fail(COIL_E_INVAL, "coil %d: layers, turns and ne must be >= 1", i);
+        if (c->ne[i] * c->ne[i] > kMaxWireElems)
+            return fail(COIL_E_INVAL, "coil %d: ne^2 = %d exceeds %d elements per wire", i,
+                        c->ne[i] * c->ne[i], kMaxWireElems);
+        const long long nr = (long long)c->layers[i] * c->ne[i], nz = (long long)c->turns[i] * c->ne[i];
+        if (nr > 2048 || nz > 2048)
+            return fail(COIL_E_INVAL, "coil %d: grid %lld x %lld exceeds 2048 per side", i, nr, nz);
+        if (!finite_pos(c->r_inner[i]) || !finite_pos(c->wire_side[i]) || !std::isfinite(c->z_center[i]) ||
+            !std::isfinite(c->ramp[i]))
+            return fail(COIL_E_INVAL, "coil %d: bad geometry or ramp", i);
+        N += nr * nz;
+    }
+    if (N > (1LL << 30)) return fail(COIL_E_INVAL, "too many elements");
+    if (!finite_pos(c->dt) || !finite_pos(c->Ec) || !(std::isfinite(c->n) && c->n >= 1.0) ||
+        !finite_pos(c->Jc0) || !finite_pos(c->Tc) || !finite_pos(c->B0) || !finite_pos(c->C0) ||
+        !finite_pos(c->T_ref) || !finite_pos(c->k0) || !(std::isfinite(c->h0) && c->h0 >= 0.0) ||
+        !finite_pos(c->T_bath) || !(std::isfinite(c->cp_exp) && c->cp_exp >= 0.0) ||
+        !std::isfinite(c->dBa_dt) || !(std::isfinite(c->eps_coef) && std::isfinite(c->eps_pow)))
+        return fail(COIL_E_INVAL, "material or time-step constant out of range");
+    if (c->precision != COIL_FP64 && c->precision != COIL_MIXED)
+        return fail(COIL_E_INVAL, "unknown precision %d", c->precision);
+    if (!(c->near_k == 0.0 || (c->near_k > 0.0 && c->near_k < 1.0)))
+        return fail(COIL_E_INVAL, "near_k must be in (0, 1) or 0");
+    if (c->heat_substeps < 0 || c->heat_substeps > 100000) return fail(COIL_E_INVAL, "heat_substeps out of range");
+    if (!(c->tile_targets == 0 || c->tile_targets == 64 || c->tile_targets == 128 || c->tile_targets == 256))
+        return fail(COIL_E_INVAL, "tile_targets must be 0, 64, 128 or 256");
+    if (c->tile_sources < 0 || c->tile_sources % kStage != 0)
+        return fail(COIL_E_INVAL, "tile_sources must be a non-negative multiple of %d", kStage);
+    if (c->grid_limit < 0) return fail(COIL_E_INVAL, "grid_limit must be >= 0");
+    return COIL_OK;
+}
+
+int make_plan(const coil_config *c, Plan &p) {
+    p = Plan();
+    int off = 0, woff = 0, loff = 0, goff = 0;
+    int tb = c->tile_targets;
+    long long total_blocks = 0;
+    for (int i = 0; i < c->n_coils; ++i) {
+        CoilDev d{};
+        d.ne = c->ne[i];
+        d.ne2 = d.ne * d.ne;
+        d.layers = c->layers[i];
+        d.turns = c->turns[i];
+        d.n = d.layers * d.turns * d.ne2;
+        d.off = off;
+        d.wire_off = woff;
+        d.layer_off = loff;
+        d.group_off = goff;
+        d.d = c->wire_side[i] / d.ne;
+        const double rho0 = c->r_inner[i] / d.d;
+        d.c2d = 2.0 * rho0 + 1.0;
+        d.c2f = (float)d.c2d;
+        d.kscale = kMu0 / (2.0 * kPi * d.d);
+        d.dIt = c->ramp[i] * c->dt;
+        off += d.n;
+        woff += d.layers * d.turns;
+        loff += d.layers;
+        goff += (d.n + kGroup - 1) / kGroup;
+        p.max_ne2 = std::max(p.max_ne2, d.ne2);
+        p.coils.push_back(d);
+    }
+    p.N = off;
+    p.Nw = woff;
+    p.nlayers = loff;
+    p.ngroups = goff;
+    if (tb == 0) tb = p.N <= 8192 ? 64 : 256;
+    p.tile_targets = tb;
+    for (auto &d : p.coils) total_blocks += (d.n + tb - 1) / tb;
+    // source chunks: enough work items to fill the chip (>= ~2048), chunk a
+    // multiple of the LDS stage
+    for (auto &d : p.coils) {
+        int cs = c->tile_sources;
+        if (cs == 0) {
+            long long want = std::max<long long>(1, (2048 + total_blocks - 1) / total_blocks);
+            long long maxch = (d.n + kStage - 1) / kStage;
+            long long ch = std::min(want, maxch);
+            cs = (int)(((d.n + ch - 1) / ch + kStage - 1) / kStage * kStage);
+        }
+        d.nchunk = (d.n + cs - 1) / cs;
+        p.nchunk_max = std::max(p.nchunk_max, d.nchunk);
+        for (int t0 = 0; t0 < d.n; t0 += tb)
+            for (int k = 0; k < d.nchunk; ++k) {
+                PairItem it;
+                it.coil = (int)(&d - &p.coils[0]);
+                it.t0 = d.off + t0;
+                it.tn = std::min(tb, d.n - t0);
+                it.s0 = d.off + k * cs;
+                it.sn = std::min(cs, d.n - k * cs);
+                it.chunk = k;
+                p.items.push_back(it);
+            }
+    }
+    p.nheat_blocks = (p.N + 255) / 256;
+    return COIL_OK;
+}
+
+int heat_substeps(const coil_config *c, const Plan &p) {
+    if (c->heat_substeps > 0) return c->heat_substeps;
+    // explicit stability limit at T_bath: h_max = min_e V_e C(T_bath) / (sum of
+    // the element's face and border conductances)
+    const double Cb = c->C0 * std::pow(c->T_bath / c->T_ref, c->cp_exp);
+    double hmax = INFINITY;
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        const CoilDev &d = p.coils[ci];
+        const int nr = d.layers * d.ne, nz = d.turns * d.ne;
+        const double rin = c->r_inner[ci];
+        for (int ir = 0; ir < nr; ++ir) {
+            const double re = rin + (ir + 0.5) * d.d;
+            const double V = 2.0 * kPi * re * d.d * d.d;
+            const double faces[4] = {2.0 * kPi * (rin + ir * d.d) * d.d, 2.0 * kPi * (rin + (ir + 1) * d.d) * d.d,
+                                     2.0 * kPi * re * d.d, 2.0 * kPi * re * d.d};
+            for (int iz = 0; iz < nz; ++iz) {
+                const bool has[4] = {ir > 0, ir < nr - 1, iz > 0, iz < nz - 1};
+                double g = 0.0;
+                for (int f = 0; f < 4; ++f) {
+                    if (has[f]) g += c->k0 * faces[f] / d.d;
+                    else if (c->h0 > 0.0) g += faces[f] / (1.0 / c->h0 + d.d / (2.0 * c->k0));
+                }
+                if (g > 0.0) hmax = std::min(hmax, V * Cb / g);
+            }
+        }
+    }
+    const double qt = c->dt / (0.9 * hmax);
+    const long ns = (long)std::ceil(qt * (1.0 - 1.0e-9));
+    return (int)std::max(1L, ns);
+}
+
+size_t layout(Plan &p) {
+    size_t cur = 0;
+    const size_t N = p.N, Nw = p.Nw, d8 = sizeof(double);
+    p.coils_b = carve(cur, sizeof(CoilDev) * p.coils.size());
+    p.items_b = carve(cur, sizeof(PairItem) * std::max<size_t>(1, p.items.size()));
+    p.bbox_b = carve(cur, sizeof(int4) * std::max(1, p.ngroups));
+    p.gpos_b = carve(cur, sizeof(float2) * N);
+    p.rho_b = carve(cur, d8 * N);
+    p.r_b = carve(cur, d8 * N);
+    p.V_b = carve(cur, d8 * N);
+    p.invV_b = carve(cur, d8 * N);
+    p.jcs_b = carve(cur, d8 * N);
+    p.psi_b = carve(cur, d8 * N);
+    p.G_b = carve(cur, d8 * 4 * N);
+    p.Gb_b = carve(cur, d8 * N);
+    p.nb_b = carve(cur, sizeof(int) * 4 * N);
+    p.perm_b = carve(cur, sizeof(int) * N);
+    p.wire_coil_b = carve(cur, sizeof(int) * Nw);
+    p.elem_coil_b = carve(cur, sizeof(int) * N);
+    size_t mlay = 0;
+    for (auto &d : p.coils) mlay += (size_t)d.layers * d.ne2 * d.ne2;
+    p.Mlay_b = carve(cur, d8 * mlay);
+    p.cw_b = carve(cur, d8 * Nw);
+    p.I_b = carve(cur, d8 * N);
+    p.Phi_b = carve(cur, d8 * N);
+    p.Br_b = carve(cur, d8 * N);
+    p.Bz_b = carve(cur, d8 * N);
+    p.E_b = carve(cur, d8 * N);
+    p.Ep_b = carve(cur, d8 * N);
+    p.dI_b = carve(cur, d8 * N);
+    p.q_b = carve(cur, d8 * N);
+    p.Jc_b = carve(cur, d8 * N);
+    for (int i = 0; i < 3; ++i) {
+        p.u_b[i] = carve(cur, d8 * N);
+        p.T_b[i] = carve(cur, d8 * N);
+    }
+    p.part_b = carve(cur, sizeof(double2) * N * p.nchunk_max);
+    p.Uw_b = carve(cur, d8 * Nw);
+    p.Qw_b = carve(cur, d8 * Nw);
+    p.wq_b = carve(cur, d8 * Nw);
+    p.wmaxx_b = carve(cur, d8 * Nw);
+    p.hb_max_b = carve(cur, d8 * p.nheat_blocks);
+    p.hb_arg_b = carve(cur, sizeof(long long) * p.nheat_blocks);
+    p.hb_out_b = carve(cur, d8 * (size_t)p.nheat_blocks * p.nsub);
+    p.sc_b = carve(cur, sizeof(Scalars));
+    p.tmp_b = carve(cur, d8 * std::max<size_t>(N, Nw));
+    p.misc_b = carve(cur, d8 * 64);
+    p.total = (cur + 255) & ~size_t(255);
+    return p.total;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ handle
+struct coil_s {
+    Plan plan;
+    RunConst rc{};
+    DevState ds{};
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    int grid_limit = 0;
+    double T_bath = 4.2;
+    std::vector<double> r_pub, z_pub;  // public order, for COIL_F_R / COIL_F_Z
+    // timing
+    bool timing = false;
+    struct Pending {
+        int phase;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Pending> pending;
+    double ms[4] = {0, 0, 0, 0};
+    long long launches[4] = {0, 0, 0, 0};
+    // graph
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    long long gsteps = 0;
+    bool capturing = false;
+};
+
+namespace {
+
+template <typename T>
+T *at(coil_t *h, const Buf &b) {
+    return reinterpret_cast<T *>(h->ws + b.off);
+}
+
+int ev_get(coil_t *h, hipEvent_t *e) {
+    if (!h->pool.empty()) {
+        *e = h->pool.back();
+        h->pool.pop_back();
+        return COIL_OK;
+    }
+    HIPCHECK(hipEventCreate(e));
+    return COIL_OK;
+}
+
+int t_begin(coil_t *h, hipEvent_t *a) {
+    if (!h->timing) return COIL_OK;
+    int rc = ev_get(h, a);
+    if (rc) return rc;
+    HIPCHECK(hipEventRecord(*a, h->stream));
+    return COIL_OK;
+}
+
+int t_end(coil_t *h, int phase, hipEvent_t a, int nlaunch) {
+    if (!h->timing) return COIL_OK;
+    hipEvent_t b;
+    int rc = ev_get(h, &b);
+    if (rc) return rc;
+    HIPCHECK(hipEventRecord(b, h->stream));
+    h->pending.push_back({phase, a, b});
+    h->launches[phase] += nlaunch;
+    return COIL_OK;
+}
+
+int t_flush(coil_t *h) {
+    if (h->pending.empty()) return COIL_OK;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    for (auto &p : h->pending) {
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, p.a, p.b));
+        h->ms[p.phase] += ms;
+        h->pool.push_back(p.a);
+        h->pool.push_back(p.b);
+    }
+    h->pending.clear();
+    return COIL_OK;
+}
+
+int enqueue_step(coil_t *h) {
+    hipEvent_t a = nullptr;
+    int rc;
+    if ((rc = t_begin(h, &a))) return rc;
+    HIPCHECK(launch_field(h->ds, h->rc, h->grid_limit, h->stream));
+    if ((rc = t_end(h, 0, a, 1))) return rc;
+    if ((rc = t_begin(h, &a))) return rc;
+    HIPCHECK(launch_wire(h->ds, h->rc, h->stream));
+    if ((rc = t_end(h, 1, a, 1))) return rc;
+    if ((rc = t_begin(h, &a))) return rc;
+    for (int sub = 0; sub < h->ds.nsub; ++sub) HIPCHECK(launch_heat(h->ds, h->rc, sub, h->stream));
+    if ((rc = t_end(h, 2, a, h->ds.nsub))) return rc;
+    if ((rc = t_begin(h, &a))) return rc;
+    HIPCHECK(launch_finalize(h->ds, h->rc, h->stream));
+    if ((rc = t_end(h, 3, a, 1))) return rc;
+    if (h->timing && h->pending.size() > 16384) return t_flush(h);
+    return COIL_OK;
+}
+
+int reset_state(coil_t *h) {
+    const DevState &s = h->ds;
+    hipStream_t st = h->stream;
+    HIPCHECK(launch_fill(s.I, 0.0, s.N, st));
+    HIPCHECK(launch_fill(s.Phi, 0.0, s.N, st));
+    HIPCHECK(launch_fill(s.Br, 0.0, s.N, st));
+    HIPCHECK(launch_fill(s.Bz, 0.0, s.N, st));
+    HIPCHECK(launch_fill(s.E, 0.0, s.N, st));
+    HIPCHECK(launch_fill(s.Ep, 0.0, s.N, st));
+    HIPCHECK(launch_fill(s.dI, 0.0, s.N, st));
+    HIPCHECK(launch_fill(s.q, 0.0, s.N, st));
+    HIPCHECK(launch_fill(s.Jc, 0.0, s.N, st));
+    for (int i = 0; i < 3; ++i) {
+        HIPCHECK(launch_fill(s.u[i], 0.0, s.N, st));
+        HIPCHECK(launch_fill(s.T[i], h->T_bath, s.N, st));
+    }
+    HIPCHECK(launch_fill(reinterpret_cast<double *>(s.part), 0.0, 2 * s.N * h->plan.nchunk_max, st));
+    HIPCHECK(launch_fill(s.Uw, 0.0, s.Nw, st));
+    HIPCHECK(launch_fill(s.Qw, 0.0, s.Nw, st));
+    HIPCHECK(launch_fill(s.wq, 0.0, s.Nw, st));
+    HIPCHECK(launch_fill(s.wmaxx, 0.0, s.Nw, st));
+    HIPCHECK(launch_reset_scalars(s.sc, h->T_bath, st));
+    return COIL_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ ABI
+extern "C" int coil_query(const coil_config *cfg, coil_sizes *out) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!out) return fail(COIL_E_INVAL, "out is NULL");
+    Plan p;
+    if ((rc = make_plan(cfg, p))) return rc;
+    p.nsub = heat_substeps(cfg, p);
+    layout(p);
+    out->workspace_bytes = p.total;
+    out->n_elem = p.N;
+    out->n_wire = p.Nw;
+    out->heat_substeps = p.nsub;
+    out->n_work_items = (int32_t)p.items.size();
+    return COIL_OK;
+}
+
+extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *workspace,
+                         size_t workspace_bytes, void *stream, coil_t **out) {
+    int rc = validate(cfg);
+    if (rc) return rc;
+    if (!out) return fail(COIL_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!workspace) return fail(COIL_E_INVAL, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(COIL_E_INVAL, "workspace must be 256-byte aligned");
+    coil_t *h = new (std::nothrow) coil_t();
+    if (!h) return fail(COIL_E_NOMEM, "host allocation failed");
+    std::unique_ptr<coil_t, void (*)(coil_t *)> guard(h, [](coil_t *p) { coil_destroy(p); });
+    Plan &p = h->plan;
+    if ((rc = make_plan(cfg, p))) return rc;
+    p.nsub = heat_substeps(cfg, p);
+    layout(p);
+    if (workspace_bytes < p.total)
+        return fail(COIL_E_NOMEM, "workspace of %zu bytes is smaller than the %zu needed", workspace_bytes,
+                    p.total);
+    h->ws = static_cast<char *>(workspace);
+    h->stream = static_cast<hipStream_t>(stream);
+    h->grid_limit = cfg->grid_limit;
+    h->T_bath = cfg->T_bath;
+    const int N = p.N, Nw = p.Nw;
+
+    // run constants
+    RunConst &r = h->rc;
+    r.Ec = cfg->Ec;
+    r.n = cfg->n;
+    r.Tc = cfg->Tc;
+    r.B0 = cfg->B0;
+    r.dt = cfg->dt;
+    r.dBa_dt = cfg->dBa_dt;
+    r.T_bath = cfg->T_bath;
+    r.T_ref = cfg->T_ref;
+    r.C0 = cfg->C0;
+    r.cp_exp = cfg->cp_exp;
+    const double p1 = cfg->cp_exp + 1.0;
+    r.u_a1 = p1 / (cfg->C0 * cfg->T_ref);
+    r.u_a0 = std::pow(cfg->T_bath / cfg->T_ref, p1);
+    r.u_inv = 1.0 / p1;
+    const double nk = cfg->near_k > 0.0 ? cfg->near_k : 0.99;
+    r.m1_near = (float)(1.0 - nk * nk);
+    r.prec = cfg->precision;
+
+    // host precompute, internal (wire-major) order
+    std::vector<float2> gpos(N);
+    std::vector<double> rho(N), rr(N), V(N), invV(N), jcs(N), G(4 * (size_t)N), Gb(N);
+    std::vector<int> nb(4 * (size_t)N), perm(N), wire_coil(Nw), elem_coil(N);
+    std::vector<int4> bbox(std::max(1, p.ngroups));
+    std::vector<double> Mlay;
+    std::vector<int> pub2int(N);
+    h->r_pub.assign(N, 0.0);
+    h->z_pub.assign(N, 0.0);
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        const CoilDev &d = p.coils[ci];
+        const int ne = d.ne, nz = d.turns * ne;
+        const double rin = cfg->r_inner[ci];
+        const double zbot = cfg->z_center[ci] - 0.5 * d.turns * cfg->wire_side[ci];
+        for (int L = 0; L < d.layers; ++L)
+            for (int Tn = 0; Tn < d.turns; ++Tn) {
+                const int w = d.wire_off + L * d.turns + Tn;
+                wire_coil[w] = (int)ci;
+                for (int a = 0; a < ne; ++a)
+                    for (int b = 0; b < ne; ++b) {
+                        const int e = d.off + (L * d.turns + Tn) * d.ne2 + a * ne + b;
+                        const int ir = L * ne + a, iz = Tn * ne + b;
+                        const int pub = d.off + ir * nz + iz;
+                        perm[e] = pub;
+                        pub2int[pub] = e;
+                        elem_coil[e] = (int)ci;
+                        gpos[e] = make_float2((float)ir, (float)iz);
+                        rho[e] = rin / d.d + ir + 0.5;
+                        rr[e] = rin + (ir + 0.5) * d.d;
+                        V[e] = 2.0 * kPi * rr[e] * d.d * d.d;
+                        invV[e] = 1.0 / V[e];
+                        h->r_pub[pub] = rr[e];
+                        h->z_pub[pub] = zbot + (iz + 0.5) * d.d;
+                    }
+            }
+    }
+    // Jc static part and per-wire multiplier
+    std::vector<double> cw(Nw, 1.0);
+    for (int e = 0; e < N; ++e) {
+        const int pub = perm[e];
+        const double mu = (in && in->jc0_mult) ? in->jc0_mult[pub] : 1.0;
+        const double ep = (in && in->strain) ? in->strain[pub] : 0.0;
+        jcs[e] = cfg->Jc0 * mu * (1.0 - cfg->eps_coef * std::pow(std::fabs(ep), cfg->eps_pow));
+        if (!std::isfinite(jcs[e])) return fail(COIL_E_INVAL, "non-finite Jc0 multiplier or strain at %d", pub);
+    }
+    if (in && in->c_wire)
+        for (int w = 0; w < Nw; ++w) {
+            cw[w] = in->c_wire[w];
+            if (!std::isfinite(cw[w])) return fail(COIL_E_INVAL, "non-finite c_wire at %d", w);
+        }
+    // heat conductances (axisymmetric finite volumes)
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        const CoilDev &d = p.coils[ci];
+        const int ne = d.ne, nr = d.layers * ne, nz = d.turns * ne;
+        const double rin = cfg->r_inner[ci];
+        for (int ir = 0; ir < nr; ++ir)
+            for (int iz = 0; iz < nz; ++iz) {
+                const int pub = d.off + ir * nz + iz;
+                const int e = pub2int[pub];
+                const double re = rin + (ir + 0.5) * d.d;
+                const double area[4] = {2.0 * kPi * (rin + ir * d.d) * d.d, 2.0 * kPi * (rin + (ir + 1) * d.d) * d.d,
+                                        2.0 * kPi * re * d.d, 2.0 * kPi * re * d.d};
+                const int nbp[4] = {ir > 0 ? pub - nz : -1, ir < nr - 1 ? pub + nz : -1, iz > 0 ? pub - 1 : -1,
+                                    iz < nz - 1 ? pub + 1 : -1};
+                double gb = 0.0;
+                for (int f = 0; f < 4; ++f) {
+                    if (nbp[f] >= 0) {
+                        nb[4 * (size_t)e + f] = pub2int[nbp[f]];
+                        G[4 * (size_t)e + f] = cfg->k0 * area[f] / d.d;
+                    } else {
+                        nb[4 * (size_t)e + f] = -1;
+                        G[4 * (size_t)e + f] = 0.0;
+                        if (cfg->h0 > 0.0) gb += area[f] / (1.0 / cfg->h0 + d.d / (2.0 * cfg->k0));
+                    }
+                }
+                Gb[e] = gb;
+            }
+    }
+    // bounding boxes of 64-element groups (grid indices)
+    for (const CoilDev &d : p.coils)
+        for (int g = 0; g < (d.n + kGroup - 1) / kGroup; ++g) {
+            int4 bb = make_int4(1 << 30, -(1 << 30), 1 << 30, -(1 << 30));
+            for (int e = d.off + g * kGroup; e < std::min(d.off + d.n, d.off + (g + 1) * kGroup); ++e) {
+                const int ir = (int)gpos[e].x, iz = (int)gpos[e].y;
+                bb.x = std::min(bb.x, ir);
+                bb.y = std::max(bb.y, ir);
+                bb.z = std::min(bb.z, iz);
+                bb.w = std::max(bb.w, iz);
+            }
+            bbox[d.group_off + g] = bb;
+        }
+    // per-layer inductance blocks (column-major), grid units
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        const CoilDev &d = p.coils[ci];
+        const int ne = d.ne, n = d.ne2;
+        const double rho0 = cfg->r_inner[ci] / d.d;
+        for (int L = 0; L < d.layers; ++L) {
+            const size_t base = Mlay.size();
+            Mlay.resize(base + (size_t)n * n);
+            for (int j = 0; j < n; ++j)
+                for (int i = 0; i < n; ++i) {
+                    const int ai = i / ne, bi = i % ne, aj = j / ne, bj = j % ne;
+                    const double ri = rho0 + L * ne + ai + 0.5, rj = rho0 + L * ne + aj + 0.5;
+                    double m;
+                    if (i == j) {
+                        m = kMu0 * ri * d.d * (std::log(8.0 * ri / kGmdSquare) - 2.0);
+                    } else {
+                        const double dr = (double)(ai - aj), dz = (double)(bi - bj);
+                        const double sr = ri + rj;
+                        const double al2 = dr * dr + dz * dz, be2 = sr * sr + dz * dz;
+                        const double m1 = al2 / be2;
+                        double K, E;
+                        host_ellip_f64(m1, &K, &E);
+                        m = kMu0 * std::sqrt(be2) * d.d * (0.5 * (1.0 + m1) * K - E);
+                    }
+                    Mlay[base + (size_t)j * n + i] = m;
+                }
+        }
+    }
+
+    // device pointers
+    DevState &s = h->ds;
+    s.N = N;
+    s.Nw = Nw;
+    s.ngroups = p.ngroups;
+    s.nitems = (int)p.items.size();
+    s.nheat_blocks = p.nheat_blocks;
+    s.nsub = p.nsub;
+    s.max_ne2 = p.max_ne2;
+    s.tile_targets = p.tile_targets;
+    s.coils = at<CoilDev>(h, p.coils_b);
+    s.items = at<PairItem>(h, p.items_b);
+    s.bbox = at<int4>(h, p.bbox_b);
+    s.gpos = at<float2>(h, p.gpos_b);
+    s.rho = at<double>(h, p.rho_b);
+    s.r = at<double>(h, p.r_b);
+    s.V = at<double>(h, p.V_b);
+    s.invV = at<double>(h, p.invV_b);
+    s.jcs = at<double>(h, p.jcs_b);
+    s.psi = at<double>(h, p.psi_b);
+    s.G = at<double>(h, p.G_b);
+    s.Gb = at<double>(h, p.Gb_b);
+    s.nb = at<int>(h, p.nb_b);
+    s.perm = at<int>(h, p.perm_b);
+    s.wire_coil = at<int>(h, p.wire_coil_b);
+    s.elem_coil = at<int>(h, p.elem_coil_b);
+    s.Mlay = at<double>(h, p.Mlay_b);
+    s.cw = at<double>(h, p.cw_b);
+    s.I = at<double>(h, p.I_b);
+    s.Phi = at<double>(h, p.Phi_b);
+    s.Br = at<double>(h, p.Br_b);
+    s.Bz = at<double>(h, p.Bz_b);
+    s.E = at<double>(h, p.E_b);
+    s.Ep = at<double>(h, p.Ep_b);
+    s.dI = at<double>(h, p.dI_b);
+    s.q = at<double>(h, p.q_b);
+    s.Jc = at<double>(h, p.Jc_b);
+    for (int i = 0; i < 3; ++i) {
+        s.u[i] = at<double>(h, p.u_b[i]);
+        s.T[i] = at<double>(h, p.T_b[i]);
+    }
+    s.part = at<double2>(h, p.part_b);
+    s.Uw = at<double>(h, p.Uw_b);
+    s.Qw = at<double>(h, p.Qw_b);
+    s.wq = at<double>(h, p.wq_b);
+    s.wmaxx = at<double>(h, p.wmaxx_b);
+    s.hb_max = at<double>(h, p.hb_max_b);
+    s.hb_arg = at<long long>(h, p.hb_arg_b);
+    s.hb_out = at<double>(h, p.hb_out_b);
+    s.sc = at<Scalars>(h, p.sc_b);
+    s.tmp = at<double>(h, p.tmp_b);
+
+    hipStream_t st = h->stream;
+    auto up = [&](void *dst, const void *src, size_t bytes) -> hipError_t {
+        if (bytes == 0) return hipSuccess;
+        return hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st);
+    };
+    HIPCHECK(up((void *)s.coils, p.coils.data(), sizeof(CoilDev) * p.coils.size()));
+    HIPCHECK(up((void *)s.items, p.items.data(), sizeof(PairItem) * p.items.size()));
+    HIPCHECK(up((void *)s.bbox, bbox.data(), sizeof(int4) * p.ngroups));
+    HIPCHECK(up((void *)s.gpos, gpos.data(), sizeof(float2) * N));
+    HIPCHECK(up((void *)s.rho, rho.data(), sizeof(double) * N));
+    HIPCHECK(up((void *)s.r, rr.data(), sizeof(double) * N));
+    HIPCHECK(up((void *)s.V, V.data(), sizeof(double) * N));
+    HIPCHECK(up((void *)s.invV, invV.data(), sizeof(double) * N));
+    HIPCHECK(up((void *)s.jcs, jcs.data(), sizeof(double) * N));
+    HIPCHECK(up((void *)s.G, G.data(), sizeof(double) * 4 * N));
+    HIPCHECK(up((void *)s.Gb, Gb.data(), sizeof(double) * N));
+    HIPCHECK(up((void *)s.nb, nb.data(), sizeof(int) * 4 * N));
+    HIPCHECK(up((void *)s.perm, perm.data(), sizeof(int) * N));
+    HIPCHECK(up((void *)s.wire_coil, wire_coil.data(), sizeof(int) * Nw));
+    HIPCHECK(up((void *)s.elem_coil, elem_coil.data(), sizeof(int) * N));
+    HIPCHECK(up((void *)s.Mlay, Mlay.data(), sizeof(double) * Mlay.size()));
+    HIPCHECK(up((void *)s.cw, cw.data(), sizeof(double) * Nw));
+    // transport-flux pattern: FP64 all-pairs pass on the device
+    HIPCHECK(launch_psi(s, const_cast<double *>(s.psi), st));
+    if ((rc = reset_state(h))) return rc;
+    HIPCHECK(hipStreamSynchronize(st));  // host vectors above go out of scope
+    *out = guard.release();
+    return COIL_OK;
+}
+
+extern "C" int coil_step(coil_t *h) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    return enqueue_step(h);
+}
+
+extern "C" int coil_compute_field(coil_t *h) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    HIPCHECK(launch_field(h->ds, h->rc, h->grid_limit, h->stream));
+    HIPCHECK(launch_field_finalize(h->ds, h->rc, h->stream));
+    return COIL_OK;
+}
+
+static int read_scalars(coil_t *h, Scalars *out) {
+    HIPCHECK(hipMemcpyAsync(out, h->ds.sc, sizeof(Scalars), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return COIL_OK;
+}
+
+static int max_B(coil_t *h, double *out) {
+    const int N = h->ds.N;
+    std::vector<double> br(N), bz(N);
+    HIPCHECK(hipMemcpyAsync(br.data(), h->ds.Br, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipMemcpyAsync(bz.data(), h->ds.Bz, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    double m = 0.0;
+    for (int i = 0; i < N; ++i) m = std::max(m, std::hypot(br[i], bz[i]));
+    *out = m;
+    return COIL_OK;
+}
+
+extern "C" int coil_run(coil_t *h, int64_t nsteps, int64_t report_every, coil_report_fn cb, void *user) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (nsteps < 0 || report_every < 0) return fail(COIL_E_INVAL, "negative step count");
+    int rc;
+    int64_t done = 0;
+    while (done < nsteps) {
+        int64_t chunk = nsteps - done;
+        if (report_every > 0 && cb) chunk = std::min<int64_t>(chunk, report_every);
+        int64_t k = 0;
+        if (h->gexec && !h->timing && h->gsteps > 0) {
+            for (; k + h->gsteps <= chunk; k += h->gsteps) HIPCHECK(hipGraphLaunch(h->gexec, h->stream));
+        }
+        for (; k < chunk; ++k)
+            if ((rc = enqueue_step(h))) return rc;
+        done += chunk;
+        if (report_every > 0 && cb) {
+            Scalars sc;
+            if ((rc = read_scalars(h, &sc))) return rc;
+            double mb = 0.0;
+            if ((rc = max_B(h, &mb))) return rc;
+            const double t = (double)sc.step * h->rc.dt;
+            const double It0 = h->plan.coils[0].dIt / h->rc.dt * t;
+            const double diag[8] = {t, (double)sc.step, It0, mb, sc.Tpeak, sc.Q, sc.sumU, sc.maxx};
+            cb(diag, 8, user);
+            if (sc.status) return fail(COIL_E_NONFINITE, "non-finite state (status 0x%x) at step %lld", sc.status, sc.step);
+        }
+    }
+    Scalars sc;
+    if ((rc = read_scalars(h, &sc))) return rc;
+    if (sc.status) return fail(COIL_E_NONFINITE, "non-finite state (status 0x%x) at step %lld", sc.status, sc.step);
+    return COIL_OK;
+}
+
+static int field_len(coil_t *h, int field, int *len, int *per_wire) {
+    *per_wire = 0;
+    switch (field) {
+        case COIL_F_QW:
+        case COIL_F_UW:
+            *per_wire = 1;
+            *len = h->ds.Nw;
+            return COIL_OK;
+        case COIL_F_I: case COIL_F_J: case COIL_F_BR: case COIL_F_BZ: case COIL_F_T: case COIL_F_PHI:
+        case COIL_F_E: case COIL_F_EP: case COIL_F_U: case COIL_F_Q: case COIL_F_PSI: case COIL_F_R:
+        case COIL_F_Z: case COIL_F_DI: case COIL_F_JC:
+            *len = h->ds.N;
+            return COIL_OK;
+        default:
+            return fail(COIL_E_INVAL, "unknown field %d", field);
+    }
+}
+
+extern "C" int coil_get(coil_t *h, int32_t field, double *dst, int64_t count, int32_t dst_on_device) {
+    if (!h || !dst) return fail(COIL_E_INVAL, "NULL argument");
+    int len, pw, rc;
+    if ((rc = field_len(h, field, &len, &pw))) return rc;
+    if (count < len) return fail(COIL_E_INVAL, "count %lld < field length %d", (long long)count, len);
+    const DevState &s = h->ds;
+    hipStream_t st = h->stream;
+    const hipMemcpyKind kind = dst_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (field == COIL_F_R || field == COIL_F_Z) {
+        const std::vector<double> &v = field == COIL_F_R ? h->r_pub : h->z_pub;
+        HIPCHECK(hipMemcpyAsync(dst, v.data(), sizeof(double) * len,
+                                dst_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+        return COIL_OK;
+    }
+    if (pw) {
+        const double *src = field == COIL_F_QW ? s.Qw : s.Uw;
+        HIPCHECK(hipMemcpyAsync(dst, src, sizeof(double) * len, kind, st));
+        if (!dst_on_device) HIPCHECK(hipStreamSynchronize(st));
+        return COIL_OK;
+    }
+    const double *src = nullptr;
+    switch (field) {
+        case COIL_F_I: src = s.I; break;
+        case COIL_F_BR: src = s.Br; break;
+        case COIL_F_BZ: src = s.Bz; break;
+        case COIL_F_T: src = s.T[0]; break;
+        case COIL_F_PHI: src = s.Phi; break;
+        case COIL_F_E: src = s.E; break;
+        case COIL_F_EP: src = s.Ep; break;
+        case COIL_F_U: src = s.u[0]; break;
+        case COIL_F_Q: src = s.q; break;
+        case COIL_F_PSI: src = s.psi; break;
+        case COIL_F_DI: src = s.dI; break;
+        case COIL_F_JC: src = s.Jc; break;
+        case COIL_F_J: src = s.I; break;
+        default: return fail(COIL_E_INVAL, "field %d not readable", field);
+    }
+    double *stage = dst_on_device ? dst : s.tmp;
+    HIPCHECK(launch_gather(src, s.perm, len, stage, st));
+    if (!dst_on_device) {
+        HIPCHECK(hipMemcpyAsync(dst, s.tmp, sizeof(double) * len, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+    }
+    if (field == COIL_F_J) {
+        // J = I / d^2 per coil (public order is coil-concatenated)
+        if (dst_on_device) {
+            std::vector<double> tmp(len);
+            HIPCHECK(hipMemcpyAsync(tmp.data(), dst, sizeof(double) * len, hipMemcpyDeviceToHost, st));
+            HIPCHECK(hipStreamSynchronize(st));
+            for (const CoilDev &d : h->plan.coils)
+                for (int i = d.off; i < d.off + d.n; ++i) tmp[i] /= d.d * d.d;
+            HIPCHECK(hipMemcpyAsync(dst, tmp.data(), sizeof(double) * len, hipMemcpyHostToDevice, st));
+            HIPCHECK(hipStreamSynchronize(st));
+        } else {
+            for (const CoilDev &d : h->plan.coils)
+                for (int i = d.off; i < d.off + d.n; ++i) dst[i] /= d.d * d.d;
+        }
+    }
+    return COIL_OK;
+}
+
+extern "C" int coil_set_state(coil_t *h, int32_t field, const double *src, int64_t count,
+                              int32_t src_on_device) {
+    if (!h || !src) return fail(COIL_E_INVAL, "NULL argument");
+    if (field != COIL_F_I && field != COIL_F_T) return fail(COIL_E_INVAL, "field %d is not settable", field);
+    const DevState &s = h->ds;
+    if (count < s.N) return fail(COIL_E_INVAL, "count %lld < %d", (long long)count, s.N);
+    hipStream_t st = h->stream;
+    const double *pub = src;
+    if (!src_on_device) {
+        HIPCHECK(hipMemcpyAsync(s.tmp, src, sizeof(double) * s.N, hipMemcpyHostToDevice, st));
+        pub = s.tmp;
+    }
+    if (field == COIL_F_I) {
+        HIPCHECK(launch_scatter(pub, s.perm, s.N, s.I, st));
+    } else {
+        HIPCHECK(launch_scatter(pub, s.perm, s.N, s.T[0], st));
+        HIPCHECK(launch_u_of_T(s, h->rc, st));
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    return COIL_OK;
+}
+
+extern "C" int coil_scalars(coil_t *h, double *dst, int32_t n) {
+    if (!h || !dst) return fail(COIL_E_INVAL, "NULL argument");
+    Scalars sc;
+    int rc;
+    if ((rc = read_scalars(h, &sc))) return rc;
+    double *misc = at<double>(h, h->plan.misc_b);
+    HIPCHECK(launch_stored(h->ds, misc, h->stream));
+    double stored = 0.0;
+    HIPCHECK(hipMemcpyAsync(&stored, misc, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    const double v[13] = {(double)sc.step * h->rc.dt, (double)sc.step, sc.Q, sc.Tpeak, sc.sumU, sc.maxx,
+                          sc.Qout, stored, (double)sc.status, (double)sc.Tpeak_pub, (double)sc.Tpeak_step,
+                          (double)h->ds.nsub, (double)h->ds.nitems};
+    for (int i = 0; i < n && i < 13; ++i) dst[i] = v[i];
+    return COIL_OK;
+}
+
+extern "C" int coil_reset(coil_t *h) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    int rc = reset_state(h);
+    if (rc) return rc;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return COIL_OK;
+}
+
+extern "C" int coil_timing(coil_t *h, int32_t enable) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (h->capturing) return fail(COIL_E_STATE, "timing cannot change during graph capture");
+    int rc = t_flush(h);
+    if (rc) return rc;
+    h->timing = enable != 0;
+    if (h->timing)
+        for (int i = 0; i < 4; ++i) {
+            h->ms[i] = 0.0;
+            h->launches[i] = 0;
+        }
+    return COIL_OK;
+}
+
+extern "C" int coil_timing_read(coil_t *h, double *ms, int64_t *launches, int32_t n) {
+    if (!h || !ms || !launches) return fail(COIL_E_INVAL, "NULL argument");
+    int rc = t_flush(h);
+    if (rc) return rc;
+    for (int i = 0; i < n && i < 4; ++i) {
+        ms[i] = h->ms[i];
+        launches[i] = h->launches[i];
+    }
+    return COIL_OK;
+}
+
+extern "C" int coil_graph(coil_t *h, int64_t steps) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (steps < 0) return fail(COIL_E_INVAL, "steps < 0");
+    if (h->gexec) {
+        HIPCHECK(hipGraphExecDestroy(h->gexec));
+        h->gexec = nullptr;
+    }
+    if (h->graph) {
+        HIPCHECK(hipGraphDestroy(h->graph));
+        h->graph = nullptr;
+    }
+    h->gsteps = 0;
+    if (steps == 0) return COIL_OK;
+    if (h->stream == nullptr) return fail(COIL_E_STATE, "graph capture needs a non-default stream");
+    if (h->timing) return fail(COIL_E_STATE, "disable timing before capturing a graph");
+    h->capturing = true;
+    HIPCHECK(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    int rc = COIL_OK;
+    for (int64_t k = 0; k < steps && rc == COIL_OK; ++k) rc = enqueue_step(h);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->stream, &g);
+    h->capturing = false;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(COIL_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    h->graph = g;
+    HIPCHECK(hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0));
+    h->gsteps = steps;
+    return COIL_OK;
+}
+
+extern "C" void coil_destroy(coil_t *h) {
+    if (!h) return;
+    if (h->stream || h->ws) (void)hipStreamSynchronize(h->stream);
+    for (auto &p : h->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : h->pool) (void)hipEventDestroy(e);
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    delete h;
+}
+
+extern "C" int coil_host_ellip(double m1, int32_t precision, double *K, double *E) {
+    if (!K || !E) return fail(COIL_E_INVAL, "NULL argument");
+    if (!(m1 > 0.0 && m1 <= 1.0)) return fail(COIL_E_INVAL, "m1 must be in (0, 1]");
+    if (precision == COIL_FP64) {
+        host_ellip_f64(m1, K, E);
+    } else if (precision == COIL_MIXED) {
+        float k, e;
+        host_ellip_f32((float)m1, &k, &e);
+        *K = k;
+        *E = e;
+    } else {
+        return fail(COIL_E_INVAL, "unknown precision");
+    }
+    return COIL_OK;
+}

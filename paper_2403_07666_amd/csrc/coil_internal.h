@@ -1,0 +1,117 @@
+// coil_internal.h -- device data layout and kernel launchers shared by the
+// C-ABI host code (coil_api.hip) and the kernels (coil_kernels.hip).
+//
+// Internal element order ("wire-major"): coils concatenated; inside a coil
+// wires in order w = layer*turns + turn, inside a wire the ne x ne elements in
+// order a*ne + b (a radial, b axial).  A wire's elements are contiguous, so a
+// 64-lane wavefront covers one wire (ne = 8) or a compact block of wires, and
+// the per-wire solve reads contiguous memory.  perm[] maps internal -> public.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "coil.h"
+
+namespace coilq {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kMu0 = 4.0e-7 * kPi;
+// geometric mean distance of a unit square from itself, exp(<ln|p-q|>)
+constexpr double kGmdSquare = 0.4470491559036625;
+constexpr int kGroup = 64;       // bounding-box group = one wavefront of targets
+constexpr int kMaxWireElems = 64;  // per-wire solve keeps one element per lane
+constexpr int kStage = 256;      // sources staged in LDS per pass
+
+struct CoilDev {
+    int off;        // first element (internal order)
+    int n;          // elements
+    int ne, ne2;    // elements per wire side, per wire
+    int layers, turns;
+    int wire_off;   // first wire
+    int layer_off;  // first per-layer inductance block
+    int group_off;  // first 64-element bounding-box group
+    int nchunk;     // source chunks of the field pass (partial-sum slots)
+    float c2f;      // 2 r_inner/d + 1 in grid units (FP32)
+    double c2d;     // same, FP64
+    double kscale;  // mu0 / (2 pi d): field per ampere in grid units
+    double d;       // element side
+    double dIt;     // transport-current increment per step
+};
+
+struct PairItem {
+    int coil, t0, tn, s0, sn, chunk;
+};
+
+// device-resident scalars
+struct Scalars {
+    double Q, Tpeak, sumU, maxx, Qout;
+    long long step, Tpeak_pub, Tpeak_step;
+    unsigned int status;
+    unsigned int pad;
+};
+
+enum : unsigned { ST_NONFINITE = 1u, ST_PIVOT = 2u, ST_JC = 4u };
+
+// global constants of a run
+struct RunConst {
+    double Ec, n, Tc, B0, dt, dBa_dt;
+    double T_bath, T_ref, C0, cp_exp;
+    double u_a1;    // (p+1)/(C0 T_ref)
+    double u_a0;    // (T_bath/T_ref)^(p+1)
+    double u_inv;   // 1/(p+1)
+    float m1_near;  // mixed mode: pairs with m1 < m1_near run in FP64
+    int prec;
+};
+
+// all device pointers of a handle
+struct DevState {
+    int N, Nw, ngroups, nitems, nheat_blocks, nsub;
+    const CoilDev *coils;
+    const PairItem *items;
+    const int4 *bbox;        // per group: min ir, max ir, min iz, max iz
+    const float2 *gpos;      // (i_r, i_z) grid indices inside the coil
+    const double *rho;       // radius in grid units
+    const double *r, *V, *invV, *jcs, *psi;
+    const double *G, *Gb;    // heat face conductances (4 per element), border
+    const int *nb;           // 4 neighbours per element, -1 = border
+    const int *perm;         // internal -> public index
+    const int *wire_coil;    // coil of each wire
+    const int *elem_coil;    // coil of each element
+    int max_ne2;             // largest elements-per-wire over the coils
+    int tile_targets;        // field pass: targets per workgroup (= block size)
+    const double *Mlay;      // per layer ne2 x ne2, column-major
+    const double *cw;        // per-wire Jc multiplier
+    double *I, *Phi, *Br, *Bz, *E, *Ep, *dI, *q, *Jc;
+    double *u[3], *T[3];     // [0] canonical state, [1], [2] heat scratch
+    double2 *part;           // field partial sums: [chunk][N]
+    double *Uw, *Qw, *wq, *wmaxx;
+    double *hb_max;          // per heat block: max T of the last substep
+    long long *hb_arg;       // its public index
+    double *hb_out;          // [nsub][blocks]: heat out through the borders
+    Scalars *sc;
+    double *tmp;             // N doubles of staging for get/set
+};
+
+// ---- launchers (coil_kernels.hip) ----
+hipError_t launch_field(const DevState &s, const RunConst &rc, int grid_limit, hipStream_t st);
+hipError_t launch_field_finalize(const DevState &s, const RunConst &rc, hipStream_t st);
+hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st);
+hipError_t launch_heat(const DevState &s, const RunConst &rc, int sub, hipStream_t st);
+hipError_t launch_finalize(const DevState &s, const RunConst &rc, hipStream_t st);
+hipError_t launch_psi(const DevState &s, double *psi_out, hipStream_t st);
+hipError_t launch_gather(const double *src, const int *perm, int n, double *dst, hipStream_t st);
+hipError_t launch_scatter(const double *src, const int *perm, int n, double *dst, hipStream_t st);
+hipError_t launch_u_of_T(const DevState &s, const RunConst &rc, hipStream_t st);
+hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
+hipError_t launch_reset_scalars(Scalars *sc, double T_bath, hipStream_t st);
+hipError_t launch_stored(const DevState &s, double *out, hipStream_t st);
+void heat_buffers(int nsub, int sub, int *src, int *dst);
+
+// host-side copies of the elliptic approximations (same coefficients)
+void host_ellip_f64(double m1, double *K, double *E);
+void host_ellip_f32(float m1, float *K, float *E);
+
+}  // namespace coilq

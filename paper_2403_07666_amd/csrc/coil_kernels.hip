@@ -1,0 +1,642 @@
+// coil_kernels.hip -- gfx950 kernels of the coil quench time step.
+//
+// Field pass (the O(N^2) part; paper, Methods "Numerical Algorithm": the field
+// of every subelement is updated from the net currents of all subelements):
+//   B_e = sum_{j != e} G_B(e, j) I_j over the elements of the same coil, with
+//   the coaxial-ring Green's function
+//     B_z = mu0 I / (2 pi al2 be) [ (a^2 - r^2 - dz^2) E + al2 K ]
+//     B_r = mu0 I dz / (2 pi r al2 be) [ (a^2 + r^2 + dz^2) E - al2 K ]
+//   al2 = (r-a)^2 + dz^2, be2 = (r+a)^2 + dz^2, m1 = 1 - k^2 = al2 / be2,
+//   K, E the complete elliptic integrals (polynomial-log forms, on the fly).
+// Coordinates are grid indices inside the coil (r = (rho0 + i_r + 1/2) d,
+// z = (i_z + 1/2) d + z0): r - a and dz are exact small integers in FP32 as in
+// FP64, so al2 is exact and the near-singular argument m1 carries one rounding.
+//
+// Tiling: a workgroup of 64..256 threads owns as many targets (one per thread);
+// sources stream through LDS in stages of 256 and are read as wave-wide
+// broadcasts.  Work items (target block x source chunk) write partial sums to
+// part[chunk][target]; the consumer reduces them in a fixed order.
+// Mixed precision: per (64-target group, 64-source group) pair the bounding
+// boxes bound m1 from below; pairs that may reach m1 < m1_near (k > near_k)
+// run entirely in FP64, the others in FP32 with one plain FP32 partial per
+// 64-source group and Kahan compensation across groups.  The branch is uniform
+// per wavefront.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "coil_internal.h"
+#include "ellip_coeffs.h"
+
+namespace coilq {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+// FP64 pair: adds the (B_r * rho_t, B_z) contribution of a source of strength
+// sv (= mu0 I / (2 pi d)) at grid offsets (dr, dz), sr = rho_t + rho_s.
+__device__ __forceinline__ void pair64(double dr, double dz, double sr, double sv, double &ar,
+                                       double &az) {
+    const double dz2 = dz * dz;
+    const double al2 = fma(dr, dr, dz2);
+    const double be2 = fma(sr, sr, dz2);
+    const double rb = rsqrt(be2);
+    const double m1 = al2 * (rb * rb);
+    const double L = -log(m1);
+    const double K = fma(ellipk64_Q(m1), L, ellipk64_P(m1));
+    const double E = fma(ellipe64_Q(m1), L, ellipe64_P(m1));
+    const double f = sv * rb / al2;
+    const double alK = al2 * K;
+    const double gz = fma(fma(-dr, sr, -dz2), E, alK);
+    const double gr = dz * fma(0.5 * (al2 + be2), E, -alK);
+    const bool ok = al2 > 0.0;  // the element's own ring is excluded
+    az = ok ? fma(f, gz, az) : az;
+    ar = ok ? fma(f, gr, ar) : ar;
+}
+
+// FP32 pair (far field): same formula; -log2(m1), rsqrt, rcp in hardware.
+__device__ __forceinline__ void pair32(float dr, float dz, float sr, float sv, float &ar,
+                                       float &az) {
+    const float dz2 = dz * dz;
+    const float al2 = fmaf(dr, dr, dz2);
+    const float be2 = fmaf(sr, sr, dz2);
+    const float rb = __builtin_amdgcn_rsqf(be2);
+    const float m1 = al2 * (rb * rb);
+    const float L2 = -__builtin_amdgcn_logf(m1);
+    const float K = fmaf(ellipk32_Q(m1), L2, ellipk32_P(m1));
+    const float E = fmaf(ellipe32_Q(m1), L2, ellipe32_P(m1));
+    const float f = sv * rb * __builtin_amdgcn_rcpf(al2);
+    const float alK = al2 * K;
+    const float gz = fmaf(fmaf(-dr, sr, -dz2), E, alK);
+    const float gr = dz * fmaf(0.5f * (al2 + be2), E, -alK);
+    az = fmaf(f, gz, az);
+    ar = fmaf(f, gr, ar);
+}
+
+// Can a pair of 64-element groups with these grid bounding boxes reach
+// m1 < m1_near?  m1 >= min al2 / max be2 over the boxes.
+__device__ __forceinline__ bool groups_near(int4 a, int4 b, float c2f, float m1_near) {
+    const int dr = max(0, max(b.x - a.y, a.x - b.y));
+    const int dz = max(0, max(b.z - a.w, a.z - b.w));
+    const float al2 = (float)(dr * dr + dz * dz);
+    const float sr = c2f + (float)(a.y + b.y);
+    const int dzm = max(abs(a.w - b.z), abs(b.w - a.z));
+    const float be2 = fmaf(sr, sr, (float)dzm * (float)dzm);
+    return al2 < m1_near * be2 * 1.0001f;
+}
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// ------------------------------------------------------------------ field pass
+template <int MIXED>
+__global__ __launch_bounds__(256) void k_field(DevState s, RunConst rc) {
+    __shared__ float4 sp[kStage];  // (i_r, i_z, strength fp32, 0)
+    __shared__ double ss[kStage];  // strength fp64
+    const int tid = threadIdx.x;
+    for (int it = blockIdx.x; it < s.nitems; it += gridDim.x) {
+        const PairItem item = s.items[it];
+        const CoilDev c = s.coils[item.coil];
+        const int t = item.t0 + tid;
+        const bool tact = tid < item.tn;
+        const float2 tp = s.gpos[tact ? t : item.t0];
+        const double tr = tp.x, tz = tp.y;
+        const double c2t = c.c2d + tr;
+        const float tr32 = tp.x, tz32 = tp.y;
+        const float c2t32 = c.c2f + tp.x;
+        // this wavefront's target group (t0 is group aligned)
+        const int wbase = item.t0 + (tid & ~63);
+        const bool wact = wbase < item.t0 + item.tn;
+        int4 tb = make_int4(0, 0, 0, 0);
+        if (MIXED && wact) tb = s.bbox[c.group_off + (wbase - c.off) / kGroup];
+        double nr = 0.0, nz = 0.0;
+        float fr = 0.f, fz = 0.f, cr = 0.f, cz = 0.f;
+        const int send = item.s0 + item.sn;
+        for (int s0 = item.s0; s0 < send; s0 += kStage) {
+            const int cnt = min(kStage, send - s0);
+            __syncthreads();
+            for (int i = tid; i < cnt; i += blockDim.x) {
+                const float2 p = s.gpos[s0 + i];
+                const double sv = s.I[s0 + i] * c.kscale;
+                sp[i] = make_float4(p.x, p.y, (float)sv, 0.f);
+                ss[i] = sv;
+            }
+            __syncthreads();
+            if (!wact) continue;
+            for (int g0 = 0; g0 < cnt; g0 += kGroup) {
+                const int gn = min(kGroup, cnt - g0);
+                bool near = true;
+                if (MIXED) {
+                    const int4 sb = s.bbox[c.group_off + (s0 + g0 - c.off) / kGroup];
+                    near = groups_near(tb, sb, c.c2f, rc.m1_near);
+                }
+                if (near) {
+#pragma unroll 4
+                    for (int j = g0; j < g0 + gn; ++j) {
+                        const float4 q = sp[j];
+                        pair64(tr - (double)q.x, tz - (double)q.y, c2t + (double)q.x, ss[j], nr, nz);
+                    }
+                } else {
+                    float pr = 0.f, pz = 0.f;
+#pragma unroll 8
+                    for (int j = g0; j < g0 + gn; ++j) {
+                        const float4 q = sp[j];
+                        pair32(tr32 - q.x, tz32 - q.y, c2t32 + q.x, q.z, pr, pz);
+                    }
+                    kahan_add(fr, cr, pr);
+                    kahan_add(fz, cz, pz);
+                }
+            }
+        }
+        if (tact) {
+            const double br = nr + ((double)fr - (double)cr);
+            const double bz = nz + ((double)fz - (double)cz);
+            s.part[(size_t)item.chunk * s.N + t] = make_double2(br, bz);
+        }
+    }
+}
+
+// B at element e from the partial sums (FP64, fixed order)
+__device__ __forceinline__ void field_at(const DevState &s, const CoilDev &c, int e, double Ba,
+                                         double &br, double &bz) {
+    double xr = 0.0, xz = 0.0;
+    for (int k = 0; k < c.nchunk; ++k) {
+        const double2 p = s.part[(size_t)k * s.N + e];
+        xr += p.x;
+        xz += p.y;
+    }
+    br = xr / s.rho[e];
+    bz = xz + Ba;
+}
+
+__global__ __launch_bounds__(256) void k_field_finalize(DevState s, RunConst rc, const int *elem_coil) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= s.N) return;
+    const CoilDev c = s.coils[elem_coil[e]];
+    const double Ba = rc.dBa_dt * (double)s.sc->step * rc.dt;
+    double br, bz;
+    field_at(s, c, e, Ba, br, bz);
+    s.Br[e] = br;
+    s.Bz[e] = bz;
+}
+
+// ------------------------------------------------------------------ local law + per-wire A-V solve
+// One wavefront per wire, one element per lane (n_e <= 64).  The wire's
+// matrix A = M_ww + dt diag(2 pi r E'/d^2) lives in LDS, column-major with
+// leading dimension n_e + 1; right-looking Cholesky, then two triangular
+// solves for the right-hand sides b and 1 with the solutions in registers.
+__global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
+    extern __shared__ double sm[];
+    const int w = blockIdx.x;
+    const int lane = threadIdx.x;
+    const CoilDev c = s.coils[s.wire_coil[w]];
+    const int lw = w - c.wire_off;
+    const int layer = lw / c.turns;
+    const int n = c.ne2;
+    const int ld = n + 1;
+    const bool act = lane < n;
+    const int e = c.off + lw * n + (act ? lane : 0);
+    const double dt = rc.dt;
+    const double tk = (double)s.sc->step * dt;
+    const double dBa = rc.dBa_dt * dt;
+    unsigned bad = 0;
+
+    double br, bz;
+    field_at(s, c, e, rc.dBa_dt * tk, br, bz);
+    const double I0 = s.I[e];
+    const double d2 = c.d * c.d;
+    const double J = I0 / d2;
+    const double T = s.T[0][e];
+    const double Bm = sqrt(br * br + bz * bz);
+    const double fT = fmax(0.0, 1.0 - T / rc.Tc);
+    const double Jc = s.cw[w] * s.jcs[e] * fT * rc.B0 / (rc.B0 + Bm);
+    double E = 0.0, Ep = 0.0, x = 0.0;
+    if (act && J != 0.0) {
+        if (!(Jc > 0.0)) {
+            bad |= ST_JC;
+        } else {
+            x = fabs(J) / Jc;
+            const double p = pow(x, rc.n - 1.0);
+            Ep = rc.n * rc.Ec / Jc * p;
+            E = copysign(rc.Ec * p * x, J);
+        }
+    }
+    const double re = s.r[e];
+    const double* M = s.Mlay + (size_t)(c.layer_off + layer) * n * n;
+    if (act)
+        for (int col = 0; col < n; ++col) sm[col * ld + lane] = M[col * n + lane];
+    __syncthreads();
+    if (act) sm[lane * ld + lane] += dt * 2.0 * kPi * re * Ep / d2;
+    const double b = act ? (-c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * E) : 0.0;
+
+    for (int j = 0; j < n; ++j) {
+        __syncthreads();
+        const double djj = sm[j * ld + j];
+        if (!(djj > 0.0)) bad |= ST_PIVOT;
+        const double ljj = sqrt(djj);
+        __syncthreads();
+        if (act && lane > j) sm[j * ld + lane] /= ljj;
+        if (lane == j) sm[j * ld + j] = ljj;
+        __syncthreads();
+        const double lij = (act && lane > j) ? sm[j * ld + lane] : 0.0;
+        for (int k = j + 1; k < n; ++k) {
+            const double lkj = sm[j * ld + k];
+            if (act && lane >= k) sm[k * ld + lane] -= lij * lkj;
+        }
+    }
+    __syncthreads();
+    double xv = b, yv = act ? 1.0 : 0.0;
+    for (int j = 0; j < n; ++j) {  // L z = rhs
+        const double ljj = sm[j * ld + j];
+        const double xj = __shfl(xv, j) / ljj;
+        const double yj = __shfl(yv, j) / ljj;
+        if (lane == j) { xv = xj; yv = yj; }
+        if (act && lane > j) {
+            const double l = sm[j * ld + lane];
+            xv -= l * xj;
+            yv -= l * yj;
+        }
+    }
+    for (int j = n - 1; j >= 0; --j) {  // L^T x = z
+        const double ljj = sm[j * ld + j];
+        const double xj = __shfl(xv, j) / ljj;
+        const double yj = __shfl(yv, j) / ljj;
+        if (lane == j) { xv = xj; yv = yj; }
+        if (act && lane < j) {
+            const double l = sm[lane * ld + j];
+            xv -= l * xj;
+            yv -= l * yj;
+        }
+    }
+    const double sx = wave_sum(act ? xv : 0.0);
+    const double sy = wave_sum(act ? yv : 0.0);
+    const double U = (sx - c.dIt) / (dt * sy);
+    const double dI = act ? xv - dt * U * yv : 0.0;
+    // flux update Phi += M_ww dI + dI_t Psi_u + pi r^2 dB_a
+    double mdi = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double dj = __shfl(dI, j);
+        if (act) mdi += M[j * n + lane] * dj;
+    }
+    double qv = 0.0;
+    if (act) {
+        const double I1 = I0 + dI;
+        const double Elin = E + Ep * dI / d2;
+        qv = Elin * (I1 / d2);
+        s.Phi[e] += mdi + c.dIt * s.psi[e] + kPi * re * re * dBa;
+        s.I[e] = I1;
+        s.dI[e] = dI;
+        s.E[e] = E;
+        s.Ep[e] = Ep;
+        s.q[e] = qv;
+        s.Jc[e] = Jc;
+        s.Br[e] = br;
+        s.Bz[e] = bz;
+        if (!isfinite(I1) || !isfinite(qv)) bad |= ST_NONFINITE;
+    }
+    const double qw = wave_sum(act ? dt * s.V[e] * qv : 0.0);
+    const double mx = wave_max(x);
+    bad = wave_or(bad);
+    if (lane == 0) {
+        s.Uw[w] = U;
+        s.wq[w] = qw;
+        s.Qw[w] += qw;
+        s.wmaxx[w] = mx;
+        if (bad) atomicOr(&s.sc->status, bad);
+    }
+}
+
+// ------------------------------------------------------------------ heat
+__device__ __forceinline__ double T_of_u(const RunConst &rc, double u) {
+    const double x = fma(u, rc.u_a1, rc.u_a0);
+    return rc.T_ref * (rc.cp_exp == 3.0 ? sqrt(sqrt(x)) : pow(x, rc.u_inv));
+}
+
+// one explicit substep: (u, T)[src] -> (u, T)[dst]
+__global__ __launch_bounds__(256) void k_heat(DevState s, RunConst rc, int src, int dst, int sub,
+                                              int last) {
+    __shared__ double red_o[256];
+    __shared__ double red_t[256];
+    __shared__ long long red_i[256];
+    const int tid = threadIdx.x;
+    const int e = blockIdx.x * 256 + tid;
+    const double hs = rc.dt / (double)s.nsub;
+    double outv = 0.0, Tn = -INFINITY;
+    long long pub = LLONG_MAX;
+    if (e < s.N) {
+        const double *Ts = s.T[src];
+        const double Te = Ts[e];
+        double flux = s.Gb[e] * (rc.T_bath - Te);
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+            const int nbr = s.nb[4 * e + f];
+            if (nbr >= 0) flux += s.G[4 * e + f] * (Ts[nbr] - Te);
+        }
+        const double un = s.u[src][e] + hs * s.invV[e] * flux + hs * s.q[e];
+        Tn = T_of_u(rc, un);
+        s.u[dst][e] = un;
+        s.T[dst][e] = Tn;
+        outv = hs * s.Gb[e] * (Te - rc.T_bath);
+        pub = s.perm[e];
+        if (!isfinite(Tn)) atomicOr(&s.sc->status, ST_NONFINITE);
+    }
+    red_o[tid] = outv;
+    red_t[tid] = Tn;
+    red_i[tid] = pub;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) {
+            red_o[tid] += red_o[tid + o];
+            const double a = red_t[tid], b = red_t[tid + o];
+            if (b > a || (b == a && red_i[tid + o] < red_i[tid])) {
+                red_t[tid] = b;
+                red_i[tid] = red_i[tid + o];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        s.hb_out[(size_t)sub * s.nheat_blocks + blockIdx.x] = red_o[0];
+        if (last) {
+            s.hb_max[blockIdx.x] = red_t[0];
+            s.hb_arg[blockIdx.x] = red_i[0];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ reductions
+__global__ __launch_bounds__(256) void k_finalize(DevState s, RunConst rc) {
+    __shared__ double a_q[256], a_u[256], a_x[256], a_o[256], a_t[256];
+    __shared__ long long a_i[256];
+    const int tid = threadIdx.x;
+    double q = 0.0, u = 0.0, x = 0.0, o = 0.0, tm = -INFINITY;
+    long long ti = LLONG_MAX;
+    for (int w = tid; w < s.Nw; w += 256) {
+        q += s.wq[w];
+        u += s.Uw[w];
+        x = fmax(x, s.wmaxx[w]);
+    }
+    const int no = s.nsub * s.nheat_blocks;
+    for (int i = tid; i < no; i += 256) o += s.hb_out[i];
+    for (int b = tid; b < s.nheat_blocks; b += 256) {
+        const double v = s.hb_max[b];
+        const long long iv = s.hb_arg[b];
+        if (v > tm || (v == tm && iv < ti)) { tm = v; ti = iv; }
+    }
+    a_q[tid] = q; a_u[tid] = u; a_x[tid] = x; a_o[tid] = o; a_t[tid] = tm; a_i[tid] = ti;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (tid < k) {
+            a_q[tid] += a_q[tid + k];
+            a_u[tid] += a_u[tid + k];
+            a_x[tid] = fmax(a_x[tid], a_x[tid + k]);
+            a_o[tid] += a_o[tid + k];
+            const double v = a_t[tid + k];
+            if (v > a_t[tid] || (v == a_t[tid] && a_i[tid + k] < a_i[tid])) {
+                a_t[tid] = v;
+                a_i[tid] = a_i[tid + k];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        Scalars *sc = s.sc;
+        sc->Q += a_q[0];
+        sc->sumU = a_u[0];
+        sc->maxx = a_x[0];
+        sc->Qout += a_o[0];
+        const long long stepn = sc->step + 1;
+        if (a_t[0] > sc->Tpeak) {
+            sc->Tpeak = a_t[0];
+            sc->Tpeak_pub = a_i[0];
+            sc->Tpeak_step = stepn;
+        }
+        if (!isfinite(sc->Q)) sc->status |= ST_NONFINITE;
+        sc->step = stepn;
+    }
+}
+
+// ------------------------------------------------------------------ transport-flux pattern (init)
+// Psi_u,e = sum over the other wires' elements j of M(e, j) / n_e(j), with
+// Maxwell's M = mu0 be [ (1+m1)/2 K - E ] (be in metres), FP64.
+__global__ __launch_bounds__(256) void k_psi(DevState s, const int *elem_coil, double *psi) {
+    __shared__ float2 sp[kStage];
+    const int tid = threadIdx.x;
+    const int t = blockIdx.x * 256 + tid;
+    const bool tact = t < s.N;
+    // every element of a 256-block belongs to one coil only if coils are
+    // 256-aligned; handle mixed blocks by looping over the coils it touches
+    const int t_first = blockIdx.x * 256;
+    const int t_last = min(s.N, t_first + 256) - 1;
+    const int c_first = elem_coil[t_first], c_last = elem_coil[t_last];
+    const int tc = tact ? elem_coil[t] : -1;
+    double acc = 0.0;
+    const float2 tp = s.gpos[tact ? t : t_first];
+    for (int ci = c_first; ci <= c_last; ++ci) {
+        const CoilDev c = s.coils[ci];
+        const int twire = tact && tc == ci ? (t - c.off) / c.ne2 : -1;
+        const double tr = tp.x, tz = tp.y;
+        for (int s0 = c.off; s0 < c.off + c.n; s0 += kStage) {
+            const int cnt = min(kStage, c.off + c.n - s0);
+            __syncthreads();
+            if (tid < cnt) sp[tid] = s.gpos[s0 + tid];
+            __syncthreads();
+            if (tc != ci) continue;
+            for (int j = 0; j < cnt; ++j) {
+                const int swire = (s0 + j - c.off) / c.ne2;
+                if (swire == twire) continue;
+                const float2 q = sp[j];
+                const double dr = tr - (double)q.x, dz = tz - (double)q.y;
+                const double sr = c.c2d + tr + (double)q.x;
+                const double al2 = fma(dr, dr, dz * dz);
+                const double be2 = fma(sr, sr, dz * dz);
+                const double m1 = al2 / be2;
+                const double L = -log(m1);
+                const double K = fma(ellipk64_Q(m1), L, ellipk64_P(m1));
+                const double E = fma(ellipe64_Q(m1), L, ellipe64_P(m1));
+                acc += kMu0 * sqrt(be2) * c.d * (0.5 * (1.0 + m1) * K - E) / (double)c.ne2;
+            }
+        }
+    }
+    if (tact) psi[t] = acc;
+}
+
+// ------------------------------------------------------------------ small kernels
+__global__ void k_gather(const double *src, const int *perm, int n, double *dst) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[perm[i]] = src[i];  // internal i -> public perm[i]
+}
+__global__ void k_scatter(const double *src, const int *perm, int n, double *dst) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[perm[i]];  // public perm[i] -> internal i
+}
+__global__ void k_fill(double *p, double v, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+__global__ void k_u_of_T(DevState s, RunConst rc) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= s.N) return;
+    const double T = s.T[0][e];
+    const double p1 = rc.cp_exp + 1.0;
+    s.u[0][e] = rc.C0 * rc.T_ref / p1 * (pow(T / rc.T_ref, p1) - rc.u_a0);
+}
+__global__ void k_reset_scalars(Scalars *sc, double T_bath) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc->Q = 0.0;
+        sc->Tpeak = T_bath;
+        sc->sumU = 0.0;
+        sc->maxx = 0.0;
+        sc->Qout = 0.0;
+        sc->step = 0;
+        sc->Tpeak_pub = -1;
+        sc->Tpeak_step = -1;
+        sc->status = 0;
+        sc->pad = 0;
+    }
+}
+__global__ __launch_bounds__(256) void k_stored(DevState s, double *out) {
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    double a = 0.0;
+    for (int e = tid; e < s.N; e += 256) a += s.V[e] * s.u[0][e];
+    red[tid] = a;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if (tid < k) red[tid] += red[tid + k];
+        __syncthreads();
+    }
+    if (tid == 0) *out = red[0];
+}
+
+__global__ void k_copy2(const double *a, const double *b, double *ad, double *bd, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) {
+        ad[i] = a[i];
+        bd[i] = b[i];
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+static inline int blocks_for(int n) { return (n + 255) / 256; }
+
+hipError_t launch_field(const DevState &s, const RunConst &rc, int grid_limit, hipStream_t st) {
+    if (s.nitems == 0) return hipSuccess;
+    const int grid = grid_limit > 0 ? min(grid_limit, s.nitems) : s.nitems;
+    if (rc.prec == COIL_MIXED)
+        hipLaunchKernelGGL(k_field<1>, dim3(grid), dim3(s.tile_targets), 0, st, s, rc);
+    else
+        hipLaunchKernelGGL(k_field<0>, dim3(grid), dim3(s.tile_targets), 0, st, s, rc);
+    return hipGetLastError();
+}
+
+hipError_t launch_field_finalize(const DevState &s, const RunConst &rc, hipStream_t st) {
+    hipLaunchKernelGGL(k_field_finalize, dim3(blocks_for(s.N)), dim3(256), 0, st, s, rc, s.elem_coil);
+    return hipGetLastError();
+}
+
+hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st) {
+    const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
+    hipLaunchKernelGGL(k_wire, dim3(s.Nw), dim3(64), lds, st, s, rc);
+    return hipGetLastError();
+}
+
+void heat_buffers(int nsub, int sub, int *src, int *dst) {
+    // substep sub reads buffer src and writes dst; the last substep of a step
+    // lands in buffer 0 (for nsub = 1 the result goes to 1 and is copied back)
+    if (nsub == 1) {
+        *src = 0;
+        *dst = 1;
+    } else {
+        *src = (sub == 0) ? 0 : 1 + ((sub - 1) & 1);
+        *dst = (sub == nsub - 1) ? 0 : 1 + (sub & 1);
+    }
+}
+
+hipError_t launch_heat(const DevState &s, const RunConst &rc, int sub, hipStream_t st) {
+    int src, dst;
+    heat_buffers(s.nsub, sub, &src, &dst);
+    hipLaunchKernelGGL(k_heat, dim3(s.nheat_blocks), dim3(256), 0, st, s, rc, src, dst, sub,
+                       sub == s.nsub - 1 ? 1 : 0);
+    hipError_t err = hipGetLastError();
+    if (err == hipSuccess && s.nsub == 1) {
+        hipLaunchKernelGGL(k_copy2, dim3(blocks_for(s.N)), dim3(256), 0, st, s.u[1], s.T[1],
+                           s.u[0], s.T[0], s.N);
+        err = hipGetLastError();
+    }
+    return err;
+}
+
+hipError_t launch_finalize(const DevState &s, const RunConst &rc, hipStream_t st) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, s, rc);
+    return hipGetLastError();
+}
+
+hipError_t launch_psi(const DevState &s, double *psi_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_psi, dim3(blocks_for(s.N)), dim3(256), 0, st, s, s.elem_coil, psi_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const double *src, const int *perm, int n, double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(n)), dim3(256), 0, st, src, perm, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const double *src, const int *perm, int n, double *dst, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter, dim3(blocks_for(n)), dim3(256), 0, st, src, perm, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_u_of_T(const DevState &s, const RunConst &rc, hipStream_t st) {
+    hipLaunchKernelGGL(k_u_of_T, dim3(blocks_for(s.N)), dim3(256), 0, st, s, rc);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double *p, double v, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset_scalars(Scalars *sc, double T_bath, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(64), 0, st, sc, T_bath);
+    return hipGetLastError();
+}
+
+hipError_t launch_stored(const DevState &s, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_stored, dim3(1), dim3(256), 0, st, s, out);
+    return hipGetLastError();
+}
+
+// host copies of the elliptic approximations (test hook)
+void host_ellip_f64(double m1, double *K, double *E) {
+    const double L = -std::log(m1);
+    *K = std::fma(ellipk64_Q(m1), L, ellipk64_P(m1));
+    *E = std::fma(ellipe64_Q(m1), L, ellipe64_P(m1));
+}
+void host_ellip_f32(float m1, float *K, float *E) {
+    const float L2 = -std::log2(m1);
+    *K = std::fma(ellipk32_Q(m1), L2, ellipk32_P(m1));
+    *E = std::fma(ellipe32_Q(m1), L2, ellipe32_P(m1));
+}
+
+}  // namespace coilq

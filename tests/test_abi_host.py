@@ -1,0 +1,82 @@
+"""Host-side checks of the HIP library: it loads, exports every symbol the
+header declares, validates configurations, sizes workspaces, and its
+elliptic approximations match library values (no GPU work)."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import coil_synth as cs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _pk():
+    import paper_2403_07666_amd as pk
+    return pk
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "coil.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(coil_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    pk = _pk()
+    L = pk.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(L, name), name
+    assert set(declared) == set(pk.EXPORTS)
+
+
+def test_query_sizes_and_substeps_match_workloads():
+    import oracle
+    pk = _pk()
+    for name, N, Nw, nsub in [("c1", 512, 32, 2), ("c2", 131072, 2048, 4), ("c5", 384000, 6000, 4)]:
+        w = cs.workload(name)
+        s = pk.query(w)
+        assert (s.n_elem, s.n_wire, s.heat_substeps) == (N, Nw, nsub)
+        assert s.workspace_bytes > 8 * 20 * N
+    # the library's substep rule agrees with the oracle's on ensembles too
+    w = cs.workload("c4").replace(coils=[cs.Coil(2, 3, 6), cs.Coil(3, 2, 6, ramp=2.0)])
+    assert pk.query(w).heat_substeps == oracle.Sim(w).n_sub == 4
+
+
+def test_validation_errors():
+    pk = _pk()
+    w = cs.workload("c1")
+    bad = [
+        w.replace(dt=0.0),
+        w.replace(Jc0=-1.0),
+        w.replace(coils=[cs.Coil(layers=1, turns=1, ne=9)]),  # 81 elements per wire
+        w.replace(coils=[cs.Coil(layers=0, turns=1, ne=2)]),
+        w.replace(h0=-1.0),
+        w.replace(n=0.5),
+    ]
+    for b in bad:
+        with pytest.raises(pk.CoilError) as ei:
+            pk.query(b)
+        assert ei.value.code == -1
+    with pytest.raises(pk.CoilError):
+        pk.query(w, precision=7)
+    with pytest.raises(pk.CoilError):
+        pk.query(w, tile_targets=100)
+    with pytest.raises(pk.CoilError):
+        pk.query(w, tile_sources=100)
+
+
+def test_library_elliptic_approximations():
+    from scipy.special import ellipe, ellipkm1
+    pk = _pk()
+    for m1 in np.concatenate([np.logspace(-9, -1, 33), np.linspace(0.02, 1.0, 50)]):
+        K, E = pk.host_ellip(m1, pk.FP64)
+        assert abs(K / ellipkm1(m1) - 1) < 1e-15
+        assert abs(E / ellipe(1 - m1) - 1) < 1e-15 * max(1.0, -math.log(m1))
+        k32, e32 = pk.host_ellip(m1, pk.MIXED)
+        assert abs(k32 / ellipkm1(m1) - 1) < 3e-7
+        assert abs(e32 / ellipe(1 - m1) - 1) < 3e-7
