@@ -1,0 +1,201 @@
+"""Benchmark of the coil quench hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2] [--precision mixed]
+
+A step is one full coil_step (field pass, local law + per-wire A-V solve,
+explicit heat substeps, reductions) of the 131,072-element coil
+(32 layers x 64 turns x 8x8 elements, seeded synthetic inputs), in mixed
+precision, with all inputs resident in HBM.  The timed region is K steps
+bracketed by device synchronisation; per-kernel durations come from HIP
+events the library records on its own stream inside that region.
+
+Validity: after the timed run the same number of steps is run in FP64 from
+the same initial state and the normwise relative error of B and T (mixed
+against FP64) is reported; the run is flagged invalid above 1e-5.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks (dense, per GPU)
+PEAK_FP32_TFLOPS = 157.3      # vector FP32 with packed FMA
+PEAK_FP32_UNPACKED = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+# algorithmic work of one (target, source) pair of the field pass, FP32 path:
+# coordinate differences 3, al2/be2/dz^2 5, rsqrt 1, m1 2, log2 1, K 18, E 18,
+# f 3, al2 K 1, B_z bracket 4, B_r bracket 5, accumulation 4 -> 65 flop
+# (an FMA counts 2, a hardware transcendental 1)
+FLOP_PER_PAIR = 65
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def nerr(a, b):
+    import numpy as np
+    s = np.abs(b).max()
+    return float(np.abs(a - b).max() / s) if s > 0 else float(np.abs(a).max())
+
+
+def cpu_baseline(w, budget_s: float = 12.0) -> dict:
+    """The oracle's field sum (the O(N^2) part of a step) on a bounded sample
+    of targets of the same coil, all N sources, on the host cores; scaled to
+    steps/s of the full coil."""
+    import coil_synth as cs
+    import oracle
+    o = oracle.Sim(w, field_only=True)
+    I = cs.random_currents(w.n_elem, seed=5)
+    n = 32
+    while True:
+        tg = cs.sample_indices(w.n_elem, n, seed=9)
+        t0 = time.perf_counter()
+        o.field_targets(I, tg)
+        dt = time.perf_counter() - t0
+        if dt * 4 > budget_s or n >= w.n_elem:
+            break
+        n = min(w.n_elem, int(n * max(2.0, min(8.0, budget_s / max(dt, 1e-3) / 2))))
+    pairs = n * (w.n_elem - 1)
+    pps = pairs / dt
+    return {
+        "value": pps / w.pairs_per_pass(),
+        "unit": "steps/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": f"field sum at {n} seeded targets x {w.n_elem} sources "
+                  f"({pairs:.3g} pair evaluations, {dt:.1f} s); scaled by pairs per step",
+        "pairs_per_s": pps,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--no-check", action="store_true", help="skip the FP64 validity run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--graph", type=int, default=0, help="capture the step loop in HIP graphs of this many steps")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
+              "implementation in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import coil_synth as cs
+    import paper_2403_07666_amd as pk
+
+    w = cs.workload(args.workload)
+    inp = cs.generate(w)
+    log(f"[bench] {w.name}: N={w.n_elem} wires={w.n_wire} precision={args.precision}")
+    t0 = time.perf_counter()
+    g = pk.Coil(w, inp, precision=args.precision)
+    log(f"[bench] init {time.perf_counter() - t0:.2f} s, substeps {g.n_sub}, "
+        f"work items {g.sizes.n_work_items}")
+    g.run(args.warmup)
+    if args.graph > 0:
+        g.graph(args.graph)
+    else:
+        g.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = g.timing_read() if args.graph == 0 else None
+    g.timing(False)
+    sps = args.steps / elapsed
+    log(f"[bench] {args.steps} steps in {elapsed:.3f} s -> {sps:.2f} steps/s")
+
+    pairs = w.pairs_per_pass()
+    roofline = None
+    if tm is not None and tm["field"]["launches"] > 0:
+        avg_ms = tm["field"]["ms"] / tm["field"]["launches"]
+        achieved = FLOP_PER_PAIR * pairs / (avg_ms * 1e-3) / 1e12
+        roofline = {
+            "bound": "alu",
+            "kernel": "k_field (all-pairs ring field pass)",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "frac_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
+            "traffic": None,
+            "avg_launch_ms": avg_ms,
+            "flop_per_pair": FLOP_PER_PAIR,
+            "pairs_per_launch": pairs,
+            "phase_ms_per_step": {k: v["ms"] / max(1, args.steps) for k, v in tm.items()},
+        }
+
+    check = None
+    if not args.no_check and args.precision == "mixed":
+        total = args.warmup + args.steps
+        Bm = (g.get(pk.F_BR), g.get(pk.F_BZ))
+        Tm = g.get(pk.F_T)
+        g.close()
+        log(f"[bench] FP64 reference run of {total} steps")
+        r = pk.Coil(w, inp, precision="fp64")
+        r.run(total)
+        eb = max(nerr(Bm[0], r.get(pk.F_BR)), nerr(Bm[1], r.get(pk.F_BZ)))
+        et = nerr(Tm, r.get(pk.F_T))
+        r.close()
+        check = {"steps": total, "rel_err_B": eb, "rel_err_T": et, "valid": bool(eb <= 1e-5 and et <= 1e-5)}
+        log(f"[bench] mixed vs FP64: B {eb:.2e} T {et:.2e}")
+    else:
+        g.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU oracle baseline")
+        cpu = cpu_baseline(w)
+        log(f"[bench] oracle {cpu['pairs_per_s']:.3g} pairs/s on {cpu['cores']} threads")
+
+    out = {
+        "metric": "steps/s @131k elems mixed vs FP64 (rel err<=1e-5); Ginteractions/s; adjoint/fwd",
+        "value": sps,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "n_elem": w.n_elem,
+            "n_wire": w.n_wire,
+            "coil": f"{w.coils[0].layers} layers x {w.coils[0].turns} turns x "
+                    f"{w.coils[0].ne}x{w.coils[0].ne} elements" if len(w.coils) == 1 else len(w.coils),
+            "precision": args.precision,
+            "dt": w.dt,
+            "heat_substeps": g.n_sub,
+            "seed": w.seed,
+            "graph_steps": args.graph,
+        },
+        "ginteractions_per_s": pairs * sps / 1e9,
+        "mixed_vs_fp64": check,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

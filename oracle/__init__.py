@@ -73,8 +73,11 @@ def lib():
         L.orc_ring_M.restype = C.c_double
         L.orc_self_L.argtypes = [C.c_double] * 2
         L.orc_self_L.restype = C.c_double
+        L.orc_threads.restype = C.c_int
         L.orc_create.argtypes = [C.POINTER(Cfg), _dp, _dp, _dp]
         L.orc_create.restype = C.c_void_p
+        L.orc_create_ex.argtypes = [C.POINTER(Cfg), _dp, _dp, _dp, C.c_int]
+        L.orc_create_ex.restype = C.c_void_p
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_n_elem.argtypes = [C.c_void_p]
         L.orc_n_elem.restype = C.c_long
@@ -134,6 +137,11 @@ def self_L(r, d):
     return lib().orc_self_L(float(r), float(d))
 
 
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return int(lib().orc_threads())
+
+
 # ---------------------------------------------------------------- simulation
 def make_cfg(w, n_sub: int | None = None, planar: bool = False) -> Cfg:
     """Oracle configuration from a ``coil_synth.Workload``."""
@@ -157,7 +165,7 @@ class Sim:
     """One oracle simulation (public element order)."""
 
     def __init__(self, w, inputs: dict | None = None, n_sub: int | None = None,
-                 planar: bool = False):
+                 planar: bool = False, field_only: bool = False):
         self.w = w
         self.cfg = make_cfg(w, n_sub=n_sub, planar=planar)
         L = lib()
@@ -166,7 +174,7 @@ class Sim:
         self._keep = [_f64(inputs[k]) if k in inputs else None
                       for k in ("jc0_mult", "strain", "c_wire")]
         ptrs = [(_p(a) if a is not None else None) for a in self._keep]
-        self.h = L.orc_create(C.byref(self.cfg), *ptrs)
+        self.h = L.orc_create_ex(C.byref(self.cfg), *ptrs, 1 if field_only else 0)
         if not self.h:
             raise ValueError("oracle rejected the configuration")
         self.N = L.orc_n_elem(self.h)

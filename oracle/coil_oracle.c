@@ -52,6 +52,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PI 3.14159265358979323846
 #define ORC_MU0 (4.0e-7 * ORC_PI)
@@ -196,7 +199,16 @@ struct orc_sim {
     double *I, *u, *T, *Phi, *Br, *Bz, *E, *Ep, *Jc, *dI, *q, *Qw, *U;
     double Q, Tpeak, Qout, maxx, sumU;
     long step, Tpeak_e, Tpeak_k;
+    int field_only;  /* geometry only: no inductance blocks, no transport flux */
 };
+
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 long orc_n_elem(const orc_sim *s) { return s->N; }
 long orc_n_wire(const orc_sim *s) { return s->Nw; }
@@ -295,6 +307,11 @@ static void build_heat(orc_sim *s) {
 
 orc_sim *orc_create(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
                     const double *c_wire) {
+    return orc_create_ex(cfg, jc0_mult, strain, c_wire, 0);
+}
+
+orc_sim *orc_create_ex(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
+                       const double *c_wire, int field_only) {
     if (!cfg || !cfg_valid(cfg)) return NULL;
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
     s->cfg = *cfg;
@@ -358,8 +375,9 @@ orc_sim *orc_create(const orc_cfg *cfg, const double *jc0_mult, const double *st
     for (long w = 0; w < Nw; ++w) s->cw[w] = c_wire ? c_wire[w] : 1.0;
     /* per-wire inductance blocks (R2) */
     s->Mww = (double **)calloc((size_t)Nw, sizeof(double *));
+    s->field_only = field_only;
     #pragma omp parallel for schedule(dynamic, 4)
-    for (long w = 0; w < Nw; ++w) {
+    for (long w = 0; w < (field_only ? 0 : Nw); ++w) {
         const int n = s->wn[w];
         const long *el = s->welem + s->wire_off[w];
         double *M = dalloc((long)n * n);
@@ -375,7 +393,7 @@ orc_sim *orc_create(const orc_cfg *cfg, const double *jc0_mult, const double *st
        current carried uniformly by every other wire of the same coil */
     s->psi = dalloc(N);
     #pragma omp parallel for schedule(dynamic, 64)
-    for (long e = 0; e < N; ++e) {
+    for (long e = 0; e < (field_only ? 0 : N); ++e) {
         const int ci = s->coil[e];
         nsum acc = {0.0, 0.0};
         for (long j = s->coil_off[ci]; j < s->coil_off[ci + 1]; ++j) {
@@ -494,6 +512,7 @@ static void chol_solve(const double *L, int n, double *x) { /* L L^T x = b in pl
 /* one time step                                                       */
 /* ------------------------------------------------------------------ */
 int orc_step(orc_sim *s) {
+    if (s->field_only) return -1;
     const orc_cfg *c = &s->cfg;
     const long N = s->N, Nw = s->Nw;
     const double dt = c->dt;

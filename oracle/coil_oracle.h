@@ -55,11 +55,18 @@ double orc_ring_M(double a, double zs, double r, double z);
 /* self inductance of a ring of radius r with a square d x d section */
 double orc_self_L(double r, double d);
 
+/* OpenMP threads the oracle's parallel loops use */
+int    orc_threads(void);
+
 /* ---- simulation ---- */
 /* inputs in public order: jc0_mult[N], strain[N], c_wire[Nw].  Returns NULL
    on invalid configuration. */
 orc_sim *orc_create(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
                     const double *c_wire);
+/* field_only = 1: geometry only (no inductance blocks, no transport-flux
+   pattern); orc_field_targets/points work, orc_step returns -1 */
+orc_sim *orc_create_ex(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
+                       const double *c_wire, int field_only);
 void   orc_destroy(orc_sim *s);
 long   orc_n_elem(const orc_sim *s);
 long   orc_n_wire(const orc_sim *s);
