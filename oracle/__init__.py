@@ -232,3 +232,22 @@ class Sim:
         out = np.empty(4096, dtype=np.int64)
         n = lib().orc_wire_elems(self.h, int(w), out.ctypes.data_as(_lp))
         return out[:n].copy()
+
+
+def tangent(w, inputs: dict, dc_wire=None, dramp=None, nsteps: int | None = None):
+    """Forward-mode directional derivatives of (Q, T_peak) after nsteps along
+    (dc_wire, dramp).  Returns (obj, dobj) as two 2-tuples."""
+    cfg = make_cfg(w)
+    keep = [_f64(inputs[k]) if inputs.get(k) is not None else None
+            for k in ("jc0_mult", "strain", "c_wire")]
+    ptr = [(_p(a) if a is not None else None) for a in keep]
+    dcw = _f64(dc_wire) if dc_wire is not None else None
+    drp = _f64(dramp) if dramp is not None else None
+    obj = np.zeros(2)
+    dobj = np.zeros(2)
+    rc = lib().orc_tangent(C.byref(cfg), *ptr, _p(dcw) if dcw is not None else None,
+                           _p(drp) if drp is not None else None, int(nsteps or w.steps),
+                           _p(obj), _p(dobj))
+    if rc:
+        raise RuntimeError(f"oracle tangent failed ({rc})")
+    return tuple(obj), tuple(dobj)

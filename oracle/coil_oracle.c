@@ -727,3 +727,143 @@ int orc_scalars(const orc_sim *s, double *dst, int n) {
     for (int i = 0; i < n && i < 12; ++i) dst[i] = v[i];
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* tangent-linear model (forward-mode derivative of the step)          */
+/* ------------------------------------------------------------------ */
+/* Differentiates the same discrete step along a direction in the per-wire Jc
+   multipliers c_w and the per-coil ramp rates.  The primal step is
+   orc_step(); the tangent lines below use its intermediate values (B^k, Jc,
+   E, E', dI at step k) and re-derive the heat substep temperatures.
+   Non-smooth points take the zero branch: |B| = 0, T >= Tc, J = 0.  The peak
+   temperature's derivative is that of the element and step where the peak was
+   last raised. */
+int orc_tangent(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
+                const double *c_wire, const double *dc_wire, const double *dramp,
+                long nsteps, double *obj, double *dobj) {
+    orc_sim *s = orc_create(cfg, jc0_mult, strain, c_wire);
+    if (!s) return -1;
+    const orc_cfg *c = &s->cfg;
+    const long N = s->N, Nw = s->Nw;
+    const double dt = c->dt;
+    const double hs = dt / (double)s->n_sub;
+    double *dI = dalloc(N), *du = dalloc(N), *Ik = dalloc(N), *Tk = dalloc(N), *uk = dalloc(N);
+    double *dBr = dalloc(N), *dBz = dalloc(N), *dE = dalloc(N), *dEp = dalloc(N), *ddI = dalloc(N);
+    double *dq = dalloc(N), *Tsub = dalloc(N), *usub = dalloc(N), *dTsub = dalloc(N);
+    double *unew = dalloc(N), *dunew = dalloc(N);
+    double dQ = 0.0, dTpeak = 0.0;
+    int rc = 0;
+    for (long k = 0; k < nsteps && rc == 0; ++k) {
+        memcpy(Ik, s->I, sizeof(double) * (size_t)N);
+        memcpy(Tk, s->T, sizeof(double) * (size_t)N);
+        memcpy(uk, s->u, sizeof(double) * (size_t)N);
+        rc = orc_step(s);
+        if (rc) break;
+        /* 1. field tangent */
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (long e = 0; e < N; ++e) field_at_element(s, dI, e, &dBr[e], &dBz[e]);
+        /* 2. local law tangent at step k */
+        for (long e = 0; e < N; ++e) {
+            const double d2 = s->d[e] * s->d[e];
+            const double J = Ik[e] / d2;
+            dE[e] = 0.0;
+            dEp[e] = 0.0;
+            if (J == 0.0) continue;
+            const double Br = s->Br[e], Bz = s->Bz[e];
+            const double Bm = sqrt(Br * Br + Bz * Bz);
+            const double dBm = Bm > 0.0 ? (Br * dBr[e] + Bz * dBz[e]) / Bm : 0.0;
+            const double Ck = c->C0 * pow(Tk[e] / c->T_ref, c->cp_exp);
+            const double dT = du[e] / Ck;
+            const double fT = fmax(0.0, 1.0 - Tk[e] / c->Tc);
+            const double dfT = (Tk[e] < c->Tc) ? -dT / c->Tc : 0.0;
+            const double fB = c->B0 / (c->B0 + Bm);
+            const double dfB = -c->B0 / ((c->B0 + Bm) * (c->B0 + Bm)) * dBm;
+            const int w = s->wire[e];
+            const double Jc = s->Jc[e];
+            const double dJc = (dc_wire ? dc_wire[w] : 0.0) * s->jcs[e] * fT * fB
+                             + s->cw[w] * s->jcs[e] * (dfT * fB + fT * dfB);
+            const double x = fabs(J) / Jc;
+            const double dx = x * ((dI[e] / d2) / J - dJc / Jc);
+            const double sg = J > 0.0 ? 1.0 : -1.0;
+            dE[e] = c->Ec * c->n * pow(x, c->n - 1.0) * dx * sg;
+            dEp[e] = c->n * c->Ec * ((c->n - 1.0) * pow(x, c->n - 2.0) * dx / Jc
+                                     - pow(x, c->n - 1.0) * dJc / (Jc * Jc));
+        }
+        /* 3. per-wire KKT tangent */
+        #pragma omp parallel for schedule(dynamic, 4)
+        for (long w = 0; w < Nw; ++w) {
+            const int n = s->wn[w];
+            const int ci = s->wcoil[w];
+            const double ddIt = (dramp ? dramp[ci] : 0.0) * dt;
+            const long *el = s->welem + s->wire_off[w];
+            double *A = dalloc((long)n * n), *x = dalloc(n), *y = dalloc(n);
+            memcpy(A, s->Mww[w], sizeof(double) * (size_t)n * n);
+            for (int i = 0; i < n; ++i) {
+                const long e = el[i];
+                const double d2 = s->d[e] * s->d[e];
+                const double kap = 2.0 * ORC_PI * s->r[e] / d2;
+                A[i * n + i] += dt * kap * s->Ep[e];
+                x[i] = -ddIt * s->psi[e] - dt * 2.0 * ORC_PI * s->r[e] * dE[e]
+                       - dt * kap * dEp[e] * s->dI[e];
+                y[i] = 1.0;
+            }
+            if (cholesky(A, n) == 0) {
+                chol_solve(A, n, x);
+                chol_solve(A, n, y);
+                double sx = 0.0, sy = 0.0;
+                for (int i = 0; i < n; ++i) { sx += x[i]; sy += y[i]; }
+                const double dmu = (sx - ddIt) / sy;
+                for (int i = 0; i < n; ++i) ddI[el[i]] = x[i] - dmu * y[i];
+            }
+            free(A); free(x); free(y);
+        }
+        /* 4. current and Joule-source tangents */
+        nsum qs = {0.0, 0.0};
+        for (long e = 0; e < N; ++e) {
+            const double d2 = s->d[e] * s->d[e];
+            const double I1 = s->I[e];
+            dI[e] += ddI[e];
+            const double Elin = s->E[e] + s->Ep[e] * s->dI[e] / d2;
+            const double dElin = dE[e] + dEp[e] * s->dI[e] / d2 + s->Ep[e] * ddI[e] / d2;
+            dq[e] = dElin * (I1 / d2) + Elin * (dI[e] / d2);
+            ns_add(&qs, dt * s->V[e] * dq[e]);
+        }
+        dQ += ns_val(&qs);
+        /* 5. heat tangent, re-deriving the primal substeps from u^k */
+        memcpy(usub, uk, sizeof(double) * (size_t)N);
+        memcpy(Tsub, Tk, sizeof(double) * (size_t)N);
+        for (int sub = 0; sub < s->n_sub; ++sub) {
+            for (long e = 0; e < N; ++e)
+                dTsub[e] = du[e] / (c->C0 * pow(Tsub[e] / c->T_ref, c->cp_exp));
+            for (long e = 0; e < N; ++e) {
+                double flux = s->Gb[e] * (c->T_bath - Tsub[e]);
+                double dflux = -s->Gb[e] * dTsub[e];
+                for (int f = 0; f < 4; ++f) {
+                    const long nbr = s->nb[4 * e + f];
+                    if (nbr >= 0) {
+                        flux += s->G[4 * e + f] * (Tsub[nbr] - Tsub[e]);
+                        dflux += s->G[4 * e + f] * (dTsub[nbr] - dTsub[e]);
+                    }
+                }
+                unew[e] = usub[e] + hs / s->V[e] * flux + hs * s->q[e];
+                dunew[e] = du[e] + hs / s->V[e] * dflux + hs * dq[e];
+            }
+            for (long e = 0; e < N; ++e) {
+                usub[e] = unew[e];
+                Tsub[e] = T_of_u(c, unew[e]);
+                du[e] = dunew[e];
+            }
+        }
+        /* 6. peak temperature raised in this step */
+        if (s->Tpeak_k == s->step && s->Tpeak_e >= 0) {
+            const long e = s->Tpeak_e;
+            dTpeak = du[e] / (c->C0 * pow(s->T[e] / c->T_ref, c->cp_exp));
+        }
+    }
+    if (obj) { obj[0] = s->Q; obj[1] = s->Tpeak; }
+    if (dobj) { dobj[0] = dQ; dobj[1] = dTpeak; }
+    void *p[] = {dI, du, Ik, Tk, uk, dBr, dBz, dE, dEp, ddI, dq, Tsub, usub, dTsub, unew, dunew};
+    for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
+    orc_destroy(s);
+    return rc;
+}

@@ -96,6 +96,14 @@ void   orc_field_points(const orc_sim *s, const double *I, long np, const double
 /* elements of wire w (public indices), returns count */
 int    orc_wire_elems(const orc_sim *s, long w, long *dst);
 
+/* tangent-linear (forward-mode) derivative of the run's objectives
+   Q (time-integrated Joule heat) and T_peak along the direction
+   (dc_wire[Nw], dramp[n_coils]) for nsteps from the initial state.
+   obj[2] = (Q, T_peak), dobj[2] = directional derivatives. */
+int    orc_tangent(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
+                   const double *c_wire, const double *dc_wire, const double *dramp,
+                   long nsteps, double *obj, double *dobj);
+
 #ifdef __cplusplus
 }
 #endif
