@@ -185,6 +185,43 @@ int coil_timing_read(coil_t *h, double *ms, int64_t *launches, int32_t n);
    drops the graph.  The graph holds only kernel nodes. */
 int coil_graph(coil_t *h, int64_t steps);
 
+/* Replace the per-wire Jc multipliers c_w (N_w host values, or NULL to keep)
+   and the per-coil ramp rates (n_coils host values, or NULL to keep); the state
+   is not touched.  Synchronises. */
+int coil_set_params(coil_t *h, const double *c_wire, const double *ramp);
+
+/* ---- discrete adjoint (checkpointed) ----
+   Objective J = wQ Q + wTpeak T_peak after nsteps from t = 0, with Q the
+   time-integrated Joule heat and T_peak the peak temperature (paper, Results:
+   per-wire time-integrated Joule heat as the quantity that orders flux-jump and
+   quench propagation).  coil_adjoint resets the handle, runs the forward pass
+   storing the state (I, u, T) every ckpt_every steps (and, if store_field, the
+   field B of every step), then the reverse sweep: each segment is recomputed
+   from its checkpoint with the step's intermediates recorded, and the adjoint
+   of every step is applied in reverse order (heat substeps, Joule source,
+   per-wire KKT system with the same Cholesky factor, local law and Jc, and a
+   transposed all-pairs field pass).  The peak temperature's gradient is that
+   of its element and step (ties resolved to the lowest step, then the lowest
+   public element index); zero-measure kinks (|B| = 0, T = Tc, J = 0) take the
+   zero branch.
+   Outputs: g_c_wire[N_w] = dJ/dc_w, g_ramp[n_coils] = dJ/d(ramp rate),
+   objectives[2] = (Q, T_peak).  `workspace` is caller-owned device memory of
+   at least coil_adjoint_query() bytes (256-byte aligned); it is free again on
+   return.  The handle is left reset to t = 0.  Synchronises.
+   Returns COIL_E_NONFINITE if the forward pass produced a non-finite value. */
+int coil_adjoint_query(coil_t *h, int64_t nsteps, int32_t ckpt_every, int32_t store_field,
+                       size_t *bytes);
+int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak, int32_t ckpt_every,
+                 int32_t store_field, void *workspace, size_t bytes, double *g_c_wire,
+                 double *g_ramp, double *objectives);
+
+/* Test hook: out = G^T bbar, the transposed field pass.  bbar_r, bbar_z, out
+   in public order (host, or device if on_device).  out_j = sum_e dB_e/dI_j .
+   bbar_e over the elements e of j's coil.  Overwrites the stored field
+   (COIL_F_BR/BZ) and COIL_F_DI.  Synchronises. */
+int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, double *out,
+                         int32_t on_device);
+
 void coil_destroy(coil_t *h);  /* does not free the caller's workspace */
 const char *coil_last_error(void);
 

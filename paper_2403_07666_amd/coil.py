@@ -63,7 +63,8 @@ REPORT_FN = C.CFUNCTYPE(None, _dp, C.c_int32, C.c_void_p)
 EXPORTS = [
     "coil_query", "coil_init", "coil_step", "coil_run", "coil_compute_field", "coil_get",
     "coil_set_state", "coil_scalars", "coil_reset", "coil_timing", "coil_timing_read",
-    "coil_graph", "coil_destroy", "coil_last_error", "coil_host_ellip",
+    "coil_graph", "coil_destroy", "coil_last_error", "coil_host_ellip", "coil_set_params",
+    "coil_adjoint_query", "coil_adjoint", "coil_field_transpose",
 ]
 
 _lib = None
@@ -93,6 +94,11 @@ def lib():
         L.coil_destroy.restype = None
         L.coil_last_error.restype = C.c_char_p
         L.coil_host_ellip.argtypes = [C.c_double, C.c_int32, _dp, _dp]
+        L.coil_set_params.argtypes = [vp, _dp, _dp]
+        L.coil_adjoint_query.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+        L.coil_adjoint.argtypes = [vp, C.c_int64, C.c_double, C.c_double, C.c_int32, C.c_int32, vp,
+                                   C.c_size_t, _dp, _dp, _dp]
+        L.coil_field_transpose.argtypes = [vp, vp, vp, vp, C.c_int32]
         _lib = L
     return _lib
 
@@ -279,3 +285,53 @@ class Coil:
                                      n.ctypes.data_as(C.POINTER(C.c_int64)), 4))
         names = ["field", "wire", "heat", "reduce"]
         return {nm: {"ms": float(ms[i]), "launches": int(n[i])} for i, nm in enumerate(names)}
+
+    # -------------------------------------------------------------- parameters and adjoint
+    def set_params(self, c_wire=None, ramp=None) -> None:
+        cw = np.ascontiguousarray(c_wire, dtype=np.float64) if c_wire is not None else None
+        rp = np.ascontiguousarray(ramp, dtype=np.float64) if ramp is not None else None
+        if cw is not None and cw.size != self.Nw:
+            raise ValueError("c_wire has the wrong length")
+        if rp is not None and rp.size != len(self.w.coils):
+            raise ValueError("ramp needs one value per coil")
+        check(lib().coil_set_params(self.h, cw.ctypes.data_as(_dp) if cw is not None else None,
+                                    rp.ctypes.data_as(_dp) if rp is not None else None))
+
+    def field_transpose(self, bbar_r, bbar_z) -> np.ndarray:
+        br = np.ascontiguousarray(bbar_r, dtype=np.float64)
+        bz = np.ascontiguousarray(bbar_z, dtype=np.float64)
+        out = np.empty(self.N, dtype=np.float64)
+        check(lib().coil_field_transpose(self.h, br.ctypes.data_as(C.c_void_p), bz.ctypes.data_as(C.c_void_p),
+                                         out.ctypes.data_as(C.c_void_p), 0))
+        return out
+
+    def adjoint_bytes(self, nsteps: int, ckpt_every: int = 50, store_field: bool = True) -> int:
+        b = C.c_size_t()
+        check(lib().coil_adjoint_query(self.h, int(nsteps), int(ckpt_every), 1 if store_field else 0, C.byref(b)))
+        return int(b.value)
+
+    def adjoint(self, nsteps: int, wQ: float = 1.0, wT: float = 0.0, ckpt_every: int = 50,
+                store_field: bool = True):
+        """Gradients of wQ Q + wT T_peak after nsteps with respect to the per-wire
+        Jc multipliers and the per-coil ramp rates.  Returns (g_c_wire, g_ramp,
+        (Q, T_peak)); leaves the handle reset to t = 0."""
+        import torch
+        nb = self.adjoint_bytes(nsteps, ckpt_every, store_field)
+        with torch.cuda.device(self.device):
+            ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.device)
+            torch.cuda.synchronize(self.device)
+        gcw = np.zeros(self.Nw)
+        gr = np.zeros(len(self.w.coils))
+        obj = np.zeros(2)
+        check(lib().coil_adjoint(self.h, int(nsteps), float(wQ), float(wT), int(ckpt_every),
+                                 1 if store_field else 0, C.c_void_p(ws.data_ptr()), C.c_size_t(ws.numel()),
+                                 gcw.ctypes.data_as(_dp), gr.ctypes.data_as(_dp), obj.ctypes.data_as(_dp)))
+        del ws
+        return gcw, gr, (float(obj[0]), float(obj[1]))
+
+    def objectives(self, nsteps: int):
+        """Reset, run nsteps and return (Q, T_peak)."""
+        self.reset()
+        self.run(nsteps)
+        sc = self.scalars()
+        return sc["Q"], sc["T_peak"]

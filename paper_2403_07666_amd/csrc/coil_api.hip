@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "coil_adjoint.h"
 #include "coil_internal.h"
 
 using namespace coilq;
@@ -267,6 +268,7 @@ struct coil_s {
     int grid_limit = 0;
     double T_bath = 4.2;
     std::vector<double> r_pub, z_pub;  // public order, for COIL_F_R / COIL_F_Z
+    std::vector<int> pub2int;          // public -> internal element index
     // timing
     bool timing = false;
     struct Pending {
@@ -640,6 +642,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(launch_psi(s, const_cast<double *>(s.psi), st));
     if ((rc = reset_state(h))) return rc;
     HIPCHECK(hipStreamSynchronize(st));  // host vectors above go out of scope
+    h->pub2int.swap(pub2int);
     *out = guard.release();
     return COIL_OK;
 }
@@ -918,5 +921,241 @@ extern "C" int coil_host_ellip(double m1, int32_t precision, double *K, double *
     } else {
         return fail(COIL_E_INVAL, "unknown precision");
     }
+    return COIL_OK;
+}
+
+// ------------------------------------------------------------------ parameters
+extern "C" int coil_set_params(coil_t *h, const double *c_wire, const double *ramp) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (h->capturing) return fail(COIL_E_STATE, "cannot change parameters during graph capture");
+    if (c_wire) {
+        for (int w = 0; w < h->ds.Nw; ++w)
+            if (!std::isfinite(c_wire[w])) return fail(COIL_E_INVAL, "non-finite c_wire at %d", w);
+        HIPCHECK(hipMemcpyAsync((void *)h->ds.cw, c_wire, sizeof(double) * h->ds.Nw, hipMemcpyHostToDevice,
+                                h->stream));
+    }
+    if (ramp) {
+        for (size_t i = 0; i < h->plan.coils.size(); ++i) {
+            if (!std::isfinite(ramp[i])) return fail(COIL_E_INVAL, "non-finite ramp of coil %zu", i);
+            h->plan.coils[i].dIt = ramp[i] * h->rc.dt;
+        }
+        HIPCHECK(hipMemcpyAsync((void *)h->ds.coils, h->plan.coils.data(), sizeof(CoilDev) * h->plan.coils.size(),
+                                hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return COIL_OK;
+}
+
+// ------------------------------------------------------------------ transposed field pass (test hook)
+extern "C" int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, double *out,
+                                    int32_t on_device) {
+    if (!h || !bbar_r || !bbar_z || !out) return fail(COIL_E_INVAL, "NULL argument");
+    if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
+    const DevState &s = h->ds;
+    hipStream_t st = h->stream;
+    const int N = s.N;
+    // public inputs -> internal order in the Br / Bz buffers, then weights in place
+    const double *pr = bbar_r, *pz = bbar_z;
+    if (!on_device) {
+        HIPCHECK(hipMemcpyAsync(s.tmp, bbar_r, sizeof(double) * N, hipMemcpyHostToDevice, st));
+        HIPCHECK(launch_scatter(s.tmp, s.perm, N, s.Br, st));
+        HIPCHECK(hipMemcpyAsync(s.tmp, bbar_z, sizeof(double) * N, hipMemcpyHostToDevice, st));
+        HIPCHECK(launch_scatter(s.tmp, s.perm, N, s.Bz, st));
+    } else {
+        HIPCHECK(launch_scatter(pr, s.perm, N, s.Br, st));
+        HIPCHECK(launch_scatter(pz, s.perm, N, s.Bz, st));
+    }
+    HIPCHECK(launch_field_weights(s, s.Br, s.Bz, st));
+    double *partT = reinterpret_cast<double *>(s.part);
+    HIPCHECK(launch_fieldT(s, h->rc, h->grid_limit, s.Br, s.Bz, partT, st));
+    HIPCHECK(launch_fieldT_sum(s, partT, s.dI, 0, st));
+    if (on_device) {
+        HIPCHECK(launch_gather(s.dI, s.perm, N, out, st));
+    } else {
+        HIPCHECK(launch_gather(s.dI, s.perm, N, s.tmp, st));
+        HIPCHECK(hipMemcpyAsync(out, s.tmp, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    }
+    HIPCHECK(hipStreamSynchronize(st));
+    return COIL_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+namespace {
+struct AdjLayout {
+    size_t ckI, ckU, ckT, hBr, hBz, sI, sdI, sT, sBr, sBz, Ib, ub0, ub1, qb, wr, wz, partT, cb, dIb, total;
+    long long nseg;
+};
+
+AdjLayout adj_layout(const Plan &p, long long K, long long C, int store_field) {
+    AdjLayout L{};
+    const size_t N = p.N, Nw = p.Nw, d8 = sizeof(double);
+    L.nseg = (K + C - 1) / C;
+    size_t cur = 0;
+    auto take = [&](size_t bytes) {
+        cur = (cur + 255) & ~size_t(255);
+        const size_t o = cur;
+        cur += bytes;
+        return o;
+    };
+    L.ckI = take(d8 * N * L.nseg);
+    L.ckU = take(d8 * N * L.nseg);
+    L.ckT = take(d8 * N * L.nseg);
+    if (store_field) {
+        L.hBr = take(d8 * N * K);
+        L.hBz = take(d8 * N * K);
+    } else {
+        L.sBr = take(d8 * N * C);
+        L.sBz = take(d8 * N * C);
+    }
+    L.sI = take(d8 * N * C);
+    L.sdI = take(d8 * N * C);
+    L.sT = take(d8 * N * C * p.nsub);
+    L.Ib = take(d8 * N);
+    L.ub0 = take(d8 * N);
+    L.ub1 = take(d8 * N);
+    L.qb = take(d8 * N);
+    L.wr = take(d8 * N);
+    L.wz = take(d8 * N);
+    L.partT = take(d8 * N * p.nchunk_max);
+    L.cb = take(d8 * Nw);
+    L.dIb = take(d8 * Nw);
+    L.total = (cur + 255) & ~size_t(255);
+    return L;
+}
+}  // namespace
+
+extern "C" int coil_adjoint_query(coil_t *h, int64_t nsteps, int32_t ckpt_every, int32_t store_field,
+                                  size_t *bytes) {
+    if (!h || !bytes) return fail(COIL_E_INVAL, "NULL argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(COIL_E_INVAL, "nsteps and ckpt_every must be >= 1");
+    *bytes = adj_layout(h->plan, nsteps, ckpt_every, store_field != 0).total;
+    return COIL_OK;
+}
+
+extern "C" int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak, int32_t ckpt_every,
+                            int32_t store_field, void *workspace, size_t bytes, double *g_c_wire,
+                            double *g_ramp, double *objectives) {
+    if (!h || !workspace || !g_c_wire || !g_ramp || !objectives) return fail(COIL_E_INVAL, "NULL argument");
+    if (nsteps < 1 || ckpt_every < 1) return fail(COIL_E_INVAL, "nsteps and ckpt_every must be >= 1");
+    if (!std::isfinite(wQ) || !std::isfinite(wTpeak)) return fail(COIL_E_INVAL, "non-finite objective weight");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(COIL_E_INVAL, "workspace must be 256-byte aligned");
+    if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
+    const long long K = nsteps, C = ckpt_every;
+    const int sf = store_field != 0;
+    const AdjLayout L = adj_layout(h->plan, K, C, sf);
+    if (bytes < L.total) return fail(COIL_E_NOMEM, "adjoint workspace of %zu bytes < %zu needed", bytes, L.total);
+    char *wb = static_cast<char *>(workspace);
+    auto P = [&](size_t off) { return reinterpret_cast<double *>(wb + off); };
+    const DevState base = h->ds;
+    const RunConst &rc = h->rc;
+    hipStream_t st = h->stream;
+    const int N = base.N, Nw = base.Nw, nsub = base.nsub;
+    const size_t Ns = (size_t)N;
+    int rc_ = COIL_OK;
+    const bool timing = h->timing;
+    h->timing = false;
+
+    auto step_with = [&](const DevState &d, bool field) -> int {
+        if (field) HIPCHECK(launch_field(d, rc, h->grid_limit, st));
+        HIPCHECK(launch_wire(d, rc, st));
+        for (int sub = 0; sub < nsub; ++sub) HIPCHECK(launch_heat(d, rc, sub, st));
+        HIPCHECK(launch_finalize(d, rc, st));
+        return COIL_OK;
+    };
+
+    // forward pass with checkpoints (and the field history)
+    if ((rc_ = reset_state(h))) return rc_;
+    for (long long k = 0; k < K; ++k) {
+        if (k % C == 0) {
+            const long long sg = k / C;
+            HIPCHECK(launch_copy(base.I, P(L.ckI) + sg * Ns, N, st));
+            HIPCHECK(launch_copy(base.u[0], P(L.ckU) + sg * Ns, N, st));
+            HIPCHECK(launch_copy(base.T[0], P(L.ckT) + sg * Ns, N, st));
+        }
+        DevState d = base;
+        if (sf) {
+            d.rec_Br = P(L.hBr) + k * Ns;
+            d.rec_Bz = P(L.hBz) + k * Ns;
+        }
+        if ((rc_ = step_with(d, true))) return rc_;
+    }
+    Scalars sc;
+    if ((rc_ = read_scalars(h, &sc))) return rc_;
+    if (sc.status) {
+        h->timing = timing;
+        return fail(COIL_E_NONFINITE, "non-finite state in the forward pass (status 0x%x)", sc.status);
+    }
+    objectives[0] = sc.Q;
+    objectives[1] = sc.Tpeak;
+    const int e_star = sc.Tpeak_pub >= 0 ? h->pub2int[sc.Tpeak_pub] : -1;
+    const double Cpk = rc.C0 * std::pow(sc.Tpeak / rc.T_ref, rc.cp_exp);
+
+    // reverse sweep
+    double *Ib = P(L.Ib), *ub = P(L.ub0), *ubn = P(L.ub1), *qb = P(L.qb);
+    HIPCHECK(launch_fill(Ib, 0.0, N, st));
+    HIPCHECK(launch_fill(ub, 0.0, N, st));
+    HIPCHECK(launch_fill(P(L.cb), 0.0, Nw, st));
+    HIPCHECK(launch_fill(P(L.dIb), 0.0, Nw, st));
+    for (long long sg = L.nseg - 1; sg >= 0; --sg) {
+        const long long k0 = sg * C, k1 = std::min(K, k0 + C);
+        HIPCHECK(launch_copy(P(L.ckI) + sg * Ns, base.I, N, st));
+        HIPCHECK(launch_copy(P(L.ckU) + sg * Ns, base.u[0], N, st));
+        HIPCHECK(launch_copy(P(L.ckT) + sg * Ns, base.T[0], N, st));
+        HIPCHECK(launch_set_step(base.sc, k0, st));
+        for (long long k = k0; k < k1; ++k) {
+            const long long j = k - k0;
+            DevState d = base;
+            d.rec_I = P(L.sI) + j * Ns;
+            d.rec_dI = P(L.sdI) + j * Ns;
+            d.rec_T = P(L.sT) + j * nsub * Ns;
+            if (sf) {
+                d.src_Br = P(L.hBr) + k * Ns;
+                d.src_Bz = P(L.hBz) + k * Ns;
+            } else {
+                d.rec_Br = P(L.sBr) + j * Ns;
+                d.rec_Bz = P(L.sBz) + j * Ns;
+            }
+            if ((rc_ = step_with(d, !sf))) return rc_;
+        }
+        for (long long k = k1 - 1; k >= k0; --k) {
+            const long long j = k - k0;
+            if (wTpeak != 0.0 && e_star >= 0 && k + 1 == sc.Tpeak_step)
+                HIPCHECK(launch_add_at(ub, e_star, wTpeak / Cpk, st));
+            HIPCHECK(launch_qbar_init(base, qb, wQ * rc.dt, st));
+            for (int sub = nsub - 1; sub >= 0; --sub) {
+                HIPCHECK(launch_heat_adj(base, rc, ub, ubn, P(L.sT) + (j * nsub + sub) * Ns, qb, st));
+                std::swap(ub, ubn);
+            }
+            AdjPtrs a;
+            a.I = P(L.sI) + j * Ns;
+            a.T = P(L.sT) + j * nsub * Ns;
+            a.Br = sf ? P(L.hBr) + k * Ns : P(L.sBr) + j * Ns;
+            a.Bz = sf ? P(L.hBz) + k * Ns : P(L.sBz) + j * Ns;
+            a.dI = P(L.sdI) + j * Ns;
+            a.qbar = qb;
+            a.Ibar = Ib;
+            a.ubar = ub;
+            a.wr = P(L.wr);
+            a.wz = P(L.wz);
+            a.cbar = P(L.cb);
+            a.dItbar = P(L.dIb);
+            HIPCHECK(launch_wire_adj(base, rc, a, st));
+            HIPCHECK(launch_fieldT(base, rc, h->grid_limit, a.wr, a.wz, P(L.partT), st));
+            HIPCHECK(launch_fieldT_sum(base, P(L.partT), Ib, 1, st));
+        }
+    }
+    std::vector<double> dIb(Nw);
+    HIPCHECK(hipMemcpyAsync(g_c_wire, P(L.cb), sizeof(double) * Nw, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(dIb.data(), P(L.dIb), sizeof(double) * Nw, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    for (size_t ci = 0; ci < h->plan.coils.size(); ++ci) {
+        const CoilDev &c = h->plan.coils[ci];
+        double sgr = 0.0;
+        for (int w = c.wire_off; w < c.wire_off + c.layers * c.turns; ++w) sgr += dIb[w];
+        g_ramp[ci] = rc.dt * sgr;
+    }
+    if ((rc_ = reset_state(h))) return rc_;
+    HIPCHECK(hipStreamSynchronize(st));
+    h->timing = timing;
     return COIL_OK;
 }

@@ -1,0 +1,217 @@
+// coil_device.h -- device functions shared by the forward and adjoint
+// kernels: the ring-field pair (FP64 and FP32 forms, forward and transposed),
+// the local power law, the wire matrix factorisation and solves in LDS.
+// Forward and adjoint call the same functions, so a recomputed forward
+// quantity is bitwise the one the forward pass produced.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "coil_internal.h"
+#include "ellip_coeffs.h"
+
+namespace coilq {
+
+// ------------------------------------------------------------------ helpers
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ unsigned wave_or(unsigned v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    return v;
+}
+
+// FP64 pair: adds the (B_r * rho_t, B_z) contribution of a source of strength
+// sv (= mu0 I / (2 pi d)) at grid offsets (dr, dz), sr = rho_t + rho_s.
+__device__ __forceinline__ void pair64(double dr, double dz, double sr, double sv, double &ar,
+                                       double &az) {
+    const double dz2 = dz * dz;
+    const double al2 = fma(dr, dr, dz2);
+    const double be2 = fma(sr, sr, dz2);
+    const double rb = rsqrt(be2);
+    const double m1 = al2 * (rb * rb);
+    const double L = -log(m1);
+    const double K = fma(ellipk64_Q(m1), L, ellipk64_P(m1));
+    const double E = fma(ellipe64_Q(m1), L, ellipe64_P(m1));
+    const double f = sv * rb / al2;
+    const double alK = al2 * K;
+    const double gz = fma(fma(-dr, sr, -dz2), E, alK);
+    const double gr = dz * fma(0.5 * (al2 + be2), E, -alK);
+    const bool ok = al2 > 0.0;  // the element's own ring is excluded
+    az = ok ? fma(f, gz, az) : az;
+    ar = ok ? fma(f, gr, ar) : ar;
+}
+
+// FP32 pair (far field): same formula; -log2(m1), rsqrt, rcp in hardware.
+__device__ __forceinline__ void pair32(float dr, float dz, float sr, float sv, float &ar,
+                                       float &az) {
+    const float dz2 = dz * dz;
+    const float al2 = fmaf(dr, dr, dz2);
+    const float be2 = fmaf(sr, sr, dz2);
+    const float rb = __builtin_amdgcn_rsqf(be2);
+    const float m1 = al2 * (rb * rb);
+    const float L2 = -__builtin_amdgcn_logf(m1);
+    const float K = fmaf(ellipk32_Q(m1), L2, ellipk32_P(m1));
+    const float E = fmaf(ellipe32_Q(m1), L2, ellipe32_P(m1));
+    const float f = sv * rb * __builtin_amdgcn_rcpf(al2);
+    const float alK = al2 * K;
+    const float gz = fmaf(fmaf(-dr, sr, -dz2), E, alK);
+    const float gr = dz * fmaf(0.5f * (al2 + be2), E, -alK);
+    az = fmaf(f, gz, az);
+    ar = fmaf(f, gr, ar);
+}
+
+// Can a pair of 64-element groups with these grid bounding boxes reach
+// m1 < m1_near?  m1 >= min al2 / max be2 over the boxes.
+__device__ __forceinline__ bool groups_near(int4 a, int4 b, float c2f, float m1_near) {
+    const int dr = max(0, max(b.x - a.y, a.x - b.y));
+    const int dz = max(0, max(b.z - a.w, a.z - b.w));
+    const float al2 = (float)(dr * dr + dz * dz);
+    const float sr = c2f + (float)(a.y + b.y);
+    const int dzm = max(abs(a.w - b.z), abs(b.w - a.z));
+    const float be2 = fmaf(sr, sr, (float)dzm * (float)dzm);
+    return al2 < m1_near * be2 * 1.0001f;
+}
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Transposed pairs: contribution of target e (weights wr, wz) to the
+// unit-strength source j: wr * g_r(e, j) + wz * g_z(e, j).  (dr, dz, sr) are the
+// target-minus-source offsets and radius sum, as in pair64 / pair32.
+__device__ __forceinline__ void pairT64(double dr, double dz, double sr, double wr, double wz,
+                                        double &acc) {
+    const double dz2 = dz * dz;
+    const double al2 = fma(dr, dr, dz2);
+    const double be2 = fma(sr, sr, dz2);
+    const double rb = rsqrt(be2);
+    const double m1 = al2 * (rb * rb);
+    const double L = -log(m1);
+    const double K = fma(ellipk64_Q(m1), L, ellipk64_P(m1));
+    const double E = fma(ellipe64_Q(m1), L, ellipe64_P(m1));
+    const double f = rb / al2;
+    const double alK = al2 * K;
+    const double gz = fma(fma(-dr, sr, -dz2), E, alK);
+    const double gr = dz * fma(0.5 * (al2 + be2), E, -alK);
+    const bool ok = al2 > 0.0;
+    acc = ok ? fma(f, fma(wr, gr, wz * gz), acc) : acc;
+}
+
+__device__ __forceinline__ void pairT32(float dr, float dz, float sr, float wr, float wz, float &acc) {
+    const float dz2 = dz * dz;
+    const float al2 = fmaf(dr, dr, dz2);
+    const float be2 = fmaf(sr, sr, dz2);
+    const float rb = __builtin_amdgcn_rsqf(be2);
+    const float m1 = al2 * (rb * rb);
+    const float L2 = -__builtin_amdgcn_logf(m1);
+    const float K = fmaf(ellipk32_Q(m1), L2, ellipk32_P(m1));
+    const float E = fmaf(ellipe32_Q(m1), L2, ellipe32_P(m1));
+    const float f = rb * __builtin_amdgcn_rcpf(al2);
+    const float alK = al2 * K;
+    const float gz = fmaf(fmaf(-dr, sr, -dz2), E, alK);
+    const float gr = dz * fmaf(0.5f * (al2 + be2), E, -alK);
+    acc = fmaf(f, fmaf(wr, gr, wz * gz), acc);
+}
+
+__device__ __forceinline__ double T_of_u(const RunConst &rc, double u) {
+    const double x = fma(u, rc.u_a1, rc.u_a0);
+    return rc.T_ref * (rc.cp_exp == 3.0 ? sqrt(sqrt(x)) : pow(x, rc.u_inv));
+}
+
+// Local power law at step k: Jc(B, T, eps) and E, dE/dJ.  Returns the status
+// bits (ST_JC when J != 0 and Jc <= 0).
+struct Local {
+    double Jc, x, E, Ep, fT, fB, Bm;
+};
+__device__ __forceinline__ unsigned local_law(const RunConst &rc, double cw, double jcs, double J,
+                                              double T, double br, double bz, Local &o) {
+    o.Bm = sqrt(br * br + bz * bz);
+    o.fT = fmax(0.0, 1.0 - T / rc.Tc);
+    o.fB = rc.B0 / (rc.B0 + o.Bm);
+    o.Jc = cw * jcs * o.fT * o.fB;
+    o.E = 0.0;
+    o.Ep = 0.0;
+    o.x = 0.0;
+    if (J == 0.0) return 0u;
+    if (!(o.Jc > 0.0)) return ST_JC;
+    o.x = fabs(J) / o.Jc;
+    const double p = pow(o.x, rc.n - 1.0);
+    o.Ep = rc.n * rc.Ec / o.Jc * p;
+    o.E = copysign(rc.Ec * p * o.x, J);
+    return 0u;
+}
+
+// Cholesky of the n x n matrix in LDS (column-major, leading dimension ld),
+// one wavefront, one row per lane; lower factor in place.
+__device__ __forceinline__ unsigned chol_lds(double *sm, int n, int ld, int lane, bool act) {
+    unsigned bad = 0;
+    for (int j = 0; j < n; ++j) {
+        __syncthreads();
+        const double djj = sm[j * ld + j];
+        if (!(djj > 0.0)) bad |= ST_PIVOT;
+        const double ljj = sqrt(djj);
+        __syncthreads();
+        if (act && lane > j) sm[j * ld + lane] /= ljj;
+        if (lane == j) sm[j * ld + j] = ljj;
+        __syncthreads();
+        const double lij = (act && lane > j) ? sm[j * ld + lane] : 0.0;
+        for (int k = j + 1; k < n; ++k) {
+            const double lkj = sm[j * ld + k];
+            if (act && lane >= k) sm[k * ld + lane] -= lij * lkj;
+        }
+    }
+    __syncthreads();
+    return bad;
+}
+
+// Solve L L^T [x y] = [x y] with the factor in LDS; lane i holds entry i.
+__device__ __forceinline__ void solve2_lds(const double *sm, int n, int ld, int lane, bool act,
+                                           double &xv, double &yv) {
+    for (int j = 0; j < n; ++j) {
+        const double ljj = sm[j * ld + j];
+        const double xj = __shfl(xv, j) / ljj;
+        const double yj = __shfl(yv, j) / ljj;
+        if (lane == j) { xv = xj; yv = yj; }
+        if (act && lane > j) {
+            const double l = sm[j * ld + lane];
+            xv -= l * xj;
+            yv -= l * yj;
+        }
+    }
+    for (int j = n - 1; j >= 0; --j) {
+        const double ljj = sm[j * ld + j];
+        const double xj = __shfl(xv, j) / ljj;
+        const double yj = __shfl(yv, j) / ljj;
+        if (lane == j) { xv = xj; yv = yj; }
+        if (act && lane < j) {
+            const double l = sm[lane * ld + j];
+            xv -= l * xj;
+            yv -= l * yj;
+        }
+    }
+}
+
+// Load the layer's inductance block into LDS and add dt diag(2 pi r E'/d^2).
+__device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, int n, int ld, int lane,
+                                                 bool act, double diag_add) {
+    if (act)
+        for (int col = 0; col < n; ++col) sm[col * ld + lane] = M[col * n + lane];
+    __syncthreads();
+    if (act) sm[lane * ld + lane] += diag_add;
+}
+
+}  // namespace coilq

@@ -93,6 +93,10 @@ struct DevState {
     double *hb_out;          // [nsub][blocks]: heat out through the borders
     Scalars *sc;
     double *tmp;             // N doubles of staging for get/set
+    // adjoint support (null in normal stepping)
+    const double *src_Br, *src_Bz;    // take B^k from here instead of the field pass
+    double *rec_I, *rec_Br, *rec_Bz, *rec_dI;  // record I^k, B^k, dI of the step
+    double *rec_T;                    // record T at the start of each heat substep [sub][N]
 };
 
 // ---- launchers (coil_kernels.hip) ----

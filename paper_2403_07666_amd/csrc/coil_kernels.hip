@@ -27,85 +27,9 @@
 #include <cmath>
 
 #include "coil_internal.h"
-#include "ellip_coeffs.h"
+#include "coil_device.h"
 
 namespace coilq {
-
-// ------------------------------------------------------------------ helpers
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
-}
-__device__ __forceinline__ unsigned wave_or(unsigned v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
-    return v;
-}
-
-// FP64 pair: adds the (B_r * rho_t, B_z) contribution of a source of strength
-// sv (= mu0 I / (2 pi d)) at grid offsets (dr, dz), sr = rho_t + rho_s.
-__device__ __forceinline__ void pair64(double dr, double dz, double sr, double sv, double &ar,
-                                       double &az) {
-    const double dz2 = dz * dz;
-    const double al2 = fma(dr, dr, dz2);
-    const double be2 = fma(sr, sr, dz2);
-    const double rb = rsqrt(be2);
-    const double m1 = al2 * (rb * rb);
-    const double L = -log(m1);
-    const double K = fma(ellipk64_Q(m1), L, ellipk64_P(m1));
-    const double E = fma(ellipe64_Q(m1), L, ellipe64_P(m1));
-    const double f = sv * rb / al2;
-    const double alK = al2 * K;
-    const double gz = fma(fma(-dr, sr, -dz2), E, alK);
-    const double gr = dz * fma(0.5 * (al2 + be2), E, -alK);
-    const bool ok = al2 > 0.0;  // the element's own ring is excluded
-    az = ok ? fma(f, gz, az) : az;
-    ar = ok ? fma(f, gr, ar) : ar;
-}
-
-// FP32 pair (far field): same formula; -log2(m1), rsqrt, rcp in hardware.
-__device__ __forceinline__ void pair32(float dr, float dz, float sr, float sv, float &ar,
-                                       float &az) {
-    const float dz2 = dz * dz;
-    const float al2 = fmaf(dr, dr, dz2);
-    const float be2 = fmaf(sr, sr, dz2);
-    const float rb = __builtin_amdgcn_rsqf(be2);
-    const float m1 = al2 * (rb * rb);
-    const float L2 = -__builtin_amdgcn_logf(m1);
-    const float K = fmaf(ellipk32_Q(m1), L2, ellipk32_P(m1));
-    const float E = fmaf(ellipe32_Q(m1), L2, ellipe32_P(m1));
-    const float f = sv * rb * __builtin_amdgcn_rcpf(al2);
-    const float alK = al2 * K;
-    const float gz = fmaf(fmaf(-dr, sr, -dz2), E, alK);
-    const float gr = dz * fmaf(0.5f * (al2 + be2), E, -alK);
-    az = fmaf(f, gz, az);
-    ar = fmaf(f, gr, ar);
-}
-
-// Can a pair of 64-element groups with these grid bounding boxes reach
-// m1 < m1_near?  m1 >= min al2 / max be2 over the boxes.
-__device__ __forceinline__ bool groups_near(int4 a, int4 b, float c2f, float m1_near) {
-    const int dr = max(0, max(b.x - a.y, a.x - b.y));
-    const int dz = max(0, max(b.z - a.w, a.z - b.w));
-    const float al2 = (float)(dr * dr + dz * dz);
-    const float sr = c2f + (float)(a.y + b.y);
-    const int dzm = max(abs(a.w - b.z), abs(b.w - a.z));
-    const float be2 = fmaf(sr, sr, (float)dzm * (float)dzm);
-    return al2 < m1_near * be2 * 1.0001f;
-}
-
-__device__ __forceinline__ void kahan_add(float &s, float &c, float x) {
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
 
 // ------------------------------------------------------------------ field pass
 template <int MIXED>
@@ -204,6 +128,8 @@ __global__ __launch_bounds__(256) void k_field_finalize(DevState s, RunConst rc,
 // matrix A = M_ww + dt diag(2 pi r E'/d^2) lives in LDS, column-major with
 // leading dimension n_e + 1; right-looking Cholesky, then two triangular
 // solves for the right-hand sides b and 1 with the solutions in registers.
+// Optional recording (adjoint recompute): I^k, B^k and dI of the step; optional
+// field source (adjoint recompute from a stored field history).
 __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     extern __shared__ double sm[];
     const int w = blockIdx.x;
@@ -218,75 +144,26 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     const double dt = rc.dt;
     const double tk = (double)s.sc->step * dt;
     const double dBa = rc.dBa_dt * dt;
-    unsigned bad = 0;
 
     double br, bz;
-    field_at(s, c, e, rc.dBa_dt * tk, br, bz);
+    if (s.src_Br) {
+        br = s.src_Br[e];
+        bz = s.src_Bz[e];
+    } else {
+        field_at(s, c, e, rc.dBa_dt * tk, br, bz);
+    }
     const double I0 = s.I[e];
     const double d2 = c.d * c.d;
-    const double J = I0 / d2;
-    const double T = s.T[0][e];
-    const double Bm = sqrt(br * br + bz * bz);
-    const double fT = fmax(0.0, 1.0 - T / rc.Tc);
-    const double Jc = s.cw[w] * s.jcs[e] * fT * rc.B0 / (rc.B0 + Bm);
-    double E = 0.0, Ep = 0.0, x = 0.0;
-    if (act && J != 0.0) {
-        if (!(Jc > 0.0)) {
-            bad |= ST_JC;
-        } else {
-            x = fabs(J) / Jc;
-            const double p = pow(x, rc.n - 1.0);
-            Ep = rc.n * rc.Ec / Jc * p;
-            E = copysign(rc.Ec * p * x, J);
-        }
-    }
+    Local lo;
+    unsigned bad = act ? local_law(rc, s.cw[w], s.jcs[e], I0 / d2, s.T[0][e], br, bz, lo) : 0u;
+    if (!act) { lo.E = lo.Ep = lo.x = lo.Jc = 0.0; }
     const double re = s.r[e];
-    const double* M = s.Mlay + (size_t)(c.layer_off + layer) * n * n;
-    if (act)
-        for (int col = 0; col < n; ++col) sm[col * ld + lane] = M[col * n + lane];
-    __syncthreads();
-    if (act) sm[lane * ld + lane] += dt * 2.0 * kPi * re * Ep / d2;
-    const double b = act ? (-c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * E) : 0.0;
-
-    for (int j = 0; j < n; ++j) {
-        __syncthreads();
-        const double djj = sm[j * ld + j];
-        if (!(djj > 0.0)) bad |= ST_PIVOT;
-        const double ljj = sqrt(djj);
-        __syncthreads();
-        if (act && lane > j) sm[j * ld + lane] /= ljj;
-        if (lane == j) sm[j * ld + j] = ljj;
-        __syncthreads();
-        const double lij = (act && lane > j) ? sm[j * ld + lane] : 0.0;
-        for (int k = j + 1; k < n; ++k) {
-            const double lkj = sm[j * ld + k];
-            if (act && lane >= k) sm[k * ld + lane] -= lij * lkj;
-        }
-    }
-    __syncthreads();
+    const double *M = s.Mlay + (size_t)(c.layer_off + layer) * n * n;
+    load_wire_matrix(sm, M, n, ld, lane, act, dt * 2.0 * kPi * re * lo.Ep / d2);
+    const double b = act ? (-c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * lo.E) : 0.0;
+    bad |= chol_lds(sm, n, ld, lane, act);
     double xv = b, yv = act ? 1.0 : 0.0;
-    for (int j = 0; j < n; ++j) {  // L z = rhs
-        const double ljj = sm[j * ld + j];
-        const double xj = __shfl(xv, j) / ljj;
-        const double yj = __shfl(yv, j) / ljj;
-        if (lane == j) { xv = xj; yv = yj; }
-        if (act && lane > j) {
-            const double l = sm[j * ld + lane];
-            xv -= l * xj;
-            yv -= l * yj;
-        }
-    }
-    for (int j = n - 1; j >= 0; --j) {  // L^T x = z
-        const double ljj = sm[j * ld + j];
-        const double xj = __shfl(xv, j) / ljj;
-        const double yj = __shfl(yv, j) / ljj;
-        if (lane == j) { xv = xj; yv = yj; }
-        if (act && lane < j) {
-            const double l = sm[lane * ld + j];
-            xv -= l * xj;
-            yv -= l * yj;
-        }
-    }
+    solve2_lds(sm, n, ld, lane, act, xv, yv);
     const double sx = wave_sum(act ? xv : 0.0);
     const double sy = wave_sum(act ? yv : 0.0);
     const double U = (sx - c.dIt) / (dt * sy);
@@ -300,21 +177,27 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     double qv = 0.0;
     if (act) {
         const double I1 = I0 + dI;
-        const double Elin = E + Ep * dI / d2;
+        const double Elin = lo.E + lo.Ep * dI / d2;
         qv = Elin * (I1 / d2);
         s.Phi[e] += mdi + c.dIt * s.psi[e] + kPi * re * re * dBa;
         s.I[e] = I1;
         s.dI[e] = dI;
-        s.E[e] = E;
-        s.Ep[e] = Ep;
+        s.E[e] = lo.E;
+        s.Ep[e] = lo.Ep;
         s.q[e] = qv;
-        s.Jc[e] = Jc;
+        s.Jc[e] = lo.Jc;
         s.Br[e] = br;
         s.Bz[e] = bz;
+        if (s.rec_I) s.rec_I[e] = I0;
+        if (s.rec_Br) {
+            s.rec_Br[e] = br;
+            s.rec_Bz[e] = bz;
+        }
+        if (s.rec_dI) s.rec_dI[e] = dI;
         if (!isfinite(I1) || !isfinite(qv)) bad |= ST_NONFINITE;
     }
     const double qw = wave_sum(act ? dt * s.V[e] * qv : 0.0);
-    const double mx = wave_max(x);
+    const double mx = wave_max(lo.x);
     bad = wave_or(bad);
     if (lane == 0) {
         s.Uw[w] = U;
@@ -326,11 +209,6 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
 }
 
 // ------------------------------------------------------------------ heat
-__device__ __forceinline__ double T_of_u(const RunConst &rc, double u) {
-    const double x = fma(u, rc.u_a1, rc.u_a0);
-    return rc.T_ref * (rc.cp_exp == 3.0 ? sqrt(sqrt(x)) : pow(x, rc.u_inv));
-}
-
 // one explicit substep: (u, T)[src] -> (u, T)[dst]
 __global__ __launch_bounds__(256) void k_heat(DevState s, RunConst rc, int src, int dst, int sub,
                                               int last) {
@@ -345,6 +223,7 @@ __global__ __launch_bounds__(256) void k_heat(DevState s, RunConst rc, int src, 
     if (e < s.N) {
         const double *Ts = s.T[src];
         const double Te = Ts[e];
+        if (s.rec_T) s.rec_T[(size_t)sub * s.N + e] = Te;
         double flux = s.Gb[e] * (rc.T_bath - Te);
 #pragma unroll
         for (int f = 0; f < 4; ++f) {
