@@ -222,6 +222,20 @@ int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak, int32_t ck
 int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, double *out,
                          int32_t on_device);
 
+/* ---- field-pass tiling (batched and single coils) ----
+   coil_set_tiles: tile_targets in {64, 128, 256} targets per workgroup,
+   chunks = source chunks per coil (0 = automatic, at most 16), grid_limit = 0
+   for one workgroup per work item or > 0 for a persistent grid striding over
+   the (coil, target block, source chunk) items.  Drops a captured graph.
+   coil_autotune: times every candidate (3 tile sizes x 5 chunk counts x 3 grid
+   shapes) over `reps` field passes on the handle's current currents and keeps
+   the fastest; with cache_path it first looks the configuration up in that
+   JSON-lines file (key: arch / precision / log2 pairs / coils) and appends the
+   new choice.  chosen[3] (optional) receives (tile_targets, chunks,
+   grid_limit).  Results differ between tilings only by summation order. */
+int coil_set_tiles(coil_t *h, int32_t tile_targets, int32_t chunks, int32_t grid_limit);
+int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, int32_t *chosen);
+
 void coil_destroy(coil_t *h);  /* does not free the caller's workspace */
 const char *coil_last_error(void);
 

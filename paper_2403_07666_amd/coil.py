@@ -64,7 +64,7 @@ EXPORTS = [
     "coil_query", "coil_init", "coil_step", "coil_run", "coil_compute_field", "coil_get",
     "coil_set_state", "coil_scalars", "coil_reset", "coil_timing", "coil_timing_read",
     "coil_graph", "coil_destroy", "coil_last_error", "coil_host_ellip", "coil_set_params",
-    "coil_adjoint_query", "coil_adjoint", "coil_field_transpose",
+    "coil_adjoint_query", "coil_adjoint", "coil_field_transpose", "coil_set_tiles", "coil_autotune",
 ]
 
 _lib = None
@@ -99,6 +99,8 @@ def lib():
         L.coil_adjoint.argtypes = [vp, C.c_int64, C.c_double, C.c_double, C.c_int32, C.c_int32, vp,
                                    C.c_size_t, _dp, _dp, _dp]
         L.coil_field_transpose.argtypes = [vp, vp, vp, vp, C.c_int32]
+        L.coil_set_tiles.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.coil_autotune.argtypes = [vp, C.c_int32, C.c_char_p, _i32p]
         _lib = L
     return _lib
 
@@ -335,3 +337,15 @@ class Coil:
         self.run(nsteps)
         sc = self.scalars()
         return sc["Q"], sc["T_peak"]
+
+    # -------------------------------------------------------------- tiling
+    def set_tiles(self, tile_targets: int, chunks: int = 0, grid_limit: int = 0) -> None:
+        check(lib().coil_set_tiles(self.h, int(tile_targets), int(chunks), int(grid_limit)))
+
+    def autotune(self, reps: int = 3, cache_path: Optional[str] = None):
+        """Time the tile candidates and keep the fastest; returns
+        (tile_targets, chunks, grid_limit)."""
+        ch = np.zeros(3, dtype=np.int32)
+        path = cache_path.encode() if cache_path else None
+        check(lib().coil_autotune(self.h, int(reps), path, ch.ctypes.data_as(_i32p)))
+        return tuple(int(v) for v in ch)

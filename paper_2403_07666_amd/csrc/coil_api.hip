@@ -53,6 +53,8 @@ struct Plan {
     std::vector<CoilDev> coils;
     std::vector<PairItem> items;
     int nchunk_max = 1;
+    size_t items_cap = 0;  // work-item capacity (autotuner candidates)
+    int nchunk_cap = 1;    // partial-sum capacity in chunks
     size_t total = 0;
     // regions
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
@@ -110,11 +112,47 @@ int validate(const coil_config *c) {
     return COIL_OK;
 }
 
+constexpr int kMaxChunks = 16;
+
+// Field-pass work items: targets in blocks of tb, sources of each coil in
+// chunks.  nch_req > 0 asks for that many chunks per coil, cs_req > 0 for a
+// chunk size; both 0: enough chunks for >= ~2048 items in total.  Chunks are
+// multiples of the LDS stage.
+void build_items(Plan &p, int tb, int nch_req, int cs_req) {
+    p.items.clear();
+    p.tile_targets = tb;
+    p.nchunk_max = 1;
+    long long total_blocks = 0;
+    for (auto &d : p.coils) total_blocks += (d.n + tb - 1) / tb;
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        CoilDev &d = p.coils[ci];
+        int cs = cs_req;
+        if (cs == 0) {
+            const long long want = nch_req > 0 ? nch_req
+                                               : std::max<long long>(1, (2048 + total_blocks - 1) / total_blocks);
+            const long long maxch = (d.n + kStage - 1) / kStage;
+            const long long ch = std::min(want, maxch);
+            cs = (int)(((d.n + ch - 1) / ch + kStage - 1) / kStage * kStage);
+        }
+        d.nchunk = (d.n + cs - 1) / cs;
+        p.nchunk_max = std::max(p.nchunk_max, d.nchunk);
+        for (int t0 = 0; t0 < d.n; t0 += tb)
+            for (int k = 0; k < d.nchunk; ++k) {
+                PairItem it;
+                it.coil = (int)ci;
+                it.t0 = d.off + t0;
+                it.tn = std::min(tb, d.n - t0);
+                it.s0 = d.off + k * cs;
+                it.sn = std::min(cs, d.n - k * cs);
+                it.chunk = k;
+                p.items.push_back(it);
+            }
+    }
+}
+
 int make_plan(const coil_config *c, Plan &p) {
     p = Plan();
     int off = 0, woff = 0, loff = 0, goff = 0;
-    int tb = c->tile_targets;
-    long long total_blocks = 0;
     for (int i = 0; i < c->n_coils; ++i) {
         CoilDev d{};
         d.ne = c->ne[i];
@@ -143,34 +181,23 @@ int make_plan(const coil_config *c, Plan &p) {
     p.Nw = woff;
     p.nlayers = loff;
     p.ngroups = goff;
-    if (tb == 0) tb = p.N <= 8192 ? 64 : 256;
-    p.tile_targets = tb;
-    for (auto &d : p.coils) total_blocks += (d.n + tb - 1) / tb;
-    // source chunks: enough work items to fill the chip (>= ~2048), chunk a
-    // multiple of the LDS stage
-    for (auto &d : p.coils) {
-        int cs = c->tile_sources;
-        if (cs == 0) {
-            long long want = std::max<long long>(1, (2048 + total_blocks - 1) / total_blocks);
-            long long maxch = (d.n + kStage - 1) / kStage;
-            long long ch = std::min(want, maxch);
-            cs = (int)(((d.n + ch - 1) / ch + kStage - 1) / kStage * kStage);
-        }
-        d.nchunk = (d.n + cs - 1) / cs;
-        p.nchunk_max = std::max(p.nchunk_max, d.nchunk);
-        for (int t0 = 0; t0 < d.n; t0 += tb)
-            for (int k = 0; k < d.nchunk; ++k) {
-                PairItem it;
-                it.coil = (int)(&d - &p.coils[0]);
-                it.t0 = d.off + t0;
-                it.tn = std::min(tb, d.n - t0);
-                it.s0 = d.off + k * cs;
-                it.sn = std::min(cs, d.n - k * cs);
-                it.chunk = k;
-                p.items.push_back(it);
-            }
-    }
     p.nheat_blocks = (p.N + 255) / 256;
+    int tb = c->tile_targets;
+    if (tb == 0) tb = p.N <= 8192 ? 64 : 256;
+    build_items(p, tb, 0, c->tile_sources);
+    // capacity for the autotuner's candidates: targets per item >= 64 and at
+    // most kMaxChunks source chunks per coil
+    Plan q = p;
+    size_t cap = p.items.size();
+    int pcap = p.nchunk_max;
+    for (int t : {64, 128, 256})
+        for (int ch : {1, 2, 4, 8, kMaxChunks}) {
+            build_items(q, t, ch, 0);
+            cap = std::max(cap, q.items.size());
+            pcap = std::max(pcap, q.nchunk_max);
+        }
+    p.items_cap = cap;
+    p.nchunk_cap = pcap;
     return COIL_OK;
 }
 
@@ -209,7 +236,7 @@ size_t layout(Plan &p) {
     size_t cur = 0;
     const size_t N = p.N, Nw = p.Nw, d8 = sizeof(double);
     p.coils_b = carve(cur, sizeof(CoilDev) * p.coils.size());
-    p.items_b = carve(cur, sizeof(PairItem) * std::max<size_t>(1, p.items.size()));
+    p.items_b = carve(cur, sizeof(PairItem) * std::max<size_t>(1, std::max(p.items.size(), p.items_cap)));
     p.bbox_b = carve(cur, sizeof(int4) * std::max(1, p.ngroups));
     p.gpos_b = carve(cur, sizeof(float2) * N);
     p.rho_b = carve(cur, d8 * N);
@@ -241,7 +268,7 @@ size_t layout(Plan &p) {
         p.u_b[i] = carve(cur, d8 * N);
         p.T_b[i] = carve(cur, d8 * N);
     }
-    p.part_b = carve(cur, sizeof(double2) * N * p.nchunk_max);
+    p.part_b = carve(cur, sizeof(double2) * N * std::max(p.nchunk_max, p.nchunk_cap));
     p.Uw_b = carve(cur, d8 * Nw);
     p.Qw_b = carve(cur, d8 * Nw);
     p.wq_b = carve(cur, d8 * Nw);
@@ -371,7 +398,8 @@ int reset_state(coil_t *h) {
         HIPCHECK(launch_fill(s.u[i], 0.0, s.N, st));
         HIPCHECK(launch_fill(s.T[i], h->T_bath, s.N, st));
     }
-    HIPCHECK(launch_fill(reinterpret_cast<double *>(s.part), 0.0, 2 * s.N * h->plan.nchunk_max, st));
+    HIPCHECK(launch_fill(reinterpret_cast<double *>(s.part), 0.0,
+                         2 * s.N * std::max(h->plan.nchunk_max, h->plan.nchunk_cap), st));
     HIPCHECK(launch_fill(s.Uw, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.Qw, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.wq, 0.0, s.Nw, st));
@@ -1157,5 +1185,140 @@ extern "C" int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak,
     if ((rc_ = reset_state(h))) return rc_;
     HIPCHECK(hipStreamSynchronize(st));
     h->timing = timing;
+    return COIL_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+namespace {
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+std::string tune_key(const coil_t *h) {
+    long double pairs = 0;
+    for (const CoilDev &d : h->plan.coils) pairs += (long double)d.n * (d.n - 1);
+    const int lg = pairs > 1 ? (int)std::floor(std::log2((double)pairs)) : 0;
+    char buf[128];
+    snprintf(buf, sizeof(buf), "%s/%s/p%d/c%zu", arch_name().c_str(), h->rc.prec == COIL_MIXED ? "mixed" : "fp64",
+             lg, h->plan.coils.size());
+    return buf;
+}
+
+int apply_tiles(coil_t *h, int tb, int nch, int grid) {
+    Plan q = h->plan;
+    build_items(q, tb, nch, 0);
+    if (q.items.size() > h->plan.items_cap && q.items.size() > h->plan.items.size())
+        return fail(COIL_E_INVAL, "tile shape needs %zu work items, capacity %zu", q.items.size(), h->plan.items_cap);
+    if (q.nchunk_max > std::max(h->plan.nchunk_cap, h->plan.nchunk_max))
+        return fail(COIL_E_INVAL, "tile shape needs %d source chunks", q.nchunk_max);
+    HIPCHECK(hipMemcpyAsync((void *)h->ds.items, q.items.data(), sizeof(PairItem) * q.items.size(),
+                            hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(hipMemcpyAsync((void *)h->ds.coils, q.coils.data(), sizeof(CoilDev) * q.coils.size(),
+                            hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    const size_t cap = h->plan.items_cap;
+    const int pcap = h->plan.nchunk_cap;
+    h->plan.items = q.items;
+    h->plan.coils = q.coils;
+    h->plan.tile_targets = q.tile_targets;
+    h->plan.nchunk_max = q.nchunk_max;
+    h->plan.items_cap = cap;
+    h->plan.nchunk_cap = pcap;
+    h->ds.nitems = (int)q.items.size();
+    h->ds.tile_targets = tb;
+    h->grid_limit = grid;
+    return COIL_OK;
+}
+}  // namespace
+
+extern "C" int coil_set_tiles(coil_t *h, int32_t tile_targets, int32_t chunks, int32_t grid_limit) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (!(tile_targets == 64 || tile_targets == 128 || tile_targets == 256))
+        return fail(COIL_E_INVAL, "tile_targets must be 64, 128 or 256");
+    if (chunks < 0 || chunks > kMaxChunks) return fail(COIL_E_INVAL, "chunks must be in [0, %d]", kMaxChunks);
+    if (grid_limit < 0) return fail(COIL_E_INVAL, "grid_limit must be >= 0");
+    if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
+    int rc = coil_graph(h, 0);
+    if (rc) return rc;
+    return apply_tiles(h, tile_targets, chunks, grid_limit);
+}
+
+extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, int32_t *chosen) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (reps < 1) return fail(COIL_E_INVAL, "reps must be >= 1");
+    if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
+    int rc = coil_graph(h, 0);
+    if (rc) return rc;
+    const std::string key = tune_key(h);
+    // cached choice?
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "r");
+        if (f) {
+            char line[512];
+            int best_tb = 0, best_ch = 0, best_g = 0;
+            while (fgets(line, sizeof(line), f)) {
+                char k[200];
+                int tb, ch, g;
+                double ms;
+                if (sscanf(line, "{\"key\": \"%199[^\"]\", \"tile_targets\": %d, \"chunks\": %d, \"grid_limit\": %d, \"ms\": %lf}",
+                           k, &tb, &ch, &g, &ms) == 5 && key == k) {
+                    best_tb = tb;
+                    best_ch = ch;
+                    best_g = g;
+                }
+            }
+            fclose(f);
+            if (best_tb) {
+                if ((rc = apply_tiles(h, best_tb, best_ch, best_g))) return rc;
+                if (chosen) { chosen[0] = best_tb; chosen[1] = best_ch; chosen[2] = best_g; }
+                return COIL_OK;
+            }
+        }
+    }
+    int dev = 0, cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        cus = prop.multiProcessorCount;
+    hipEvent_t a, b;
+    HIPCHECK(hipEventCreate(&a));
+    HIPCHECK(hipEventCreate(&b));
+    double best = INFINITY;
+    int btb = h->ds.tile_targets, bch = 0, bg = h->grid_limit;
+    for (int tb : {64, 128, 256})
+        for (int ch : {1, 2, 4, 8, kMaxChunks})
+            for (int g : {0, 2 * cus, 4 * cus}) {
+                if ((rc = apply_tiles(h, tb, ch, g))) continue;  // over capacity: skip
+                HIPCHECK(launch_field(h->ds, h->rc, h->grid_limit, h->stream));
+                HIPCHECK(hipEventRecord(a, h->stream));
+                for (int r = 0; r < reps; ++r) HIPCHECK(launch_field(h->ds, h->rc, h->grid_limit, h->stream));
+                HIPCHECK(hipEventRecord(b, h->stream));
+                HIPCHECK(hipEventSynchronize(b));
+                float ms = 0.f;
+                HIPCHECK(hipEventElapsedTime(&ms, a, b));
+                if (ms / reps < best) {
+                    best = ms / reps;
+                    btb = tb;
+                    bch = ch;
+                    bg = g;
+                }
+            }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    g_err.clear();
+    if ((rc = apply_tiles(h, btb, bch, bg))) return rc;
+    if (chosen) { chosen[0] = btb; chosen[1] = bch; chosen[2] = bg; }
+    if (cache_path) {
+        FILE *f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "{\"key\": \"%s\", \"tile_targets\": %d, \"chunks\": %d, \"grid_limit\": %d, \"ms\": %.6f}\n",
+                    key.c_str(), btb, bch, bg, best);
+            fclose(f);
+        }
+    }
     return COIL_OK;
 }
