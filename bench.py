@@ -29,12 +29,17 @@ sys.path.insert(0, ROOT)
 # MI355X published peaks (dense, per GPU)
 PEAK_FP32_TFLOPS = 157.3      # vector FP32 with packed FMA
 PEAK_FP32_UNPACKED = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_FP64_TFLOPS = 78.6       # vector FP64 (one FMA per lane per clock)
 PEAK_HBM_GBS = 8000.0
-# algorithmic work of one (target, source) pair of the field pass, FP32 path:
-# coordinate differences 3, al2/be2/dz^2 5, rsqrt 1, m1 2, log2 1, K 18, E 18,
-# f 3, al2 K 1, B_z bracket 4, B_r bracket 5, accumulation 4 -> 65 flop
-# (an FMA counts 2, a hardware transcendental 1)
-FLOP_PER_PAIR = 65
+# Algorithmic work of the field pass (an FMA counts 2, a hardware
+# transcendental 1).  One Green's-function evaluation (FP32 formula):
+# al2/be2/dz^2 5, rsqrt 1, m1 2, log2 1, K 18, E 18, f 3, al2 K 1, B_z bracket
+# 4, B_r bracket 5 -> 58 flop, plus 3 for the coordinates -> 61.  Direct pass:
+# one evaluation and 2 accumulation FMAs per pair -> 65 flop per pair.
+# Translation pass: each distinct value evaluated once per tile (61 flop) and
+# 2 FP64 FMAs per pair (4 flop).
+FLOP_PER_EVAL = 61
+FLOP_PER_PAIR_ACC = 4
 
 
 def log(*a):
@@ -87,6 +92,8 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 validity run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--graph", type=int, default=0, help="capture the step loop in HIP graphs of this many steps")
+    ap.add_argument("--algo", default="auto", choices=["auto", "direct", "translation"],
+                    help="field-pass evaluation (both compute the same all-pairs sum)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
@@ -103,9 +110,10 @@ def main():
     inp = cs.generate(w)
     log(f"[bench] {w.name}: N={w.n_elem} wires={w.n_wire} precision={args.precision}")
     t0 = time.perf_counter()
-    g = pk.Coil(w, inp, precision=args.precision)
+    g = pk.Coil(w, inp, precision=args.precision, algo=args.algo)
     log(f"[bench] init {time.perf_counter() - t0:.2f} s, substeps {g.n_sub}, "
         f"work items {g.sizes.n_work_items}")
+    field_stats = g.field_stats()
     g.run(args.warmup)
     if args.graph > 0:
         g.graph(args.graph)
@@ -122,22 +130,32 @@ def main():
     log(f"[bench] {args.steps} steps in {elapsed:.3f} s -> {sps:.2f} steps/s")
 
     pairs = w.pairs_per_pass()
+    fs = field_stats
     roofline = None
     if tm is not None and tm["field"]["launches"] > 0:
         avg_ms = tm["field"]["ms"] / tm["field"]["launches"]
-        achieved = FLOP_PER_PAIR * pairs / (avg_ms * 1e-3) / 1e12
+        flop = FLOP_PER_EVAL * fs["kernel_evals"] + FLOP_PER_PAIR_ACC * fs["pairs"]
+        achieved = flop / (avg_ms * 1e-3) / 1e12
+        tz = fs["algo"] == "translation"
+        # translation pass: FP64 FMA accumulation dominates -> FP64 vector peak;
+        # direct pass: FP32 transcendental + FMA per pair -> FP32 vector peak
+        peak = PEAK_FP64_TFLOPS if tz else PEAK_FP32_TFLOPS
         roofline = {
             "bound": "alu",
-            "kernel": "k_field (all-pairs ring field pass)",
+            "kernel": ("k_field_tz (translation-reuse all-pairs field pass)" if tz
+                       else "k_field (direct all-pairs field pass)"),
             "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
-            "frac_unpacked_peak": achieved / PEAK_FP32_UNPACKED,
+            "frac": achieved / peak,
+            "frac_unpacked_fp32_peak": achieved / PEAK_FP32_UNPACKED,
             "traffic": None,
             "avg_launch_ms": avg_ms,
-            "flop_per_pair": FLOP_PER_PAIR,
-            "pairs_per_launch": pairs,
+            "flop_per_launch": flop,
+            "pairs_per_launch": fs["pairs"],
+            "kernel_evals_per_launch": fs["kernel_evals"],
+            "flop_per_eval": FLOP_PER_EVAL,
+            "flop_per_pair": FLOP_PER_PAIR_ACC,
             "phase_ms_per_step": {k: v["ms"] / max(1, args.steps) for k, v in tm.items()},
         }
 
@@ -148,7 +166,7 @@ def main():
         Tm = g.get(pk.F_T)
         g.close()
         log(f"[bench] FP64 reference run of {total} steps")
-        r = pk.Coil(w, inp, precision="fp64")
+        r = pk.Coil(w, inp, precision="fp64", algo="direct")
         r.run(total)
         eb = max(nerr(Bm[0], r.get(pk.F_BR)), nerr(Bm[1], r.get(pk.F_BZ)))
         et = nerr(Tm, r.get(pk.F_T))
@@ -188,6 +206,7 @@ def main():
             "heat_substeps": g.n_sub,
             "seed": w.seed,
             "graph_steps": args.graph,
+            "field_algo": field_stats["algo"],
         },
         "ginteractions_per_s": pairs * sps / 1e9,
         "mixed_vs_fp64": check,

@@ -67,6 +67,15 @@ enum coil_precision {
                        all state (I, Phi, u, T, Q) in FP64 */
 };
 
+/* Field-pass evaluation.  Both compute the same all-pairs sum (every pair
+   contributes G_B(e,j) I_j once, kernel values evaluated on the fly every step):
+   DIRECT evaluates K, E per pair (tiled N-body sum, any element positions);
+   TRANSLATION uses that on a coil's regular (r,z) grid G_B depends on
+   (i_r, j_r, i_z - j_z) only: per tile each distinct kernel value is evaluated
+   once and reused along z (a per-row-pair 1-D convolution, FP64 accumulation).
+   AUTO = TRANSLATION. */
+enum coil_algo { COIL_ALGO_AUTO = 0, COIL_ALGO_DIRECT = 1, COIL_ALGO_TRANSLATION = 2 };
+
 /* fields for coil_get / coil_set_state */
 enum coil_field {
     COIL_F_I = 0,     /* element current, A                (settable) */
@@ -107,6 +116,7 @@ typedef struct {
     int32_t tile_sources;   /* sources per work item (0 -> automatic) */
     int32_t grid_limit;     /* 0: one workgroup per work item; > 0: persistent grid of at
                                most this many workgroups striding over the work items */
+    int32_t algo;           /* enum coil_algo: how the field pass is evaluated */
 } coil_config;
 
 typedef struct {
@@ -235,6 +245,12 @@ int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, 
    grid_limit).  Results differ between tilings only by summation order. */
 int coil_set_tiles(coil_t *h, int32_t tile_targets, int32_t chunks, int32_t grid_limit);
 int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, int32_t *chosen);
+
+/* Work of one field pass as planned: out[0] ordered (target, source) pairs,
+   out[1] Green's-function evaluations (= pairs for DIRECT), out[2] the algorithm
+   (enum coil_algo), out[3] work items, out[4] direct-pass targets per workgroup.
+   Writes min(n, 5) values.  No device work. */
+int coil_field_stats(coil_t *h, double *out, int32_t n);
 
 void coil_destroy(coil_t *h);  /* does not free the caller's workspace */
 const char *coil_last_error(void);

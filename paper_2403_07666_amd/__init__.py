@@ -7,6 +7,6 @@
     B = c.get(F_BZ)
 """
 from .coil import (  # noqa: F401
-    FP64, MIXED, F_I, F_J, F_BR, F_BZ, F_T, F_PHI, F_QW, F_UW, F_E, F_EP, F_U, F_Q, F_PSI, F_R, F_Z,
+    FP64, MIXED, ALGO_AUTO, ALGO_DIRECT, ALGO_TRANSLATION, F_I, F_J, F_BR, F_BZ, F_T, F_PHI, F_QW, F_UW, F_E, F_EP, F_U, F_Q, F_PSI, F_R, F_Z,
     F_DI, F_JC, Coil, CoilError, host_ellip, lib, query, EXPORTS,
 )

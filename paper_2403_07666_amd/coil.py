@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libcoil.so")
 # enum coil_status / coil_precision / coil_field (include/coil.h)
 OK, E_INVAL, E_NOMEM, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
+ALGO_AUTO, ALGO_DIRECT, ALGO_TRANSLATION = 0, 1, 2
 F_I, F_J, F_BR, F_BZ, F_T, F_PHI, F_QW, F_UW, F_E, F_EP, F_U, F_Q, F_PSI, F_R, F_Z, F_DI, F_JC = range(17)
 PER_WIRE = (F_QW, F_UW)
 
@@ -46,6 +47,7 @@ class Config(C.Structure):
         ("heat_substeps", C.c_int32), ("precision", C.c_int32),
         ("near_k", C.c_double),
         ("tile_targets", C.c_int32), ("tile_sources", C.c_int32), ("grid_limit", C.c_int32),
+        ("algo", C.c_int32),
     ]
 
 
@@ -65,6 +67,7 @@ EXPORTS = [
     "coil_set_state", "coil_scalars", "coil_reset", "coil_timing", "coil_timing_read",
     "coil_graph", "coil_destroy", "coil_last_error", "coil_host_ellip", "coil_set_params",
     "coil_adjoint_query", "coil_adjoint", "coil_field_transpose", "coil_set_tiles", "coil_autotune",
+    "coil_field_stats",
 ]
 
 _lib = None
@@ -101,6 +104,7 @@ def lib():
         L.coil_field_transpose.argtypes = [vp, vp, vp, vp, C.c_int32]
         L.coil_set_tiles.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
         L.coil_autotune.argtypes = [vp, C.c_int32, C.c_char_p, _i32p]
+        L.coil_field_stats.argtypes = [vp, _dp, C.c_int32]
         _lib = L
     return _lib
 
@@ -131,7 +135,7 @@ class _CfgHolder:
     """Keeps the per-coil arrays of a Config alive."""
 
     def __init__(self, w, precision=None, tile_targets=0, tile_sources=0, grid_limit=0,
-                 near_k=0.0, heat_substeps=None):
+                 near_k=0.0, heat_substeps=None, algo=ALGO_AUTO):
         co = w.coils
         self.arr = {
             "layers": np.array([c.layers for c in co], dtype=np.int32),
@@ -159,6 +163,7 @@ class _CfgHolder:
         cfg.tile_targets = int(tile_targets)
         cfg.tile_sources = int(tile_sources)
         cfg.grid_limit = int(grid_limit)
+        cfg.algo = {"auto": ALGO_AUTO, "direct": ALGO_DIRECT, "translation": ALGO_TRANSLATION}.get(algo, algo)
         self.cfg = cfg
 
 
@@ -349,3 +354,10 @@ class Coil:
         path = cache_path.encode() if cache_path else None
         check(lib().coil_autotune(self.h, int(reps), path, ch.ctypes.data_as(_i32p)))
         return tuple(int(v) for v in ch)
+
+    def field_stats(self) -> dict:
+        """Work of one field pass: pairs, Green's-function evaluations, algorithm, items."""
+        v = np.zeros(5)
+        check(lib().coil_field_stats(self.h, v.ctypes.data_as(_dp), 5))
+        return {"pairs": v[0], "kernel_evals": v[1], "algo": "translation" if v[2] == 2 else "direct",
+                "items": int(v[3]), "tile_targets": int(v[4])}

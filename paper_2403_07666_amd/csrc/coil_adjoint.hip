@@ -92,8 +92,9 @@ __global__ void k_fieldT_sum(DevState s, const double *partT, double *out, int a
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= s.N) return;
     const CoilDev c = s.coils[s.elem_coil[j]];
+    const int nk = s.algo_tz ? c.nslot_tz : c.nchunk;
     double v = 0.0;
-    for (int k = 0; k < c.nchunk; ++k) v += partT[(size_t)k * s.N + j];
+    for (int k = 0; k < nk; ++k) v += partT[(size_t)k * s.N + j];
     out[j] = accumulate ? out[j] + v : v;
 }
 

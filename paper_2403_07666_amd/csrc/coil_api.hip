@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "coil_adjoint.h"
+#include "coil_field_tz.h"
 #include "coil_internal.h"
 
 using namespace coilq;
@@ -54,13 +55,19 @@ struct Plan {
     std::vector<PairItem> items;
     int nchunk_max = 1;
     size_t items_cap = 0;  // work-item capacity (autotuner candidates)
+    std::vector<TzItem> tz_items;  // translation-reuse pass, grouped by W
+    int tz_first[3] = {0, 0, 0}, tz_count[3] = {0, 0, 0};
+    int nslot_tz_max = 1;
+    int part_slots = 2;  // capacity of part[] in double2 slots of N
+    double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
+    int algo = COIL_ALGO_TRANSLATION;
     int nchunk_cap = 1;    // partial-sum capacity in chunks
     size_t total = 0;
     // regions
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
         perm_b, wire_coil_b, elem_coil_b, Mlay_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
-        sc_b, tmp_b, misc_b;
+        sc_b, tmp_b, misc_b, tz_b, Ipub_b, pub2int_b;
 };
 
 Buf carve(size_t &cur, size_t bytes) {
@@ -109,6 +116,7 @@ int validate(const coil_config *c) {
     if (c->tile_sources < 0 || c->tile_sources % kStage != 0)
         return fail(COIL_E_INVAL, "tile_sources must be a non-negative multiple of %d", kStage);
     if (c->grid_limit < 0) return fail(COIL_E_INVAL, "grid_limit must be >= 0");
+    if (c->algo < COIL_ALGO_AUTO || c->algo > COIL_ALGO_TRANSLATION) return fail(COIL_E_INVAL, "unknown algo %d", c->algo);
     return COIL_OK;
 }
 
@@ -147,6 +155,67 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
                 it.chunk = k;
                 p.items.push_back(it);
             }
+    }
+}
+
+// Translation-reuse work items: per coil a per-thread target count W in
+// {2, 4, 8} (target row segments of 64 W), rows x segments x source-row groups.
+void build_tz(Plan &p) {
+    std::vector<TzItem> by[3];
+    const int Ws[3] = {2, 4, 8};
+    const double eff[3] = {0.55, 0.8, 1.0};  // relative throughput of the W variants
+    std::vector<int> wsel(p.coils.size());
+    long long segs = 0;
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        const CoilDev &d = p.coils[ci];
+        const int nz = d.turns * d.ne, nr = d.layers * d.ne;
+        double best = -1.0;
+        for (int k = 0; k < 3; ++k) {
+            const int span = 64 * Ws[k];
+            const double util = (double)nz / (double)(((nz + span - 1) / span) * span);
+            if (util * eff[k] > best) {
+                best = util * eff[k];
+                wsel[ci] = k;
+            }
+        }
+        segs += (long long)nr * ((nz + 64 * Ws[wsel[ci]] - 1) / (64 * Ws[wsel[ci]]));
+    }
+    const int nsplit = (int)std::max<long long>(1, std::min<long long>(16, (4096 + segs - 1) / segs));
+    p.nslot_tz_max = 1;
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        CoilDev &d = p.coils[ci];
+        const int nz = d.turns * d.ne, nr = d.layers * d.ne;
+        const int k = wsel[ci], span = 64 * Ws[k];
+        const int ns = std::min(nsplit, nr);
+        d.nslot_tz = ns;
+        p.nslot_tz_max = std::max(p.nslot_tz_max, ns);
+        for (int ir = 0; ir < nr; ++ir)
+            for (int z0 = 0; z0 < nz; z0 += span)
+                for (int g = 0; g < ns; ++g) {
+                    TzItem it{};
+                    it.coil = (int)ci;
+                    it.ir = ir;
+                    it.z0 = z0;
+                    it.jr0 = (int)((long long)g * nr / ns);
+                    it.jr1 = (int)((long long)(g + 1) * nr / ns);
+                    it.slot = g;
+                    by[k].push_back(it);
+                }
+    }
+    // kernel-value evaluations per pass: per item, source row and z-chunk of
+    // 256 the table holds 64 W + 256 - 1 + W entries
+    p.tz_evals = 0.0;
+    for (int k = 0; k < 3; ++k)
+        for (const TzItem &it : by[k]) {
+            const CoilDev &d = p.coils[it.coil];
+            const int nz = d.turns * d.ne;
+            p.tz_evals += (double)(it.jr1 - it.jr0) * ((nz + 255) / 256) * (64 * Ws[k] + 255 + Ws[k]);
+        }
+    p.tz_items.clear();
+    for (int k = 0; k < 3; ++k) {
+        p.tz_first[k] = (int)p.tz_items.size();
+        p.tz_count[k] = (int)by[k].size();
+        p.tz_items.insert(p.tz_items.end(), by[k].begin(), by[k].end());
     }
 }
 
@@ -198,6 +267,8 @@ int make_plan(const coil_config *c, Plan &p) {
         }
     p.items_cap = cap;
     p.nchunk_cap = pcap;
+    build_tz(p);
+    p.algo = c->algo == COIL_ALGO_DIRECT ? COIL_ALGO_DIRECT : COIL_ALGO_TRANSLATION;
     return COIL_OK;
 }
 
@@ -268,7 +339,13 @@ size_t layout(Plan &p) {
         p.u_b[i] = carve(cur, d8 * N);
         p.T_b[i] = carve(cur, d8 * N);
     }
-    p.part_b = carve(cur, sizeof(double2) * N * std::max(p.nchunk_max, p.nchunk_cap));
+    // partial sums: every tiling's slot count, and at least 2 slots so that the
+    // transposed test hook can stage 2N doubles after N partials
+    p.part_slots = std::max({p.nchunk_max, p.nchunk_cap, p.nslot_tz_max, 2});
+    p.part_b = carve(cur, sizeof(double2) * N * p.part_slots);
+    p.tz_b = carve(cur, sizeof(TzItem) * std::max<size_t>(1, p.tz_items.size()));
+    p.Ipub_b = carve(cur, sizeof(double) * N);
+    p.pub2int_b = carve(cur, sizeof(int) * N);
     p.Uw_b = carve(cur, d8 * Nw);
     p.Qw_b = carve(cur, d8 * Nw);
     p.wq_b = carve(cur, d8 * Nw);
@@ -296,6 +373,9 @@ struct coil_s {
     double T_bath = 4.2;
     std::vector<double> r_pub, z_pub;  // public order, for COIL_F_R / COIL_F_Z
     std::vector<int> pub2int;          // public -> internal element index
+    TzPlan tz{};                       // device items of the translation-reuse pass
+    double *Ipub = nullptr;            // currents in public order (its input)
+    int *d_pub2int = nullptr;
     // timing
     bool timing = false;
     struct Pending {
@@ -363,11 +443,25 @@ int t_flush(coil_t *h) {
     return COIL_OK;
 }
 
+// transposed field pass into partT, by the handle's algorithm; wpub: 2N doubles
+hipError_t launch_fieldT_any(coil_t *h, const double *wr, const double *wz, double *wpub, double *partT,
+                             hipStream_t st) {
+    const DevState &d = h->ds;
+    if (d.algo_tz)
+        return launch_fieldT_tz(d, h->rc, h->tz, wr, wz, wpub, wpub + d.N, h->d_pub2int, partT, st);
+    return launch_fieldT(d, h->rc, h->grid_limit, wr, wz, partT, st);
+}
+
+hipError_t launch_field_any(coil_t *h, const DevState &d, hipStream_t st) {
+    if (d.algo_tz) return launch_field_tz(d, h->rc, h->tz, h->Ipub, h->d_pub2int, 0, st);
+    return launch_field(d, h->rc, h->grid_limit, st);
+}
+
 int enqueue_step(coil_t *h) {
     hipEvent_t a = nullptr;
     int rc;
     if ((rc = t_begin(h, &a))) return rc;
-    HIPCHECK(launch_field(h->ds, h->rc, h->grid_limit, h->stream));
+    HIPCHECK(launch_field_any(h, h->ds, h->stream));
     if ((rc = t_end(h, 0, a, 1))) return rc;
     if ((rc = t_begin(h, &a))) return rc;
     HIPCHECK(launch_wire(h->ds, h->rc, h->stream));
@@ -398,8 +492,7 @@ int reset_state(coil_t *h) {
         HIPCHECK(launch_fill(s.u[i], 0.0, s.N, st));
         HIPCHECK(launch_fill(s.T[i], h->T_bath, s.N, st));
     }
-    HIPCHECK(launch_fill(reinterpret_cast<double *>(s.part), 0.0,
-                         2 * s.N * std::max(h->plan.nchunk_max, h->plan.nchunk_cap), st));
+    HIPCHECK(launch_fill(reinterpret_cast<double *>(s.part), 0.0, 2 * s.N * h->plan.part_slots, st));
     HIPCHECK(launch_fill(s.Uw, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.Qw, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.wq, 0.0, s.Nw, st));
@@ -602,6 +695,14 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     s.nsub = p.nsub;
     s.max_ne2 = p.max_ne2;
     s.tile_targets = p.tile_targets;
+    s.algo_tz = p.algo == COIL_ALGO_TRANSLATION ? 1 : 0;
+    h->Ipub = at<double>(h, p.Ipub_b);
+    h->d_pub2int = at<int>(h, p.pub2int_b);
+    h->tz.items = at<TzItem>(h, p.tz_b);
+    for (int k = 0; k < 3; ++k) {
+        h->tz.first[k] = p.tz_first[k];
+        h->tz.count[k] = p.tz_count[k];
+    }
     s.coils = at<CoilDev>(h, p.coils_b);
     s.items = at<PairItem>(h, p.items_b);
     s.bbox = at<int4>(h, p.bbox_b);
@@ -666,6 +767,8 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)s.elem_coil, elem_coil.data(), sizeof(int) * N));
     HIPCHECK(up((void *)s.Mlay, Mlay.data(), sizeof(double) * Mlay.size()));
     HIPCHECK(up((void *)s.cw, cw.data(), sizeof(double) * Nw));
+    HIPCHECK(up((void *)h->tz.items, p.tz_items.data(), sizeof(TzItem) * p.tz_items.size()));
+    HIPCHECK(up((void *)h->d_pub2int, pub2int.data(), sizeof(int) * N));
     // transport-flux pattern: FP64 all-pairs pass on the device
     HIPCHECK(launch_psi(s, const_cast<double *>(s.psi), st));
     if ((rc = reset_state(h))) return rc;
@@ -682,7 +785,7 @@ extern "C" int coil_step(coil_t *h) {
 
 extern "C" int coil_compute_field(coil_t *h) {
     if (!h) return fail(COIL_E_INVAL, "handle is NULL");
-    HIPCHECK(launch_field(h->ds, h->rc, h->grid_limit, h->stream));
+    HIPCHECK(launch_field_any(h, h->ds, h->stream));
     HIPCHECK(launch_field_finalize(h->ds, h->rc, h->stream));
     return COIL_OK;
 }
@@ -995,7 +1098,13 @@ extern "C" int coil_field_transpose(coil_t *h, const double *bbar_r, const doubl
     }
     HIPCHECK(launch_field_weights(s, s.Br, s.Bz, st));
     double *partT = reinterpret_cast<double *>(s.part);
-    HIPCHECK(launch_fieldT(s, h->rc, h->grid_limit, s.Br, s.Bz, partT, st));
+    // staging for public-order weights: the second half of the partial buffer
+    // (partT needs at most nslot N doubles of its 2 nslot N)
+    const int nsl = std::max({h->plan.nchunk_max, h->plan.nchunk_cap, h->plan.nslot_tz_max});
+    double *wpub = partT + (size_t)nsl * N;  // nsl N + 2 N <= 2 part_slots N doubles
+    if ((size_t)nsl * N + 2 * (size_t)N > 2 * (size_t)h->plan.part_slots * N)
+        return fail(COIL_E_NOMEM, "partial buffer too small for the transposed pass");
+    HIPCHECK(launch_fieldT_any(h, s.Br, s.Bz, wpub, partT, st));
     HIPCHECK(launch_fieldT_sum(s, partT, s.dI, 0, st));
     if (on_device) {
         HIPCHECK(launch_gather(s.dI, s.perm, N, out, st));
@@ -1010,7 +1119,7 @@ extern "C" int coil_field_transpose(coil_t *h, const double *bbar_r, const doubl
 // ------------------------------------------------------------------ adjoint
 namespace {
 struct AdjLayout {
-    size_t ckI, ckU, ckT, hBr, hBz, sI, sdI, sT, sBr, sBz, Ib, ub0, ub1, qb, wr, wz, partT, cb, dIb, total;
+    size_t ckI, ckU, ckT, hBr, hBz, sI, sdI, sT, sBr, sBz, Ib, ub0, ub1, qb, wr, wz, partT, wpub, cb, dIb, total;
     long long nseg;
 };
 
@@ -1044,7 +1153,8 @@ AdjLayout adj_layout(const Plan &p, long long K, long long C, int store_field) {
     L.qb = take(d8 * N);
     L.wr = take(d8 * N);
     L.wz = take(d8 * N);
-    L.partT = take(d8 * N * p.nchunk_max);
+    L.partT = take(d8 * N * std::max({p.nchunk_max, p.nchunk_cap, p.nslot_tz_max}));
+    L.wpub = take(d8 * N * 2);
     L.cb = take(d8 * Nw);
     L.dIb = take(d8 * Nw);
     L.total = (cur + 255) & ~size_t(255);
@@ -1084,7 +1194,7 @@ extern "C" int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak,
     h->timing = false;
 
     auto step_with = [&](const DevState &d, bool field) -> int {
-        if (field) HIPCHECK(launch_field(d, rc, h->grid_limit, st));
+        if (field) HIPCHECK(launch_field_any(h, d, st));
         HIPCHECK(launch_wire(d, rc, st));
         for (int sub = 0; sub < nsub; ++sub) HIPCHECK(launch_heat(d, rc, sub, st));
         HIPCHECK(launch_finalize(d, rc, st));
@@ -1168,7 +1278,7 @@ extern "C" int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak,
             a.cbar = P(L.cb);
             a.dItbar = P(L.dIb);
             HIPCHECK(launch_wire_adj(base, rc, a, st));
-            HIPCHECK(launch_fieldT(base, rc, h->grid_limit, a.wr, a.wz, P(L.partT), st));
+            HIPCHECK(launch_fieldT_any(h, a.wr, a.wz, P(L.wpub), P(L.partT), st));
             HIPCHECK(launch_fieldT_sum(base, P(L.partT), Ib, 1, st));
         }
     }
@@ -1320,5 +1430,17 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
             fclose(f);
         }
     }
+    return COIL_OK;
+}
+
+extern "C" int coil_field_stats(coil_t *h, double *out, int32_t n) {
+    if (!h || !out) return fail(COIL_E_INVAL, "NULL argument");
+    double pairs = 0.0;
+    for (const CoilDev &d : h->plan.coils) pairs += (double)d.n * (double)(d.n - 1);
+    const bool tz = h->ds.algo_tz != 0;
+    const double v[5] = {pairs, tz ? h->plan.tz_evals : pairs, tz ? 2.0 : 1.0,
+                         tz ? (double)h->plan.tz_items.size() : (double)h->plan.items.size(),
+                         (double)h->ds.tile_targets};
+    for (int i = 0; i < n && i < 5; ++i) out[i] = v[i];
     return COIL_OK;
 }

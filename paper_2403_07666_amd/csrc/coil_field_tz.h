@@ -1,0 +1,29 @@
+// coil_field_tz.h -- work items and launcher of the translation-reuse field pass
+// (coil_field_tz.hip).
+#pragma once
+
+#include "coil_internal.h"
+
+namespace coilq {
+
+// one target row segment [z0, z0 + 64 W) of row ir, source rows [jr0, jr1)
+struct TzItem {
+    int coil, ir, z0, jr0, jr1, slot, pad0, pad1;
+};
+
+// items grouped by the per-thread target count W = 2, 4, 8
+struct TzPlan {
+    const TzItem *items;
+    int first[3], count[3];
+};
+
+hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
+                           const int *pub2int, int grid_limit, hipStream_t st);
+
+// transposed pass: partT[slot][j] for the weights (wr, wz) in internal order;
+// wr_pub / wz_pub are N-element staging buffers
+hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *wr,
+                            const double *wz, double *wr_pub, double *wz_pub, const int *pub2int,
+                            double *partT, hipStream_t st);
+
+}  // namespace coilq

@@ -1,0 +1,293 @@
+// coil_field_tz.hip -- field pass that evaluates each distinct Green's
+// function value once per tile (z-translation invariance of the coaxial-ring
+// kernel on a regular grid).
+//
+// For a coil on a regular (r, z) grid, the field of source (j_r, j_z) at
+// target (i_r, i_z) depends only on (i_r, j_r, i_z - j_z): the ring Green's
+// function is invariant under a common shift in z.  The all-pairs sum
+//   B(i_r, i_z) = sum_{j_r, j_z} g(i_r, j_r, i_z - j_z) I(j_r, j_z)
+// is therefore, for every pair of rows (i_r, j_r), a 1-D convolution along z.
+// A work item owns one target row segment of 64*W consecutive z (one target
+// per lane and W per thread) and a range of source rows; for every source row
+// and every chunk of S source z it
+//   1. evaluates the 64*W + S - 1 distinct kernel values g(delta) on the fly
+//      (elliptic integrals as in the direct pass; mixed precision: FP32 where
+//      m1 >= m1_near, FP64 for the near values) into LDS, stored de-interleaved
+//      by delta mod W so that every lane reads a different bank;
+//   2. streams the S source currents through LDS and accumulates
+//      acc[c] += g(delta) * I with a W-register sliding window over delta:
+//      one LDS read of g feeds 2W FP64 FMAs.
+// Every pair still contributes g * I exactly once; only redundant evaluations
+// of identical kernel values are removed.  Accumulation is FP64 in both
+// precision modes (FP64 FMA runs at the non-packed FP32 rate on this GPU).
+#include <hip/hip_runtime.h>
+
+#include "coil_device.h"
+#include "coil_field_tz.h"
+
+namespace coilq {
+
+// unit-current kernel values (grid units): f g_r, f g_z as in pair64/pair32
+__device__ __forceinline__ double2 kern64(double dr, double dz, double sr) {
+    const double dz2 = dz * dz;
+    const double al2 = fma(dr, dr, dz2);
+    const double be2 = fma(sr, sr, dz2);
+    if (!(al2 > 0.0)) return make_double2(0.0, 0.0);  // the element's own ring
+    const double rb = rsqrt(be2);
+    const double m1 = al2 * (rb * rb);
+    const double L = -log(m1);
+    const double K = fma(ellipk64_Q(m1), L, ellipk64_P(m1));
+    const double E = fma(ellipe64_Q(m1), L, ellipe64_P(m1));
+    const double f = rb / al2;
+    const double alK = al2 * K;
+    const double gz = fma(fma(-dr, sr, -dz2), E, alK);
+    const double gr = dz * fma(0.5 * (al2 + be2), E, -alK);
+    return make_double2(f * gr, f * gz);
+}
+
+__device__ __forceinline__ double2 kern32(float dr, float dz, float sr) {
+    const float dz2 = dz * dz;
+    const float al2 = fmaf(dr, dr, dz2);
+    const float be2 = fmaf(sr, sr, dz2);
+    const float rb = __builtin_amdgcn_rsqf(be2);
+    const float m1 = al2 * (rb * rb);
+    const float L2 = -__builtin_amdgcn_logf(m1);
+    const float K = fmaf(ellipk32_Q(m1), L2, ellipk32_P(m1));
+    const float E = fmaf(ellipe32_Q(m1), L2, ellipe32_P(m1));
+    const float f = rb * __builtin_amdgcn_rcpf(al2);
+    const float alK = al2 * K;
+    const float gz = fmaf(fmaf(-dr, sr, -dz2), E, alK);
+    const float gr = dz * fmaf(0.5f * (al2 + be2), E, -alK);
+    return make_double2((double)(f * gr), (double)(f * gz));
+}
+
+template <int MIXED>
+__device__ __forceinline__ double2 kern(double dr, double dz, double sr, float m1_near) {
+    if (MIXED) {
+        // the argument m1 = al2 / be2 decides in FP64 whether the value is near
+        const double al2 = dr * dr + dz * dz;
+        const double be2 = sr * sr + dz * dz;
+        if (al2 >= (double)m1_near * be2) return kern32((float)dr, (float)dz, (float)sr);
+    }
+    return kern64(dr, dz, sr);
+}
+
+// Table layout: entry tau (0 <= tau < NT + W) at [(tau % W) * Q + tau / W].
+template <int W>
+struct TzShape {
+    static constexpr int S = 256;                 // source z per chunk
+    static constexpr int TZ = 64 * W;             // target z per item
+    static constexpr int NT = TZ + S - 1 + W;     // table entries incl. W of padding
+    static constexpr int Q = (NT + W - 1) / W;    // de-interleave stride
+};
+
+template <int MIXED, int W>
+__global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const TzItem *items,
+                                                 int nitems, const double *Ipub, const int *pub2int) {
+    using Sh = TzShape<W>;
+    constexpr int S = Sh::S, NT = Sh::NT, Q = Sh::Q;
+    __shared__ double2 gt[W * Q];
+    __shared__ double Is[S];
+    const int lane = threadIdx.x;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TzItem item = items[it];
+        const CoilDev c = s.coils[item.coil];
+        const int nz = c.turns * c.ne;
+        const int ir = item.ir, z0 = item.z0;
+        double ar[W], az[W];
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) ar[cc] = az[cc] = 0.0;
+        for (int jr = item.jr0; jr < item.jr1; ++jr) {
+            const double dr = (double)(ir - jr);
+            const double sr = c.c2d + (double)(ir + jr);
+            const double *Irow = Ipub + c.off + (size_t)jr * nz;
+            for (int s0 = 0; s0 < nz; s0 += S) {
+                const int sn = min(S, nz - s0);
+                // delta = z_target - z_source; tau = delta - dmin + W (W entries of padding)
+                const int dmin = z0 - (s0 + S - 1);
+                __syncthreads();
+                for (int tau = lane; tau < NT; tau += 64) {
+                    const double dz = (double)(dmin + tau - W);
+                    gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, dz, sr, rc.m1_near);
+                }
+                for (int t = lane; t < S; t += 64) Is[t] = t < sn ? c.kscale * Irow[s0 + t] : 0.0;
+                __syncthreads();
+                // sliding window: at step t, lane needs tau = W*lane + S - 1 - t + cc + W
+                double2 ring[W];
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc) {
+                    const int tau = W * lane + S - 1 + cc + W;  // residue (W - 1 + cc) mod W
+                    ring[(W - 1 + cc) % W] = gt[((W - 1 + cc) % W) * Q + tau / W];
+                }
+                for (int t0 = 0; t0 < S; t0 += W) {
+#pragma unroll
+                    for (int u = 0; u < W; ++u) {
+                        const int t = t0 + u;
+                        const double I = Is[t];
+                        // tau_lo = W*lane + S - 1 - t + W  ==  (W - 1 - u) mod W
+#pragma unroll
+                        for (int cc = 0; cc < W; ++cc) {
+                            const double2 g = ring[(2 * W - 1 - u + cc) % W];
+                            ar[cc] = fma(g.x, I, ar[cc]);
+                            az[cc] = fma(g.y, I, az[cc]);
+                        }
+                        // next value entering the window: tau_lo - 1
+                        const int taun = W * lane + S - 2 - t + W;
+                        ring[(2 * W - 2 - u) % W] = gt[((2 * W - 2 - u) % W) * Q + taun / W];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) {
+            const int z = z0 + W * lane + cc;
+            if (z < nz) {
+                const int e = pub2int[c.off + ir * nz + z];
+                s.part[(size_t)item.slot * s.N + e] = make_double2(ar[cc], az[cc]);
+            }
+        }
+    }
+}
+
+// Transposed pass (adjoint): out(j_r, j_z) = sum over target rows i_r and
+// targets i_z of g_r(i_r, j_r, i_z - j_z) wr(i_r, i_z) + g_z(...) wz(i_r, i_z),
+// a correlation along z for every pair of rows.  Item fields: ir = output row
+// j_r, z0 = output segment, [jr0, jr1) = target rows.  The window slides up in
+// delta as the target index grows; the table carries one more entry than the
+// forward one so that the last prefetch stays inside it.
+template <int W>
+struct TzShapeT {
+    static constexpr int S = 256;
+    static constexpr int TZ = 64 * W;
+    static constexpr int NT = TZ + S + W;
+    static constexpr int Q = (NT + W - 1) / W;
+};
+
+template <int MIXED, int W>
+__global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const TzItem *items,
+                                                  int nitems, const double *wr_pub, const double *wz_pub,
+                                                  const int *pub2int, double *partT) {
+    using Sh = TzShapeT<W>;
+    constexpr int S = Sh::S, TZ = Sh::TZ, NT = Sh::NT, Q = Sh::Q;
+    __shared__ double2 gt[W * Q];
+    __shared__ double2 ws[S];
+    const int lane = threadIdx.x;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TzItem item = items[it];
+        const CoilDev c = s.coils[item.coil];
+        const int nz = c.turns * c.ne;
+        const int jr = item.ir, z0 = item.z0;
+        double acc[W];
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) acc[cc] = 0.0;
+        for (int ir = item.jr0; ir < item.jr1; ++ir) {
+            const double dr = (double)(ir - jr);
+            const double sr = c.c2d + (double)(ir + jr);
+            const size_t rowoff = c.off + (size_t)ir * nz;
+            for (int s0 = 0; s0 < nz; s0 += S) {
+                const int sn = min(S, nz - s0);
+                // delta = z_target - z_output; tau = delta - dmin + W
+                const int dmin = s0 - (z0 + TZ - 1);
+                __syncthreads();
+                for (int tau = lane; tau < NT; tau += 64) {
+                    const double dz = (double)(dmin + tau - W);
+                    gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, dz, sr, rc.m1_near);
+                }
+                for (int t = lane; t < S; t += 64)
+                    ws[t] = t < sn ? make_double2(wr_pub[rowoff + s0 + t], wz_pub[rowoff + s0 + t])
+                                   : make_double2(0.0, 0.0);
+                __syncthreads();
+                double2 ring[W];
+#pragma unroll
+                for (int cc = 0; cc < W; ++cc) {
+                    const int tau = -W * lane - cc + TZ - 1 + W;  // residue (W - 1 - cc) mod W
+                    ring[(W - 1 - cc) % W] = gt[((W - 1 - cc) % W) * Q + tau / W];
+                }
+                for (int t0 = 0; t0 < S; t0 += W) {
+#pragma unroll
+                    for (int u = 0; u < W; ++u) {
+                        const int t = t0 + u;
+                        const double2 wv = ws[t];
+#pragma unroll
+                        for (int cc = 0; cc < W; ++cc) {
+                            const double2 g = ring[(u + W - 1 - cc) % W];
+                            acc[cc] = fma(g.x, wv.x, fma(g.y, wv.y, acc[cc]));
+                        }
+                        const int taun = t + 1 - W * lane + TZ - 1 + W;  // residue u mod W
+                        ring[u % W] = gt[(u % W) * Q + taun / W];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) {
+            const int z = z0 + W * lane + cc;
+            if (z < nz) partT[(size_t)item.slot * s.N + pub2int[c.off + jr * nz + z]] = acc[cc];
+        }
+    }
+}
+
+// I in public (row-major) order for the convolution pass
+__global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) Ipub[perm[i]] = I[i];
+}
+
+hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
+                           const int *pub2int, int grid_limit, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N,
+                       const_cast<double *>(Ipub));
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    for (int wi = 0; wi < 3; ++wi) {
+        const int n = tp.count[wi];
+        if (n == 0) continue;
+        const TzItem *items = tp.items + tp.first[wi];
+        const int grid = grid_limit > 0 ? min(grid_limit, n) : n;
+        const bool mixed = rc.prec == COIL_MIXED;
+#define COILQ_TZ_LAUNCH(Wv)                                                                        \
+    if (mixed)                                                                                     \
+        hipLaunchKernelGGL((k_field_tz<1, Wv>), dim3(grid), dim3(64), 0, st, s, rc, items, n, Ipub, \
+                           pub2int);                                                               \
+    else                                                                                           \
+        hipLaunchKernelGGL((k_field_tz<0, Wv>), dim3(grid), dim3(64), 0, st, s, rc, items, n, Ipub, pub2int);
+        if (wi == 0) { COILQ_TZ_LAUNCH(2) }
+        else if (wi == 1) { COILQ_TZ_LAUNCH(4) }
+        else { COILQ_TZ_LAUNCH(8) }
+#undef COILQ_TZ_LAUNCH
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *wr,
+                            const double *wz, double *wr_pub, double *wz_pub, const int *pub2int,
+                            double *partT, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wr, s.perm, s.N, wr_pub);
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wz, s.perm, s.N, wz_pub);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    for (int wi = 0; wi < 3; ++wi) {
+        const int n = tp.count[wi];
+        if (n == 0) continue;
+        const TzItem *items = tp.items + tp.first[wi];
+        const bool mixed = rc.prec == COIL_MIXED;
+#define COILQ_TZT_LAUNCH(Wv)                                                                            \
+    if (mixed)                                                                                          \
+        hipLaunchKernelGGL((k_fieldT_tz<1, Wv>), dim3(n), dim3(64), 0, st, s, rc, items, n, wr_pub, wz_pub, \
+                           pub2int, partT);                                                             \
+    else                                                                                                \
+        hipLaunchKernelGGL((k_fieldT_tz<0, Wv>), dim3(n), dim3(64), 0, st, s, rc, items, n, wr_pub, wz_pub, \
+                           pub2int, partT);
+        if (wi == 0) { COILQ_TZT_LAUNCH(2) }
+        else if (wi == 1) { COILQ_TZT_LAUNCH(4) }
+        else { COILQ_TZT_LAUNCH(8) }
+#undef COILQ_TZT_LAUNCH
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
+}  // namespace coilq

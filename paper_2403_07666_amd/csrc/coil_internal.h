@@ -33,7 +33,8 @@ struct CoilDev {
     int wire_off;   // first wire
     int layer_off;  // first per-layer inductance block
     int group_off;  // first 64-element bounding-box group
-    int nchunk;     // source chunks of the field pass (partial-sum slots)
+    int nchunk;     // source chunks of the direct field pass (partial-sum slots)
+    int nslot_tz;   // source-row groups of the translation-reuse pass (partial-sum slots)
     float c2f;      // 2 r_inner/d + 1 in grid units (FP32)
     double c2d;     // same, FP64
     double kscale;  // mu0 / (2 pi d): field per ampere in grid units
@@ -82,6 +83,7 @@ struct DevState {
     const int *elem_coil;    // coil of each element
     int max_ne2;             // largest elements-per-wire over the coils
     int tile_targets;        // field pass: targets per workgroup (= block size)
+    int algo_tz;             // 1: the field partials come from the translation-reuse pass
     const double *Mlay;      // per layer ne2 x ne2, column-major
     const double *cw;        // per-wire Jc multiplier
     double *I, *Phi, *Br, *Bz, *E, *Ep, *dI, *q, *Jc;

@@ -103,7 +103,8 @@ __global__ __launch_bounds__(256) void k_field(DevState s, RunConst rc) {
 __device__ __forceinline__ void field_at(const DevState &s, const CoilDev &c, int e, double Ba,
                                          double &br, double &bz) {
     double xr = 0.0, xz = 0.0;
-    for (int k = 0; k < c.nchunk; ++k) {
+    const int nk = s.algo_tz ? c.nslot_tz : c.nchunk;
+    for (int k = 0; k < nk; ++k) {
         const double2 p = s.part[(size_t)k * s.N + e];
         xr += p.x;
         xz += p.y;

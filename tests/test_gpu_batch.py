@@ -78,7 +78,7 @@ def test_tile_shapes_agree_and_autotune_cache(tmp_path):
     inp = cs.generate(w)
     ref = None
     for tb, ch, grid in ((64, 1, 0), (128, 4, 0), (256, 16, 512), (64, 2, 64)):
-        g = pk.Coil(w, inp)
+        g = pk.Coil(w, inp, algo="direct")
         g.set_tiles(tb, ch, grid)
         g.run(60)
         cur = (g.get(pk.F_I), g.get(pk.F_BZ), g.get(pk.F_T))
@@ -88,12 +88,12 @@ def test_tile_shapes_agree_and_autotune_cache(tmp_path):
             for a, b in zip(cur, ref):
                 assert nerr(a, b) <= 1e-12
     path = os.path.join(str(tmp_path), "tune.jsonl")
-    g = pk.Coil(w, inp)
+    g = pk.Coil(w, inp, algo="direct")
     g.run(3)
     chosen = g.autotune(reps=2, cache_path=path)
     lines = open(path).read().splitlines()
     assert len(lines) == 1 and '"key": "gfx950/fp64/' in lines[0]
-    g2 = pk.Coil(w, inp)
+    g2 = pk.Coil(w, inp, algo="direct")
     assert g2.autotune(reps=2, cache_path=path) == chosen
     assert len(open(path).read().splitlines()) == 1  # served from the cache
     g2.run(60)

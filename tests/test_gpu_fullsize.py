@@ -23,8 +23,9 @@ def _say(*a):
     sys.stdout.flush()
 
 
+@pytest.mark.parametrize("algo", ["direct", "translation"])
 @pytest.mark.parametrize("name", ["c2", "c5"])
-def test_field_pass_sampled_targets(name):
+def test_field_pass_sampled_targets(name, algo):
     pk = _pk()
     w = cs.workload(name)
     I = cs.random_currents(w.n_elem, seed=31)
@@ -35,11 +36,11 @@ def test_field_pass_sampled_targets(name):
     obr, obz = o.field_targets(I, tg)
     scale = max(np.abs(obr).max(), np.abs(obz).max())
     for prec, tol in (("fp64", 1e-10), ("mixed", 1e-5)):
-        g = pk.Coil(w, precision=prec)
+        g = pk.Coil(w, precision=prec, algo=algo)
         g.set_state(pk.F_I, I)
         g.compute_field()
         e = max(np.abs(g.get(pk.F_BR)[tg] - obr).max(), np.abs(g.get(pk.F_BZ)[tg] - obz).max()) / scale
-        _say(f"{name} field {prec}: {e:.2e} ({g.sizes.n_work_items} items)")
+        _say(f"{name} {algo} field {prec}: {e:.2e}")
         assert e <= tol
         g.close()
 

@@ -40,14 +40,18 @@ def _coil(layers, turns, ne, **kw):
 SHAPES = [(1, 1, 1), (1, 1, 8), (2, 3, 3), (3, 5, 4), (4, 8, 4), (5, 7, 6), (3, 9, 8)]
 
 
+ALGOS = ["direct", "translation"]
+
+
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("shape", SHAPES)
-def test_field_pass_random_currents(prec, shape):
+def test_field_pass_random_currents(prec, shape, algo):
     """Field pass alone on seeded random currents: every target."""
     pk = _pk()
     w = _coil(*shape)
-    _say("field", prec, shape)
-    g = pk.Coil(w, precision=prec)
+    _say("field", prec, shape, algo)
+    g = pk.Coil(w, precision=prec, algo=algo)
     o = oracle.Sim(w)
     I = cs.random_currents(w.n_elem, seed=100 + sum(shape))
     g.set_state(pk.F_I, I)
@@ -62,13 +66,15 @@ def test_field_pass_random_currents(prec, shape):
     assert e <= TOL[prec]
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_field_pass_ensemble_of_coils(prec):
+def test_field_pass_ensemble_of_coils(prec, algo):
     pk = _pk()
     w = cs.Workload(name="ens", coils=[cs.Coil(2, 3, 4, ramp=1.0), cs.Coil(3, 2, 6, r_inner=0.03, ramp=2.0),
-                                        cs.Coil(1, 5, 8, z_center=0.01, ramp=0.5)],
+                                        cs.Coil(1, 5, 8, z_center=0.01, ramp=0.5),
+                                        cs.Coil(2, 70, 8, r_inner=0.021, ramp=0.7)],
                     steps=1, dt=1e-4)
-    g = pk.Coil(w, precision=prec)
+    g = pk.Coil(w, precision=prec, algo=algo)
     o = oracle.Sim(w)
     I = cs.random_currents(w.n_elem, seed=7)
     g.set_state(pk.F_I, I)
@@ -79,14 +85,15 @@ def test_field_pass_ensemble_of_coils(prec):
     assert e <= TOL[prec]
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_c1_full_run(prec):
+def test_c1_full_run(prec, algo):
     """C1 (4 layers x 8 turns x 4x4 elements), literal constants, 500 steps."""
     pk = _pk()
     w = cs.workload("c1")
     inp = cs.generate(w)
-    _say("c1 run", prec)
-    g = pk.Coil(w, inp, precision=prec)
+    _say("c1 run", prec, algo)
+    g = pk.Coil(w, inp, precision=prec, algo=algo)
     o = oracle.Sim(w, inp)
     for k in range(5):
         g.run(100)
@@ -98,14 +105,15 @@ def test_c1_full_run(prec):
         assert eb <= TOL[prec] and ei <= TOL[prec] and et <= TOL[prec]
 
 
+@pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_c1_active_run_temperature_and_joule(prec):
+def test_c1_active_run_temperature_and_joule(prec, algo):
     """Active variant: flux penetrates, E ~ Ec, T rises; T parity relative to
     the rise above the bath, Q and per-wire Q_w, peak temperature."""
     pk = _pk()
     w = cs.workload("c1_active")
     inp = cs.generate(w)
-    g = pk.Coil(w, inp, precision=prec)
+    g = pk.Coil(w, inp, precision=prec, algo=algo)
     o = oracle.Sim(w, inp)
     g.run(350)
     assert o.run(350) == 0
