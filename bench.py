@@ -82,6 +82,62 @@ def cpu_baseline(w, budget_s: float = 12.0) -> dict:
     }
 
 
+def batched_leg(pk, cs, torch, steps: int = 50, warmup: int = 3, graph: int = 10) -> dict:
+    """The 16-coil ensemble (seeded uneven sizes) in one launch per kernel,
+    mixed precision, autotuned field pass, time loop replayed as a HIP graph."""
+    w = cs.workload("c4")
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision="mixed")
+    g.run(2)
+    t0 = time.perf_counter()
+    chosen = g.autotune(reps=2)
+    tune_s = time.perf_counter() - t0
+    g.reset()
+    g.run(warmup)
+    g.graph(graph)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pairs = w.pairs_per_pass()
+    g.close()
+    out = {
+        "workload": w.name, "n_coils": len(w.coils), "n_elem": w.n_elem,
+        "coils": [f"{c.layers}x{c.turns}" for c in w.coils],
+        "steps": steps, "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
+        "ginteractions_per_s": pairs * steps / dt / 1e9, "pairs_per_step": pairs,
+        "graph_steps": graph, "autotuned": list(chosen), "autotune_s": tune_s,
+    }
+    log(f"[bench] ensemble {w.n_elem} elements: {out['steps_per_s']:.1f} steps/s, autotuned {chosen}")
+    return out
+
+
+def adjoint_leg(pk, cs, torch, steps: int, ckpt: int = 50) -> dict:
+    """Wall time of coil_adjoint (its own forward with checkpoints, recompute,
+    reverse sweep) over that of a plain forward run, 384,000 elements, mixed."""
+    w = cs.workload("c5")
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision="mixed")
+    g.run(2)
+    g.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run(steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gcw, gr, obj = g.adjoint(steps, wQ=1.0, wT=1.0, ckpt_every=ckpt)
+    torch.cuda.synchronize()
+    adj = time.perf_counter() - t0
+    g.close()
+    out = {"workload": w.name, "n_elem": w.n_elem, "steps": steps, "ckpt_every": ckpt,
+           "forward_s": fwd, "adjoint_s": adj, "adjoint_over_forward": adj / fwd,
+           "field_history_in_hbm": True, "objectives": list(obj)}
+    log(f"[bench] adjoint/forward at {w.n_elem} elements, {steps} steps: {adj:.2f} s / {fwd:.2f} s = {adj / fwd:.2f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +150,13 @@ def main():
     ap.add_argument("--graph", type=int, default=0, help="capture the step loop in HIP graphs of this many steps")
     ap.add_argument("--algo", default="auto", choices=["auto", "direct", "translation"],
                     help="field-pass evaluation (both compute the same all-pairs sum)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 16-coil ensemble leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward leg")
+    ap.add_argument("--adjoint-steps", type=int, default=200,
+                    help="horizon of the adjoint/forward timing at 384,000 elements")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="first run a plain device copy of this many MB three times (a known-size "
+                         "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
@@ -105,6 +168,16 @@ def main():
 
     import coil_synth as cs
     import paper_2403_07666_amd as pk
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: 3 x {args.copy_calibration} MB device copy")
+        del src, dst
 
     w = cs.workload(args.workload)
     inp = cs.generate(w)
@@ -176,6 +249,13 @@ def main():
     else:
         g.close()
 
+    batched = None
+    if not args.no_batched:
+        batched = batched_leg(pk, cs, torch)
+    adjoint = None
+    if not args.no_adjoint and args.adjoint_steps > 0:
+        adjoint = adjoint_leg(pk, cs, torch, args.adjoint_steps)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline")
@@ -212,6 +292,8 @@ def main():
         "mixed_vs_fp64": check,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "adjoint": adjoint,
     }
     print(json.dumps(out))
 

@@ -233,16 +233,19 @@ int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, 
                          int32_t on_device);
 
 /* ---- field-pass tiling (batched and single coils) ----
-   coil_set_tiles: tile_targets in {64, 128, 256} targets per workgroup,
-   chunks = source chunks per coil (0 = automatic, at most 16), grid_limit = 0
-   for one workgroup per work item or > 0 for a persistent grid striding over
-   the (coil, target block, source chunk) items.  Drops a captured graph.
-   coil_autotune: times every candidate (3 tile sizes x 5 chunk counts x 3 grid
-   shapes) over `reps` field passes on the handle's current currents and keeps
-   the fastest; with cache_path it first looks the configuration up in that
-   JSON-lines file (key: arch / precision / log2 pairs / coils) and appends the
-   new choice.  chosen[3] (optional) receives (tile_targets, chunks,
-   grid_limit).  Results differ between tilings only by summation order. */
+   coil_set_tiles: switch to the DIRECT evaluation with tile_targets in
+   {64, 128, 256} targets per workgroup, chunks = source chunks per coil (0 =
+   automatic, at most 16) and grid_limit = 0 for one workgroup per work item or
+   > 0 for a persistent grid striding over the (coil, target block, source
+   chunk) items.  Drops a captured graph.
+   coil_autotune: times every candidate over `reps` field passes on the
+   handle's current currents and keeps the fastest: TRANSLATION with 2, 4, 8 or
+   16 source-row groups per target row segment, and DIRECT with 3 tile sizes x
+   5 chunk counts x 3 grid shapes.  With cache_path it first looks the
+   configuration up in that JSON-lines file (key: arch / precision / log2 pairs /
+   coils) and appends a new choice.  chosen[4] (optional) receives (algo, p1,
+   p2, p3): (2, groups, 0, 0) or (1, tile_targets, chunks, grid_limit).
+   Results differ between candidates only by summation order. */
 int coil_set_tiles(coil_t *h, int32_t tile_targets, int32_t chunks, int32_t grid_limit);
 int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, int32_t *chosen);
 

@@ -348,9 +348,10 @@ class Coil:
         check(lib().coil_set_tiles(self.h, int(tile_targets), int(chunks), int(grid_limit)))
 
     def autotune(self, reps: int = 3, cache_path: Optional[str] = None):
-        """Time the tile candidates and keep the fastest; returns
-        (tile_targets, chunks, grid_limit)."""
-        ch = np.zeros(3, dtype=np.int32)
+        """Time the field-pass candidates and keep the fastest; returns
+        (algo, p1, p2, p3): (2, source-row groups, 0, 0) for the translation
+        evaluation or (1, tile_targets, chunks, grid_limit) for the direct one."""
+        ch = np.zeros(4, dtype=np.int32)
         path = cache_path.encode() if cache_path else None
         check(lib().coil_autotune(self.h, int(reps), path, ch.ctypes.data_as(_i32p)))
         return tuple(int(v) for v in ch)

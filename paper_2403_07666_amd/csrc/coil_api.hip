@@ -60,12 +60,13 @@ struct Plan {
     int nslot_tz_max = 1;
     int part_slots = 2;  // capacity of part[] in double2 slots of N
     double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
+    size_t tz_cap = 0;      // translation item capacity (16 source-row groups)
     int algo = COIL_ALGO_TRANSLATION;
     int nchunk_cap = 1;    // partial-sum capacity in chunks
     size_t total = 0;
     // regions
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
-        perm_b, wire_coil_b, elem_coil_b, Mlay_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
+        perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
         sc_b, tmp_b, misc_b, tz_b, Ipub_b, pub2int_b;
 };
@@ -160,7 +161,7 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
 
 // Translation-reuse work items: per coil a per-thread target count W in
 // {2, 4, 8} (target row segments of 64 W), rows x segments x source-row groups.
-void build_tz(Plan &p) {
+void build_tz(Plan &p, int nsplit_req) {
     std::vector<TzItem> by[3];
     const int Ws[3] = {2, 4, 8};
     const double eff[3] = {0.55, 0.8, 1.0};  // relative throughput of the W variants
@@ -180,7 +181,8 @@ void build_tz(Plan &p) {
         }
         segs += (long long)nr * ((nz + 64 * Ws[wsel[ci]] - 1) / (64 * Ws[wsel[ci]]));
     }
-    const int nsplit = (int)std::max<long long>(1, std::min<long long>(16, (4096 + segs - 1) / segs));
+    const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, 16)
+                                      : (int)std::max<long long>(1, std::min<long long>(16, (4096 + segs - 1) / segs));
     p.nslot_tz_max = 1;
     for (size_t ci = 0; ci < p.coils.size(); ++ci) {
         CoilDev &d = p.coils[ci];
@@ -267,7 +269,14 @@ int make_plan(const coil_config *c, Plan &p) {
         }
     p.items_cap = cap;
     p.nchunk_cap = pcap;
-    build_tz(p);
+    {
+        Plan q = p;
+        build_tz(q, 16);
+        p.tz_cap = q.tz_items.size();
+        p.nchunk_cap = std::max(p.nchunk_cap, q.nslot_tz_max);
+    }
+    build_tz(p, 0);
+    p.tz_cap = std::max(p.tz_cap, p.tz_items.size());
     p.algo = c->algo == COIL_ALGO_DIRECT ? COIL_ALGO_DIRECT : COIL_ALGO_TRANSLATION;
     return COIL_OK;
 }
@@ -325,6 +334,12 @@ size_t layout(Plan &p) {
     size_t mlay = 0;
     for (auto &d : p.coils) mlay += (size_t)d.layers * d.ne2 * d.ne2;
     p.Mlay_b = carve(cur, d8 * mlay);
+    p.Minv_b = carve(cur, d8 * mlay);
+    size_t ylen = 0;
+    for (auto &d : p.coils) ylen += (size_t)d.layers * d.ne2;
+    p.yl_b = carve(cur, d8 * ylen);
+    p.syl_b = carve(cur, d8 * p.nlayers);
+    p.wflag_b = carve(cur, sizeof(int) * Nw);
     p.cw_b = carve(cur, d8 * Nw);
     p.I_b = carve(cur, d8 * N);
     p.Phi_b = carve(cur, d8 * N);
@@ -343,7 +358,7 @@ size_t layout(Plan &p) {
     // transposed test hook can stage 2N doubles after N partials
     p.part_slots = std::max({p.nchunk_max, p.nchunk_cap, p.nslot_tz_max, 2});
     p.part_b = carve(cur, sizeof(double2) * N * p.part_slots);
-    p.tz_b = carve(cur, sizeof(TzItem) * std::max<size_t>(1, p.tz_items.size()));
+    p.tz_b = carve(cur, sizeof(TzItem) * std::max<size_t>(1, std::max(p.tz_items.size(), p.tz_cap)));
     p.Ipub_b = carve(cur, sizeof(double) * N);
     p.pub2int_b = carve(cur, sizeof(int) * N);
     p.Uw_b = carve(cur, d8 * Nw);
@@ -391,6 +406,7 @@ struct coil_s {
     hipGraphExec_t gexec = nullptr;
     long long gsteps = 0;
     bool capturing = false;
+    int tz_split = 0;  // source-row groups of the translation pass (0 = automatic)
 };
 
 namespace {
@@ -494,6 +510,7 @@ int reset_state(coil_t *h) {
     }
     HIPCHECK(launch_fill(reinterpret_cast<double *>(s.part), 0.0, 2 * s.N * h->plan.part_slots, st));
     HIPCHECK(launch_fill(s.Uw, 0.0, s.Nw, st));
+    HIPCHECK(launch_zero_int(s.wflag, s.Nw, st));
     HIPCHECK(launch_fill(s.Qw, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.wq, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.wmaxx, 0.0, s.Nw, st));
@@ -685,6 +702,54 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
         }
     }
 
+    // per-layer inverse, M^-1 1 and its sum (Cholesky on the host, FP64)
+    std::vector<double> Minv(Mlay.size()), yl, syl;
+    {
+        size_t base = 0;
+        for (const CoilDev &d : p.coils) {
+            const int n = d.ne2;
+            for (int L = 0; L < d.layers; ++L, base += (size_t)n * n) {
+                std::vector<double> Lf(Mlay.begin() + base, Mlay.begin() + base + (size_t)n * n);
+                // column-major lower Cholesky in place: Lf[j*n + i], i >= j
+                for (int j = 0; j < n; ++j) {
+                    double djj = Lf[(size_t)j * n + j];
+                    for (int k = 0; k < j; ++k) djj -= Lf[(size_t)k * n + j] * Lf[(size_t)k * n + j];
+                    if (!(djj > 0.0)) return fail(COIL_E_NONFINITE, "inductance block of layer %d is not positive definite", L);
+                    const double ljj = std::sqrt(djj);
+                    Lf[(size_t)j * n + j] = ljj;
+                    for (int i = j + 1; i < n; ++i) {
+                        double v = Lf[(size_t)j * n + i];
+                        for (int k = 0; k < j; ++k) v -= Lf[(size_t)k * n + i] * Lf[(size_t)k * n + j];
+                        Lf[(size_t)j * n + i] = v / ljj;
+                    }
+                }
+                std::vector<double> col(n);
+                double ssum = 0.0;
+                for (int c = 0; c < n; ++c) {
+                    for (int i = 0; i < n; ++i) col[i] = (i == c) ? 1.0 : 0.0;
+                    for (int i = 0; i < n; ++i) {
+                        double v = col[i];
+                        for (int k = 0; k < i; ++k) v -= Lf[(size_t)k * n + i] * col[k];
+                        col[i] = v / Lf[(size_t)i * n + i];
+                    }
+                    for (int i = n - 1; i >= 0; --i) {
+                        double v = col[i];
+                        for (int k = i + 1; k < n; ++k) v -= Lf[(size_t)i * n + k] * col[k];
+                        col[i] = v / Lf[(size_t)i * n + i];
+                    }
+                    for (int i = 0; i < n; ++i) Minv[base + (size_t)c * n + i] = col[i];
+                }
+                for (int i = 0; i < n; ++i) {
+                    double v = 0.0;
+                    for (int c = 0; c < n; ++c) v += Minv[base + (size_t)c * n + i];
+                    yl.push_back(v);
+                    ssum += v;
+                }
+                syl.push_back(ssum);
+            }
+        }
+    }
+
     // device pointers
     DevState &s = h->ds;
     s.N = N;
@@ -720,6 +785,10 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     s.wire_coil = at<int>(h, p.wire_coil_b);
     s.elem_coil = at<int>(h, p.elem_coil_b);
     s.Mlay = at<double>(h, p.Mlay_b);
+    s.Minv = at<double>(h, p.Minv_b);
+    s.yl = at<double>(h, p.yl_b);
+    s.syl = at<double>(h, p.syl_b);
+    s.wflag = at<int>(h, p.wflag_b);
     s.cw = at<double>(h, p.cw_b);
     s.I = at<double>(h, p.I_b);
     s.Phi = at<double>(h, p.Phi_b);
@@ -766,6 +835,9 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)s.wire_coil, wire_coil.data(), sizeof(int) * Nw));
     HIPCHECK(up((void *)s.elem_coil, elem_coil.data(), sizeof(int) * N));
     HIPCHECK(up((void *)s.Mlay, Mlay.data(), sizeof(double) * Mlay.size()));
+    HIPCHECK(up((void *)s.Minv, Minv.data(), sizeof(double) * Minv.size()));
+    HIPCHECK(up((void *)s.yl, yl.data(), sizeof(double) * yl.size()));
+    HIPCHECK(up((void *)s.syl, syl.data(), sizeof(double) * syl.size()));
     HIPCHECK(up((void *)s.cw, cw.data(), sizeof(double) * Nw));
     HIPCHECK(up((void *)h->tz.items, p.tz_items.data(), sizeof(TzItem) * p.tz_items.size()));
     HIPCHECK(up((void *)h->d_pub2int, pub2int.data(), sizeof(int) * N));
@@ -1309,6 +1381,32 @@ std::string arch_name() {
     return c == std::string::npos ? a : a.substr(0, c);
 }
 
+int apply_tz(coil_t *h, int nsplit) {
+    Plan q = h->plan;
+    build_tz(q, nsplit);
+    if (q.tz_items.size() > h->plan.tz_cap || q.nslot_tz_max > h->plan.part_slots)
+        return fail(COIL_E_INVAL, "translation split %d exceeds the planned capacity", nsplit);
+    HIPCHECK(hipMemcpyAsync((void *)h->tz.items, q.tz_items.data(), sizeof(TzItem) * q.tz_items.size(),
+                            hipMemcpyHostToDevice, h->stream));
+    for (size_t i = 0; i < q.coils.size(); ++i) h->plan.coils[i].nslot_tz = q.coils[i].nslot_tz;
+    HIPCHECK(hipMemcpyAsync((void *)h->ds.coils, h->plan.coils.data(), sizeof(CoilDev) * h->plan.coils.size(),
+                            hipMemcpyHostToDevice, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    const size_t cap = h->plan.tz_cap;
+    h->plan.tz_items = q.tz_items;
+    h->plan.tz_cap = cap;
+    h->plan.nslot_tz_max = q.nslot_tz_max;
+    h->plan.tz_evals = q.tz_evals;
+    for (int k = 0; k < 3; ++k) {
+        h->plan.tz_first[k] = q.tz_first[k];
+        h->plan.tz_count[k] = q.tz_count[k];
+        h->tz.first[k] = q.tz_first[k];
+        h->tz.count[k] = q.tz_count[k];
+    }
+    h->tz_split = nsplit;
+    return COIL_OK;
+}
+
 std::string tune_key(const coil_t *h) {
     long double pairs = 0;
     for (const CoilDev &d : h->plan.coils) pairs += (long double)d.n * (d.n - 1);
@@ -1355,6 +1453,8 @@ extern "C" int coil_set_tiles(coil_t *h, int32_t tile_targets, int32_t chunks, i
     if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
     int rc = coil_graph(h, 0);
     if (rc) return rc;
+    h->ds.algo_tz = 0;
+    h->plan.algo = COIL_ALGO_DIRECT;
     return apply_tiles(h, tile_targets, chunks, grid_limit);
 }
 
@@ -1365,27 +1465,35 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     int rc = coil_graph(h, 0);
     if (rc) return rc;
     const std::string key = tune_key(h);
-    // cached choice?
+    // choice: algo (1 direct, 2 translation), then (tile_targets, chunks, grid) or (split)
+    auto apply = [&](int algo, int a, int b, int c) -> int {
+        if (algo == COIL_ALGO_TRANSLATION) {
+            h->ds.algo_tz = 1;
+            h->plan.algo = COIL_ALGO_TRANSLATION;
+            return apply_tz(h, a);
+        }
+        h->ds.algo_tz = 0;
+        h->plan.algo = COIL_ALGO_DIRECT;
+        return apply_tiles(h, a, b, c);
+    };
     if (cache_path) {
         FILE *f = fopen(cache_path, "r");
         if (f) {
             char line[512];
-            int best_tb = 0, best_ch = 0, best_g = 0;
+            int ba = 0, b1 = 0, b2 = 0, b3 = 0;
             while (fgets(line, sizeof(line), f)) {
                 char k[200];
-                int tb, ch, g;
+                int al, x1, x2, x3;
                 double ms;
-                if (sscanf(line, "{\"key\": \"%199[^\"]\", \"tile_targets\": %d, \"chunks\": %d, \"grid_limit\": %d, \"ms\": %lf}",
-                           k, &tb, &ch, &g, &ms) == 5 && key == k) {
-                    best_tb = tb;
-                    best_ch = ch;
-                    best_g = g;
+                if (sscanf(line, "{\"key\": \"%199[^\"]\", \"algo\": %d, \"p1\": %d, \"p2\": %d, \"p3\": %d, \"ms\": %lf}",
+                           k, &al, &x1, &x2, &x3, &ms) == 6 && key == k) {
+                    ba = al; b1 = x1; b2 = x2; b3 = x3;
                 }
             }
             fclose(f);
-            if (best_tb) {
-                if ((rc = apply_tiles(h, best_tb, best_ch, best_g))) return rc;
-                if (chosen) { chosen[0] = best_tb; chosen[1] = best_ch; chosen[2] = best_g; }
+            if (ba) {
+                if ((rc = apply(ba, b1, b2, b3))) return rc;
+                if (chosen) { chosen[0] = ba; chosen[1] = b1; chosen[2] = b2; chosen[3] = b3; }
                 return COIL_OK;
             }
         }
@@ -1394,39 +1502,41 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         cus = prop.multiProcessorCount;
-    hipEvent_t a, b;
-    HIPCHECK(hipEventCreate(&a));
-    HIPCHECK(hipEventCreate(&b));
+    hipEvent_t ea, eb;
+    HIPCHECK(hipEventCreate(&ea));
+    HIPCHECK(hipEventCreate(&eb));
     double best = INFINITY;
-    int btb = h->ds.tile_targets, bch = 0, bg = h->grid_limit;
+    int ba = h->plan.algo, b1 = 0, b2 = 0, b3 = 0;
+    struct Cand { int algo, a, b, c; };
+    std::vector<Cand> cands;
+    for (int sp : {2, 4, 8, 16}) cands.push_back({COIL_ALGO_TRANSLATION, sp, 0, 0});
     for (int tb : {64, 128, 256})
         for (int ch : {1, 2, 4, 8, kMaxChunks})
-            for (int g : {0, 2 * cus, 4 * cus}) {
-                if ((rc = apply_tiles(h, tb, ch, g))) continue;  // over capacity: skip
-                HIPCHECK(launch_field(h->ds, h->rc, h->grid_limit, h->stream));
-                HIPCHECK(hipEventRecord(a, h->stream));
-                for (int r = 0; r < reps; ++r) HIPCHECK(launch_field(h->ds, h->rc, h->grid_limit, h->stream));
-                HIPCHECK(hipEventRecord(b, h->stream));
-                HIPCHECK(hipEventSynchronize(b));
-                float ms = 0.f;
-                HIPCHECK(hipEventElapsedTime(&ms, a, b));
-                if (ms / reps < best) {
-                    best = ms / reps;
-                    btb = tb;
-                    bch = ch;
-                    bg = g;
-                }
-            }
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
+            for (int g : {0, 2 * cus, 4 * cus}) cands.push_back({COIL_ALGO_DIRECT, tb, ch, g});
+    for (const Cand &cd : cands) {
+        if (apply(cd.algo, cd.a, cd.b, cd.c)) continue;  // over capacity: skip
+        HIPCHECK(launch_field_any(h, h->ds, h->stream));
+        HIPCHECK(hipEventRecord(ea, h->stream));
+        for (int r = 0; r < reps; ++r) HIPCHECK(launch_field_any(h, h->ds, h->stream));
+        HIPCHECK(hipEventRecord(eb, h->stream));
+        HIPCHECK(hipEventSynchronize(eb));
+        float ms = 0.f;
+        HIPCHECK(hipEventElapsedTime(&ms, ea, eb));
+        if (ms / reps < best) {
+            best = ms / reps;
+            ba = cd.algo; b1 = cd.a; b2 = cd.b; b3 = cd.c;
+        }
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
     g_err.clear();
-    if ((rc = apply_tiles(h, btb, bch, bg))) return rc;
-    if (chosen) { chosen[0] = btb; chosen[1] = bch; chosen[2] = bg; }
+    if ((rc = apply(ba, b1, b2, b3))) return rc;
+    if (chosen) { chosen[0] = ba; chosen[1] = b1; chosen[2] = b2; chosen[3] = b3; }
     if (cache_path) {
         FILE *f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "{\"key\": \"%s\", \"tile_targets\": %d, \"chunks\": %d, \"grid_limit\": %d, \"ms\": %.6f}\n",
-                    key.c_str(), btb, bch, bg, best);
+            fprintf(f, "{\"key\": \"%s\", \"algo\": %d, \"p1\": %d, \"p2\": %d, \"p3\": %d, \"ms\": %.6f}\n",
+                    key.c_str(), ba, b1, b2, b3, best);
             fclose(f);
         }
     }

@@ -114,16 +114,15 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
                 __syncthreads();
                 // sliding window: at step t, lane needs tau = W*lane + S - 1 - t + cc + W
                 double2 ring[W];
+                // tau = W*lane + c with c >= 0 constant: tau / W = lane + c / W
 #pragma unroll
-                for (int cc = 0; cc < W; ++cc) {
-                    const int tau = W * lane + S - 1 + cc + W;  // residue (W - 1 + cc) mod W
-                    ring[(W - 1 + cc) % W] = gt[((W - 1 + cc) % W) * Q + tau / W];
-                }
-                for (int t0 = 0; t0 < S; t0 += W) {
+                for (int cc = 0; cc < W; ++cc)  // residue (W - 1 + cc) mod W
+                    ring[(W - 1 + cc) % W] = gt[((W - 1 + cc) % W) * Q + lane + (S - 1 + cc + W) / W];
+                for (int tb = 0; tb < S / W; ++tb) {
+                    const int base = lane - tb;
 #pragma unroll
                     for (int u = 0; u < W; ++u) {
-                        const int t = t0 + u;
-                        const double I = Is[t];
+                        const double I = Is[tb * W + u];
                         // tau_lo = W*lane + S - 1 - t + W  ==  (W - 1 - u) mod W
 #pragma unroll
                         for (int cc = 0; cc < W; ++cc) {
@@ -132,8 +131,8 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
                             az[cc] = fma(g.y, I, az[cc]);
                         }
                         // next value entering the window: tau_lo - 1
-                        const int taun = W * lane + S - 2 - t + W;
-                        ring[(2 * W - 2 - u) % W] = gt[((2 * W - 2 - u) % W) * Q + taun / W];
+                        //   = W (lane - tb) + (S - 2 + W - u), so tau / W = base + (S - 2 + W - u) / W
+                        ring[(2 * W - 2 - u) % W] = gt[((2 * W - 2 - u) % W) * Q + base + (S - 2 + W - u) / W];
                     }
                 }
             }
@@ -198,23 +197,22 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
                                    : make_double2(0.0, 0.0);
                 __syncthreads();
                 double2 ring[W];
+                // tau = -W*lane + c with c >= 0 constant: tau / W = -lane + c / W
 #pragma unroll
-                for (int cc = 0; cc < W; ++cc) {
-                    const int tau = -W * lane - cc + TZ - 1 + W;  // residue (W - 1 - cc) mod W
-                    ring[(W - 1 - cc) % W] = gt[((W - 1 - cc) % W) * Q + tau / W];
-                }
-                for (int t0 = 0; t0 < S; t0 += W) {
+                for (int cc = 0; cc < W; ++cc)  // residue (W - 1 - cc) mod W
+                    ring[(W - 1 - cc) % W] = gt[((W - 1 - cc) % W) * Q - lane + (TZ - 1 + W - cc) / W];
+                for (int tb = 0; tb < S / W; ++tb) {
+                    const int base = tb - lane;
 #pragma unroll
                     for (int u = 0; u < W; ++u) {
-                        const int t = t0 + u;
-                        const double2 wv = ws[t];
+                        const double2 wv = ws[tb * W + u];
 #pragma unroll
                         for (int cc = 0; cc < W; ++cc) {
                             const double2 g = ring[(u + W - 1 - cc) % W];
                             acc[cc] = fma(g.x, wv.x, fma(g.y, wv.y, acc[cc]));
                         }
-                        const int taun = t + 1 - W * lane + TZ - 1 + W;  // residue u mod W
-                        ring[u % W] = gt[(u % W) * Q + taun / W];
+                        // next: tau = W (tb - lane) + (u + TZ + W), residue u mod W
+                        ring[u % W] = gt[(u % W) * Q + base + (u + TZ + W) / W];
                     }
                 }
             }

@@ -85,6 +85,10 @@ struct DevState {
     int tile_targets;        // field pass: targets per workgroup (= block size)
     int algo_tz;             // 1: the field partials come from the translation-reuse pass
     const double *Mlay;      // per layer ne2 x ne2, column-major
+    const double *Minv;      // per layer inverse of Mlay, column-major
+    const double *yl;        // per layer Minv * 1
+    const double *syl;       // per layer sum of yl
+    int *wflag;              // per wire: 1 = needs the factorising wire kernel
     const double *cw;        // per-wire Jc multiplier
     double *I, *Phi, *Br, *Bz, *E, *Ep, *dI, *q, *Jc;
     double *u[3], *T[3];     // [0] canonical state, [1], [2] heat scratch
@@ -112,6 +116,7 @@ hipError_t launch_gather(const double *src, const int *perm, int n, double *dst,
 hipError_t launch_scatter(const double *src, const int *perm, int n, double *dst, hipStream_t st);
 hipError_t launch_u_of_T(const DevState &s, const RunConst &rc, hipStream_t st);
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
+hipError_t launch_zero_int(int *p, int n, hipStream_t st);
 hipError_t launch_reset_scalars(Scalars *sc, double T_bath, hipStream_t st);
 hipError_t launch_stored(const DevState &s, double *out, hipStream_t st);
 void heat_buffers(int nsub, int sub, int *src, int *dst);

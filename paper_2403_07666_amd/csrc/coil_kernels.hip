@@ -125,16 +125,22 @@ __global__ __launch_bounds__(256) void k_field_finalize(DevState s, RunConst rc,
 }
 
 // ------------------------------------------------------------------ local law + per-wire A-V solve
-// One wavefront per wire, one element per lane (n_e <= 64).  The wire's
-// matrix A = M_ww + dt diag(2 pi r E'/d^2) lives in LDS, column-major with
-// leading dimension n_e + 1; right-looking Cholesky, then two triangular
-// solves for the right-hand sides b and 1 with the solutions in registers.
+// One wavefront per wire, one element per lane (n_e <= 64).  The wire matrix is
+// A = M_ww + dt diag(2 pi r E'/d^2).  Two kernels per step:
+//   k_wire<1> (no LDS): when every diagonal addition leaves M_ee unchanged in
+//     FP64, A equals the layer's inductance block bitwise and the solution uses
+//     the layer's precomputed inverse (x = M^-1 b, y = M^-1 1); otherwise the
+//     wire is flagged and left untouched;
+//   k_wire<0>: flagged wires only; A in LDS (column-major, leading dimension
+//     n_e + 1), right-looking Cholesky and two triangular solves.
 // Optional recording (adjoint recompute): I^k, B^k and dI of the step; optional
 // field source (adjoint recompute from a stored field history).
+template <int FAST>
 __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     extern __shared__ double sm[];
     const int w = blockIdx.x;
     const int lane = threadIdx.x;
+    if (!FAST && s.wflag[w] == 0) return;
     const CoilDev c = s.coils[s.wire_coil[w]];
     const int lw = w - c.wire_off;
     const int layer = lw / c.turns;
@@ -159,14 +165,35 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     unsigned bad = act ? local_law(rc, s.cw[w], s.jcs[e], I0 / d2, s.T[0][e], br, bz, lo) : 0u;
     if (!act) { lo.E = lo.Ep = lo.x = lo.Jc = 0.0; }
     const double re = s.r[e];
-    const double *M = s.Mlay + (size_t)(c.layer_off + layer) * n * n;
-    load_wire_matrix(sm, M, n, ld, lane, act, dt * 2.0 * kPi * re * lo.Ep / d2);
+    const size_t lay = (size_t)(c.layer_off + layer);
+    const double *M = s.Mlay + lay * n * n;
+    const double diag_add = dt * 2.0 * kPi * re * lo.Ep / d2;
     const double b = act ? (-c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * lo.E) : 0.0;
-    bad |= chol_lds(sm, n, ld, lane, act);
-    double xv = b, yv = act ? 1.0 : 0.0;
-    solve2_lds(sm, n, ld, lane, act, xv, yv);
+    double xv, yv, sy;
+    if (FAST) {
+        const double mee = act ? M[(size_t)lane * n + lane] : 1.0;
+        const int same = act ? (mee + diag_add == mee) : 1;
+        if (!__all(same)) {
+            if (lane == 0) s.wflag[w] = 1;
+            return;
+        }
+        const double *Mi = s.Minv + lay * n * n;
+        xv = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double bj = __shfl(b, j);
+            if (act) xv = fma(Mi[(size_t)j * n + lane], bj, xv);
+        }
+        yv = act ? s.yl[lay * n + lane] : 0.0;
+        sy = s.syl[lay];
+    } else {
+        load_wire_matrix(sm, M, n, ld, lane, act, diag_add);
+        bad |= chol_lds(sm, n, ld, lane, act);
+        xv = b;
+        yv = act ? 1.0 : 0.0;
+        solve2_lds(sm, n, ld, lane, act, xv, yv);
+        sy = wave_sum(act ? yv : 0.0);
+    }
     const double sx = wave_sum(act ? xv : 0.0);
-    const double sy = wave_sum(act ? yv : 0.0);
     const double U = (sx - c.dIt) / (dt * sy);
     const double dI = act ? xv - dt * U * yv : 0.0;
     // flux update Phi += M_ww dI + dI_t Psi_u + pi r^2 dB_a
@@ -205,6 +232,7 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
         s.wq[w] = qw;
         s.Qw[w] += qw;
         s.wmaxx[w] = mx;
+        if (!FAST) s.wflag[w] = 0;
         if (bad) atomicOr(&s.sc->status, bad);
     }
 }
@@ -369,6 +397,10 @@ __global__ void k_scatter(const double *src, const int *perm, int n, double *dst
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) dst[i] = src[perm[i]];  // public perm[i] -> internal i
 }
+__global__ void k_zero_int(int *p, int n) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
 __global__ void k_fill(double *p, double v, int n) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = v;
@@ -435,8 +467,9 @@ hipError_t launch_field_finalize(const DevState &s, const RunConst &rc, hipStrea
 }
 
 hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st) {
+    hipLaunchKernelGGL(k_wire<1>, dim3(s.Nw), dim3(64), 0, st, s, rc);
     const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
-    hipLaunchKernelGGL(k_wire, dim3(s.Nw), dim3(64), lds, st, s, rc);
+    hipLaunchKernelGGL(k_wire<0>, dim3(s.Nw), dim3(64), lds, st, s, rc);
     return hipGetLastError();
 }
 
@@ -494,6 +527,12 @@ hipError_t launch_u_of_T(const DevState &s, const RunConst &rc, hipStream_t st) 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_int(int *p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_int, dim3(blocks_for(n)), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 
