@@ -41,6 +41,25 @@ PEAK_HBM_GBS = 8000.0
 FLOP_PER_EVAL = 61
 FLOP_PER_PAIR_ACC = 4
 
+# HBM bytes per launch of the field pass from the two rocprofv3 PMC runs
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a 256 MiB copy; see
+# profiles/), valid only for the kernel source the counters were taken on.
+MEASURED_TRAFFIC = {
+    # (kernel source file, workload, precision): (sha1 of the source, bytes per launch)
+}
+
+
+def _traffic(workload: str, precision: str, algo: str):
+    import hashlib
+    src = "coil_field_tz.hip" if algo == "translation" else "coil_kernels.hip"
+    rec = MEASURED_TRAFFIC.get((src, workload, precision))
+    if rec is None:
+        return None
+    path = os.path.join(ROOT, "paper_2403_07666_amd", "csrc", src)
+    with open(path, "rb") as f:
+        sha = hashlib.sha1(f.read()).hexdigest()
+    return rec[1] if sha == rec[0] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -222,7 +241,8 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "frac_unpacked_fp32_peak": achieved / PEAK_FP32_UNPACKED,
-            "traffic": None,
+            "traffic": _traffic(w.name, args.precision, fs["algo"]),
+            "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
             "avg_launch_ms": avg_ms,
             "flop_per_launch": flop,
             "pairs_per_launch": fs["pairs"],
