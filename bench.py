@@ -46,6 +46,7 @@ FLOP_PER_PAIR_ACC = 4
 # profiles/), valid only for the kernel source the counters were taken on.
 MEASURED_TRAFFIC = {
     # (kernel source file, workload, precision): (sha1 of the source, bytes per launch)
+    ("coil_field_tz.hip", "c2_medium_131k", "mixed"): ("6bd20e3de9aa023ed496e7aab55f94cf6c43b924", 39418253),
 }
 
 
