@@ -158,6 +158,81 @@ def adjoint_leg(pk, cs, torch, steps: int, ckpt: int = 50) -> dict:
     return out
 
 
+def c5_full(pk, cs, torch, precision: str, fd_steps: int) -> dict:
+    """Full-size adjoint configuration: 60 layers x 100 turns x 8x8 elements,
+    2000 steps, checkpoints every 50; gradients of Q with respect to the 6000
+    per-wire Jc multipliers and the ramp rate."""
+    import numpy as np
+    w = cs.workload("c5")
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision=precision)
+    g.run(2)
+    g.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run(w.steps)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    log(f"[c5] forward {w.steps} steps: {fwd:.1f} s")
+    t0 = time.perf_counter()
+    gcw, gr, obj = g.adjoint(w.steps, wQ=1.0, wT=1.0, ckpt_every=50)
+    torch.cuda.synchronize()
+    adj = time.perf_counter() - t0
+    log(f"[c5] adjoint {w.steps} steps: {adj:.1f} s -> {adj / fwd:.2f}")
+    out = {
+        "metric": "adjoint/forward wall time, 384k elements, 2000 steps, checkpoints every 50",
+        "value": adj / fwd, "unit": "ratio", "higher_is_better": False, "precision": precision,
+        "forward_s": fwd, "adjoint_s": adj, "objectives": list(obj),
+    }
+    g.close()
+    # central differences in FP64 on the seeded wires over a bounded horizon, on the
+    # literal configuration (whose Joule heat is tiny and vanishes on quiet wires)
+    # and on its driven variant
+    out["fd"] = [_fd_check(pk, cs, name, fd_steps) for name in ("c5", "c5_active")]
+    return out
+
+
+def _fd_check(pk, cs, name: str, fd_steps: int) -> dict:
+    import numpy as np
+    w = cs.workload(name)
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision="fp64")
+    wires = cs.fd_wires(w.n_wire, 20, 55)
+    gq, gqr, obj = g.adjoint(fd_steps, wQ=1.0, wT=0.0, ckpt_every=50)
+    h = 1e-4
+    per_wire = []
+    for wi in wires:
+        vals = []
+        for sgn in (+1, -1):
+            cw = inp["c_wire"].copy()
+            cw[wi] += sgn * h
+            g.set_params(cw, None)
+            vals.append(g.objectives(fd_steps)[0])
+        per_wire.append((int(wi), float(gq[wi]), (vals[0] - vals[1]) / (2 * h)))
+        log(f"[{name}] FD wire {wi}: adjoint {gq[wi]:.6e} fd {per_wire[-1][2]:.6e}")
+    g.set_params(inp["c_wire"], None)
+    rvals = []
+    for sgn in (+1, -1):
+        g.set_params(None, np.array([w.coils[0].ramp + sgn * h]))
+        rvals.append(g.objectives(fd_steps)[0])
+    g.close()
+    fdr = (rvals[0] - rvals[1]) / (2 * h)
+    # relative error where the difference quotient carries a signal; wires whose
+    # Joule heat underflows give fd == 0 and are counted, and their adjoint is
+    # reported beside it
+    live = [(a, f) for _, a, f in per_wire if abs(f) > 0.0]
+    rel = [abs(a - f) / abs(f) for a, f in live]
+    res = {"workload": name, "steps": fd_steps, "h": h, "Q": float(obj[0]),
+           "wires": per_wire, "n_zero_signal": len(per_wire) - len(live),
+           "max_abs_adjoint_zero_signal": max([abs(a) for _, a, f in per_wire if f == 0.0], default=0.0),
+           "max_rel_err_dQ_dcw": max(rel) if rel else None,
+           "dQ_dramp": [float(gqr[0]), fdr],
+           "rel_err_dQ_dramp": abs(gqr[0] - fdr) / abs(fdr) if fdr != 0 else None}
+    log(f"[{name}] FD over {fd_steps} steps (Q {obj[0]:.3e}): {len(live)} live wires, max rel err "
+        f"dQ/dc_w {res['max_rel_err_dQ_dcw']}, dQ/dramp {res['rel_err_dQ_dramp']}")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -174,6 +249,11 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward leg")
     ap.add_argument("--adjoint-steps", type=int, default=200,
                     help="horizon of the adjoint/forward timing at 384,000 elements")
+    ap.add_argument("--c5-full", action="store_true",
+                    help="instead of the default legs: time forward vs adjoint on the full 384,000-element, "
+                         "2000-step configuration (checkpoints every 50) and check dQ/dc_w against central "
+                         "differences (h = 1e-4) on the 20 seeded wires over --fd-steps steps")
+    ap.add_argument("--fd-steps", type=int, default=100)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="first run a plain device copy of this many MB three times (a known-size "
                          "reference for hardware byte counters)")
@@ -198,6 +278,10 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: 3 x {args.copy_calibration} MB device copy")
         del src, dst
+
+    if args.c5_full:
+        print(json.dumps(c5_full(pk, cs, torch, args.precision, args.fd_steps)))
+        return
 
     w = cs.workload(args.workload)
     inp = cs.generate(w)

@@ -183,6 +183,19 @@ int coil_scalars(coil_t *h, double *dst, int32_t n);
 /* Back to the t = 0 state (keeps the precompute). */
 int coil_reset(coil_t *h);
 
+/* Field at npts arbitrary points (host arrays, metres; r >= 0) from the current
+   element currents of every coil, FP64 direct sum; B_r = 0 on the axis.  The
+   background field is not included.  Synchronises. */
+int coil_field_at(coil_t *h, int64_t npts, const double *r, const double *z, double *Br, double *Bz);
+
+/* Host snapshot of the state (I, u, T, Phi, Q_w, step, Q, T_peak and its
+   argmax, heat outflow, status) for checkpoint and resume.  coil_save with
+   host_buf = NULL only reports the size in *needed.  coil_load restores a
+   snapshot taken from a handle of the same configuration; stepping on from it
+   reproduces the uninterrupted run bitwise.  Both synchronise. */
+int coil_save(coil_t *h, void *host_buf, size_t bytes, size_t *needed);
+int coil_load(coil_t *h, const void *host_buf, size_t bytes);
+
 /* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
    recording (clears totals), 0 stops.  coil_timing_read synchronises and
    returns per-phase totals: ms[p] and launches[p] for p = 0 field pass,

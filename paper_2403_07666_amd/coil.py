@@ -67,7 +67,7 @@ EXPORTS = [
     "coil_set_state", "coil_scalars", "coil_reset", "coil_timing", "coil_timing_read",
     "coil_graph", "coil_destroy", "coil_last_error", "coil_host_ellip", "coil_set_params",
     "coil_adjoint_query", "coil_adjoint", "coil_field_transpose", "coil_set_tiles", "coil_autotune",
-    "coil_field_stats",
+    "coil_field_stats", "coil_field_at", "coil_save", "coil_load",
 ]
 
 _lib = None
@@ -105,6 +105,9 @@ def lib():
         L.coil_set_tiles.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
         L.coil_autotune.argtypes = [vp, C.c_int32, C.c_char_p, _i32p]
         L.coil_field_stats.argtypes = [vp, _dp, C.c_int32]
+        L.coil_field_at.argtypes = [vp, C.c_int64, _dp, _dp, _dp, _dp]
+        L.coil_save.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.coil_load.argtypes = [vp, vp, C.c_size_t]
         _lib = L
     return _lib
 
@@ -362,3 +365,25 @@ class Coil:
         check(lib().coil_field_stats(self.h, v.ctypes.data_as(_dp), 5))
         return {"pairs": v[0], "kernel_evals": v[1], "algo": "translation" if v[2] == 2 else "direct",
                 "items": int(v[3]), "tile_targets": int(v[4])}
+
+    # -------------------------------------------------------------- probes and snapshots
+    def field_at(self, r, z):
+        """B_r, B_z (T) at points (r, z) in metres from the current currents."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        z = np.ascontiguousarray(z, dtype=np.float64)
+        br = np.empty(r.size)
+        bz = np.empty(r.size)
+        check(lib().coil_field_at(self.h, r.size, r.ctypes.data_as(_dp), z.ctypes.data_as(_dp),
+                                  br.ctypes.data_as(_dp), bz.ctypes.data_as(_dp)))
+        return br, bz
+
+    def save(self) -> bytes:
+        need = C.c_size_t()
+        check(lib().coil_save(self.h, None, 0, C.byref(need)))
+        buf = (C.c_char * need.value)()
+        check(lib().coil_save(self.h, C.cast(buf, C.c_void_p), need.value, None))
+        return bytes(buf)
+
+    def load(self, snap: bytes) -> None:
+        buf = (C.c_char * len(snap)).from_buffer_copy(snap)
+        check(lib().coil_load(self.h, C.cast(buf, C.c_void_p), len(snap)))

@@ -68,7 +68,7 @@ struct Plan {
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
         perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
-        sc_b, tmp_b, misc_b, tz_b, Ipub_b, pub2int_b;
+        sc_b, tmp_b, misc_b, tz_b, Ipub_b, pub2int_b, zphys_b;
 };
 
 Buf carve(size_t &cur, size_t bytes) {
@@ -361,6 +361,7 @@ size_t layout(Plan &p) {
     p.tz_b = carve(cur, sizeof(TzItem) * std::max<size_t>(1, std::max(p.tz_items.size(), p.tz_cap)));
     p.Ipub_b = carve(cur, sizeof(double) * N);
     p.pub2int_b = carve(cur, sizeof(int) * N);
+    p.zphys_b = carve(cur, sizeof(double) * N);
     p.Uw_b = carve(cur, d8 * Nw);
     p.Qw_b = carve(cur, d8 * Nw);
     p.wq_b = carve(cur, d8 * Nw);
@@ -584,6 +585,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
 
     // host precompute, internal (wire-major) order
     std::vector<float2> gpos(N);
+    std::vector<double> zphys(N);
     std::vector<double> rho(N), rr(N), V(N), invV(N), jcs(N), G(4 * (size_t)N), Gb(N);
     std::vector<int> nb(4 * (size_t)N), perm(N), wire_coil(Nw), elem_coil(N);
     std::vector<int4> bbox(std::max(1, p.ngroups));
@@ -615,6 +617,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
                         invV[e] = 1.0 / V[e];
                         h->r_pub[pub] = rr[e];
                         h->z_pub[pub] = zbot + (iz + 0.5) * d.d;
+                        zphys[e] = h->z_pub[pub];
                     }
             }
     }
@@ -841,6 +844,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)s.cw, cw.data(), sizeof(double) * Nw));
     HIPCHECK(up((void *)h->tz.items, p.tz_items.data(), sizeof(TzItem) * p.tz_items.size()));
     HIPCHECK(up((void *)h->d_pub2int, pub2int.data(), sizeof(int) * N));
+    HIPCHECK(up((void *)at<double>(h, p.zphys_b), zphys.data(), sizeof(double) * N));
     // transport-flux pattern: FP64 all-pairs pass on the device
     HIPCHECK(launch_psi(s, const_cast<double *>(s.psi), st));
     if ((rc = reset_state(h))) return rc;
@@ -1552,5 +1556,115 @@ extern "C" int coil_field_stats(coil_t *h, double *out, int32_t n) {
                          tz ? (double)h->plan.tz_items.size() : (double)h->plan.items.size(),
                          (double)h->ds.tile_targets};
     for (int i = 0; i < n && i < 5; ++i) out[i] = v[i];
+    return COIL_OK;
+}
+
+// ------------------------------------------------------------------ probes
+extern "C" int coil_field_at(coil_t *h, int64_t npts, const double *r, const double *z, double *Br, double *Bz) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (npts < 0) return fail(COIL_E_INVAL, "npts < 0");
+    if (npts == 0) return COIL_OK;
+    if (!r || !z || !Br || !Bz) return fail(COIL_E_INVAL, "NULL argument");
+    for (int64_t i = 0; i < npts; ++i)
+        if (!std::isfinite(r[i]) || !std::isfinite(z[i]) || r[i] < 0.0)
+            return fail(COIL_E_INVAL, "probe %lld: r must be finite and >= 0, z finite", (long long)i);
+    const DevState &s = h->ds;
+    hipStream_t st = h->stream;
+    // staging: the partial buffer holds >= 4 N doubles; probes go in chunks of N
+    double *buf = reinterpret_cast<double *>(s.part);
+    const int64_t chunk = std::max<int64_t>(1, s.N);
+    for (int64_t p0 = 0; p0 < npts; p0 += chunk) {
+        const int np = (int)std::min<int64_t>(chunk, npts - p0);
+        double *dr = buf, *dz = buf + chunk, *ob = buf + 2 * chunk, *oz = buf + 3 * chunk;
+        HIPCHECK(hipMemcpyAsync(dr, r + p0, sizeof(double) * np, hipMemcpyHostToDevice, st));
+        HIPCHECK(hipMemcpyAsync(dz, z + p0, sizeof(double) * np, hipMemcpyHostToDevice, st));
+        HIPCHECK(launch_probe(s, at<double>(h, h->plan.zphys_b), np, dr, dz, ob, oz, st));
+        HIPCHECK(hipMemcpyAsync(Br + p0, ob, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipMemcpyAsync(Bz + p0, oz, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+        HIPCHECK(hipStreamSynchronize(st));
+    }
+    return COIL_OK;
+}
+
+// ------------------------------------------------------------------ snapshots
+namespace {
+struct SnapHeader {
+    char magic[8];
+    int64_t N, Nw, step;
+    double Q, Tpeak, Qout;
+    int64_t Tpeak_pub, Tpeak_step;
+    uint32_t status, nsub;
+};
+size_t snap_bytes(const coil_t *h) {
+    return sizeof(SnapHeader) + sizeof(double) * (4 * (size_t)h->ds.N + (size_t)h->ds.Nw);
+}
+}  // namespace
+
+extern "C" int coil_save(coil_t *h, void *host_buf, size_t bytes, size_t *needed) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    const size_t need = snap_bytes(h);
+    if (needed) *needed = need;
+    if (!host_buf) return COIL_OK;
+    if (bytes < need) return fail(COIL_E_INVAL, "snapshot buffer of %zu bytes < %zu", bytes, need);
+    Scalars sc;
+    int rc = read_scalars(h, &sc);
+    if (rc) return rc;
+    SnapHeader hd{};
+    std::memcpy(hd.magic, "COILSNP1", 8);
+    hd.N = h->ds.N;
+    hd.Nw = h->ds.Nw;
+    hd.step = sc.step;
+    hd.Q = sc.Q;
+    hd.Tpeak = sc.Tpeak;
+    hd.Qout = sc.Qout;
+    hd.Tpeak_pub = sc.Tpeak_pub;
+    hd.Tpeak_step = sc.Tpeak_step;
+    hd.status = sc.status;
+    hd.nsub = (uint32_t)h->ds.nsub;
+    char *b = static_cast<char *>(host_buf);
+    std::memcpy(b, &hd, sizeof(hd));
+    double *d = reinterpret_cast<double *>(b + sizeof(hd));
+    const size_t N = h->ds.N;
+    hipStream_t st = h->stream;
+    // internal order: a snapshot restores into a handle of the same configuration
+    HIPCHECK(hipMemcpyAsync(d, h->ds.I, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(d + N, h->ds.u[0], sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(d + 2 * N, h->ds.T[0], sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(d + 3 * N, h->ds.Phi, sizeof(double) * N, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(d + 4 * N, h->ds.Qw, sizeof(double) * h->ds.Nw, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    return COIL_OK;
+}
+
+extern "C" int coil_load(coil_t *h, const void *host_buf, size_t bytes) {
+    if (!h || !host_buf) return fail(COIL_E_INVAL, "NULL argument");
+    if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
+    if (bytes < sizeof(SnapHeader)) return fail(COIL_E_INVAL, "snapshot too small");
+    SnapHeader hd;
+    std::memcpy(&hd, host_buf, sizeof(hd));
+    if (std::memcmp(hd.magic, "COILSNP1", 8) != 0) return fail(COIL_E_INVAL, "not a coil snapshot");
+    if (hd.N != h->ds.N || hd.Nw != h->ds.Nw || (int)hd.nsub != h->ds.nsub)
+        return fail(COIL_E_INVAL, "snapshot of a different configuration");
+    if (bytes < snap_bytes(h)) return fail(COIL_E_INVAL, "snapshot truncated");
+    int rc = reset_state(h);  // clears scratch buffers and partial sums
+    if (rc) return rc;
+    const double *d = reinterpret_cast<const double *>(static_cast<const char *>(host_buf) + sizeof(hd));
+    const size_t N = h->ds.N;
+    hipStream_t st = h->stream;
+    HIPCHECK(hipMemcpyAsync(h->ds.I, d, sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(h->ds.u[0], d + N, sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(h->ds.T[0], d + 2 * N, sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(h->ds.Phi, d + 3 * N, sizeof(double) * N, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(h->ds.Qw, d + 4 * N, sizeof(double) * h->ds.Nw, hipMemcpyHostToDevice, st));
+    Scalars sc{};
+    sc.Q = hd.Q;
+    sc.Tpeak = hd.Tpeak;
+    sc.Qout = hd.Qout;
+    sc.step = hd.step;
+    sc.Tpeak_pub = hd.Tpeak_pub;
+    sc.Tpeak_step = hd.Tpeak_step;
+    sc.status = hd.status;
+    HIPCHECK(hipMemcpyAsync(h->ds.sc, &sc, sizeof(sc), hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
     return COIL_OK;
 }

@@ -72,6 +72,31 @@ __device__ __forceinline__ double2 kern(double dr, double dz, double sr, float m
     return kern64(dr, dz, sr);
 }
 
+// Table of kernel values g(delta) for delta = dmin + tau - W, tau in [0, NT),
+// stored at [(tau % W) * Q + tau / W].  g_z is even and g_r odd in delta
+// (g_z depends on delta^2 only, g_r on delta times the same factor, and the
+// near/far choice on delta^2), so an entry whose mirror -delta lies in the
+// table is copied from it with g_r negated: bitwise the value a direct
+// evaluation gives, with about a third fewer evaluations.
+template <int MIXED, int W, int NT, int Q>
+__device__ __forceinline__ void fill_table(double2 *gt, int lane, int dmin, double dr, double sr,
+                                           float m1_near) {
+    for (int tau = lane; tau < NT; tau += 64) {
+        const int delta = dmin + tau - W;
+        const int mt = -delta - dmin + W;  // table index of -delta
+        if (delta >= 0 || mt >= NT) gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, (double)delta, sr, m1_near);
+    }
+    __syncthreads();
+    for (int tau = lane; tau < NT; tau += 64) {
+        const int delta = dmin + tau - W;
+        const int mt = -delta - dmin + W;
+        if (delta < 0 && mt < NT) {
+            const double2 v = gt[(mt % W) * Q + mt / W];
+            gt[(tau % W) * Q + tau / W] = make_double2(-v.x, v.y);
+        }
+    }
+}
+
 // Table layout: entry tau (0 <= tau < NT + W) at [(tau % W) * Q + tau / W].
 template <int W>
 struct TzShape {
@@ -106,10 +131,7 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
                 // delta = z_target - z_source; tau = delta - dmin + W (W entries of padding)
                 const int dmin = z0 - (s0 + S - 1);
                 __syncthreads();
-                for (int tau = lane; tau < NT; tau += 64) {
-                    const double dz = (double)(dmin + tau - W);
-                    gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, dz, sr, rc.m1_near);
-                }
+                fill_table<MIXED, W, NT, Q>(gt, lane, dmin, dr, sr, rc.m1_near);
                 for (int t = lane; t < S; t += 64) Is[t] = t < sn ? c.kscale * Irow[s0 + t] : 0.0;
                 __syncthreads();
                 // sliding window: at step t, lane needs tau = W*lane + S - 1 - t + cc + W
@@ -188,10 +210,7 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
                 // delta = z_target - z_output; tau = delta - dmin + W
                 const int dmin = s0 - (z0 + TZ - 1);
                 __syncthreads();
-                for (int tau = lane; tau < NT; tau += 64) {
-                    const double dz = (double)(dmin + tau - W);
-                    gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, dz, sr, rc.m1_near);
-                }
+                fill_table<MIXED, W, NT, Q>(gt, lane, dmin, dr, sr, rc.m1_near);
                 for (int t = lane; t < S; t += 64)
                     ws[t] = t < sn ? make_double2(wr_pub[rowoff + s0 + t], wz_pub[rowoff + s0 + t])
                                    : make_double2(0.0, 0.0);

@@ -119,6 +119,8 @@ hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
 hipError_t launch_zero_int(int *p, int n, hipStream_t st);
 hipError_t launch_reset_scalars(Scalars *sc, double T_bath, hipStream_t st);
 hipError_t launch_stored(const DevState &s, double *out, hipStream_t st);
+hipError_t launch_probe(const DevState &s, const double *zphys, int np, const double *pr, const double *pz,
+                        double *br, double *bz, hipStream_t st);
 void heat_buffers(int nsub, int sub, int *src, int *dst);
 
 // host-side copies of the elliptic approximations (same coefficients)

@@ -388,6 +388,39 @@ __global__ __launch_bounds__(256) void k_psi(DevState s, const int *elem_coil, d
     if (tact) psi[t] = acc;
 }
 
+// ------------------------------------------------------------------ field at arbitrary points
+// B at probe points (r, z) from every element of every coil, FP64, physical
+// coordinates (metres); B_r = 0 on the axis.  One thread per probe, sources
+// staged through LDS.
+__global__ __launch_bounds__(256) void k_probe(DevState s, const double *zphys, int np, const double *pr,
+                                               const double *pz, double *out_br, double *out_bz) {
+    __shared__ double2 sp[kStage];  // (r, z)
+    __shared__ double si[kStage];   // mu0 I / (2 pi)
+    const int tid = threadIdx.x;
+    const int p = blockIdx.x * 256 + tid;
+    const bool act = p < np;
+    const double r = act ? pr[p] : 1.0, z = act ? pz[p] : 0.0;
+    double ar = 0.0, az = 0.0;
+    for (int s0 = 0; s0 < s.N; s0 += kStage) {
+        const int cnt = min(kStage, s.N - s0);
+        __syncthreads();
+        if (tid < cnt) {
+            sp[tid] = make_double2(s.r[s0 + tid], zphys[s0 + tid]);
+            si[tid] = kMu0 / (2.0 * kPi) * s.I[s0 + tid];
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const double2 q = sp[j];
+            // same pair formula in metres: dr = r - a, sr = r + a
+            pair64(r - q.x, z - q.y, r + q.x, si[j], ar, az);
+        }
+    }
+    if (act) {
+        out_br[p] = r > 0.0 ? ar / r : 0.0;
+        out_bz[p] = az;
+    }
+}
+
 // ------------------------------------------------------------------ small kernels
 __global__ void k_gather(const double *src, const int *perm, int n, double *dst) {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -538,6 +571,13 @@ hipError_t launch_zero_int(int *p, int n, hipStream_t st) {
 
 hipError_t launch_reset_scalars(Scalars *sc, double T_bath, hipStream_t st) {
     hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(64), 0, st, sc, T_bath);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe(const DevState &s, const double *zphys, int np, const double *pr, const double *pz,
+                        double *br, double *bz, hipStream_t st) {
+    if (np <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_probe, dim3(blocks_for(np)), dim3(256), 0, st, s, zphys, np, pr, pz, br, bz);
     return hipGetLastError();
 }
 

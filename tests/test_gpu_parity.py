@@ -166,3 +166,47 @@ def test_graph_replay_matches_eager_bitwise():
     b.reset()
     b.run(200)
     assert np.array_equal(a.get(pk.F_T), b.get(pk.F_T))
+
+
+def test_field_at_probes_against_oracle():
+    pk = _pk()
+    w = cs.Workload(name="t", coils=[cs.Coil(4, 8, 4), cs.Coil(2, 3, 6, r_inner=0.05, z_center=0.02)],
+                    steps=1, dt=1e-4)
+    g = pk.Coil(w)
+    o = oracle.Sim(w, field_only=True)
+    I = cs.random_currents(w.n_elem, seed=61)
+    g.set_state(pk.F_I, I)
+    r = np.array([0.0, 0.0, 0.005, 0.019, 0.0215, 0.03, 0.06, 0.1])
+    z = np.array([0.0, 0.03, -0.01, 0.0, 0.0011, 0.004, 0.02, -0.05])
+    br, bz = g.field_at(r, z)
+    obr, obz = o.field_points(I, r, z)
+    scale = max(np.abs(obr).max(), np.abs(obz).max())
+    assert np.abs(br - obr).max() <= 1e-12 * scale and np.abs(bz - obz).max() <= 1e-12 * scale
+    assert br[0] == 0.0 and br[1] == 0.0
+    with pytest.raises(pk.CoilError):
+        g.field_at(np.array([-1.0]), np.array([0.0]))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_save_load_resume_is_bitwise(prec):
+    pk = _pk()
+    w = cs.workload("c1_active")
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision=prec)
+    g.run(150)
+    snap = g.save()
+    g.run(150)
+    a = [g.get(f) for f in (pk.F_I, pk.F_T, pk.F_PHI, pk.F_QW, pk.F_BZ)]
+    sa = g.scalars()
+    h = pk.Coil(w, inp, precision=prec)  # a fresh handle of the same configuration
+    h.load(snap)
+    assert h.scalars()["step"] == 150
+    h.run(150)
+    b = [h.get(f) for f in (pk.F_I, pk.F_T, pk.F_PHI, pk.F_QW, pk.F_BZ)]
+    sb = h.scalars()
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    for k in ("Q", "T_peak", "T_peak_elem", "T_peak_step", "Q_out", "stored"):
+        assert sa[k] == sb[k], k
+    with pytest.raises(pk.CoilError):
+        pk.Coil(cs.workload("c1"), cs.generate(cs.workload("c1"))).load(snap[:100])
