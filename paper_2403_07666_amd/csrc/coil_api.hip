@@ -198,21 +198,33 @@ void build_tz(Plan &p, int nsplit_req) {
                     it.coil = (int)ci;
                     it.ir = ir;
                     it.z0 = z0;
-                    it.jr0 = (int)((long long)g * nr / ns);
-                    it.jr1 = (int)((long long)(g + 1) * nr / ns);
+                    it.jr0 = g;  // source rows g, g + ns, g + 2 ns, ...
+                    it.jr1 = nr;
+                    it.jstep = ns;
                     it.slot = g;
                     by[k].push_back(it);
                 }
     }
-    // kernel-value evaluations per pass: per item, source row and z-chunk of
-    // 256 the table holds 64 W + 256 - 1 + W entries
+    // kernel-value evaluations per pass: for a chunk of se sources the forward
+    // table holds 64 W + se entries at delta = dlo + tau, dlo = z0 - s0 - se; an
+    // entry is evaluated unless delta < 0 and its mirror -delta is in the table
     p.tz_evals = 0.0;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 3; ++k) {
+        const int W = Ws[k], smax = W >= 8 ? 512 : 256;
         for (const TzItem &it : by[k]) {
             const CoilDev &d = p.coils[it.coil];
             const int nz = d.turns * d.ne;
-            p.tz_evals += (double)(it.jr1 - it.jr0) * ((nz + 255) / 256) * (64 * Ws[k] + 255 + Ws[k]);
+            const int rows = (it.jr1 - it.jr0 + it.jstep - 1) / it.jstep;
+            for (int s0 = 0; s0 < nz; s0 += smax) {
+                const int se = (std::min(smax, nz - s0) + W - 1) / W * W;
+                const int nt = 64 * W + se, dlo = it.z0 - s0 - se;
+                // evaluated: tau >= -dlo (delta >= 0), or tau < -dlo with -2 dlo - tau >= nt
+                const long long pos = std::max(0, nt - std::max(0, -dlo));
+                const long long neg_far = std::max(0, std::min(-dlo, -2 * dlo - nt + 1));
+                p.tz_evals += (double)rows * (double)(pos + std::max(0LL, std::min(neg_far, (long long)nt)));
+            }
         }
+    }
     p.tz_items.clear();
     for (int k = 0; k < 3; ++k) {
         p.tz_first[k] = (int)p.tz_items.size();

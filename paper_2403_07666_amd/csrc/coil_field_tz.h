@@ -6,9 +6,9 @@
 
 namespace coilq {
 
-// one target row segment [z0, z0 + 64 W) of row ir, source rows [jr0, jr1)
+// one target row segment [z0, z0 + 64 W) of row ir and a set of source rows
 struct TzItem {
-    int coil, ir, z0, jr0, jr1, slot, pad0, pad1;
+    int coil, ir, z0, jr0, jr1, slot, jstep, pad;  // source rows jr0, jr0 + jstep, ... < jr1
 };
 
 // items grouped by the per-thread target count W = 2, 4, 8

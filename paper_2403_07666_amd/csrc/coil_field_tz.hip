@@ -8,13 +8,14 @@
 //   B(i_r, i_z) = sum_{j_r, j_z} g(i_r, j_r, i_z - j_z) I(j_r, j_z)
 // is therefore, for every pair of rows (i_r, j_r), a 1-D convolution along z.
 // A work item owns one target row segment of 64*W consecutive z (one target
-// per lane and W per thread) and a range of source rows; for every source row
-// and every chunk of S source z it
-//   1. evaluates the 64*W + S - 1 distinct kernel values g(delta) on the fly
+// per lane and W per thread) and an interleaved set of source rows; for every
+// source row and every chunk of up to SMAX source z it
+//   1. evaluates the 64*W + se distinct kernel values g(delta) on the fly
 //      (elliptic integrals as in the direct pass; mixed precision: FP32 where
 //      m1 >= m1_near, FP64 for the near values) into LDS, stored de-interleaved
-//      by delta mod W so that every lane reads a different bank;
-//   2. streams the S source currents through LDS and accumulates
+//      by delta mod W so that every lane reads a different bank, and copies
+//      the entries whose mirror -delta is already there (g_r odd, g_z even);
+//   2. streams the source currents through LDS and accumulates
 //      acc[c] += g(delta) * I with a W-register sliding window over delta:
 //      one LDS read of g feeds 2W FP64 FMAs.
 // Every pair still contributes g * I exactly once; only redundant evaluations
@@ -72,47 +73,73 @@ __device__ __forceinline__ double2 kern(double dr, double dz, double sr, float m
     return kern64(dr, dz, sr);
 }
 
-// Table of kernel values g(delta) for delta = dmin + tau - W, tau in [0, NT),
+// Table of kernel values g(delta) for delta = dlo + tau, tau in [0, nt),
 // stored at [(tau % W) * Q + tau / W].  g_z is even and g_r odd in delta
 // (g_z depends on delta^2 only, g_r on delta times the same factor, and the
 // near/far choice on delta^2), so an entry whose mirror -delta lies in the
 // table is copied from it with g_r negated: bitwise the value a direct
-// evaluation gives, with about a third fewer evaluations.
-template <int MIXED, int W, int NT, int Q>
-__device__ __forceinline__ void fill_table(double2 *gt, int lane, int dmin, double dr, double sr,
+// evaluation gives.  When the table spans a whole row pair (targets and
+// sources of one z segment) about half of the entries are copies.
+template <int MIXED, int W, int Q>
+__device__ __forceinline__ void fill_table(double2 *gt, int lane, int nt, int dlo, double dr, double sr,
                                            float m1_near) {
-    for (int tau = lane; tau < NT; tau += 64) {
-        const int delta = dmin + tau - W;
-        const int mt = -delta - dmin + W;  // table index of -delta
-        if (delta >= 0 || mt >= NT) gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, (double)delta, sr, m1_near);
+    for (int tau = lane; tau < nt; tau += 64) {
+        const int delta = dlo + tau;
+        const int mt = -delta - dlo;  // table index of -delta
+        if (delta >= 0 || mt >= nt) gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, (double)delta, sr, m1_near);
     }
     __syncthreads();
-    for (int tau = lane; tau < NT; tau += 64) {
-        const int delta = dmin + tau - W;
-        const int mt = -delta - dmin + W;
-        if (delta < 0 && mt < NT) {
+    for (int tau = lane; tau < nt; tau += 64) {
+        const int delta = dlo + tau;
+        const int mt = -delta - dlo;
+        if (delta < 0 && mt < nt) {
             const double2 v = gt[(mt % W) * Q + mt / W];
             gt[(tau % W) * Q + tau / W] = make_double2(-v.x, v.y);
         }
     }
 }
 
-// Table layout: entry tau (0 <= tau < NT + W) at [(tau % W) * Q + tau / W].
+// Forward pass shape: 64 W targets per item; sources in chunks of up to SMAX
+// (a whole row of the benchmark coils, so that the mirror halves the table);
+// the table holds TZ + se entries for a chunk of se sources (se = the chunk
+// length rounded up to W), W * Q of them at most.  For W = 8 table and
+// currents take 20 KiB, so eight items fit in the 160 KiB of LDS of a CU.
 template <int W>
 struct TzShape {
-    static constexpr int S = 256;                 // source z per chunk
-    static constexpr int TZ = 64 * W;             // target z per item
-    static constexpr int NT = TZ + S - 1 + W;     // table entries incl. W of padding
-    static constexpr int Q = (NT + W - 1) / W;    // de-interleave stride
+    static constexpr int SMAX = W >= 8 ? 512 : 256;
+    static constexpr int TZ = 64 * W;
+    static constexpr int Q = (TZ + SMAX) / W;
 };
 
+// One block of W sources t = W tb + u.  Target cc of a lane reads entry
+// tau = W (lane - tb + se / W) + cc - u, whose residue (cc - u) mod W names its
+// ring register; after source u the entry leaving the window (residue
+// W - 1 - u) is replaced by the one entering it, whose quotient is
+// base = lane - tb + se / W - 1 for every u of the block.
+template <int W, int Q>
+__device__ __forceinline__ void tz_block(const double2 *gt, double2 (&ring)[W], double (&ar)[W],
+                                         double (&az)[W], const double (&Iv)[W], int base) {
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+        const double I = Iv[u];
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) {
+            const double2 g = ring[(cc - u + W) % W];
+            ar[cc] = fma(g.x, I, ar[cc]);
+            az[cc] = fma(g.y, I, az[cc]);
+        }
+        ring[(W - 1 - u) % W] = gt[((W - 1 - u) % W) * Q + base];
+    }
+}
+
 template <int MIXED, int W>
-__global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const TzItem *items,
-                                                 int nitems, const double *Ipub, const int *pub2int) {
+__global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
+                                                 int nitems, const double *__restrict__ Ipub,
+                                                 const int *__restrict__ pub2int) {
     using Sh = TzShape<W>;
-    constexpr int S = Sh::S, NT = Sh::NT, Q = Sh::Q;
+    constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
     __shared__ double2 gt[W * Q];
-    __shared__ double Is[S];
+    __shared__ double Is[SMAX];
     const int lane = threadIdx.x;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TzItem item = items[it];
@@ -122,39 +149,42 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
         double ar[W], az[W];
 #pragma unroll
         for (int cc = 0; cc < W; ++cc) ar[cc] = az[cc] = 0.0;
-        for (int jr = item.jr0; jr < item.jr1; ++jr) {
+        // source rows jr0, jr0 + jstep, ... (interleaved, so that every item of
+        // a target row gets a like share of the near rows)
+        for (int jr = item.jr0; jr < item.jr1; jr += item.jstep) {
             const double dr = (double)(ir - jr);
             const double sr = c.c2d + (double)(ir + jr);
             const double *Irow = Ipub + c.off + (size_t)jr * nz;
-            for (int s0 = 0; s0 < nz; s0 += S) {
-                const int sn = min(S, nz - s0);
-                // delta = z_target - z_source; tau = delta - dmin + W (W entries of padding)
-                const int dmin = z0 - (s0 + S - 1);
+            for (int s0 = 0; s0 < nz; s0 += SMAX) {
+                const int sn = min(SMAX, nz - s0);
+                const int nb = (sn + W - 1) / W;
+                const int se = nb * W;
+                // delta = z_target - z_source = dlo + tau
+                const int dlo = z0 - s0 - se;
                 __syncthreads();
-                fill_table<MIXED, W, NT, Q>(gt, lane, dmin, dr, sr, rc.m1_near);
-                for (int t = lane; t < S; t += 64) Is[t] = t < sn ? c.kscale * Irow[s0 + t] : 0.0;
+                fill_table<MIXED, W, Q>(gt, lane, TZ + se, dlo, dr, sr, rc.m1_near);
+                for (int t = lane; t < se; t += 64) Is[t] = t < sn ? c.kscale * Irow[s0 + t] : 0.0;
                 __syncthreads();
-                // sliding window: at step t, lane needs tau = W*lane + S - 1 - t + cc + W
                 double2 ring[W];
-                // tau = W*lane + c with c >= 0 constant: tau / W = lane + c / W
 #pragma unroll
-                for (int cc = 0; cc < W; ++cc)  // residue (W - 1 + cc) mod W
-                    ring[(W - 1 + cc) % W] = gt[((W - 1 + cc) % W) * Q + lane + (S - 1 + cc + W) / W];
-                for (int tb = 0; tb < S / W; ++tb) {
-                    const int base = lane - tb;
+                for (int cc = 0; cc < W; ++cc) ring[cc] = gt[cc * Q + lane + nb];
+                // the W currents of block tb + 1 are read while block tb is
+                // accumulated (two register sets, the loop unrolled twice)
+                double Ia[W], Ib[W];
 #pragma unroll
-                    for (int u = 0; u < W; ++u) {
-                        const double I = Is[tb * W + u];
-                        // tau_lo = W*lane + S - 1 - t + W  ==  (W - 1 - u) mod W
+                for (int u = 0; u < W; ++u) Ia[u] = Is[u];
+                for (int tb = 0; tb < nb; tb += 2) {
+                    if (tb + 1 < nb) {
 #pragma unroll
-                        for (int cc = 0; cc < W; ++cc) {
-                            const double2 g = ring[(2 * W - 1 - u + cc) % W];
-                            ar[cc] = fma(g.x, I, ar[cc]);
-                            az[cc] = fma(g.y, I, az[cc]);
+                        for (int u = 0; u < W; ++u) Ib[u] = Is[(tb + 1) * W + u];
+                    }
+                    tz_block<W, Q>(gt, ring, ar, az, Ia, lane - tb + nb - 1);
+                    if (tb + 1 < nb) {
+                        if (tb + 2 < nb) {
+#pragma unroll
+                            for (int u = 0; u < W; ++u) Ia[u] = Is[(tb + 2) * W + u];
                         }
-                        // next value entering the window: tau_lo - 1
-                        //   = W (lane - tb) + (S - 2 + W - u), so tau / W = base + (S - 2 + W - u) / W
-                        ring[(2 * W - 2 - u) % W] = gt[((2 * W - 2 - u) % W) * Q + base + (S - 2 + W - u) / W];
+                        tz_block<W, Q>(gt, ring, ar, az, Ib, lane - tb + nb - 2);
                     }
                 }
             }
@@ -173,7 +203,7 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
 // Transposed pass (adjoint): out(j_r, j_z) = sum over target rows i_r and
 // targets i_z of g_r(i_r, j_r, i_z - j_z) wr(i_r, i_z) + g_z(...) wz(i_r, i_z),
 // a correlation along z for every pair of rows.  Item fields: ir = output row
-// j_r, z0 = output segment, [jr0, jr1) = target rows.  The window slides up in
+// j_r, z0 = output segment, target rows jr0, jr0 + jstep, ... < jr1.  The window slides up in
 // delta as the target index grows; the table carries one more entry than the
 // forward one so that the last prefetch stays inside it.
 template <int W>
@@ -201,7 +231,7 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
         double acc[W];
 #pragma unroll
         for (int cc = 0; cc < W; ++cc) acc[cc] = 0.0;
-        for (int ir = item.jr0; ir < item.jr1; ++ir) {
+        for (int ir = item.jr0; ir < item.jr1; ir += item.jstep) {
             const double dr = (double)(ir - jr);
             const double sr = c.c2d + (double)(ir + jr);
             const size_t rowoff = c.off + (size_t)ir * nz;
@@ -210,7 +240,7 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
                 // delta = z_target - z_output; tau = delta - dmin + W
                 const int dmin = s0 - (z0 + TZ - 1);
                 __syncthreads();
-                fill_table<MIXED, W, NT, Q>(gt, lane, dmin, dr, sr, rc.m1_near);
+                fill_table<MIXED, W, Q>(gt, lane, NT, dmin - W, dr, sr, rc.m1_near);
                 for (int t = lane; t < S; t += 64)
                     ws[t] = t < sn ? make_double2(wr_pub[rowoff + s0 + t], wz_pub[rowoff + s0 + t])
                                    : make_double2(0.0, 0.0);
