@@ -60,7 +60,7 @@ struct Plan {
     int nslot_tz_max = 1;
     int part_slots = 2;  // capacity of part[] in double2 slots of N
     double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
-    size_t tz_cap = 0;      // translation item capacity (16 source-row groups)
+    size_t tz_cap = 0;      // translation item capacity (32 source-row groups)
     int algo = COIL_ALGO_TRANSLATION;
     int nchunk_cap = 1;    // partial-sum capacity in chunks
     size_t total = 0;
@@ -181,8 +181,8 @@ void build_tz(Plan &p, int nsplit_req) {
         }
         segs += (long long)nr * ((nz + 64 * Ws[wsel[ci]] - 1) / (64 * Ws[wsel[ci]]));
     }
-    const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, 16)
-                                      : (int)std::max<long long>(1, std::min<long long>(16, (4096 + segs - 1) / segs));
+    const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, 32)
+                                      : (int)std::max<long long>(1, std::min<long long>(32, (8192 + segs - 1) / segs));
     p.nslot_tz_max = 1;
     for (size_t ci = 0; ci < p.coils.size(); ++ci) {
         CoilDev &d = p.coils[ci];
@@ -283,7 +283,7 @@ int make_plan(const coil_config *c, Plan &p) {
     p.nchunk_cap = pcap;
     {
         Plan q = p;
-        build_tz(q, 16);
+        build_tz(q, 32);
         p.tz_cap = q.tz_items.size();
         p.nchunk_cap = std::max(p.nchunk_cap, q.nslot_tz_max);
     }
@@ -1525,7 +1525,7 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     int ba = h->plan.algo, b1 = 0, b2 = 0, b3 = 0;
     struct Cand { int algo, a, b, c; };
     std::vector<Cand> cands;
-    for (int sp : {2, 4, 8, 16}) cands.push_back({COIL_ALGO_TRANSLATION, sp, 0, 0});
+    for (int sp : {4, 8, 16, 32}) cands.push_back({COIL_ALGO_TRANSLATION, sp, 0, 0});
     for (int tb : {64, 128, 256})
         for (int ch : {1, 2, 4, 8, kMaxChunks})
             for (int g : {0, 2 * cus, 4 * cus}) cands.push_back({COIL_ALGO_DIRECT, tb, ch, g});

@@ -80,13 +80,14 @@ __device__ __forceinline__ double2 kern(double dr, double dz, double sr, float m
 // table is copied from it with g_r negated: bitwise the value a direct
 // evaluation gives.  When the table spans a whole row pair (targets and
 // sources of one z segment) about half of the entries are copies.
-template <int MIXED, int W, int Q>
+template <int MIXED, int W, int Q, bool NEG = false>
 __device__ __forceinline__ void fill_table(double2 *gt, int lane, int nt, int dlo, double dr, double sr,
                                            float m1_near) {
     for (int tau = lane; tau < nt; tau += 64) {
         const int delta = dlo + tau;
         const int mt = -delta - dlo;  // table index of -delta
-        if (delta >= 0 || mt >= nt) gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, (double)delta, sr, m1_near);
+        if (delta >= 0 || mt >= nt)
+            gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, (double)(NEG ? -delta : delta), sr, m1_near);
     }
     __syncthreads();
     for (int tau = lane; tau < nt; tau += 64) {
@@ -201,27 +202,42 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
 }
 
 // Transposed pass (adjoint): out(j_r, j_z) = sum over target rows i_r and
-// targets i_z of g_r(i_r, j_r, i_z - j_z) wr(i_r, i_z) + g_z(...) wz(i_r, i_z),
-// a correlation along z for every pair of rows.  Item fields: ir = output row
-// j_r, z0 = output segment, target rows jr0, jr0 + jstep, ... < jr1.  The window slides up in
-// delta as the target index grows; the table carries one more entry than the
-// forward one so that the last prefetch stays inside it.
+// targets i_z of g_r(i_r, j_r, i_z - j_z) wr(i_r, i_z) + g_z(...) wz(i_r, i_z).
+// With d = j_z - i_z this is, for every pair of rows, the same convolution as
+// the forward pass with the kernel G(d) = g(i_r, j_r, -d) (G_r odd, G_z even,
+// so the mirror fill applies) and two weights per source.  Item fields: ir =
+// output row j_r, z0 = output segment, summed rows jr0, jr0 + jstep, ... < jr1.
+// Chunks of up to 256 summed targets keep table and weights at 16 KiB.
 template <int W>
 struct TzShapeT {
-    static constexpr int S = 256;
+    static constexpr int SMAX = 256;
     static constexpr int TZ = 64 * W;
-    static constexpr int NT = TZ + S + W;
-    static constexpr int Q = (NT + W - 1) / W;
+    static constexpr int Q = (TZ + SMAX) / W;
 };
 
+template <int W, int Q>
+__device__ __forceinline__ void tzT_block(const double2 *gt, double2 (&ring)[W], double (&acc)[W],
+                                          const double2 (&wv)[W], int base) {
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) {
+            const double2 g = ring[(cc - u + W) % W];
+            acc[cc] = fma(g.x, wv[u].x, fma(g.y, wv[u].y, acc[cc]));
+        }
+        ring[(W - 1 - u) % W] = gt[((W - 1 - u) % W) * Q + base];
+    }
+}
+
 template <int MIXED, int W>
-__global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const TzItem *items,
-                                                  int nitems, const double *wr_pub, const double *wz_pub,
-                                                  const int *pub2int, double *partT) {
+__global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
+                                                  int nitems, const double *__restrict__ wr_pub,
+                                                  const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
+                                                  double *partT) {
     using Sh = TzShapeT<W>;
-    constexpr int S = Sh::S, TZ = Sh::TZ, NT = Sh::NT, Q = Sh::Q;
+    constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
     __shared__ double2 gt[W * Q];
-    __shared__ double2 ws[S];
+    __shared__ double2 ws[SMAX];
     const int lane = threadIdx.x;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TzItem item = items[it];
@@ -235,33 +251,36 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
             const double dr = (double)(ir - jr);
             const double sr = c.c2d + (double)(ir + jr);
             const size_t rowoff = c.off + (size_t)ir * nz;
-            for (int s0 = 0; s0 < nz; s0 += S) {
-                const int sn = min(S, nz - s0);
-                // delta = z_target - z_output; tau = delta - dmin + W
-                const int dmin = s0 - (z0 + TZ - 1);
+            for (int s0 = 0; s0 < nz; s0 += SMAX) {
+                const int sn = min(SMAX, nz - s0);
+                const int nb = (sn + W - 1) / W;
+                const int se = nb * W;
+                // d = j_z - i_z = dlo + tau; entries hold g(i_r, j_r, -d)
+                const int dlo = z0 - s0 - se;
                 __syncthreads();
-                fill_table<MIXED, W, Q>(gt, lane, NT, dmin - W, dr, sr, rc.m1_near);
-                for (int t = lane; t < S; t += 64)
+                fill_table<MIXED, W, Q, true>(gt, lane, TZ + se, dlo, dr, sr, rc.m1_near);
+                for (int t = lane; t < se; t += 64)
                     ws[t] = t < sn ? make_double2(wr_pub[rowoff + s0 + t], wz_pub[rowoff + s0 + t])
                                    : make_double2(0.0, 0.0);
                 __syncthreads();
                 double2 ring[W];
-                // tau = -W*lane + c with c >= 0 constant: tau / W = -lane + c / W
 #pragma unroll
-                for (int cc = 0; cc < W; ++cc)  // residue (W - 1 - cc) mod W
-                    ring[(W - 1 - cc) % W] = gt[((W - 1 - cc) % W) * Q - lane + (TZ - 1 + W - cc) / W];
-                for (int tb = 0; tb < S / W; ++tb) {
-                    const int base = tb - lane;
+                for (int cc = 0; cc < W; ++cc) ring[cc] = gt[cc * Q + lane + nb];
+                double2 wa[W], wb[W];
 #pragma unroll
-                    for (int u = 0; u < W; ++u) {
-                        const double2 wv = ws[tb * W + u];
+                for (int u = 0; u < W; ++u) wa[u] = ws[u];
+                for (int tb = 0; tb < nb; tb += 2) {
+                    if (tb + 1 < nb) {
 #pragma unroll
-                        for (int cc = 0; cc < W; ++cc) {
-                            const double2 g = ring[(u + W - 1 - cc) % W];
-                            acc[cc] = fma(g.x, wv.x, fma(g.y, wv.y, acc[cc]));
+                        for (int u = 0; u < W; ++u) wb[u] = ws[(tb + 1) * W + u];
+                    }
+                    tzT_block<W, Q>(gt, ring, acc, wa, lane - tb + nb - 1);
+                    if (tb + 1 < nb) {
+                        if (tb + 2 < nb) {
+#pragma unroll
+                            for (int u = 0; u < W; ++u) wa[u] = ws[(tb + 2) * W + u];
                         }
-                        // next: tau = W (tb - lane) + (u + TZ + W), residue u mod W
-                        ring[u % W] = gt[(u % W) * Q + base + (u + TZ + W) / W];
+                        tzT_block<W, Q>(gt, ring, acc, wb, lane - tb + nb - 2);
                     }
                 }
             }
