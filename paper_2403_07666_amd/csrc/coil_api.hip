@@ -56,7 +56,7 @@ struct Plan {
     int nchunk_max = 1;
     size_t items_cap = 0;  // work-item capacity (autotuner candidates)
     std::vector<TzItem> tz_items;  // translation-reuse pass, grouped by W
-    int tz_first[3] = {0, 0, 0}, tz_count[3] = {0, 0, 0};
+    int tz_first[kTzNW] = {}, tz_count[kTzNW] = {};
     int nslot_tz_max = 1;
     int part_slots = 2;  // capacity of part[] in double2 slots of N
     double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
@@ -159,40 +159,56 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
     }
 }
 
-// Translation-reuse work items: per coil a per-thread target count W in
-// {2, 4, 8} (target row segments of 64 W), rows x segments x source-row groups.
+// Translation-reuse work items: target row segments of 64 W (W = 2 .. 8
+// targets per thread) x source-row groups.  Each coil's rows are cut into the
+// segment widths that minimise the estimated time, sum over segments of
+// 64 W / eff(W), where eff(W) is the measured relative throughput per target
+// slot of the width-W kernel on this GPU (single coils of 64 layers and 64 W k
+// turns-elements, k = 1, 2; the window holds 2W accumulators per LDS read, and
+// W = 5 is LDS-bound at nine items per CU).  Each width is one launch, so the
+// source rows are split into enough groups that the smallest launch still has
+// about four items per LDS slot of the GPU.
 void build_tz(Plan &p, int nsplit_req) {
-    std::vector<TzItem> by[3];
-    const int Ws[3] = {2, 4, 8};
-    const double eff[3] = {0.55, 0.8, 1.0};  // relative throughput of the W variants
-    std::vector<int> wsel(p.coils.size());
-    long long segs = 0;
+    static const double eff[kTzNW] = {0.46, 0.59, 0.69, 0.69, 0.88, 0.94, 1.0};
+    std::vector<TzItem> by[kTzNW];
+    std::vector<std::vector<int>> segw(p.coils.size());  // width index per segment
+    long long wsegs[kTzNW] = {};
     for (size_t ci = 0; ci < p.coils.size(); ++ci) {
         const CoilDev &d = p.coils[ci];
         const int nz = d.turns * d.ne, nr = d.layers * d.ne;
-        double best = -1.0;
-        for (int k = 0; k < 3; ++k) {
-            const int span = 64 * Ws[k];
-            const double util = (double)nz / (double)(((nz + span - 1) / span) * span);
-            if (util * eff[k] > best) {
-                best = util * eff[k];
-                wsel[ci] = k;
+        std::vector<double> cost(nz + 1, 0.0);
+        std::vector<int> pick(nz + 1, 0);
+        for (int rem = 1; rem <= nz; ++rem) {
+            cost[rem] = INFINITY;
+            for (int wi = 0; wi < kTzNW; ++wi) {
+                const int span = 64 * (wi + 2);
+                const double c = span / eff[wi] + cost[std::max(0, rem - span)];
+                if (c < cost[rem]) {
+                    cost[rem] = c;
+                    pick[rem] = wi;
+                }
             }
         }
-        segs += (long long)nr * ((nz + 64 * Ws[wsel[ci]] - 1) / (64 * Ws[wsel[ci]]));
+        for (int z0 = 0; z0 < nz; z0 += 64 * (pick[nz - z0] + 2)) segw[ci].push_back(pick[nz - z0]);
+        for (int wi : segw[ci]) wsegs[wi] += nr;
     }
+    long long segs = 0;  // target segments of the smallest launch
+    for (int wi = 0; wi < kTzNW; ++wi)
+        if (wsegs[wi] > 0 && (segs == 0 || wsegs[wi] < segs)) segs = wsegs[wi];
     const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, 32)
                                       : (int)std::max<long long>(1, std::min<long long>(32, (8192 + segs - 1) / segs));
     p.nslot_tz_max = 1;
+    p.tz_evals = 0.0;
     for (size_t ci = 0; ci < p.coils.size(); ++ci) {
         CoilDev &d = p.coils[ci];
         const int nz = d.turns * d.ne, nr = d.layers * d.ne;
-        const int k = wsel[ci], span = 64 * Ws[k];
         const int ns = std::min(nsplit, nr);
         d.nslot_tz = ns;
         p.nslot_tz_max = std::max(p.nslot_tz_max, ns);
-        for (int ir = 0; ir < nr; ++ir)
-            for (int z0 = 0; z0 < nz; z0 += span)
+        int z0 = 0;
+        for (int wi : segw[ci]) {
+            const int W = wi + 2;
+            for (int ir = 0; ir < nr; ++ir)
                 for (int g = 0; g < ns; ++g) {
                     TzItem it{};
                     it.coil = (int)ci;
@@ -202,31 +218,26 @@ void build_tz(Plan &p, int nsplit_req) {
                     it.jr1 = nr;
                     it.jstep = ns;
                     it.slot = g;
-                    by[k].push_back(it);
+                    by[wi].push_back(it);
                 }
-    }
-    // kernel-value evaluations per pass: for a chunk of se sources the forward
-    // table holds 64 W + se entries at delta = dlo + tau, dlo = z0 - s0 - se; an
-    // entry is evaluated unless delta < 0 and its mirror -delta is in the table
-    p.tz_evals = 0.0;
-    for (int k = 0; k < 3; ++k) {
-        const int W = Ws[k], smax = W >= 8 ? 512 : 256;
-        for (const TzItem &it : by[k]) {
-            const CoilDev &d = p.coils[it.coil];
-            const int nz = d.turns * d.ne;
-            const int rows = (it.jr1 - it.jr0 + it.jstep - 1) / it.jstep;
+            // kernel-value evaluations per pass: for a chunk of se sources the
+            // forward table holds 64 W + se entries at delta = dlo + tau,
+            // dlo = z0 - s0 - se; an entry is evaluated unless delta < 0 and its
+            // mirror -delta is in the table
+            const int smax = W >= 5 ? 512 : 256;
             for (int s0 = 0; s0 < nz; s0 += smax) {
                 const int se = (std::min(smax, nz - s0) + W - 1) / W * W;
-                const int nt = 64 * W + se, dlo = it.z0 - s0 - se;
+                const int nt = 64 * W + se, dlo = z0 - s0 - se;
                 // evaluated: tau >= -dlo (delta >= 0), or tau < -dlo with -2 dlo - tau >= nt
                 const long long pos = std::max(0, nt - std::max(0, -dlo));
                 const long long neg_far = std::max(0, std::min(-dlo, -2 * dlo - nt + 1));
-                p.tz_evals += (double)rows * (double)(pos + std::max(0LL, std::min(neg_far, (long long)nt)));
+                p.tz_evals += (double)nr * (double)nr * (double)(pos + std::max(0LL, std::min(neg_far, (long long)nt)));
             }
+            z0 += 64 * W;
         }
     }
     p.tz_items.clear();
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kTzNW; ++k) {
         p.tz_first[k] = (int)p.tz_items.size();
         p.tz_count[k] = (int)by[k].size();
         p.tz_items.insert(p.tz_items.end(), by[k].begin(), by[k].end());
@@ -779,7 +790,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     h->Ipub = at<double>(h, p.Ipub_b);
     h->d_pub2int = at<int>(h, p.pub2int_b);
     h->tz.items = at<TzItem>(h, p.tz_b);
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kTzNW; ++k) {
         h->tz.first[k] = p.tz_first[k];
         h->tz.count[k] = p.tz_count[k];
     }
@@ -1413,7 +1424,7 @@ int apply_tz(coil_t *h, int nsplit) {
     h->plan.tz_cap = cap;
     h->plan.nslot_tz_max = q.nslot_tz_max;
     h->plan.tz_evals = q.tz_evals;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < kTzNW; ++k) {
         h->plan.tz_first[k] = q.tz_first[k];
         h->plan.tz_count[k] = q.tz_count[k];
         h->tz.first[k] = q.tz_first[k];

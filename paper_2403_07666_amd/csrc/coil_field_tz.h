@@ -11,10 +11,11 @@ struct TzItem {
     int coil, ir, z0, jr0, jr1, slot, jstep, pad;  // source rows jr0, jr0 + jstep, ... < jr1
 };
 
-// items grouped by the per-thread target count W = 2, 4, 8
+// items grouped by the per-thread target count W = 2 + wi, wi < kTzNW
+constexpr int kTzNW = 7;
 struct TzPlan {
     const TzItem *items;
-    int first[3], count[3];
+    int first[kTzNW], count[kTzNW];
 };
 
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,

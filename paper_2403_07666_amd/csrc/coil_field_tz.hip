@@ -23,6 +23,8 @@
 // precision modes (FP64 FMA runs at the non-packed FP32 rate on this GPU).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "coil_device.h"
 #include "coil_field_tz.h"
 
@@ -107,9 +109,10 @@ __device__ __forceinline__ void fill_table(double2 *gt, int lane, int nt, int dl
 // currents take 20 KiB, so eight items fit in the 160 KiB of LDS of a CU.
 template <int W>
 struct TzShape {
-    static constexpr int SMAX = W >= 8 ? 512 : 256;
+    static constexpr int SMAX = W >= 5 ? 512 : 256;
+    static constexpr int SMAXW = (SMAX + W - 1) / W * W;  // a chunk rounded up to W
     static constexpr int TZ = 64 * W;
-    static constexpr int Q = (TZ + SMAX) / W;
+    static constexpr int Q = (TZ + SMAXW) / W;
 };
 
 // One block of W sources t = W tb + u.  Target cc of a lane reads entry
@@ -140,7 +143,7 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
     using Sh = TzShape<W>;
     constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
     __shared__ double2 gt[W * Q];
-    __shared__ double Is[SMAX];
+    __shared__ double Is[Sh::SMAXW];
     const int lane = threadIdx.x;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TzItem item = items[it];
@@ -211,8 +214,9 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
 template <int W>
 struct TzShapeT {
     static constexpr int SMAX = 256;
+    static constexpr int SMAXW = (SMAX + W - 1) / W * W;
     static constexpr int TZ = 64 * W;
-    static constexpr int Q = (TZ + SMAX) / W;
+    static constexpr int Q = (TZ + SMAXW) / W;
 };
 
 template <int W, int Q>
@@ -237,7 +241,7 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
     using Sh = TzShapeT<W>;
     constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
     __shared__ double2 gt[W * Q];
-    __shared__ double2 ws[SMAX];
+    __shared__ double2 ws[Sh::SMAXW];
     const int lane = threadIdx.x;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TzItem item = items[it];
@@ -299,29 +303,45 @@ __global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub) 
     if (i < n) Ipub[perm[i]] = I[i];
 }
 
+namespace {
+
+// calls f(std::integral_constant<int, W>) for W = 2 + wi
+template <typename F>
+hipError_t with_w(int wi, F &&f) {
+    switch (wi + 2) {
+        case 2: return f(std::integral_constant<int, 2>());
+        case 3: return f(std::integral_constant<int, 3>());
+        case 4: return f(std::integral_constant<int, 4>());
+        case 5: return f(std::integral_constant<int, 5>());
+        case 6: return f(std::integral_constant<int, 6>());
+        case 7: return f(std::integral_constant<int, 7>());
+        case 8: return f(std::integral_constant<int, 8>());
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                            const int *pub2int, int grid_limit, hipStream_t st) {
     hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N,
                        const_cast<double *>(Ipub));
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    for (int wi = 0; wi < 3; ++wi) {
+    const bool mixed = rc.prec == COIL_MIXED;
+    for (int wi = 0; wi < kTzNW; ++wi) {
         const int n = tp.count[wi];
         if (n == 0) continue;
         const TzItem *items = tp.items + tp.first[wi];
         const int grid = grid_limit > 0 ? min(grid_limit, n) : n;
-        const bool mixed = rc.prec == COIL_MIXED;
-#define COILQ_TZ_LAUNCH(Wv)                                                                        \
-    if (mixed)                                                                                     \
-        hipLaunchKernelGGL((k_field_tz<1, Wv>), dim3(grid), dim3(64), 0, st, s, rc, items, n, Ipub, \
-                           pub2int);                                                               \
-    else                                                                                           \
-        hipLaunchKernelGGL((k_field_tz<0, Wv>), dim3(grid), dim3(64), 0, st, s, rc, items, n, Ipub, pub2int);
-        if (wi == 0) { COILQ_TZ_LAUNCH(2) }
-        else if (wi == 1) { COILQ_TZ_LAUNCH(4) }
-        else { COILQ_TZ_LAUNCH(8) }
-#undef COILQ_TZ_LAUNCH
-        err = hipGetLastError();
+        err = with_w(wi, [&](auto wc) {
+            constexpr int Wv = decltype(wc)::value;
+            if (mixed)
+                hipLaunchKernelGGL((k_field_tz<1, Wv>), dim3(grid), dim3(64), 0, st, s, rc, items, n, Ipub, pub2int);
+            else
+                hipLaunchKernelGGL((k_field_tz<0, Wv>), dim3(grid), dim3(64), 0, st, s, rc, items, n, Ipub, pub2int);
+            return hipGetLastError();
+        });
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
@@ -334,23 +354,21 @@ hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan 
     hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wz, s.perm, s.N, wz_pub);
     hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
-    for (int wi = 0; wi < 3; ++wi) {
+    const bool mixed = rc.prec == COIL_MIXED;
+    for (int wi = 0; wi < kTzNW; ++wi) {
         const int n = tp.count[wi];
         if (n == 0) continue;
         const TzItem *items = tp.items + tp.first[wi];
-        const bool mixed = rc.prec == COIL_MIXED;
-#define COILQ_TZT_LAUNCH(Wv)                                                                            \
-    if (mixed)                                                                                          \
-        hipLaunchKernelGGL((k_fieldT_tz<1, Wv>), dim3(n), dim3(64), 0, st, s, rc, items, n, wr_pub, wz_pub, \
-                           pub2int, partT);                                                             \
-    else                                                                                                \
-        hipLaunchKernelGGL((k_fieldT_tz<0, Wv>), dim3(n), dim3(64), 0, st, s, rc, items, n, wr_pub, wz_pub, \
-                           pub2int, partT);
-        if (wi == 0) { COILQ_TZT_LAUNCH(2) }
-        else if (wi == 1) { COILQ_TZT_LAUNCH(4) }
-        else { COILQ_TZT_LAUNCH(8) }
-#undef COILQ_TZT_LAUNCH
-        err = hipGetLastError();
+        err = with_w(wi, [&](auto wc) {
+            constexpr int Wv = decltype(wc)::value;
+            if (mixed)
+                hipLaunchKernelGGL((k_fieldT_tz<1, Wv>), dim3(n), dim3(64), 0, st, s, rc, items, n, wr_pub, wz_pub,
+                                   pub2int, partT);
+            else
+                hipLaunchKernelGGL((k_fieldT_tz<0, Wv>), dim3(n), dim3(64), 0, st, s, rc, items, n, wr_pub, wz_pub,
+                                   pub2int, partT);
+            return hipGetLastError();
+        });
         if (err != hipSuccess) return err;
     }
     return hipSuccess;
