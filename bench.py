@@ -44,22 +44,31 @@ FLOP_PER_PAIR_ACC = 4
 # HBM bytes per launch of the field pass from the two rocprofv3 PMC runs
 # (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a 256 MiB copy; see
 # profiles/), valid only for the kernel source the counters were taken on.
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 counter runs
+# (FETCH_SIZE, WRITE_SIZE) scaled by a device copy of known size.  A record
+# holds only while the sources that set the kernel's traffic (the kernel file
+# and the host code that plans its work items) are unchanged.
+TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_api.hip"), "direct": ("coil_kernels.hip", "coil_api.hip")}
 MEASURED_TRAFFIC = {
-    # (kernel source file, workload, precision): (sha1 of the source, bytes per launch)
-    ("coil_field_tz.hip", "c2_medium_131k", "mixed"): ("6bd20e3de9aa023ed496e7aab55f94cf6c43b924", 39418253),
+    # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
+    ("translation", "c2_medium_131k", "mixed"): ("66d71111fb7903e619d1bdd1203a2acb0e82f878", 73517270),
 }
 
 
-def _traffic(workload: str, precision: str, algo: str):
+def _sources_sha(algo: str) -> str:
     import hashlib
-    src = "coil_field_tz.hip" if algo == "translation" else "coil_kernels.hip"
-    rec = MEASURED_TRAFFIC.get((src, workload, precision))
+    h = hashlib.sha1()
+    for name in TRAFFIC_SOURCES[algo]:
+        with open(os.path.join(ROOT, "paper_2403_07666_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def _traffic(workload: str, precision: str, algo: str):
+    rec = MEASURED_TRAFFIC.get((algo, workload, precision))
     if rec is None:
         return None
-    path = os.path.join(ROOT, "paper_2403_07666_amd", "csrc", src)
-    with open(path, "rb") as f:
-        sha = hashlib.sha1(f.read()).hexdigest()
-    return rec[1] if sha == rec[0] else None
+    return rec[1] if _sources_sha(algo) == rec[0] else None
 
 
 def log(*a):
@@ -217,18 +226,21 @@ def _fd_check(pk, cs, name: str, fd_steps: int) -> dict:
         rvals.append(g.objectives(fd_steps)[0])
     g.close()
     fdr = (rvals[0] - rvals[1]) / (2 * h)
-    # relative error where the difference quotient carries a signal; wires whose
-    # Joule heat underflows give fd == 0 and are counted, and their adjoint is
-    # reported beside it
-    live = [(a, f) for _, a, f in per_wire if abs(f) > 0.0]
+    # relative error where the difference quotient resolves the derivative: its
+    # round-off is about eps |Q| / h, so a wire counts when |fd| exceeds that by
+    # 1e3; the others (Joule heat too small to move Q by more than an ulp, or
+    # not at all) are counted, with their largest adjoint value
+    floor = 2.220446049250313e-16 * abs(float(obj[0])) / h
+    live = [(a, f) for _, a, f in per_wire if abs(f) > 1e3 * floor]
     rel = [abs(a - f) / abs(f) for a, f in live]
     res = {"workload": name, "steps": fd_steps, "h": h, "Q": float(obj[0]),
-           "wires": per_wire, "n_zero_signal": len(per_wire) - len(live),
-           "max_abs_adjoint_zero_signal": max([abs(a) for _, a, f in per_wire if f == 0.0], default=0.0),
+           "wires": per_wire, "fd_roundoff": floor, "n_resolved": len(live),
+           "n_below_roundoff": len(per_wire) - len(live),
+           "max_abs_adjoint_unresolved": max([abs(a) for _, a, f in per_wire if abs(f) <= 1e3 * floor], default=0.0),
            "max_rel_err_dQ_dcw": max(rel) if rel else None,
            "dQ_dramp": [float(gqr[0]), fdr],
            "rel_err_dQ_dramp": abs(gqr[0] - fdr) / abs(fdr) if fdr != 0 else None}
-    log(f"[{name}] FD over {fd_steps} steps (Q {obj[0]:.3e}): {len(live)} live wires, max rel err "
+    log(f"[{name}] FD over {fd_steps} steps (Q {obj[0]:.3e}): {len(live)} resolved wires, max rel err "
         f"dQ/dc_w {res['max_rel_err_dQ_dcw']}, dQ/dramp {res['rel_err_dQ_dramp']}")
     return res
 

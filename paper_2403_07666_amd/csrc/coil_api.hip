@@ -56,7 +56,6 @@ struct Plan {
     int nchunk_max = 1;
     size_t items_cap = 0;  // work-item capacity (autotuner candidates)
     std::vector<TzItem> tz_items;  // translation-reuse pass, grouped by W
-    int tz_first[kTzNW] = {}, tz_count[kTzNW] = {};
     int nslot_tz_max = 1;
     int part_slots = 2;  // capacity of part[] in double2 slots of N
     double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
@@ -163,16 +162,16 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
 // targets per thread) x source-row groups.  Each coil's rows are cut into the
 // segment widths that minimise the estimated time, sum over segments of
 // 64 W / eff(W), where eff(W) is the measured relative throughput per target
-// slot of the width-W kernel on this GPU (single coils of 64 layers and 64 W k
-// turns-elements, k = 1, 2; the window holds 2W accumulators per LDS read, and
-// W = 5 is LDS-bound at nine items per CU).  Each width is one launch, so the
-// source rows are split into enough groups that the smallest launch still has
-// about four items per LDS slot of the GPU.
+// slot of width W on this GPU (single coils of 64 layers and 64 W k
+// turns-elements, k = 2, mixed precision; the window holds 2W accumulators
+// per LDS read, and every width runs at the register count of the widest).
+// All widths run in one launch, widest (longest) items first; the source rows
+// are split into enough groups for about four items per LDS slot of the GPU.
 void build_tz(Plan &p, int nsplit_req) {
-    static const double eff[kTzNW] = {0.46, 0.59, 0.69, 0.69, 0.88, 0.94, 1.0};
+    static const double eff[kTzNW] = {0.37, 0.51, 0.70, 0.79, 0.89, 0.94, 1.0};
     std::vector<TzItem> by[kTzNW];
     std::vector<std::vector<int>> segw(p.coils.size());  // width index per segment
-    long long wsegs[kTzNW] = {};
+    long long segs = 0;
     for (size_t ci = 0; ci < p.coils.size(); ++ci) {
         const CoilDev &d = p.coils[ci];
         const int nz = d.turns * d.ne, nr = d.layers * d.ne;
@@ -190,11 +189,8 @@ void build_tz(Plan &p, int nsplit_req) {
             }
         }
         for (int z0 = 0; z0 < nz; z0 += 64 * (pick[nz - z0] + 2)) segw[ci].push_back(pick[nz - z0]);
-        for (int wi : segw[ci]) wsegs[wi] += nr;
+        segs += (long long)nr * (long long)segw[ci].size();
     }
-    long long segs = 0;  // target segments of the smallest launch
-    for (int wi = 0; wi < kTzNW; ++wi)
-        if (wsegs[wi] > 0 && (segs == 0 || wsegs[wi] < segs)) segs = wsegs[wi];
     const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, 32)
                                       : (int)std::max<long long>(1, std::min<long long>(32, (8192 + segs - 1) / segs));
     p.nslot_tz_max = 1;
@@ -218,6 +214,7 @@ void build_tz(Plan &p, int nsplit_req) {
                     it.jr1 = nr;
                     it.jstep = ns;
                     it.slot = g;
+                    it.w = W;
                     by[wi].push_back(it);
                 }
             // kernel-value evaluations per pass: for a chunk of se sources the
@@ -236,12 +233,9 @@ void build_tz(Plan &p, int nsplit_req) {
             z0 += 64 * W;
         }
     }
+    // one launch, widest items (the longest) first
     p.tz_items.clear();
-    for (int k = 0; k < kTzNW; ++k) {
-        p.tz_first[k] = (int)p.tz_items.size();
-        p.tz_count[k] = (int)by[k].size();
-        p.tz_items.insert(p.tz_items.end(), by[k].begin(), by[k].end());
-    }
+    for (int k = kTzNW - 1; k >= 0; --k) p.tz_items.insert(p.tz_items.end(), by[k].begin(), by[k].end());
 }
 
 int make_plan(const coil_config *c, Plan &p) {
@@ -790,10 +784,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     h->Ipub = at<double>(h, p.Ipub_b);
     h->d_pub2int = at<int>(h, p.pub2int_b);
     h->tz.items = at<TzItem>(h, p.tz_b);
-    for (int k = 0; k < kTzNW; ++k) {
-        h->tz.first[k] = p.tz_first[k];
-        h->tz.count[k] = p.tz_count[k];
-    }
+    h->tz.n = (int)p.tz_items.size();
     s.coils = at<CoilDev>(h, p.coils_b);
     s.items = at<PairItem>(h, p.items_b);
     s.bbox = at<int4>(h, p.bbox_b);
@@ -1424,12 +1415,7 @@ int apply_tz(coil_t *h, int nsplit) {
     h->plan.tz_cap = cap;
     h->plan.nslot_tz_max = q.nslot_tz_max;
     h->plan.tz_evals = q.tz_evals;
-    for (int k = 0; k < kTzNW; ++k) {
-        h->plan.tz_first[k] = q.tz_first[k];
-        h->plan.tz_count[k] = q.tz_count[k];
-        h->tz.first[k] = q.tz_first[k];
-        h->tz.count[k] = q.tz_count[k];
-    }
+    h->tz.n = (int)q.tz_items.size();
     h->tz_split = nsplit;
     return COIL_OK;
 }

@@ -8,14 +8,15 @@ namespace coilq {
 
 // one target row segment [z0, z0 + 64 W) of row ir and a set of source rows
 struct TzItem {
-    int coil, ir, z0, jr0, jr1, slot, jstep, pad;  // source rows jr0, jr0 + jstep, ... < jr1
+    int coil, ir, z0, jr0, jr1, slot, jstep, w;  // source rows jr0, jr0 + jstep, ... < jr1; width W
 };
 
-// items grouped by the per-thread target count W = 2 + wi, wi < kTzNW
+// per-thread target counts W = 2 .. 8; the items of one pass are ordered
+// widest first and run in one launch
 constexpr int kTzNW = 7;
 struct TzPlan {
     const TzItem *items;
-    int first[kTzNW], count[kTzNW];
+    int n;
 };
 
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,

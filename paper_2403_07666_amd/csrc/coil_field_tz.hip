@@ -23,8 +23,6 @@
 // precision modes (FP64 FMA runs at the non-packed FP32 rate on this GPU).
 #include <hip/hip_runtime.h>
 
-#include <type_traits>
-
 #include "coil_device.h"
 #include "coil_field_tz.h"
 
@@ -136,17 +134,15 @@ __device__ __forceinline__ void tz_block(const double2 *gt, double2 (&ring)[W], 
     }
 }
 
+// One forward item of width W; gt and Is point into the launch's LDS buffer.
 template <int MIXED, int W>
-__global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
-                                                 int nitems, const double *__restrict__ Ipub,
-                                                 const int *__restrict__ pub2int) {
+__device__ __forceinline__ void tz_item(const DevState &s, const RunConst &rc, const TzItem &item,
+                                        const double *__restrict__ Ipub, const int *__restrict__ pub2int,
+                                        double2 *gt, double *Is) {
     using Sh = TzShape<W>;
     constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
-    __shared__ double2 gt[W * Q];
-    __shared__ double Is[Sh::SMAXW];
     const int lane = threadIdx.x;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const TzItem item = items[it];
+    {
         const CoilDev c = s.coils[item.coil];
         const int nz = c.turns * c.ne;
         const int ir = item.ir, z0 = item.z0;
@@ -204,6 +200,42 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
     }
 }
 
+// LDS of one item: the widest table plus its chunk of currents (W = 8: 20 KiB,
+// so eight items share the 160 KiB of a CU)
+constexpr int kTzLds2 = 20480 / 16;
+template <int W>
+constexpr bool tz_fits() {
+    return TzShape<W>::Q * W * 16 + TzShape<W>::SMAXW * 8 <= kTzLds2 * 16;
+}
+
+// All widths in one launch: items are ordered widest first, and each
+// workgroup branches (uniformly) on its item's width.
+template <int MIXED>
+__global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
+                                                 int nitems, const double *__restrict__ Ipub,
+                                                 const int *__restrict__ pub2int) {
+    __shared__ double2 lds[kTzLds2];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TzItem item = items[it];
+#define COILQ_TZ_CASE(Wv)                                                                                   \
+    case Wv:                                                                                                \
+        static_assert(tz_fits<Wv>(), "LDS");                                                                \
+        tz_item<MIXED, Wv>(s, rc, item, Ipub, pub2int, lds,                                                 \
+                           reinterpret_cast<double *>(lds + TzShape<Wv>::Q * Wv));                          \
+        break;
+        switch (item.w) {
+            COILQ_TZ_CASE(8)
+            COILQ_TZ_CASE(7)
+            COILQ_TZ_CASE(6)
+            COILQ_TZ_CASE(5)
+            COILQ_TZ_CASE(4)
+            COILQ_TZ_CASE(3)
+            COILQ_TZ_CASE(2)
+        }
+#undef COILQ_TZ_CASE
+    }
+}
+
 // Transposed pass (adjoint): out(j_r, j_z) = sum over target rows i_r and
 // targets i_z of g_r(i_r, j_r, i_z - j_z) wr(i_r, i_z) + g_z(...) wz(i_r, i_z).
 // With d = j_z - i_z this is, for every pair of rows, the same convolution as
@@ -234,17 +266,14 @@ __device__ __forceinline__ void tzT_block(const double2 *gt, double2 (&ring)[W],
 }
 
 template <int MIXED, int W>
-__global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
-                                                  int nitems, const double *__restrict__ wr_pub,
-                                                  const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
-                                                  double *partT) {
+__device__ __forceinline__ void tzT_item(const DevState &s, const RunConst &rc, const TzItem &item,
+                                         const double *__restrict__ wr_pub, const double *__restrict__ wz_pub,
+                                         const int *__restrict__ pub2int, double *partT, double2 *gt,
+                                         double2 *ws) {
     using Sh = TzShapeT<W>;
     constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
-    __shared__ double2 gt[W * Q];
-    __shared__ double2 ws[Sh::SMAXW];
     const int lane = threadIdx.x;
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const TzItem item = items[it];
+    {
         const CoilDev c = s.coils[item.coil];
         const int nz = c.turns * c.ne;
         const int jr = item.ir, z0 = item.z0;
@@ -297,54 +326,57 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
     }
 }
 
+constexpr int kTzTLds2 = 16384 / 16;
+template <int W>
+constexpr bool tzT_fits() {
+    return TzShapeT<W>::Q * W * 16 + TzShapeT<W>::SMAXW * 16 <= kTzTLds2 * 16;
+}
+
+template <int MIXED>
+__global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
+                                                  int nitems, const double *__restrict__ wr_pub,
+                                                  const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
+                                                  double *partT) {
+    __shared__ double2 lds[kTzTLds2];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const TzItem item = items[it];
+#define COILQ_TZT_CASE(Wv)                                                                                  \
+    case Wv:                                                                                                \
+        static_assert(tzT_fits<Wv>(), "LDS");                                                               \
+        tzT_item<MIXED, Wv>(s, rc, item, wr_pub, wz_pub, pub2int, partT, lds, lds + TzShapeT<Wv>::Q * Wv);  \
+        break;
+        switch (item.w) {
+            COILQ_TZT_CASE(8)
+            COILQ_TZT_CASE(7)
+            COILQ_TZT_CASE(6)
+            COILQ_TZT_CASE(5)
+            COILQ_TZT_CASE(4)
+            COILQ_TZT_CASE(3)
+            COILQ_TZT_CASE(2)
+        }
+#undef COILQ_TZT_CASE
+    }
+}
+
 // I in public (row-major) order for the convolution pass
 __global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) Ipub[perm[i]] = I[i];
 }
 
-namespace {
-
-// calls f(std::integral_constant<int, W>) for W = 2 + wi
-template <typename F>
-hipError_t with_w(int wi, F &&f) {
-    switch (wi + 2) {
-        case 2: return f(std::integral_constant<int, 2>());
-        case 3: return f(std::integral_constant<int, 3>());
-        case 4: return f(std::integral_constant<int, 4>());
-        case 5: return f(std::integral_constant<int, 5>());
-        case 6: return f(std::integral_constant<int, 6>());
-        case 7: return f(std::integral_constant<int, 7>());
-        case 8: return f(std::integral_constant<int, 8>());
-    }
-    return hipErrorInvalidValue;
-}
-
-}  // namespace
-
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                            const int *pub2int, int grid_limit, hipStream_t st) {
     hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N,
                        const_cast<double *>(Ipub));
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    const bool mixed = rc.prec == COIL_MIXED;
-    for (int wi = 0; wi < kTzNW; ++wi) {
-        const int n = tp.count[wi];
-        if (n == 0) continue;
-        const TzItem *items = tp.items + tp.first[wi];
+    const int n = tp.n;
+    if (n > 0) {
         const int grid = grid_limit > 0 ? min(grid_limit, n) : n;
-        err = with_w(wi, [&](auto wc) {
-            constexpr int Wv = decltype(wc)::value;
-            if (mixed)
-                hipLaunchKernelGGL((k_field_tz<1, Wv>), dim3(grid), dim3(64), 0, st, s, rc, items, n, Ipub, pub2int);
-            else
-                hipLaunchKernelGGL((k_field_tz<0, Wv>), dim3(grid), dim3(64), 0, st, s, rc, items, n, Ipub, pub2int);
-            return hipGetLastError();
-        });
-        if (err != hipSuccess) return err;
+        if (rc.prec == COIL_MIXED)
+            hipLaunchKernelGGL(k_field_tz<1>, dim3(grid), dim3(64), 0, st, s, rc, tp.items, n, Ipub, pub2int);
+        else
+            hipLaunchKernelGGL(k_field_tz<0>, dim3(grid), dim3(64), 0, st, s, rc, tp.items, n, Ipub, pub2int);
     }
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *wr,
@@ -352,26 +384,16 @@ hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan 
                             double *partT, hipStream_t st) {
     hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wr, s.perm, s.N, wr_pub);
     hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wz, s.perm, s.N, wz_pub);
-    hipError_t err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    const bool mixed = rc.prec == COIL_MIXED;
-    for (int wi = 0; wi < kTzNW; ++wi) {
-        const int n = tp.count[wi];
-        if (n == 0) continue;
-        const TzItem *items = tp.items + tp.first[wi];
-        err = with_w(wi, [&](auto wc) {
-            constexpr int Wv = decltype(wc)::value;
-            if (mixed)
-                hipLaunchKernelGGL((k_fieldT_tz<1, Wv>), dim3(n), dim3(64), 0, st, s, rc, items, n, wr_pub, wz_pub,
-                                   pub2int, partT);
-            else
-                hipLaunchKernelGGL((k_fieldT_tz<0, Wv>), dim3(n), dim3(64), 0, st, s, rc, items, n, wr_pub, wz_pub,
-                                   pub2int, partT);
-            return hipGetLastError();
-        });
-        if (err != hipSuccess) return err;
+    const int n = tp.n;
+    if (n > 0) {
+        if (rc.prec == COIL_MIXED)
+            hipLaunchKernelGGL(k_fieldT_tz<1>, dim3(n), dim3(64), 0, st, s, rc, tp.items, n, wr_pub, wz_pub,
+                               pub2int, partT);
+        else
+            hipLaunchKernelGGL(k_fieldT_tz<0>, dim3(n), dim3(64), 0, st, s, rc, tp.items, n, wr_pub, wz_pub,
+                               pub2int, partT);
     }
-    return hipSuccess;
+    return hipGetLastError();
 }
 
 }  // namespace coilq
