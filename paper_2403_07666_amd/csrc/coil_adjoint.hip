@@ -94,7 +94,15 @@ __global__ void k_fieldT_sum(DevState s, const double *partT, double *out, int a
     const CoilDev c = s.coils[s.elem_coil[j]];
     const int nk = s.algo_tz ? c.nslot_tz : c.nchunk;
     double v = 0.0;
-    for (int k = 0; k < nk; ++k) v += partT[(size_t)k * s.N + j];
+    int k = 0;
+    for (; k + 16 <= nk; k += 16) {  // in order, 16 loads in flight
+        double p[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) p[q] = partT[(size_t)(k + q) * s.N + j];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v += p[q];
+    }
+    for (; k < nk; ++k) v += partT[(size_t)k * s.N + j];
     out[j] = accumulate ? out[j] + v : v;
 }
 
@@ -132,19 +140,31 @@ __global__ __launch_bounds__(64) void k_wire_adj(DevState s, RunConst rc, AdjPtr
     }
     const double re = s.r[e];
     const double kap = 2.0 * kPi * re / d2;
-    const double *M = s.Mlay + (size_t)(c.layer_off + layer) * n * n;
-    load_wire_matrix(sm, M, n, ld, lane, act, dt * kap * lo.Ep);
-    chol_lds(sm, n, ld, lane, act);
+    const size_t lay = (size_t)(c.layer_off + layer);
+    const double *M = s.Mlay + lay * n * n;
+    const double diag_add = dt * kap * lo.Ep;
     const double I1 = I0 + dI;
     const double Elin = lo.E + lo.Ep * dI / d2;
     const double qb = act ? a.qbar[e] : 0.0;
     const double Ib1 = act ? a.Ibar[e] : 0.0;
     // adjoint of dI: through I^{k+1} = I^k + dI and through q
     double xv = act ? Ib1 + qb * (lo.Ep * I1 / (d2 * d2) + Elin / d2) : 0.0;
-    double yv = act ? 1.0 : 0.0;
-    solve2_lds(sm, n, ld, lane, act, xv, yv);
+    double yv, sy;
+    // A = M + dt diag(kap E') is symmetric: the same solves as the forward step,
+    // with the layer's inverse when the diagonal addition vanishes in FP64
+    const double mee = act ? M[(size_t)lane * n + lane] : 1.0;
+    if (__all(act ? (mee + diag_add == mee) : 1)) {
+        xv = matvec_cols(s.Minv + lay * n * n, n, lane, act, xv);
+        yv = act ? s.yl[lay * n + lane] : 0.0;
+        sy = s.syl[lay];
+    } else {
+        load_wire_matrix(sm, M, n, ld, lane, act, diag_add);
+        chol_lds(sm, n, ld, lane, act);
+        yv = act ? 1.0 : 0.0;
+        solve2_lds(sm, n, ld, lane, act, xv, yv);
+        sy = wave_sum(act ? yv : 0.0);
+    }
     const double sx = wave_sum(act ? xv : 0.0);
-    const double sy = wave_sum(act ? yv : 0.0);
     const double numu = sx / sy;  // adjoint of the net-current constraint
     const double nu = act ? xv - numu * yv : 0.0;
     // adjoints of E and E' (through b, the matrix diagonal and q)

@@ -209,9 +209,35 @@ __device__ __forceinline__ void solve2_lds(const double *sm, int n, int ld, int 
 __device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, int n, int ld, int lane,
                                                  bool act, double diag_add) {
     if (act)
-        for (int col = 0; col < n; ++col) sm[col * ld + lane] = M[col * n + lane];
+        for (int c0 = 0; c0 < n; c0 += 16) {  // 16 column loads in flight
+            double a[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) a[q] = c0 + q < n ? M[(size_t)(c0 + q) * n + lane] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                if (c0 + q < n) sm[(c0 + q) * ld + lane] = a[q];
+        }
     __syncthreads();
     if (act) sm[lane * ld + lane] += diag_add;
+}
+
+// y(lane) = sum_j A[j n + lane] v_j for a column-major n x n block with v held
+// one element per lane (v_j broadcast from lane j).  The FMAs run in j order;
+// the column loads are issued 16 at a time so that they are in flight together.
+__device__ __forceinline__ double matvec_cols(const double *A, int n, int lane, bool act, double v) {
+    double y = 0.0;
+    for (int j0 = 0; j0 < n; j0 += 16) {
+        double a[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) a[q] = (act && j0 + q < n) ? A[(size_t)(j0 + q) * n + lane] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            if (j0 + q < n) {
+                const double vj = __shfl(v, j0 + q);
+                if (act) y = fma(a[q], vj, y);
+            }
+    }
+    return y;
 }
 
 }  // namespace coilq

@@ -242,10 +242,11 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
 // the forward pass with the kernel G(d) = g(i_r, j_r, -d) (G_r odd, G_z even,
 // so the mirror fill applies) and two weights per source.  Item fields: ir =
 // output row j_r, z0 = output segment, summed rows jr0, jr0 + jstep, ... < jr1.
-// Chunks of up to 256 summed targets keep table and weights at 16 KiB.
+// Chunks of up to 384 summed targets keep table and weights within 20 KiB
+// (eight items per CU).
 template <int W>
 struct TzShapeT {
-    static constexpr int SMAX = 256;
+    static constexpr int SMAX = 384;
     static constexpr int SMAXW = (SMAX + W - 1) / W * W;
     static constexpr int TZ = 64 * W;
     static constexpr int Q = (TZ + SMAXW) / W;
@@ -326,7 +327,7 @@ __device__ __forceinline__ void tzT_item(const DevState &s, const RunConst &rc, 
     }
 }
 
-constexpr int kTzTLds2 = 16384 / 16;
+constexpr int kTzTLds2 = 20480 / 16;
 template <int W>
 constexpr bool tzT_fits() {
     return TzShapeT<W>::Q * W * 16 + TzShapeT<W>::SMAXW * 16 <= kTzTLds2 * 16;

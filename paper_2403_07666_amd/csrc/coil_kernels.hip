@@ -104,7 +104,20 @@ __device__ __forceinline__ void field_at(const DevState &s, const CoilDev &c, in
                                          double &br, double &bz) {
     double xr = 0.0, xz = 0.0;
     const int nk = s.algo_tz ? c.nslot_tz : c.nchunk;
-    for (int k = 0; k < nk; ++k) {
+    // the slots are summed in order; their loads are issued 16 at a time so
+    // that they are in flight together
+    int k = 0;
+    for (; k + 16 <= nk; k += 16) {
+        double2 p[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) p[q] = s.part[(size_t)(k + q) * s.N + e];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            xr += p[q].x;
+            xz += p[q].y;
+        }
+    }
+    for (; k < nk; ++k) {
         const double2 p = s.part[(size_t)k * s.N + e];
         xr += p.x;
         xz += p.y;
@@ -177,12 +190,7 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
             if (lane == 0) s.wflag[w] = 1;
             return;
         }
-        const double *Mi = s.Minv + lay * n * n;
-        xv = 0.0;
-        for (int j = 0; j < n; ++j) {
-            const double bj = __shfl(b, j);
-            if (act) xv = fma(Mi[(size_t)j * n + lane], bj, xv);
-        }
+        xv = matvec_cols(s.Minv + lay * n * n, n, lane, act, b);
         yv = act ? s.yl[lay * n + lane] : 0.0;
         sy = s.syl[lay];
     } else {
@@ -197,11 +205,7 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     const double U = (sx - c.dIt) / (dt * sy);
     const double dI = act ? xv - dt * U * yv : 0.0;
     // flux update Phi += M_ww dI + dI_t Psi_u + pi r^2 dB_a
-    double mdi = 0.0;
-    for (int j = 0; j < n; ++j) {
-        const double dj = __shfl(dI, j);
-        if (act) mdi += M[j * n + lane] * dj;
-    }
+    const double mdi = matvec_cols(M, n, lane, act, dI);
     double qv = 0.0;
     if (act) {
         const double I1 = I0 + dI;
