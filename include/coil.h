@@ -262,6 +262,15 @@ int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, 
 int coil_set_tiles(coil_t *h, int32_t tile_targets, int32_t chunks, int32_t grid_limit);
 int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, int32_t *chosen);
 
+/* Segment width of the TRANSLATION evaluation: w = 0 lets the planner cut each
+   coil's rows into the widths of least estimated time (per-width throughput
+   measured on this GPU); w in [2, 8] uses segments of 64 w targets (w per
+   thread) everywhere.  Applies to the forward and the transposed pass, whether
+   or not TRANSLATION is the current evaluation; keeps the source-row split.
+   Results differ between widths only by summation order.  Drops a captured
+   graph.  COIL_E_INVAL for other w, COIL_E_STATE during capture. */
+int coil_set_widths(coil_t *h, int32_t w);
+
 /* Work of one field pass as planned: out[0] ordered (target, source) pairs,
    out[1] Green's-function evaluations (= pairs for DIRECT), out[2] the algorithm
    (enum coil_algo), out[3] work items, out[4] direct-pass targets per workgroup.

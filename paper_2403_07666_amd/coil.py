@@ -67,7 +67,7 @@ EXPORTS = [
     "coil_set_state", "coil_scalars", "coil_reset", "coil_timing", "coil_timing_read",
     "coil_graph", "coil_destroy", "coil_last_error", "coil_host_ellip", "coil_set_params",
     "coil_adjoint_query", "coil_adjoint", "coil_field_transpose", "coil_set_tiles", "coil_autotune",
-    "coil_field_stats", "coil_field_at", "coil_save", "coil_load",
+    "coil_field_stats", "coil_field_at", "coil_save", "coil_load", "coil_set_widths",
 ]
 
 _lib = None
@@ -103,6 +103,7 @@ def lib():
                                    C.c_size_t, _dp, _dp, _dp]
         L.coil_field_transpose.argtypes = [vp, vp, vp, vp, C.c_int32]
         L.coil_set_tiles.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.coil_set_widths.argtypes = [vp, C.c_int32]
         L.coil_autotune.argtypes = [vp, C.c_int32, C.c_char_p, _i32p]
         L.coil_field_stats.argtypes = [vp, _dp, C.c_int32]
         L.coil_field_at.argtypes = [vp, C.c_int64, _dp, _dp, _dp, _dp]
@@ -349,6 +350,10 @@ class Coil:
     # -------------------------------------------------------------- tiling
     def set_tiles(self, tile_targets: int, chunks: int = 0, grid_limit: int = 0) -> None:
         check(lib().coil_set_tiles(self.h, int(tile_targets), int(chunks), int(grid_limit)))
+
+    def set_widths(self, w: int) -> None:
+        """Segment width of the translation pass: 0 = automatic, 2..8 = 64 w targets everywhere."""
+        check(lib().coil_set_widths(self.h, int(w)))
 
     def autotune(self, reps: int = 3, cache_path: Optional[str] = None):
         """Time the field-pass candidates and keep the fastest; returns

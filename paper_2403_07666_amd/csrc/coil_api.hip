@@ -167,7 +167,7 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
 // per LDS read, and every width runs at the register count of the widest).
 // All widths run in one launch, widest (longest) items first; the source rows
 // are split into enough groups for about four items per LDS slot of the GPU.
-void build_tz(Plan &p, int nsplit_req) {
+void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
     static const double eff[kTzNW] = {0.37, 0.51, 0.70, 0.79, 0.89, 0.94, 1.0};
     std::vector<TzItem> by[kTzNW];
     std::vector<std::vector<int>> segw(p.coils.size());  // width index per segment
@@ -188,7 +188,11 @@ void build_tz(Plan &p, int nsplit_req) {
                 }
             }
         }
-        for (int z0 = 0; z0 < nz; z0 += 64 * (pick[nz - z0] + 2)) segw[ci].push_back(pick[nz - z0]);
+        if (force_w >= 2 && force_w <= 8) {  // one width for every segment
+            for (int z0 = 0; z0 < nz; z0 += 64 * force_w) segw[ci].push_back(force_w - 2);
+        } else {
+            for (int z0 = 0; z0 < nz; z0 += 64 * (pick[nz - z0] + 2)) segw[ci].push_back(pick[nz - z0]);
+        }
         segs += (long long)nr * (long long)segw[ci].size();
     }
     const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, 32)
@@ -286,10 +290,10 @@ int make_plan(const coil_config *c, Plan &p) {
         }
     p.items_cap = cap;
     p.nchunk_cap = pcap;
-    {
+    for (int fw : {0, 2, 3, 4, 5, 6, 7, 8}) {  // capacity for every split and forced width
         Plan q = p;
-        build_tz(q, 32);
-        p.tz_cap = q.tz_items.size();
+        build_tz(q, 32, fw);
+        p.tz_cap = std::max(p.tz_cap, q.tz_items.size());
         p.nchunk_cap = std::max(p.nchunk_cap, q.nslot_tz_max);
     }
     build_tz(p, 0);
@@ -424,7 +428,8 @@ struct coil_s {
     hipGraphExec_t gexec = nullptr;
     long long gsteps = 0;
     bool capturing = false;
-    int tz_split = 0;  // source-row groups of the translation pass (0 = automatic)
+    int tz_split = 0;    // source-row groups of the translation pass (0 = automatic)
+    int tz_force_w = 0;  // segment width of the translation pass (0 = automatic)
 };
 
 namespace {
@@ -1401,7 +1406,7 @@ std::string arch_name() {
 
 int apply_tz(coil_t *h, int nsplit) {
     Plan q = h->plan;
-    build_tz(q, nsplit);
+    build_tz(q, nsplit, h->tz_force_w);
     if (q.tz_items.size() > h->plan.tz_cap || q.nslot_tz_max > h->plan.part_slots)
         return fail(COIL_E_INVAL, "translation split %d exceeds the planned capacity", nsplit);
     HIPCHECK(hipMemcpyAsync((void *)h->tz.items, q.tz_items.data(), sizeof(TzItem) * q.tz_items.size(),
@@ -1456,6 +1461,16 @@ int apply_tiles(coil_t *h, int tb, int nch, int grid) {
     return COIL_OK;
 }
 }  // namespace
+
+extern "C" int coil_set_widths(coil_t *h, int32_t w) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (!(w == 0 || (w >= 2 && w <= 8))) return fail(COIL_E_INVAL, "w must be 0 or in [2, 8]");
+    if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
+    int rc = coil_graph(h, 0);
+    if (rc) return rc;
+    h->tz_force_w = w;
+    return apply_tz(h, h->tz_split);
+}
 
 extern "C" int coil_set_tiles(coil_t *h, int32_t tile_targets, int32_t chunks, int32_t grid_limit) {
     if (!h) return fail(COIL_E_INVAL, "handle is NULL");

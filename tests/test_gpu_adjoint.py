@@ -51,6 +51,28 @@ def test_field_transpose_dot_product(prec, tol, shape, algo):
         assert abs(gt[j] - ref) <= 10 * tol * ref_abs
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
+def test_field_transpose_every_width(prec, tol):
+    """Transposed translation pass with every forced segment width: dot-product
+    identity with the forward pass of the same width."""
+    pk = _pk()
+    w = cs.Workload(name="t", coils=[cs.Coil(2, 70, 8), cs.Coil(3, 2, 6, r_inner=0.03)], steps=1, dt=1e-4)
+    g = pk.Coil(w, precision=prec, algo="translation")
+    x = cs.random_currents(w.n_elem, seed=31)
+    yr = cs.random_currents(w.n_elem, seed=32)
+    yz = cs.random_currents(w.n_elem, seed=33)
+    for W in (2, 3, 4, 5, 6, 7, 8):
+        g.set_widths(W)
+        g.set_state(pk.F_I, x)
+        g.compute_field()
+        lhs = np.dot(g.get(pk.F_BR), yr) + np.dot(g.get(pk.F_BZ), yz)
+        gt = g.field_transpose(yr, yz)
+        rhs = np.dot(x, gt)
+        scale = np.abs(x).sum() * np.abs(gt).max() + 1e-300
+        _say("dot width", prec, W, lhs, rhs)
+        assert abs(lhs - rhs) <= tol * scale
+
+
 def _direction(w, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.standard_normal(w.n_wire), rng.standard_normal(len(w.coils)) * 10.0

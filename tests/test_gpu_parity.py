@@ -85,6 +85,44 @@ def test_field_pass_ensemble_of_coils(prec, algo):
     assert e <= TOL[prec]
 
 
+def _ragged_ensemble():
+    # turns-element counts 12, 12, 40 and 560: every width leaves a ragged
+    # last segment, and 560 spans two source chunks of every width
+    return cs.Workload(name="ens", coils=[cs.Coil(2, 3, 4, ramp=1.0), cs.Coil(3, 2, 6, r_inner=0.03, ramp=2.0),
+                                          cs.Coil(1, 5, 8, z_center=0.01, ramp=0.5),
+                                          cs.Coil(2, 70, 8, r_inner=0.021, ramp=0.7)],
+                       steps=1, dt=1e-4)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_every_segment_width(prec):
+    """Translation pass with every forced segment width W = 2..8 against the
+    oracle at every target; the widths agree with each other to summation order."""
+    pk = _pk()
+    w = _ragged_ensemble()
+    g = pk.Coil(w, precision=prec, algo="translation")
+    o = oracle.Sim(w)
+    I = cs.random_currents(w.n_elem, seed=17)
+    obr, obz = o.field_targets(I, np.arange(w.n_elem))
+    g.set_state(pk.F_I, I)
+    with pytest.raises(pk.CoilError):
+        g.set_widths(9)
+    with pytest.raises(pk.CoilError):
+        g.set_widths(1)
+    ref = None
+    for W in [0, 2, 3, 4, 5, 6, 7, 8]:
+        g.set_widths(W)
+        g.compute_field()
+        br, bz = g.get(pk.F_BR), g.get(pk.F_BZ)
+        e = max(nerr(br, obr), nerr(bz, obz))
+        _say("width", prec, W, g.field_stats()["items"], e)
+        assert e <= TOL[prec]
+        if ref is None:
+            ref = (br, bz)
+        else:
+            assert max(nerr(br, ref[0]), nerr(bz, ref[1])) <= (1e-13 if prec == "fp64" else 1e-7)
+
+
 @pytest.mark.parametrize("algo", ALGOS)
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_c1_full_run(prec, algo):
