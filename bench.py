@@ -51,7 +51,7 @@ FLOP_PER_PAIR_ACC = 4
 TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_api.hip"), "direct": ("coil_kernels.hip", "coil_api.hip")}
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
-    ("translation", "c2_medium_131k", "mixed"): ("66d71111fb7903e619d1bdd1203a2acb0e82f878", 73517270),
+    ("translation", "c2_medium_131k", "mixed"): ("e5df47a4f6474124d366961db8e31f1da50515d3", 73577947),
 }
 
 

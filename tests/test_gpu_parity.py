@@ -206,6 +206,26 @@ def test_graph_replay_matches_eager_bitwise():
     assert np.array_equal(a.get(pk.F_T), b.get(pk.F_T))
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_translation_persistent_grid_is_bitwise(prec):
+    """The translation pass on a persistent grid (fewer workgroups than items,
+    each striding over the item list) gives the one-item-per-workgroup result
+    bit for bit: every item is computed the same way wherever it runs."""
+    pk = _pk()
+    w = _ragged_ensemble()
+    I = cs.random_currents(w.n_elem, seed=5)
+    out = []
+    for grid in (0, 7, 256):
+        g = pk.Coil(w, precision=prec, algo="translation", grid_limit=grid)
+        g.set_state(pk.F_I, I)
+        g.compute_field()
+        out.append((g.get(pk.F_BR), g.get(pk.F_BZ)))
+        _say("grid", prec, grid, g.field_stats()["items"])
+        g.close()
+    for br, bz in out[1:]:
+        assert np.array_equal(br, out[0][0]) and np.array_equal(bz, out[0][1])
+
+
 def test_field_at_probes_against_oracle():
     pk = _pk()
     w = cs.Workload(name="t", coils=[cs.Coil(4, 8, 4), cs.Coil(2, 3, 6, r_inner=0.05, z_center=0.02)],
