@@ -46,21 +46,27 @@ FLOP_PER_PAIR_ACC = 4
 # profiles/), valid only for the kernel source the counters were taken on.
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 counter runs
 # (FETCH_SIZE, WRITE_SIZE) scaled by a device copy of known size.  A record
-# holds only while the sources that set the kernel's traffic (the kernel file
-# and the host code that plans its work items) are unchanged.
-TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_api.hip"), "direct": ("coil_kernels.hip", "coil_api.hip")}
+# holds only while what sets the kernel's traffic is unchanged: the kernel
+# source and the host code that plans its work items (the marked region of
+# coil_api.hip).
+TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_field_tz.h"), "direct": ("coil_kernels.hip",)}
+PLAN_BEGIN, PLAN_END = "// ---- field-pass work plans (begin)", "// ---- field-pass work plans (end)"
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
-    ("translation", "c2_medium_131k", "mixed"): ("e5df47a4f6474124d366961db8e31f1da50515d3", 73577947),
+    ("translation", "c2_medium_131k", "mixed"): ("170db2c74da77e4a88d547f330e35c0b8fb4ceed", 73577947),
 }
 
 
 def _sources_sha(algo: str) -> str:
     import hashlib
+    csrc = os.path.join(ROOT, "paper_2403_07666_amd", "csrc")
     h = hashlib.sha1()
     for name in TRAFFIC_SOURCES[algo]:
-        with open(os.path.join(ROOT, "paper_2403_07666_amd", "csrc", name), "rb") as f:
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
+    with open(os.path.join(csrc, "coil_api.hip")) as f:
+        api = f.read()
+    h.update(api[api.index(PLAN_BEGIN):api.index(PLAN_END)].encode())
     return h.hexdigest()
 
 

@@ -251,10 +251,12 @@ int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, 
    automatic, at most 16) and grid_limit = 0 for one workgroup per work item or
    > 0 for a persistent grid striding over the (coil, target block, source
    chunk) items.  Drops a captured graph.
-   coil_autotune: times every candidate over `reps` field passes on the
-   handle's current currents and keeps the fastest: TRANSLATION with 2, 4, 8 or
-   16 source-row groups per target row segment, and DIRECT with 3 tile sizes x
-   5 chunk counts x 3 grid shapes.  With cache_path it first looks the
+   coil_autotune: times the candidates over `reps` field passes on the
+   handle's current currents and keeps the fastest: TRANSLATION with 4, 8, 16 or
+   32 source-row groups per target row segment, and DIRECT with 3 tile sizes x
+   5 chunk counts x 3 grid shapes.  A candidate whose first (timed) pass is
+   over 3x the best so far is not timed further, nor is the rest of a family
+   whose first three candidates all were.  With cache_path it first looks the
    configuration up in that JSON-lines file (key: arch / precision / log2 pairs /
    coils) and appends a new choice.  chosen[4] (optional) receives (algo, p1,
    p2, p3): (2, groups, 0, 0) or (1, tile_targets, chunks, grid_limit).

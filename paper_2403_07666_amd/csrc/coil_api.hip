@@ -122,6 +122,7 @@ int validate(const coil_config *c) {
 
 constexpr int kMaxChunks = 16;
 
+// ---- field-pass work plans (begin)
 // Field-pass work items: targets in blocks of tb, sources of each coil in
 // chunks.  nch_req > 0 asks for that many chunks per coil, cs_req > 0 for a
 // chunk size; both 0: enough chunks for >= ~2048 items in total.  Chunks are
@@ -241,6 +242,7 @@ void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
     p.tz_items.clear();
     for (int k = kTzNW - 1; k >= 0; --k) p.tz_items.insert(p.tz_items.end(), by[k].begin(), by[k].end());
 }
+// ---- field-pass work plans (end)
 
 int make_plan(const coil_config *c, Plan &p) {
     p = Plan();
@@ -1541,15 +1543,31 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     for (int tb : {64, 128, 256})
         for (int ch : {1, 2, 4, 8, kMaxChunks})
             for (int g : {0, 2 * cus, 4 * cus}) cands.push_back({COIL_ALGO_DIRECT, tb, ch, g});
-    for (const Cand &cd : cands) {
-        if (apply(cd.algo, cd.a, cd.b, cd.c)) continue;  // over capacity: skip
-        HIPCHECK(launch_field_any(h, h->ds, h->stream));
-        HIPCHECK(hipEventRecord(ea, h->stream));
-        for (int r = 0; r < reps; ++r) HIPCHECK(launch_field_any(h, h->ds, h->stream));
+    // Every candidate's first launch is timed as a screen: only candidates within
+    // 3x of the best so far get the `reps` timed launches, and a family (algorithm)
+    // whose first three candidates all stay beyond 3x is not tried further.
+    int fam_tried[3] = {0, 0, 0};
+    double fam_best[3] = {INFINITY, INFINITY, INFINITY};
+    auto elapsed = [&](float *ms) -> int {
         HIPCHECK(hipEventRecord(eb, h->stream));
         HIPCHECK(hipEventSynchronize(eb));
+        HIPCHECK(hipEventElapsedTime(ms, ea, eb));
+        return COIL_OK;
+    };
+    for (const Cand &cd : cands) {
+        if (fam_tried[cd.algo] >= 3 && fam_best[cd.algo] > 3.0 * best) continue;
+        if (apply(cd.algo, cd.a, cd.b, cd.c)) continue;  // over capacity: skip
         float ms = 0.f;
-        HIPCHECK(hipEventElapsedTime(&ms, ea, eb));
+        HIPCHECK(hipEventRecord(ea, h->stream));
+        HIPCHECK(launch_field_any(h, h->ds, h->stream));
+        if ((rc = elapsed(&ms))) return rc;
+        ++fam_tried[cd.algo];
+        fam_best[cd.algo] = std::min(fam_best[cd.algo], (double)ms);
+        if (ms > 3.0 * best) continue;
+        HIPCHECK(hipEventRecord(ea, h->stream));
+        for (int r = 0; r < reps; ++r) HIPCHECK(launch_field_any(h, h->ds, h->stream));
+        if ((rc = elapsed(&ms))) return rc;
+        fam_best[cd.algo] = std::min(fam_best[cd.algo], (double)ms / reps);
         if (ms / reps < best) {
             best = ms / reps;
             ba = cd.algo; b1 = cd.a; b2 = cd.b; b3 = cd.c;
