@@ -87,6 +87,53 @@ def nerr(a, b):
     return float(np.abs(a - b).max() / s) if s > 0 else float(np.abs(a).max())
 
 
+def precision_check(pk, cs, name: str, every: int = 100, direct_steps: int = 100, steps: int = 0) -> dict:
+    """Mixed against FP64 over the configuration's whole run: B (normwise, both
+    components) and T (literal, and relative to the rise above the bath when
+    there is one) compared every `every` steps, maxima reported.  The FP64
+    reference is the translation evaluation; the first `direct_steps` are also
+    compared with the per-pair direct FP64 evaluation, an independent sum."""
+    import numpy as np
+    w = cs.workload(name)
+    inp = cs.generate(w)
+    nsteps = steps if steps > 0 else w.steps
+    gm = pk.Coil(w, inp, precision="mixed")
+    gr = pk.Coil(w, inp, precision="fp64")
+    eb = et = 0.0
+    erise = None
+    done = 0
+    while done < nsteps:
+        k = min(every, nsteps - done)
+        gm.run(k)
+        gr.run(k)
+        done += k
+        Tr = gr.get(pk.F_T)
+        Tm = gm.get(pk.F_T)
+        eb = max(eb, nerr(gm.get(pk.F_BR), gr.get(pk.F_BR)), nerr(gm.get(pk.F_BZ), gr.get(pk.F_BZ)))
+        et = max(et, nerr(Tm, Tr))
+        rise = float(Tr.max() - w.T_bath)
+        if rise > 0.0:
+            erise = max(erise or 0.0, float(np.abs(Tm - Tr).max() / rise))
+    t_peak = gr.scalars()["T_peak"]
+    gr.close()
+    gm.reset()
+    gd = pk.Coil(w, inp, precision="fp64", algo="direct")
+    gm.run(direct_steps)
+    gd.run(direct_steps)
+    ed = max(nerr(gm.get(pk.F_BR), gd.get(pk.F_BR)), nerr(gm.get(pk.F_BZ), gd.get(pk.F_BZ)))
+    etd = nerr(gm.get(pk.F_T), gd.get(pk.F_T))
+    gd.close()
+    gm.close()
+    res = {"workload": w.name, "steps": nsteps, "every": every, "rel_err_B": eb, "rel_err_T": et,
+           "rel_err_T_rise": erise, "T_peak_fp64": t_peak,
+           "vs_direct_fp64": {"steps": direct_steps, "rel_err_B": ed, "rel_err_T": etd},
+           "valid": bool(eb <= 1e-5 and et <= 1e-5 and ed <= 1e-5 and etd <= 1e-5
+                         and (erise is None or erise <= 1e-5))}
+    log(f"[bench] {w.name}: mixed vs FP64 over {nsteps} steps: B {eb:.2e} T {et:.2e} "
+        f"(rise-relative {erise}); vs direct FP64 at step {direct_steps}: B {ed:.2e} T {etd:.2e}")
+    return res
+
+
 def cpu_baseline(w, budget_s: float = 12.0) -> dict:
     """The oracle's field sum (the O(N^2) part of a step) on a bounded sample
     of targets of the same coil, all N sources, on the host cores; scaled to
@@ -106,6 +153,12 @@ def cpu_baseline(w, budget_s: float = 12.0) -> dict:
         n = min(w.n_elem, int(n * max(2.0, min(8.0, budget_s / max(dt, 1e-3) / 2))))
     pairs = n * (w.n_elem - 1)
     pps = pairs / dt
+    # and a whole run of the small configuration (500 steps at 512 elements)
+    w1 = cs.workload("c1")
+    o1 = oracle.Sim(w1, cs.generate(w1))
+    t0 = time.perf_counter()
+    o1.run(w1.steps)
+    c1_s = time.perf_counter() - t0
     return {
         "value": pps / w.pairs_per_pass(),
         "unit": "steps/s",
@@ -114,6 +167,8 @@ def cpu_baseline(w, budget_s: float = 12.0) -> dict:
         "sample": f"field sum at {n} seeded targets x {w.n_elem} sources "
                   f"({pairs:.3g} pair evaluations, {dt:.1f} s); scaled by pairs per step",
         "pairs_per_s": pps,
+        "c1_full_run_s": c1_s,
+        "c1_steps_per_s": w1.steps / c1_s,
     }
 
 
@@ -344,6 +399,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "frac_unpacked_fp32_peak": achieved / PEAK_FP32_UNPACKED,
+            "frac_packed_fp32_peak": achieved / PEAK_FP32_TFLOPS,
             "traffic": _traffic(w.name, args.precision, fs["algo"]),
             "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
             "avg_launch_ms": avg_ms,
@@ -355,22 +411,15 @@ def main():
             "phase_ms_per_step": {k: v["ms"] / max(1, args.steps) for k, v in tm.items()},
         }
 
-    check = None
+    g.close()
+    check = check_active = None
     if not args.no_check and args.precision == "mixed":
-        total = args.warmup + args.steps
-        Bm = (g.get(pk.F_BR), g.get(pk.F_BZ))
-        Tm = g.get(pk.F_T)
-        g.close()
-        log(f"[bench] FP64 reference run of {total} steps")
-        r = pk.Coil(w, inp, precision="fp64", algo="direct")
-        r.run(total)
-        eb = max(nerr(Bm[0], r.get(pk.F_BR)), nerr(Bm[1], r.get(pk.F_BZ)))
-        et = nerr(Tm, r.get(pk.F_T))
-        r.close()
-        check = {"steps": total, "rel_err_B": eb, "rel_err_T": et, "valid": bool(eb <= 1e-5 and et <= 1e-5)}
-        log(f"[bench] mixed vs FP64: B {eb:.2e} T {et:.2e}")
-    else:
-        g.close()
+        check = precision_check(pk, cs, args.workload)
+        if args.workload in ("c1", "c2", "c3", "c5"):
+            # the driven variant until shortly before its hot spot passes Tc
+            # (C2: Jc reaches 0 near step 900, which the power law reports)
+            check_active = precision_check(pk, cs, args.workload + "_active",
+                                           steps=600 if args.workload in ("c2", "c5") else 0)
 
     batched = None
     if not args.no_batched:
@@ -413,6 +462,7 @@ def main():
         },
         "ginteractions_per_s": pairs * sps / 1e9,
         "mixed_vs_fp64": check,
+        "mixed_vs_fp64_driven": check_active,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
