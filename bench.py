@@ -99,7 +99,7 @@ def precision_check(pk, cs, name: str, every: int = 100, direct_steps: int = 100
     nsteps = steps if steps > 0 else w.steps
     gm = pk.Coil(w, inp, precision="mixed")
     gr = pk.Coil(w, inp, precision="fp64")
-    eb = et = 0.0
+    eb = et = ei = ephi = eq = etp = 0.0
     erise = None
     done = 0
     while done < nsteps:
@@ -111,6 +111,12 @@ def precision_check(pk, cs, name: str, every: int = 100, direct_steps: int = 100
         Tm = gm.get(pk.F_T)
         eb = max(eb, nerr(gm.get(pk.F_BR), gr.get(pk.F_BR)), nerr(gm.get(pk.F_BZ), gr.get(pk.F_BZ)))
         et = max(et, nerr(Tm, Tr))
+        ei = max(ei, nerr(gm.get(pk.F_I), gr.get(pk.F_I)))
+        ephi = max(ephi, nerr(gm.get(pk.F_PHI), gr.get(pk.F_PHI)))
+        sm, sr = gm.scalars(), gr.scalars()
+        if sr["Q"] != 0.0:
+            eq = max(eq, abs(sm["Q"] - sr["Q"]) / abs(sr["Q"]))
+        etp = max(etp, abs(sm["T_peak"] - sr["T_peak"]) / sr["T_peak"])
         rise = float(Tr.max() - w.T_bath)
         if rise > 0.0:
             erise = max(erise or 0.0, float(np.abs(Tm - Tr).max() / rise))
@@ -126,6 +132,7 @@ def precision_check(pk, cs, name: str, every: int = 100, direct_steps: int = 100
     gm.close()
     res = {"workload": w.name, "steps": nsteps, "every": every, "rel_err_B": eb, "rel_err_T": et,
            "rel_err_T_rise": erise, "T_peak_fp64": t_peak,
+           "rel_err_other": {"I": ei, "Phi": ephi, "Q": eq, "T_peak": etp},
            "vs_direct_fp64": {"steps": direct_steps, "rel_err_B": ed, "rel_err_T": etd},
            "valid": bool(eb <= 1e-5 and et <= 1e-5 and ed <= 1e-5 and etd <= 1e-5
                          and (erise is None or erise <= 1e-5))}
@@ -332,8 +339,8 @@ def main():
                          "reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path has no multi-GPU "
-              "implementation in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the library has no multi-GPU "
+              "path (its sharding is a design note)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -28,6 +28,23 @@
 
 namespace coilq {
 
+// a x + c with the constant c as a scalar-register operand.  Left to itself
+// the compiler keeps the 44 FP64 coefficients in vector registers for the
+// whole kernel and copies one before every v_fmac_f64 of a Horner step.
+__device__ __forceinline__ double fma_sc(double a, double x, double c) {
+    double r;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(x), "s"(c));
+    return r;
+}
+
+template <int N>
+__device__ __forceinline__ double horner_sc(const double (&c)[N], double x) {
+    double a = fma_sc(x, c[0], c[1]);
+#pragma unroll
+    for (int k = 2; k < N; ++k) a = fma_sc(a, x, c[k]);
+    return a;
+}
+
 // unit-current kernel values (grid units): f g_r, f g_z as in pair64/pair32
 __device__ __forceinline__ double2 kern64(double dr, double dz, double sr) {
     const double dz2 = dz * dz;
@@ -37,8 +54,8 @@ __device__ __forceinline__ double2 kern64(double dr, double dz, double sr) {
     const double rb = rsqrt(be2);
     const double m1 = al2 * (rb * rb);
     const double L = -log(m1);
-    const double K = fma(ellipk64_Q(m1), L, ellipk64_P(m1));
-    const double E = fma(ellipe64_Q(m1), L, ellipe64_P(m1));
+    const double K = fma(horner_sc(ellipk64_Q_c, m1), L, horner_sc(ellipk64_P_c, m1));
+    const double E = fma(horner_sc(ellipe64_Q_c, m1), L, horner_sc(ellipe64_P_c, m1));
     const double f = rb / al2;
     const double alK = al2 * K;
     const double gz = fma(fma(-dr, sr, -dz2), E, alK);

@@ -6,7 +6,9 @@ Calls only oracle/ and coil_synth/.  Cost: the oracle's transport-flux pattern
 and every field pass are O(N^2) plain-C evaluations (~1.7e10 each), about ten
 minutes each on 8 cores.
 
-    python tests/golden/make_c2_prefix.py [--steps 3]
+    python tests/golden/make_c2_prefix.py [--steps 3] [--out PATH]
+
+The file is rewritten after every step, so a long run leaves a usable prefix.
 """
 import argparse
 import json
@@ -27,7 +29,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--out", default="")
     args = ap.parse_args()
+    path = args.out or os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{args.workload}_prefix.json")
     w = cs.workload(args.workload)
     inp = cs.generate(w)
     t0 = time.time()
@@ -55,11 +59,10 @@ def main():
             "Uw": s.get(oracle.UW)[wires].tolist(),
             "Q": sc["Q"], "sumU": sc["sumU"], "max_x": sc["max_x"],
         })
-        print(f"step {k + 1} {time.time() - t0:.0f} s", flush=True)
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{args.workload}_prefix.json")
-    with open(path, "w") as f:
-        json.dump(rec, f)
-    print("wrote", path)
+        with open(path + ".tmp", "w") as f:
+            json.dump(rec, f)
+        os.replace(path + ".tmp", path)
+        print(f"step {k + 1} {time.time() - t0:.0f} s, wrote {path}", flush=True)
 
 
 if __name__ == "__main__":
