@@ -55,7 +55,8 @@ struct Plan {
     std::vector<PairItem> items;
     int nchunk_max = 1;
     size_t items_cap = 0;  // work-item capacity (autotuner candidates)
-    std::vector<TzItem> tz_items;  // translation-reuse pass, grouped by W
+    std::vector<TzItem> tz_items;  // translation-reuse pass, longest items first
+    std::vector<int> tz_rows;      // per coil, its source rows in bit-reversed order
     int nslot_tz_max = 1;
     int part_slots = 2;  // capacity of part[] in double2 slots of N
     double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
@@ -67,7 +68,7 @@ struct Plan {
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
         perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
-        sc_b, tmp_b, misc_b, tz_b, Ipub_b, pub2int_b, zphys_b;
+        sc_b, tmp_b, misc_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b;
 };
 
 Buf carve(size_t &cur, size_t bytes) {
@@ -166,11 +167,33 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
 // slot of width W on this GPU (single coils of 64 layers and 64 W k
 // turns-elements, k = 2, mixed precision; the window holds 2W accumulators
 // per LDS read, and every width runs at the register count of the widest).
-// All widths run in one launch, widest (longest) items first; the source rows
-// are split into enough groups for about four items per LDS slot of the GPU.
+// The source rows of a target segment are split into n_g groups (at most 32,
+// enough for about four items per LDS slot of the GPU).  A group is a run of
+// the coil's rows in bit-reversed order, so that it samples the whole coil
+// (a like share of near rows), and the group sizes fall linearly from 4 to 1
+// relative units.  All items run in one launch, the most FMA work first, so the
+// last items dispatched are the shortest and the end of the pass, where a SIMD
+// is left with a single wave, is short.
+std::vector<int> group_sizes(int nr, int ns) {
+    std::vector<int> sz(ns, 1);
+    if (ns <= 1) {
+        sz.assign(1, nr);
+        return sz;
+    }
+    std::vector<double> wgt(ns);
+    double tot = 0.0;
+    for (int g = 0; g < ns; ++g) tot += (wgt[g] = 4.0 - 3.0 * g / (ns - 1));
+    int used = 0;
+    for (int g = 0; g < ns; ++g) used += (sz[g] = std::max(1, (int)std::floor(wgt[g] / tot * nr)));
+    for (int g = 0; used < nr; g = (g + 1) % ns, ++used) ++sz[g];  // remainder to the first groups
+    for (int g = ns - 1; used > nr; g = g > 0 ? g - 1 : ns - 1)
+        if (sz[g] > 1) --sz[g], --used;
+    return sz;
+}
+
 void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
     static const double eff[kTzNW] = {0.37, 0.51, 0.70, 0.79, 0.89, 0.94, 1.0};
-    std::vector<TzItem> by[kTzNW];
+    std::vector<TzItem> items;
     std::vector<std::vector<int>> segw(p.coils.size());  // width index per segment
     long long segs = 0;
     for (size_t ci = 0; ci < p.coils.size(); ++ci) {
@@ -200,27 +223,40 @@ void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
                                       : (int)std::max<long long>(1, std::min<long long>(32, (8192 + segs - 1) / segs));
     p.nslot_tz_max = 1;
     p.tz_evals = 0.0;
+    p.tz_rows.clear();
     for (size_t ci = 0; ci < p.coils.size(); ++ci) {
         CoilDev &d = p.coils[ci];
         const int nz = d.turns * d.ne, nr = d.layers * d.ne;
         const int ns = std::min(nsplit, nr);
         d.nslot_tz = ns;
         p.nslot_tz_max = std::max(p.nslot_tz_max, ns);
+        // rows in bit-reversed order (ties, from rows past a power of two, by row)
+        const int base = (int)p.tz_rows.size();
+        int bits = 0;
+        while ((1 << bits) < nr) ++bits;
+        std::vector<std::pair<unsigned, int>> key(nr);
+        for (int r = 0; r < nr; ++r) {
+            unsigned v = 0;
+            for (int b = 0; b < bits; ++b) v |= ((unsigned)(r >> b) & 1u) << (bits - 1 - b);
+            key[r] = {v, r};
+        }
+        std::sort(key.begin(), key.end());
+        for (const auto &kv : key) p.tz_rows.push_back(kv.second);
+        const std::vector<int> gsz = group_sizes(nr, ns);
         int z0 = 0;
         for (int wi : segw[ci]) {
             const int W = wi + 2;
             for (int ir = 0; ir < nr; ++ir)
-                for (int g = 0; g < ns; ++g) {
+                for (int g = 0, start = 0; g < ns; start += gsz[g], ++g) {
                     TzItem it{};
                     it.coil = (int)ci;
                     it.ir = ir;
                     it.z0 = z0;
-                    it.jr0 = g;  // source rows g, g + ns, g + 2 ns, ...
-                    it.jr1 = nr;
-                    it.jstep = ns;
+                    it.roff = base + start;
+                    it.rcnt = gsz[g];
                     it.slot = g;
                     it.w = W;
-                    by[wi].push_back(it);
+                    items.push_back(it);
                 }
             // kernel-value evaluations per pass: for a chunk of se sources the
             // forward table holds 64 W + se entries at delta = dlo + tau,
@@ -238,9 +274,13 @@ void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
             z0 += 64 * W;
         }
     }
-    // one launch, widest items (the longest) first
-    p.tz_items.clear();
-    for (int k = kTzNW - 1; k >= 0; --k) p.tz_items.insert(p.tz_items.end(), by[k].begin(), by[k].end());
+    // one launch, the most FMA work (targets x source rows x sources) first
+    auto work = [&](const TzItem &it) {
+        const CoilDev &d = p.coils[it.coil];
+        return (long long)it.w * it.rcnt * (long long)(d.turns * d.ne);
+    };
+    std::stable_sort(items.begin(), items.end(), [&](const TzItem &a, const TzItem &b) { return work(a) > work(b); });
+    p.tz_items = std::move(items);
 }
 // ---- field-pass work plans (end)
 
@@ -382,6 +422,7 @@ size_t layout(Plan &p) {
     p.part_slots = std::max({p.nchunk_max, p.nchunk_cap, p.nslot_tz_max, 2});
     p.part_b = carve(cur, sizeof(double2) * N * p.part_slots);
     p.tz_b = carve(cur, sizeof(TzItem) * std::max<size_t>(1, std::max(p.tz_items.size(), p.tz_cap)));
+    p.tzrows_b = carve(cur, sizeof(int) * std::max<size_t>(1, p.tz_rows.size()));
     p.Ipub_b = carve(cur, sizeof(double) * N);
     p.pub2int_b = carve(cur, sizeof(int) * N);
     p.zphys_b = carve(cur, sizeof(double) * N);
@@ -791,6 +832,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     h->Ipub = at<double>(h, p.Ipub_b);
     h->d_pub2int = at<int>(h, p.pub2int_b);
     h->tz.items = at<TzItem>(h, p.tz_b);
+    h->tz.rows = at<int>(h, p.tzrows_b);
     h->tz.n = (int)p.tz_items.size();
     s.coils = at<CoilDev>(h, p.coils_b);
     s.items = at<PairItem>(h, p.items_b);
@@ -864,6 +906,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)s.syl, syl.data(), sizeof(double) * syl.size()));
     HIPCHECK(up((void *)s.cw, cw.data(), sizeof(double) * Nw));
     HIPCHECK(up((void *)h->tz.items, p.tz_items.data(), sizeof(TzItem) * p.tz_items.size()));
+    HIPCHECK(up((void *)h->tz.rows, p.tz_rows.data(), sizeof(int) * p.tz_rows.size()));
     HIPCHECK(up((void *)h->d_pub2int, pub2int.data(), sizeof(int) * N));
     HIPCHECK(up((void *)at<double>(h, p.zphys_b), zphys.data(), sizeof(double) * N));
     // transport-flux pattern: FP64 all-pairs pass on the device
@@ -1532,7 +1575,14 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
         cus = prop.multiProcessorCount;
-    hipEvent_t ea, eb;
+    hipEvent_t ea = nullptr, eb = nullptr;
+    struct EvGuard {  // the events are released on every return path
+        hipEvent_t *a, *b;
+        ~EvGuard() {
+            if (*a) (void)hipEventDestroy(*a);
+            if (*b) (void)hipEventDestroy(*b);
+        }
+    } guard{&ea, &eb};
     HIPCHECK(hipEventCreate(&ea));
     HIPCHECK(hipEventCreate(&eb));
     double best = INFINITY;
@@ -1573,8 +1623,6 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
             ba = cd.algo; b1 = cd.a; b2 = cd.b; b3 = cd.c;
         }
     }
-    (void)hipEventDestroy(ea);
-    (void)hipEventDestroy(eb);
     g_err.clear();
     if ((rc = apply(ba, b1, b2, b3))) return rc;
     if (chosen) { chosen[0] = ba; chosen[1] = b1; chosen[2] = b2; chosen[3] = b3; }

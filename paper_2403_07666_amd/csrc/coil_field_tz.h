@@ -8,7 +8,7 @@ namespace coilq {
 
 // one target row segment [z0, z0 + 64 W) of row ir and a set of source rows
 struct TzItem {
-    int coil, ir, z0, jr0, jr1, slot, jstep, w;  // source rows jr0, jr0 + jstep, ... < jr1; width W
+    int coil, ir, z0, roff, rcnt, slot, w, pad;  // source rows rows[roff .. roff + rcnt); width W
 };
 
 // per-thread target counts W = 2 .. 8; the items of one pass are ordered
@@ -16,6 +16,7 @@ struct TzItem {
 constexpr int kTzNW = 7;
 struct TzPlan {
     const TzItem *items;
+    const int *rows;  // source-row lists the items index
     int n;
 };
 

@@ -154,8 +154,8 @@ __device__ __forceinline__ void tz_block(const double2 *gt, double2 (&ring)[W], 
 // One forward item of width W; gt and Is point into the launch's LDS buffer.
 template <int MIXED, int W>
 __device__ __forceinline__ void tz_item(const DevState &s, const RunConst &rc, const TzItem &item,
-                                        const double *__restrict__ Ipub, const int *__restrict__ pub2int,
-                                        double2 *gt, double *Is) {
+                                        const int *__restrict__ rows, const double *__restrict__ Ipub,
+                                        const int *__restrict__ pub2int, double2 *gt, double *Is) {
     using Sh = TzShape<W>;
     constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
     const int lane = threadIdx.x;
@@ -166,9 +166,10 @@ __device__ __forceinline__ void tz_item(const DevState &s, const RunConst &rc, c
         double ar[W], az[W];
 #pragma unroll
         for (int cc = 0; cc < W; ++cc) ar[cc] = az[cc] = 0.0;
-        // source rows jr0, jr0 + jstep, ... (interleaved, so that every item of
-        // a target row gets a like share of the near rows)
-        for (int jr = item.jr0; jr < item.jr1; jr += item.jstep) {
+        // the item's source rows: a run of the coil's rows in bit-reversed order,
+        // so that every item of a target row gets a like share of the near rows
+        for (int k = 0; k < item.rcnt; ++k) {
+            const int jr = rows[item.roff + k];
             const double dr = (double)(ir - jr);
             const double sr = c.c2d + (double)(ir + jr);
             const double *Irow = Ipub + c.off + (size_t)jr * nz;
@@ -229,7 +230,8 @@ constexpr bool tz_fits() {
 // workgroup branches (uniformly) on its item's width.
 template <int MIXED>
 __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
-                                                 int nitems, const double *__restrict__ Ipub,
+                                                 const int *__restrict__ rows, int nitems,
+                                                 const double *__restrict__ Ipub,
                                                  const int *__restrict__ pub2int) {
     __shared__ double2 lds[kTzLds2];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
 #define COILQ_TZ_CASE(Wv)                                                                                   \
     case Wv:                                                                                                \
         static_assert(tz_fits<Wv>(), "LDS");                                                                \
-        tz_item<MIXED, Wv>(s, rc, item, Ipub, pub2int, lds,                                                 \
+        tz_item<MIXED, Wv>(s, rc, item, rows, Ipub, pub2int, lds,                                           \
                            reinterpret_cast<double *>(lds + TzShape<Wv>::Q * Wv));                          \
         break;
         switch (item.w) {
@@ -258,7 +260,7 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
 // With d = j_z - i_z this is, for every pair of rows, the same convolution as
 // the forward pass with the kernel G(d) = g(i_r, j_r, -d) (G_r odd, G_z even,
 // so the mirror fill applies) and two weights per source.  Item fields: ir =
-// output row j_r, z0 = output segment, summed rows jr0, jr0 + jstep, ... < jr1.
+// output row j_r, z0 = output segment, summed rows rows[roff .. roff + rcnt).
 // Chunks of up to 384 summed targets keep table and weights within 20 KiB
 // (eight items per CU).
 template <int W>
@@ -285,6 +287,7 @@ __device__ __forceinline__ void tzT_block(const double2 *gt, double2 (&ring)[W],
 
 template <int MIXED, int W>
 __device__ __forceinline__ void tzT_item(const DevState &s, const RunConst &rc, const TzItem &item,
+                                         const int *__restrict__ rows,
                                          const double *__restrict__ wr_pub, const double *__restrict__ wz_pub,
                                          const int *__restrict__ pub2int, double *partT, double2 *gt,
                                          double2 *ws) {
@@ -298,7 +301,8 @@ __device__ __forceinline__ void tzT_item(const DevState &s, const RunConst &rc, 
         double acc[W];
 #pragma unroll
         for (int cc = 0; cc < W; ++cc) acc[cc] = 0.0;
-        for (int ir = item.jr0; ir < item.jr1; ir += item.jstep) {
+        for (int k = 0; k < item.rcnt; ++k) {
+            const int ir = rows[item.roff + k];
             const double dr = (double)(ir - jr);
             const double sr = c.c2d + (double)(ir + jr);
             const size_t rowoff = c.off + (size_t)ir * nz;
@@ -352,7 +356,8 @@ constexpr bool tzT_fits() {
 
 template <int MIXED>
 __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
-                                                  int nitems, const double *__restrict__ wr_pub,
+                                                  const int *__restrict__ rows, int nitems,
+                                                  const double *__restrict__ wr_pub,
                                                   const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
                                                   double *partT) {
     __shared__ double2 lds[kTzTLds2];
@@ -361,7 +366,8 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
 #define COILQ_TZT_CASE(Wv)                                                                                  \
     case Wv:                                                                                                \
         static_assert(tzT_fits<Wv>(), "LDS");                                                               \
-        tzT_item<MIXED, Wv>(s, rc, item, wr_pub, wz_pub, pub2int, partT, lds, lds + TzShapeT<Wv>::Q * Wv);  \
+        tzT_item<MIXED, Wv>(s, rc, item, rows, wr_pub, wz_pub, pub2int, partT, lds,                        \
+                            lds + TzShapeT<Wv>::Q * Wv);                                                \
         break;
         switch (item.w) {
             COILQ_TZT_CASE(8)
@@ -390,9 +396,11 @@ hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &
     if (n > 0) {
         const int grid = grid_limit > 0 ? min(grid_limit, n) : n;
         if (rc.prec == COIL_MIXED)
-            hipLaunchKernelGGL(k_field_tz<1>, dim3(grid), dim3(64), 0, st, s, rc, tp.items, n, Ipub, pub2int);
+            hipLaunchKernelGGL(k_field_tz<1>, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
+                               pub2int);
         else
-            hipLaunchKernelGGL(k_field_tz<0>, dim3(grid), dim3(64), 0, st, s, rc, tp.items, n, Ipub, pub2int);
+            hipLaunchKernelGGL(k_field_tz<0>, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
+                               pub2int);
     }
     return hipGetLastError();
 }
@@ -405,11 +413,11 @@ hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan 
     const int n = tp.n;
     if (n > 0) {
         if (rc.prec == COIL_MIXED)
-            hipLaunchKernelGGL(k_fieldT_tz<1>, dim3(n), dim3(64), 0, st, s, rc, tp.items, n, wr_pub, wz_pub,
-                               pub2int, partT);
+            hipLaunchKernelGGL(k_fieldT_tz<1>, dim3(n), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
+                               wz_pub, pub2int, partT);
         else
-            hipLaunchKernelGGL(k_fieldT_tz<0>, dim3(n), dim3(64), 0, st, s, rc, tp.items, n, wr_pub, wz_pub,
-                               pub2int, partT);
+            hipLaunchKernelGGL(k_fieldT_tz<0>, dim3(n), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
+                               wz_pub, pub2int, partT);
     }
     return hipGetLastError();
 }
