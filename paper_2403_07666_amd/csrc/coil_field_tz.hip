@@ -17,10 +17,14 @@
 //      the entries whose mirror -delta is already there (g_r odd, g_z even);
 //   2. streams the source currents through LDS and accumulates
 //      acc[c] += g(delta) * I with a W-register sliding window over delta:
-//      one LDS read of g feeds 2W FP64 FMAs.
+//      one LDS read of g feeds 2W FMAs.
 // Every pair still contributes g * I exactly once; only redundant evaluations
-// of identical kernel values are removed.  Accumulation is FP64 in both
-// precision modes (FP64 FMA runs at the non-packed FP32 rate on this GPU).
+// of identical kernel values are removed.  FP64 mode keeps the table, the
+// currents and the accumulation in FP64.  Mixed mode stores the kernel values
+// (FP32 far, FP64 near, both rounded to FP32) and the currents in FP32 and
+// runs the pair products and partial sums in FP32 (non-packed FP32 FMA issues
+// at twice the FP64 rate on this GPU), adding the partial sums of every 4W
+// sources into FP64 accumulators.
 #include <hip/hip_runtime.h>
 
 #include "coil_device.h"
@@ -97,22 +101,26 @@ __device__ __forceinline__ double2 kern(double dr, double dz, double sr, float m
 // table is copied from it with g_r negated: bitwise the value a direct
 // evaluation gives.  When the table spans a whole row pair (targets and
 // sources of one z segment) about half of the entries are copies.
-template <int MIXED, int W, int Q, bool NEG = false>
-__device__ __forceinline__ void fill_table(double2 *gt, int lane, int nt, int dlo, double dr, double sr,
+__device__ __forceinline__ void put(double2 *p, double2 v) { *p = v; }
+__device__ __forceinline__ void put(float2 *p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+
+template <int MIXED, int W, int Q, bool NEG = false, typename T2>
+__device__ __forceinline__ void fill_table(T2 *gt, int lane, int nt, int dlo, double dr, double sr,
                                            float m1_near) {
     for (int tau = lane; tau < nt; tau += 64) {
         const int delta = dlo + tau;
         const int mt = -delta - dlo;  // table index of -delta
         if (delta >= 0 || mt >= nt)
-            gt[(tau % W) * Q + tau / W] = kern<MIXED>(dr, (double)(NEG ? -delta : delta), sr, m1_near);
+            put(&gt[(tau % W) * Q + tau / W], kern<MIXED>(dr, (double)(NEG ? -delta : delta), sr, m1_near));
     }
     __syncthreads();
     for (int tau = lane; tau < nt; tau += 64) {
         const int delta = dlo + tau;
         const int mt = -delta - dlo;
         if (delta < 0 && mt < nt) {
-            const double2 v = gt[(mt % W) * Q + mt / W];
-            gt[(tau % W) * Q + tau / W] = make_double2(-v.x, v.y);
+            T2 v = gt[(mt % W) * Q + mt / W];
+            v.x = -v.x;
+            gt[(tau % W) * Q + tau / W] = v;
         }
     }
 }
@@ -218,6 +226,91 @@ __device__ __forceinline__ void tz_item(const DevState &s, const RunConst &rc, c
     }
 }
 
+template <int W, int Q>
+__device__ __forceinline__ void tz_block32(const float2 *gt, float2 (&ring)[W], float (&br)[W], float (&bz)[W],
+                                           const float (&Iv)[W], int base) {
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+        const float I = Iv[u];
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) {
+            const float2 g = ring[(cc - u + W) % W];
+            br[cc] = fmaf(g.x, I, br[cc]);
+            bz[cc] = fmaf(g.y, I, bz[cc]);
+        }
+        ring[(W - 1 - u) % W] = gt[((W - 1 - u) % W) * Q + base];
+    }
+}
+
+// Mixed precision: the kernel values (FP32 far, FP64 near, both rounded to
+// FP32), the currents and the products are FP32; every 4W sources the FP32
+// partial sums are added into FP64 accumulators.
+template <int W>
+__device__ __forceinline__ void tz_item32(const DevState &s, const RunConst &rc, const TzItem &item,
+                                          const int *__restrict__ rows, const double *__restrict__ Ipub,
+                                          const int *__restrict__ pub2int, float2 *gt, float *Is) {
+    using Sh = TzShape<W>;
+    constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
+    const int lane = threadIdx.x;
+    const CoilDev c = s.coils[item.coil];
+    const int nz = c.turns * c.ne;
+    const int ir = item.ir, z0 = item.z0;
+    double ar[W], az[W];
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) ar[cc] = az[cc] = 0.0;
+    for (int k = 0; k < item.rcnt; ++k) {
+        const int jr = rows[item.roff + k];
+        const double dr = (double)(ir - jr);
+        const double sr = c.c2d + (double)(ir + jr);
+        const double *Irow = Ipub + c.off + (size_t)jr * nz;
+        for (int s0 = 0; s0 < nz; s0 += SMAX) {
+            const int sn = min(SMAX, nz - s0);
+            const int nb = (sn + W - 1) / W;
+            const int se = nb * W;
+            const int dlo = z0 - s0 - se;
+            __syncthreads();
+            fill_table<1, W, Q>(gt, lane, TZ + se, dlo, dr, sr, rc.m1_near);
+            for (int t = lane; t < se; t += 64) Is[t] = t < sn ? (float)(c.kscale * Irow[s0 + t]) : 0.0f;
+            __syncthreads();
+            float2 ring[W];
+#pragma unroll
+            for (int cc = 0; cc < W; ++cc) ring[cc] = gt[cc * Q + lane + nb];
+            float Ia[W], Ib[W], br[W], bz[W];
+#pragma unroll
+            for (int u = 0; u < W; ++u) Ia[u] = Is[u];
+#pragma unroll
+            for (int cc = 0; cc < W; ++cc) br[cc] = bz[cc] = 0.0f;
+            for (int tb = 0; tb < nb; tb += 2) {
+                if (tb + 1 < nb) {
+#pragma unroll
+                    for (int u = 0; u < W; ++u) Ib[u] = Is[(tb + 1) * W + u];
+                }
+                tz_block32<W, Q>(gt, ring, br, bz, Ia, lane - tb + nb - 1);
+                if (tb + 1 < nb) {
+                    if (tb + 2 < nb) {
+#pragma unroll
+                        for (int u = 0; u < W; ++u) Ia[u] = Is[(tb + 2) * W + u];
+                    }
+                    tz_block32<W, Q>(gt, ring, br, bz, Ib, lane - tb + nb - 2);
+                }
+                if ((tb & 2) || tb + 2 >= nb) {  // after every 4 blocks, and at the end
+#pragma unroll
+                    for (int cc = 0; cc < W; ++cc) {
+                        ar[cc] += (double)br[cc];
+                        az[cc] += (double)bz[cc];
+                        br[cc] = bz[cc] = 0.0f;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) {
+        const int z = z0 + W * lane + cc;
+        if (z < nz) s.part[(size_t)item.slot * s.N + pub2int[c.off + ir * nz + z]] = make_double2(ar[cc], az[cc]);
+    }
+}
+
 // LDS of one item: the widest table plus its chunk of currents (W = 8: 20 KiB,
 // so eight items share the 160 KiB of a CU)
 constexpr int kTzLds2 = 20480 / 16;
@@ -233,14 +326,18 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
                                                  const int *__restrict__ rows, int nitems,
                                                  const double *__restrict__ Ipub,
                                                  const int *__restrict__ pub2int) {
-    __shared__ double2 lds[kTzLds2];
+    __shared__ double2 lds[MIXED ? kTzLds2 / 2 : kTzLds2];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TzItem item = items[it];
 #define COILQ_TZ_CASE(Wv)                                                                                   \
     case Wv:                                                                                                \
         static_assert(tz_fits<Wv>(), "LDS");                                                                \
-        tz_item<MIXED, Wv>(s, rc, item, rows, Ipub, pub2int, lds,                                           \
-                           reinterpret_cast<double *>(lds + TzShape<Wv>::Q * Wv));                          \
+        if (MIXED)                                                                                          \
+            tz_item32<Wv>(s, rc, item, rows, Ipub, pub2int, reinterpret_cast<float2 *>(lds),                \
+                          reinterpret_cast<float *>(reinterpret_cast<float2 *>(lds) + TzShape<Wv>::Q * Wv)); \
+        else                                                                                                \
+            tz_item<MIXED, Wv>(s, rc, item, rows, Ipub, pub2int, lds,                                       \
+                               reinterpret_cast<double *>(lds + TzShape<Wv>::Q * Wv));                      \
         break;
         switch (item.w) {
             COILQ_TZ_CASE(8)
@@ -348,6 +445,91 @@ __device__ __forceinline__ void tzT_item(const DevState &s, const RunConst &rc, 
     }
 }
 
+template <int W, int Q>
+__device__ __forceinline__ void tzT_block32(const float2 *gt, float2 (&ring)[W], float (&bacc)[W],
+                                            const float2 (&wv)[W], int base) {
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+#pragma unroll
+        for (int cc = 0; cc < W; ++cc) {
+            const float2 g = ring[(cc - u + W) % W];
+            bacc[cc] = fmaf(g.x, wv[u].x, fmaf(g.y, wv[u].y, bacc[cc]));
+        }
+        ring[(W - 1 - u) % W] = gt[((W - 1 - u) % W) * Q + base];
+    }
+}
+
+// Mixed precision transposed item: FP32 table, weights, products and partial
+// sums, the partial sums of every 4W sources added into FP64 accumulators.
+template <int W>
+__device__ __forceinline__ void tzT_item32(const DevState &s, const RunConst &rc, const TzItem &item,
+                                           const int *__restrict__ rows, const double *__restrict__ wr_pub,
+                                           const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
+                                           double *partT, float2 *gt, float2 *ws) {
+    using Sh = TzShapeT<W>;
+    constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
+    const int lane = threadIdx.x;
+    const CoilDev c = s.coils[item.coil];
+    const int nz = c.turns * c.ne;
+    const int jr = item.ir, z0 = item.z0;
+    double acc[W];
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) acc[cc] = 0.0;
+    for (int k = 0; k < item.rcnt; ++k) {
+        const int ir = rows[item.roff + k];
+        const double dr = (double)(ir - jr);
+        const double sr = c.c2d + (double)(ir + jr);
+        const size_t rowoff = c.off + (size_t)ir * nz;
+        for (int s0 = 0; s0 < nz; s0 += SMAX) {
+            const int sn = min(SMAX, nz - s0);
+            const int nb = (sn + W - 1) / W;
+            const int se = nb * W;
+            const int dlo = z0 - s0 - se;
+            __syncthreads();
+            fill_table<1, W, Q, true>(gt, lane, TZ + se, dlo, dr, sr, rc.m1_near);
+            for (int t = lane; t < se; t += 64)
+                ws[t] = t < sn ? make_float2((float)wr_pub[rowoff + s0 + t], (float)wz_pub[rowoff + s0 + t])
+                               : make_float2(0.0f, 0.0f);
+            __syncthreads();
+            float2 ring[W];
+#pragma unroll
+            for (int cc = 0; cc < W; ++cc) ring[cc] = gt[cc * Q + lane + nb];
+            float2 wa[W], wb[W];
+            float bacc[W];
+#pragma unroll
+            for (int u = 0; u < W; ++u) wa[u] = ws[u];
+#pragma unroll
+            for (int cc = 0; cc < W; ++cc) bacc[cc] = 0.0f;
+            for (int tb = 0; tb < nb; tb += 2) {
+                if (tb + 1 < nb) {
+#pragma unroll
+                    for (int u = 0; u < W; ++u) wb[u] = ws[(tb + 1) * W + u];
+                }
+                tzT_block32<W, Q>(gt, ring, bacc, wa, lane - tb + nb - 1);
+                if (tb + 1 < nb) {
+                    if (tb + 2 < nb) {
+#pragma unroll
+                        for (int u = 0; u < W; ++u) wa[u] = ws[(tb + 2) * W + u];
+                    }
+                    tzT_block32<W, Q>(gt, ring, bacc, wb, lane - tb + nb - 2);
+                }
+                if ((tb & 2) || tb + 2 >= nb) {  // after every 4 blocks, and at the end
+#pragma unroll
+                    for (int cc = 0; cc < W; ++cc) {
+                        acc[cc] += (double)bacc[cc];
+                        bacc[cc] = 0.0f;
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < W; ++cc) {
+        const int z = z0 + W * lane + cc;
+        if (z < nz) partT[(size_t)item.slot * s.N + pub2int[c.off + jr * nz + z]] = acc[cc];
+    }
+}
+
 constexpr int kTzTLds2 = 20480 / 16;
 template <int W>
 constexpr bool tzT_fits() {
@@ -360,14 +542,19 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
                                                   const double *__restrict__ wr_pub,
                                                   const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
                                                   double *partT) {
-    __shared__ double2 lds[kTzTLds2];
+    __shared__ double2 lds[MIXED ? kTzTLds2 / 2 : kTzTLds2];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TzItem item = items[it];
 #define COILQ_TZT_CASE(Wv)                                                                                  \
     case Wv:                                                                                                \
         static_assert(tzT_fits<Wv>(), "LDS");                                                               \
-        tzT_item<MIXED, Wv>(s, rc, item, rows, wr_pub, wz_pub, pub2int, partT, lds,                        \
-                            lds + TzShapeT<Wv>::Q * Wv);                                                \
+        if (MIXED)                                                                                          \
+            tzT_item32<Wv>(s, rc, item, rows, wr_pub, wz_pub, pub2int, partT,                              \
+                           reinterpret_cast<float2 *>(lds),                                                 \
+                           reinterpret_cast<float2 *>(lds) + TzShapeT<Wv>::Q * Wv);                         \
+        else                                                                                                \
+            tzT_item<MIXED, Wv>(s, rc, item, rows, wr_pub, wz_pub, pub2int, partT, lds,                    \
+                                lds + TzShapeT<Wv>::Q * Wv);                                                \
         break;
         switch (item.w) {
             COILQ_TZT_CASE(8)

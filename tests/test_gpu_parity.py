@@ -120,7 +120,10 @@ def test_every_segment_width(prec):
         if ref is None:
             ref = (br, bz)
         else:
-            assert max(nerr(br, ref[0]), nerr(bz, ref[1])) <= (1e-13 if prec == "fp64" else 1e-7)
+            # FP64: the same sums in the same order; mixed: FP32 partial sums
+            # over 4W sources, so the rounding depends on W (each width is
+            # within ~1e-7 of the oracle)
+            assert max(nerr(br, ref[0]), nerr(bz, ref[1])) <= (1e-13 if prec == "fp64" else 1e-6)
 
 
 @pytest.mark.parametrize("algo", ALGOS)
