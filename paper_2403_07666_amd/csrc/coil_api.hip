@@ -62,6 +62,7 @@ struct Plan {
     double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
     size_t tz_cap = 0;      // translation item capacity (32 source-row groups)
     int algo = COIL_ALGO_TRANSLATION;
+    int prec = COIL_FP64;  // arithmetic of the field passes (sets the width choice)
     int nchunk_cap = 1;    // partial-sum capacity in chunks
     size_t total = 0;
     // regions
@@ -164,9 +165,9 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
 // targets per thread) x source-row groups.  Each coil's rows are cut into the
 // segment widths that minimise the estimated time, sum over segments of
 // 64 W / eff(W), where eff(W) is the measured relative throughput per target
-// slot of width W on this GPU (single coils of 64 layers and 64 W k
-// turns-elements, k = 2, mixed precision; the window holds 2W accumulators
-// per LDS read, and every width runs at the register count of the widest).
+// slot of width W on this GPU, per precision (single coils of 64 layers and
+// 128 W turns-elements; the window holds 2W accumulators per LDS read, and
+// every width runs at the register count of the widest).
 // The source rows of a target segment are split into n_g groups (at most 32,
 // enough for about four items per LDS slot of the GPU).  A group is a run of
 // the coil's rows in bit-reversed order, so that it samples the whole coil
@@ -192,7 +193,9 @@ std::vector<int> group_sizes(int nr, int ns) {
 }
 
 void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
-    static const double eff[kTzNW] = {0.37, 0.51, 0.70, 0.79, 0.89, 0.94, 1.0};
+    static const double eff64[kTzNW] = {0.41, 0.52, 0.71, 0.78, 0.84, 0.91, 1.0};
+    static const double eff32[kTzNW] = {0.29, 0.45, 0.63, 0.74, 0.84, 0.91, 1.0};
+    const double *eff = p.prec == COIL_MIXED ? eff32 : eff64;
     std::vector<TzItem> items;
     std::vector<std::vector<int>> segw(p.coils.size());  // width index per segment
     long long segs = 0;
@@ -286,6 +289,7 @@ void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
 
 int make_plan(const coil_config *c, Plan &p) {
     p = Plan();
+    p.prec = c->precision;
     int off = 0, woff = 0, loff = 0, goff = 0;
     for (int i = 0; i < c->n_coils; ++i) {
         CoilDev d{};
