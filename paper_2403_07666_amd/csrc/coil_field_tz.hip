@@ -322,11 +322,10 @@ constexpr bool tz_fits() {
 // All widths in one launch: items are ordered widest first, and each
 // workgroup branches (uniformly) on its item's width.
 template <int MIXED>
-__global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
-                                                 const int *__restrict__ rows, int nitems,
-                                                 const double *__restrict__ Ipub,
-                                                 const int *__restrict__ pub2int) {
-    __shared__ double2 lds[MIXED ? kTzLds2 / 2 : kTzLds2];
+__device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst &rc,
+                                               const TzItem *__restrict__ items, const int *__restrict__ rows,
+                                               int nitems, const double *__restrict__ Ipub,
+                                               const int *__restrict__ pub2int, double2 *lds) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TzItem item = items[it];
 #define COILQ_TZ_CASE(Wv)                                                                                   \
@@ -350,6 +349,24 @@ __global__ __launch_bounds__(64) void k_field_tz(DevState s, RunConst rc, const 
         }
 #undef COILQ_TZ_CASE
     }
+}
+
+// Mixed precision: 10 KiB of LDS per item and at most 128 VGPRs, so four
+// waves per SIMD; the register limit spills a few values of the FP64
+// near-value evaluation, none of the FMA loop.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_field_tz32(
+    DevState s, RunConst rc, const TzItem *__restrict__ items, const int *__restrict__ rows, int nitems,
+    const double *__restrict__ Ipub, const int *__restrict__ pub2int) {
+    __shared__ double2 lds[kTzLds2 / 2];
+    field_tz_items<1>(s, rc, items, rows, nitems, Ipub, pub2int, lds);
+}
+
+__global__ __launch_bounds__(64) void k_field_tz64(DevState s, RunConst rc, const TzItem *__restrict__ items,
+                                                   const int *__restrict__ rows, int nitems,
+                                                   const double *__restrict__ Ipub,
+                                                   const int *__restrict__ pub2int) {
+    __shared__ double2 lds[kTzLds2];
+    field_tz_items<0>(s, rc, items, rows, nitems, Ipub, pub2int, lds);
 }
 
 // Transposed pass (adjoint): out(j_r, j_z) = sum over target rows i_r and
@@ -537,12 +554,11 @@ constexpr bool tzT_fits() {
 }
 
 template <int MIXED>
-__global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const TzItem *__restrict__ items,
-                                                  const int *__restrict__ rows, int nitems,
-                                                  const double *__restrict__ wr_pub,
-                                                  const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
-                                                  double *partT) {
-    __shared__ double2 lds[MIXED ? kTzTLds2 / 2 : kTzTLds2];
+__device__ __forceinline__ void fieldT_tz_items(const DevState &s, const RunConst &rc,
+                                                const TzItem *__restrict__ items, const int *__restrict__ rows,
+                                                int nitems, const double *__restrict__ wr_pub,
+                                                const double *__restrict__ wz_pub,
+                                                const int *__restrict__ pub2int, double *partT, double2 *lds) {
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const TzItem item = items[it];
 #define COILQ_TZT_CASE(Wv)                                                                                  \
@@ -569,6 +585,25 @@ __global__ __launch_bounds__(64) void k_fieldT_tz(DevState s, RunConst rc, const
     }
 }
 
+// as the forward mixed kernel: 10 KiB of LDS and at most 128 VGPRs per item
+// (four waves per SIMD, spills outside the FMA loop)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_fieldT_tz32(
+    DevState s, RunConst rc, const TzItem *__restrict__ items, const int *__restrict__ rows, int nitems,
+    const double *__restrict__ wr_pub, const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
+    double *partT) {
+    __shared__ double2 lds[kTzTLds2 / 2];
+    fieldT_tz_items<1>(s, rc, items, rows, nitems, wr_pub, wz_pub, pub2int, partT, lds);
+}
+
+__global__ __launch_bounds__(64) void k_fieldT_tz64(DevState s, RunConst rc, const TzItem *__restrict__ items,
+                                                    const int *__restrict__ rows, int nitems,
+                                                    const double *__restrict__ wr_pub,
+                                                    const double *__restrict__ wz_pub,
+                                                    const int *__restrict__ pub2int, double *partT) {
+    __shared__ double2 lds[kTzTLds2];
+    fieldT_tz_items<0>(s, rc, items, rows, nitems, wr_pub, wz_pub, pub2int, partT, lds);
+}
+
 // I in public (row-major) order for the convolution pass
 __global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub) {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -583,10 +618,10 @@ hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &
     if (n > 0) {
         const int grid = grid_limit > 0 ? min(grid_limit, n) : n;
         if (rc.prec == COIL_MIXED)
-            hipLaunchKernelGGL(k_field_tz<1>, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
+            hipLaunchKernelGGL(k_field_tz32, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
                                pub2int);
         else
-            hipLaunchKernelGGL(k_field_tz<0>, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
+            hipLaunchKernelGGL(k_field_tz64, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
                                pub2int);
     }
     return hipGetLastError();
@@ -600,10 +635,10 @@ hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan 
     const int n = tp.n;
     if (n > 0) {
         if (rc.prec == COIL_MIXED)
-            hipLaunchKernelGGL(k_fieldT_tz<1>, dim3(n), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
+            hipLaunchKernelGGL(k_fieldT_tz32, dim3(n), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
                                wz_pub, pub2int, partT);
         else
-            hipLaunchKernelGGL(k_fieldT_tz<0>, dim3(n), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
+            hipLaunchKernelGGL(k_fieldT_tz64, dim3(n), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
                                wz_pub, pub2int, partT);
     }
     return hipGetLastError();
