@@ -466,6 +466,8 @@ def main():
             "field_algo": field_stats["algo"],
         },
         "ginteractions_per_s": pairs * sps / 1e9,
+        "paper_context": "the paper reports no wall-clock or throughput figures; its C/CUDA code ran on "
+                         "GeForce RTX 4090 and RTX 3090 cards (FP64 at 1/64 of FP32)",
         "mixed_vs_fp64": check,
         "mixed_vs_fp64_driven": check_active,
         "roofline": roofline,
