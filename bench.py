@@ -40,11 +40,9 @@ PEAK_HBM_GBS = 8000.0
 FLOP_PER_EVAL = 61
 FLOP_PER_PAIR_ACC = 4
 
-# HBM bytes per launch of the field pass from the two rocprofv3 PMC runs
-# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, calibrated on a 256 MiB copy; see
-# profiles/), valid only for the kernel source the counters were taken on.
 # HBM bytes per launch of the dominant kernel, from two rocprofv3 counter runs
-# (FETCH_SIZE, WRITE_SIZE) scaled by a device copy of known size.  A record
+# (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, the factors a 256 MiB device copy
+# reads on the same counters; profiles/ holds the runs).  A record
 # holds only while what sets the kernel's traffic is unchanged: the kernel
 # source and the host code that plans its work items (the marked region of
 # coil_api.hip).
@@ -52,7 +50,7 @@ TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_field_tz.h"), "dir
 PLAN_BEGIN, PLAN_END = "// ---- field-pass work plans (begin)", "// ---- field-pass work plans (end)"
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
-    ("translation", "c2_medium_131k", "mixed"): ("170db2c74da77e4a88d547f330e35c0b8fb4ceed", 73577947),
+    ("translation", "c2_medium_131k", "mixed"): ("3ea8d16ee4845cec6d0968a8200adf2086d3c88d", 133126015),
 }
 
 
