@@ -23,7 +23,7 @@
 // currents and the accumulation in FP64.  Mixed mode stores the kernel values
 // (FP32 far, FP64 near, both rounded to FP32) and the currents in FP32 and
 // runs the pair products and partial sums in FP32 (non-packed FP32 FMA issues
-// at twice the FP64 rate on this GPU), adding the partial sums of every 8W
+// at twice the FP64 rate on this GPU), adding the partial sums of every 16W
 // sources into FP64 accumulators.
 #include <hip/hip_runtime.h>
 
@@ -262,7 +262,7 @@ __device__ __forceinline__ void tz_block32(const float2 *gt, float2 (&ring)[W], 
 }
 
 // Mixed precision: the kernel values (FP32 far, FP64 near, both rounded to
-// FP32), the currents and the products are FP32; every 8W sources the FP32
+// FP32), the currents and the products are FP32; every 16W sources the FP32
 // partial sums are added into FP64 accumulators.
 template <int W>
 __device__ __forceinline__ void tz_item32(const DevState &s, const RunConst &rc, const TzItem &item,
@@ -313,7 +313,7 @@ __device__ __forceinline__ void tz_item32(const DevState &s, const RunConst &rc,
                     }
                     tz_block32<W, Q>(gt, ring, br, bz, Ib, lane - tb + nb - 2);
                 }
-                if ((tb & 6) == 6 || tb + 2 >= nb) {  // after every 8 blocks, and at the end
+                if ((tb & 14) == 14 || tb + 2 >= nb) {  // after every 16 blocks, and at the end
 #pragma unroll
                     for (int cc = 0; cc < W; ++cc) {
                         ar[cc] += (double)br[cc];
@@ -498,7 +498,7 @@ __device__ __forceinline__ void tzT_block32(const float2 *gt, float2 (&ring)[W],
 }
 
 // Mixed precision transposed item: FP32 table, weights, products and partial
-// sums, the partial sums of every 8W sources added into FP64 accumulators.
+// sums, the partial sums of every 16W sources added into FP64 accumulators.
 template <int W>
 __device__ __forceinline__ void tzT_item32(const DevState &s, const RunConst &rc, const TzItem &item,
                                            const int *__restrict__ rows, const double *__restrict__ wr_pub,
@@ -552,7 +552,7 @@ __device__ __forceinline__ void tzT_item32(const DevState &s, const RunConst &rc
                     }
                     tzT_block32<W, Q>(gt, ring, bacc, wb, lane - tb + nb - 2);
                 }
-                if ((tb & 6) == 6 || tb + 2 >= nb) {  // after every 8 blocks, and at the end
+                if ((tb & 14) == 14 || tb + 2 >= nb) {  // after every 16 blocks, and at the end
 #pragma unroll
                     for (int cc = 0; cc < W; ++cc) {
                         acc[cc] += (double)bacc[cc];
