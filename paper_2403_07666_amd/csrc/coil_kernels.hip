@@ -204,14 +204,18 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     const double sx = wave_sum(act ? xv : 0.0);
     const double U = (sx - c.dIt) / (dt * sy);
     const double dI = act ? xv - dt * U * yv : 0.0;
-    // flux update Phi += M_ww dI + dI_t Psi_u + pi r^2 dB_a
-    const double mdi = matvec_cols(M, n, lane, act, dI);
     double qv = 0.0;
     if (act) {
         const double I1 = I0 + dI;
         const double Elin = lo.E + lo.Ep * dI / d2;
         qv = Elin * (I1 / d2);
-        s.Phi[e] += mdi + c.dIt * s.psi[e] + kPi * re * re * dBa;
+        // flux update Phi += M_ww dI + dI_t Psi_u + pi r^2 dB_a.  The solved
+        // system A dI = b - dt U 1 (A = M_ww in the fast path, M_ww plus the
+        // diagonal otherwise) gives M_ww dI = b - dt U - (A - M_ww) dI, so the
+        // update is the circuit equation itself, without a second product:
+        // -dt (2 pi r E + U), with E linearised at I + dI when the diagonal
+        // entered the solve.
+        s.Phi[e] += -dt * (2.0 * kPi * re * (FAST ? lo.E : Elin) + U);
         s.I[e] = I1;
         s.dI[e] = dI;
         s.E[e] = lo.E;
