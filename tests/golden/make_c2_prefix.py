@@ -3,10 +3,10 @@
 seeded sampled elements and wires.
 
 Calls only oracle/ and coil_synth/.  Cost: the oracle's transport-flux pattern
-and every field pass are O(N^2) plain-C evaluations (~1.7e10 each), about ten
-minutes each on 8 cores.
+and every field pass are O(N^2) plain-C evaluations (~1.7e10 each), about 7.5
+minutes each on 8 cores (the stored 20 steps took about 2.5 hours).
 
-    python tests/golden/make_c2_prefix.py [--steps 3] [--out PATH]
+    python tests/golden/make_c2_prefix.py [--steps 20] [--out PATH]
 
 The file is rewritten after every step, so a long run leaves a usable prefix.
 """
@@ -27,7 +27,7 @@ import oracle  # noqa: E402
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
