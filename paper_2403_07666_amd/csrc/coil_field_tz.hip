@@ -27,6 +27,8 @@
 // sources into FP64 accumulators.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "coil_device.h"
 #include "coil_field_tz.h"
 
@@ -67,7 +69,7 @@ __device__ __forceinline__ double2 kern64(double dr, double dz, double sr) {
     return make_double2(f * gr, f * gz);
 }
 
-__device__ __forceinline__ double2 kern32(float dr, float dz, float sr) {
+__device__ __forceinline__ float2 kern32(float dr, float dz, float sr) {
     const float dz2 = dz * dz;
     const float al2 = fmaf(dr, dr, dz2);
     const float be2 = fmaf(sr, sr, dz2);
@@ -80,18 +82,22 @@ __device__ __forceinline__ double2 kern32(float dr, float dz, float sr) {
     const float alK = al2 * K;
     const float gz = fmaf(fmaf(-dr, sr, -dz2), E, alK);
     const float gr = dz * fmaf(0.5f * (al2 + be2), E, -alK);
-    return make_double2((double)(f * gr), (double)(f * gz));
+    return make_float2(f * gr, f * gz);
 }
 
-template <int MIXED>
-__device__ __forceinline__ double2 kern(double dr, double dz, double sr, float m1_near) {
-    if (MIXED) {
-        // the argument m1 = al2 / be2 decides in FP64 whether the value is near
-        const double al2 = dr * dr + dz * dz;
-        const double be2 = sr * sr + dz * dz;
-        if (al2 >= (double)m1_near * be2) return kern32((float)dr, (float)dz, (float)sr);
-    }
-    return kern64(dr, dz, sr);
+// Mixed precision evaluates g in FP64 where m1 = al2 / be2 < m1_near (k near
+// 1) and in FP32 elsewhere.  For one pair of rows (dr, sr fixed) m1 grows with
+// delta^2, so the near values are those with
+//   delta^2 < (m1_near sr^2 - dr^2) / (1 - m1_near),
+// and the choice is an integer comparison per entry against this bound taken
+// once per row pair (0: no near values).  It depends on delta^2 only, so an
+// entry and its mirror -delta fall on the same side.
+__device__ __forceinline__ int near_bound(double dr, double sr, float m1_near) {
+    const double m = m1_near;
+    if (!(m > 0.0)) return 0;
+    if (!(m < 1.0)) return INT_MAX;
+    const double t = (m * sr * sr - dr * dr) / (1.0 - m);
+    return t <= 0.0 ? 0 : t >= 2147483647.0 ? INT_MAX : (int)ceil(t);
 }
 
 // Table of kernel values g(delta) for delta = dlo + tau, tau in [0, nt),
@@ -103,15 +109,25 @@ __device__ __forceinline__ double2 kern(double dr, double dz, double sr, float m
 // sources of one z segment) about half of the entries are copies.
 __device__ __forceinline__ void put(double2 *p, double2 v) { *p = v; }
 __device__ __forceinline__ void put(float2 *p, double2 v) { *p = make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ void put(double2 *p, float2 v) { *p = make_double2(v.x, v.y); }
+__device__ __forceinline__ void put(float2 *p, float2 v) { *p = v; }
 
 template <int MIXED, int W, int Q, bool NEG = false, typename T2>
 __device__ __forceinline__ void fill_table(T2 *gt, int lane, int nt, int dlo, double dr, double sr,
                                            float m1_near) {
+    const int d2near = MIXED ? near_bound(dr, sr, m1_near) : 0;
+    const float drf = (float)dr, srf = (float)sr;
     for (int tau = lane; tau < nt; tau += 64) {
         const int delta = dlo + tau;
         const int mt = -delta - dlo;  // table index of -delta
-        if (delta >= 0 || mt >= nt)
-            put(&gt[(tau % W) * Q + tau / W], kern<MIXED>(dr, (double)(NEG ? -delta : delta), sr, m1_near));
+        if (delta >= 0 || mt >= nt) {
+            const int dz = NEG ? -delta : delta;
+            T2 *p = &gt[(tau % W) * Q + tau / W];
+            if (MIXED && dz * dz >= d2near)  // |dz| < 4096 (rows of at most 2048 elements)
+                put(p, kern32(drf, (float)dz, srf));
+            else
+                put(p, kern64(dr, (double)dz, sr));
+        }
     }
     __syncthreads();
     for (int tau = lane; tau < nt; tau += 64) {
