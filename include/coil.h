@@ -197,8 +197,12 @@ int coil_save(coil_t *h, void *host_buf, size_t bytes, size_t *needed);
 int coil_load(coil_t *h, const void *host_buf, size_t bytes);
 
 /* Kernel timing with HIP events on the handle's stream.  enable = 1 starts
-   recording (clears totals), 0 stops.  coil_timing_read synchronises and
-   returns per-phase totals: ms[p] and launches[p] for p = 0 field pass,
+   recording every phase, 2 only phase 0 (two events per step instead of
+   eight, for timing runs that should stay close to untimed ones); either
+   clears the totals.  0 stops; other values give COIL_E_INVAL.
+   coil_timing_read synchronises and returns per-phase totals: ms[p] and
+   launches[p] for p = 0 field pass (the all-pairs kernel alone; the
+   translation evaluation's reordering of the currents runs before it),
    1 local law + wire solve, 2 heat substeps, 3 reductions (n >= 4). */
 int coil_timing(coil_t *h, int32_t enable);
 int coil_timing_read(coil_t *h, double *ms, int64_t *launches, int32_t n);

@@ -286,8 +286,10 @@ class Coil:
         return dict(zip(keys, v.tolist()))
 
     # -------------------------------------------------------------- timing
-    def timing(self, enable: bool) -> None:
-        check(lib().coil_timing(self.h, 1 if enable else 0))
+    def timing(self, enable) -> None:
+        """True / 1: time every phase; 2: only the field kernel; False / 0: stop."""
+        mode = int(enable) if not isinstance(enable, bool) else (1 if enable else 0)
+        check(lib().coil_timing(self.h, mode))
 
     def timing_read(self) -> dict:
         ms = np.zeros(4, dtype=np.float64)

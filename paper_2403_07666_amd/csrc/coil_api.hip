@@ -462,6 +462,7 @@ struct coil_s {
     int *d_pub2int = nullptr;
     // timing
     bool timing = false;
+    bool timing_all = false;  // all phases, or only the field kernel
     struct Pending {
         int phase;
         hipEvent_t a, b;
@@ -496,8 +497,8 @@ int ev_get(coil_t *h, hipEvent_t *e) {
     return COIL_OK;
 }
 
-int t_begin(coil_t *h, hipEvent_t *a) {
-    if (!h->timing) return COIL_OK;
+int t_begin(coil_t *h, hipEvent_t *a, int phase) {
+    if (!h->timing || (phase != 0 && !h->timing_all)) return COIL_OK;
     int rc = ev_get(h, a);
     if (rc) return rc;
     HIPCHECK(hipEventRecord(*a, h->stream));
@@ -505,7 +506,7 @@ int t_begin(coil_t *h, hipEvent_t *a) {
 }
 
 int t_end(coil_t *h, int phase, hipEvent_t a, int nlaunch) {
-    if (!h->timing) return COIL_OK;
+    if (!h->timing || (phase != 0 && !h->timing_all)) return COIL_OK;
     hipEvent_t b;
     int rc = ev_get(h, &b);
     if (rc) return rc;
@@ -546,16 +547,22 @@ hipError_t launch_field_any(coil_t *h, const DevState &d, hipStream_t st) {
 int enqueue_step(coil_t *h) {
     hipEvent_t a = nullptr;
     int rc;
-    if ((rc = t_begin(h, &a))) return rc;
-    HIPCHECK(launch_field_any(h, h->ds, h->stream));
+    // phase 0 brackets the field kernel alone (its input reordering runs before)
+    const DevState &d = h->ds;
+    if (d.algo_tz) HIPCHECK(launch_field_tz_prep(d, h->Ipub, h->stream));
+    if ((rc = t_begin(h, &a, 0))) return rc;
+    if (d.algo_tz)
+        HIPCHECK(launch_field_tz_kernel(d, h->rc, h->tz, h->Ipub, h->d_pub2int, 0, h->stream));
+    else
+        HIPCHECK(launch_field(d, h->rc, h->grid_limit, h->stream));
     if ((rc = t_end(h, 0, a, 1))) return rc;
-    if ((rc = t_begin(h, &a))) return rc;
+    if ((rc = t_begin(h, &a, 1))) return rc;
     HIPCHECK(launch_wire(h->ds, h->rc, h->stream));
     if ((rc = t_end(h, 1, a, 1))) return rc;
-    if ((rc = t_begin(h, &a))) return rc;
+    if ((rc = t_begin(h, &a, 2))) return rc;
     for (int sub = 0; sub < h->ds.nsub; ++sub) HIPCHECK(launch_heat(h->ds, h->rc, sub, h->stream));
     if ((rc = t_end(h, 2, a, h->ds.nsub))) return rc;
-    if ((rc = t_begin(h, &a))) return rc;
+    if ((rc = t_begin(h, &a, 3))) return rc;
     HIPCHECK(launch_finalize(h->ds, h->rc, h->stream));
     if ((rc = t_end(h, 3, a, 1))) return rc;
     if (h->timing && h->pending.size() > 16384) return t_flush(h);
@@ -1115,9 +1122,11 @@ extern "C" int coil_reset(coil_t *h) {
 extern "C" int coil_timing(coil_t *h, int32_t enable) {
     if (!h) return fail(COIL_E_INVAL, "handle is NULL");
     if (h->capturing) return fail(COIL_E_STATE, "timing cannot change during graph capture");
+    if (enable < 0 || enable > 2) return fail(COIL_E_INVAL, "enable must be 0, 1 or 2");
     int rc = t_flush(h);
     if (rc) return rc;
     h->timing = enable != 0;
+    h->timing_all = enable == 1;
     if (h->timing)
         for (int i = 0; i < 4; ++i) {
             h->ms[i] = 0.0;

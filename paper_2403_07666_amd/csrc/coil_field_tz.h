@@ -20,8 +20,13 @@ struct TzPlan {
     int n;
 };
 
+// forward pass: the currents in public order (prep), then the field kernel;
+// launch_field_tz issues both
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                            const int *pub2int, int grid_limit, hipStream_t st);
+hipError_t launch_field_tz_prep(const DevState &s, double *Ipub, hipStream_t st);
+hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
+                                  const int *pub2int, int grid_limit, hipStream_t st);
 
 // transposed pass: partT[slot][j] for the weights (wr, wz) in internal order;
 // wr_pub / wz_pub are N-element staging buffers

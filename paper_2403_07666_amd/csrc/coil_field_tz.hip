@@ -648,10 +648,20 @@ __global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub) 
     if (i < n) Ipub[perm[i]] = I[i];
 }
 
+hipError_t launch_field_tz_prep(const DevState &s, double *Ipub, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N, Ipub);
+    return hipGetLastError();
+}
+
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                            const int *pub2int, int grid_limit, hipStream_t st) {
-    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N,
-                       const_cast<double *>(Ipub));
+    hipError_t e = launch_field_tz_prep(s, const_cast<double *>(Ipub), st);
+    if (e != hipSuccess) return e;
+    return launch_field_tz_kernel(s, rc, tp, Ipub, pub2int, grid_limit, st);
+}
+
+hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
+                                  const int *pub2int, int grid_limit, hipStream_t st) {
     const int n = tp.n;
     if (n > 0) {
         const int grid = grid_limit > 0 ? min(grid_limit, n) : n;

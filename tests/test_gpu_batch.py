@@ -150,3 +150,30 @@ def test_c4_ensemble_full_size():
         g.close()
     for a, b in zip(runs["mixed"], runs["fp64"]):
         assert nerr(a, b) <= 1e-5
+
+
+def test_timing_modes():
+    """Event timing: mode 1 times every phase, mode 2 only the field kernel;
+    neither changes the results; other modes are rejected."""
+    pk = _pk()
+    w = _ensemble()
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision="mixed")
+    g.run(5)
+    ref = g.get(pk.F_I)
+    g.reset()
+    g.timing(1)
+    g.run(3)
+    t1 = g.timing_read()
+    g.timing(2)
+    g.run(2)
+    t2 = g.timing_read()
+    g.timing(0)
+    assert np.array_equal(g.get(pk.F_I), ref)
+    assert [t1[k]["launches"] for k in ("field", "wire", "heat", "reduce")] == [3, 3, 3 * g.n_sub, 3]
+    assert all(t1[k]["ms"] > 0 for k in t1)
+    assert t2["field"]["launches"] == 2 and t2["field"]["ms"] > 0
+    assert all(t2[k]["launches"] == 0 and t2[k]["ms"] == 0 for k in ("wire", "heat", "reduce"))
+    with pytest.raises(pk.CoilError):
+        g.timing(3)
+    g.close()
