@@ -256,8 +256,8 @@ int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, 
    > 0 for a persistent grid striding over the (coil, target block, source
    chunk) items.  Drops a captured graph.
    coil_autotune: times the candidates over `reps` field passes on the
-   handle's current currents and keeps the fastest: TRANSLATION with 4, 8, 16 or
-   32 source-row groups per target row segment, and DIRECT with 3 tile sizes x
+   handle's current currents and keeps the fastest: TRANSLATION with 4, 8, 16, 32
+   or 64 source-row groups per target row segment, and DIRECT with 3 tile sizes x
    5 chunk counts x 3 grid shapes.  A candidate whose first (timed) pass is
    over 3x the best so far is not timed further, nor is the rest of a family
    whose first three candidates all were.  With cache_path it first looks the

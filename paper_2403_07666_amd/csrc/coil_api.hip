@@ -60,7 +60,7 @@ struct Plan {
     int nslot_tz_max = 1;
     int part_slots = 2;  // capacity of part[] in double2 slots of N
     double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
-    size_t tz_cap = 0;      // translation item capacity (32 source-row groups)
+    size_t tz_cap = 0;      // translation item capacity (kTzMaxSplit source-row groups)
     int algo = COIL_ALGO_TRANSLATION;
     int prec = COIL_FP64;  // arithmetic of the field passes (sets the width choice)
     int nchunk_cap = 1;    // partial-sum capacity in chunks
@@ -168,13 +168,18 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
 // slot of width W on this GPU, per precision (single coils of 64 layers and
 // 128 W turns-elements; the window holds 2W accumulators per LDS read, and
 // every width runs at the register count of the widest).
-// The source rows of a target segment are split into n_g groups (at most 32,
-// enough for about four items per LDS slot of the GPU).  A group is a run of
+// The source rows of a target segment are split into n_g groups: enough for
+// about 8192 items (four or more per LDS slot of the GPU), and more for large
+// coils, so that an item holds at most about 4e6 pairs (the end of the pass,
+// where SIMDs run out of items at different times, scales with the item);
+// at most kTzMaxSplit.  A group is a run of
 // the coil's rows in bit-reversed order, so that it samples the whole coil
 // (a like share of near rows), and the group sizes fall linearly from 4 to 1
 // relative units.  All items run in one launch, the most FMA work first, so the
 // last items dispatched are the shortest and the end of the pass, where a SIMD
 // is left with a single wave, is short.
+constexpr int kTzMaxSplit = 64;
+
 std::vector<int> group_sizes(int nr, int ns) {
     std::vector<int> sz(ns, 1);
     if (ns <= 1) {
@@ -222,8 +227,12 @@ void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
         }
         segs += (long long)nr * (long long)segw[ci].size();
     }
-    const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, 32)
-                                      : (int)std::max<long long>(1, std::min<long long>(32, (8192 + segs - 1) / segs));
+    double pairs = 0.0;
+    for (const CoilDev &d : p.coils) pairs += (double)d.n * (double)(d.n - 1);
+    const long long by_count = (8192 + segs - 1) / segs;
+    const long long by_size = (long long)std::ceil(pairs / ((double)segs * 4e6));
+    const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, kTzMaxSplit)
+                                      : (int)std::max<long long>(1, std::min<long long>(kTzMaxSplit, std::max(by_count, by_size)));
     p.nslot_tz_max = 1;
     p.tz_evals = 0.0;
     p.tz_rows.clear();
@@ -338,7 +347,7 @@ int make_plan(const coil_config *c, Plan &p) {
     p.nchunk_cap = pcap;
     for (int fw : {0, 2, 3, 4, 5, 6, 7, 8}) {  // capacity for every split and forced width
         Plan q = p;
-        build_tz(q, 32, fw);
+        build_tz(q, kTzMaxSplit, fw);
         p.tz_cap = std::max(p.tz_cap, q.tz_items.size());
         p.nchunk_cap = std::max(p.nchunk_cap, q.nslot_tz_max);
     }
@@ -1602,7 +1611,7 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     int ba = h->plan.algo, b1 = 0, b2 = 0, b3 = 0;
     struct Cand { int algo, a, b, c; };
     std::vector<Cand> cands;
-    for (int sp : {4, 8, 16, 32}) cands.push_back({COIL_ALGO_TRANSLATION, sp, 0, 0});
+    for (int sp : {4, 8, 16, 32, 64}) cands.push_back({COIL_ALGO_TRANSLATION, sp, 0, 0});
     for (int tb : {64, 128, 256})
         for (int ch : {1, 2, 4, 8, kMaxChunks})
             for (int g : {0, 2 * cus, 4 * cus}) cands.push_back({COIL_ALGO_DIRECT, tb, ch, g});
