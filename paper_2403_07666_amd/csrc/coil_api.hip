@@ -61,6 +61,8 @@ struct Plan {
     int part_slots = 2;  // capacity of part[] in double2 slots of N
     double tz_evals = 0.0;  // kernel-value evaluations of one translation-reuse pass
     size_t tz_cap = 0;      // translation item capacity (kTzMaxSplit source-row groups)
+    std::vector<int2> near_pair;  // mixed mode: per coil, per (target row, source row): (first, count)
+    size_t near_total = 0;        // near kernel values over all pairs
     int algo = COIL_ALGO_TRANSLATION;
     int prec = COIL_FP64;  // arithmetic of the field passes (sets the width choice)
     int nchunk_cap = 1;    // partial-sum capacity in chunks
@@ -69,7 +71,7 @@ struct Plan {
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
         perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
-        sc_b, tmp_b, misc_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b;
+        sc_b, tmp_b, misc_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b;
 };
 
 Buf carve(size_t &cur, size_t bytes) {
@@ -180,6 +182,43 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
 // is left with a single wave, is short.
 constexpr int kTzMaxSplit = 64;
 
+// m1 below which the mixed field passes evaluate the kernel in FP64 (k near 1)
+float m1_near_of(const coil_config *c) {
+    const double nk = c->near_k > 0.0 ? c->near_k : 0.99;
+    return (float)(1.0 - nk * nk);
+}
+
+// Near kernel values of the mixed translation pass.  For a pair of rows
+// (a, b) of a coil, m1 = al2 / be2 grows with delta^2, so m1 < m1_near holds
+// exactly for delta^2 < (m1_near sr^2 - dr^2) / (1 - m1_near) (dr = a - b,
+// sr = c2d + a + b): |delta| < count.  count is capped at the largest |delta|
+// any table of the coil can hold (n_z + 1024).
+void build_near(Plan &p, float m1_near) {
+    p.near_pair.clear();
+    p.near_total = 0;
+    for (CoilDev &d : p.coils) {
+        d.near_base = (int)p.near_pair.size();
+        if (p.prec != COIL_MIXED) continue;
+        const int nr = d.layers * d.ne, nz = d.turns * d.ne;
+        const double m = m1_near;
+        const long long amax = (long long)nz + 1024;
+        for (int a = 0; a < nr; ++a)
+            for (int b = 0; b < nr; ++b) {
+                const double dr = (double)(a - b), sr = d.c2d + (double)(a + b);
+                const double t = (m * sr * sr - dr * dr) / (1.0 - m);
+                long long cnt = 0;
+                if (t > 0.0) {
+                    long long r = (long long)std::sqrt(t);  // largest r with r^2 < t
+                    while (r > 0 && (double)(r * r) >= t) --r;
+                    while ((double)((r + 1) * (r + 1)) < t) ++r;
+                    cnt = std::min(r, amax) + 1;
+                }
+                p.near_pair.push_back(make_int2((int)p.near_total, (int)cnt));
+                p.near_total += (size_t)cnt;
+            }
+    }
+}
+
 std::vector<int> group_sizes(int nr, int ns) {
     std::vector<int> sz(ns, 1);
     if (ns <= 1) {
@@ -282,6 +321,18 @@ void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
                 const long long pos = std::max(0, nt - std::max(0, -dlo));
                 const long long neg_far = std::max(0, std::min(-dlo, -2 * dlo - nt + 1));
                 p.tz_evals += (double)nr * (double)nr * (double)(pos + std::max(0LL, std::min(neg_far, (long long)nt)));
+                if (p.prec == COIL_MIXED && !p.near_pair.empty()) {
+                    // near entries come from the set-up table: not evaluated per pass
+                    const long long p0 = std::max(dlo, 0), p1 = (long long)dlo + nt;  // delta >= 0 evaluated
+                    const long long q0 = std::max(1LL, (long long)dlo + nt), q1 = -(long long)dlo;  // |delta| of negatives
+                    long long look = 0;
+                    for (int pr = 0; pr < nr * nr; ++pr) {
+                        const long long cnt = p.near_pair[d.near_base + pr].y;
+                        look += std::max(0LL, std::min(p1, cnt) - p0);
+                        look += std::max(0LL, std::min(q1, cnt - 1) - q0 + 1);
+                    }
+                    p.tz_evals -= (double)look;
+                }
             }
             z0 += 64 * W;
         }
@@ -331,6 +382,7 @@ int make_plan(const coil_config *c, Plan &p) {
     p.nheat_blocks = (p.N + 255) / 256;
     int tb = c->tile_targets;
     if (tb == 0) tb = p.N <= 8192 ? 64 : 256;
+    build_near(p, m1_near_of(c));
     build_items(p, tb, 0, c->tile_sources);
     // capacity for the autotuner's candidates: targets per item >= 64 and at
     // most kMaxChunks source chunks per coil
@@ -439,6 +491,8 @@ size_t layout(Plan &p) {
     p.Ipub_b = carve(cur, sizeof(double) * N);
     p.pub2int_b = carve(cur, sizeof(int) * N);
     p.zphys_b = carve(cur, sizeof(double) * N);
+    p.near_pair_b = carve(cur, sizeof(int2) * std::max<size_t>(1, p.near_pair.size()));
+    p.near_val_b = carve(cur, sizeof(float2) * std::max<size_t>(1, p.near_total));
     p.Uw_b = carve(cur, d8 * Nw);
     p.Qw_b = carve(cur, d8 * Nw);
     p.wq_b = carve(cur, d8 * Nw);
@@ -664,8 +718,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     r.u_a1 = p1 / (cfg->C0 * cfg->T_ref);
     r.u_a0 = std::pow(cfg->T_bath / cfg->T_ref, p1);
     r.u_inv = 1.0 / p1;
-    const double nk = cfg->near_k > 0.0 ? cfg->near_k : 0.99;
-    r.m1_near = (float)(1.0 - nk * nk);
+    r.m1_near = m1_near_of(cfg);
     r.prec = cfg->precision;
 
     // host precompute, internal (wire-major) order
@@ -890,6 +943,8 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
         s.T[i] = at<double>(h, p.T_b[i]);
     }
     s.part = at<double2>(h, p.part_b);
+    s.near_pair = at<int2>(h, p.near_pair_b);
+    s.near_val = at<float2>(h, p.near_val_b);
     s.Uw = at<double>(h, p.Uw_b);
     s.Qw = at<double>(h, p.Qw_b);
     s.wq = at<double>(h, p.wq_b);
@@ -929,6 +984,10 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)h->tz.rows, p.tz_rows.data(), sizeof(int) * p.tz_rows.size()));
     HIPCHECK(up((void *)h->d_pub2int, pub2int.data(), sizeof(int) * N));
     HIPCHECK(up((void *)at<double>(h, p.zphys_b), zphys.data(), sizeof(double) * N));
+    HIPCHECK(up((void *)s.near_pair, p.near_pair.data(), sizeof(int2) * p.near_pair.size()));
+    if (p.prec == COIL_MIXED)
+        for (size_t ci = 0; ci < p.coils.size(); ++ci)
+            HIPCHECK(launch_near_fill(s, (int)ci, p.coils[ci].layers * p.coils[ci].ne, st));
     // transport-flux pattern: FP64 all-pairs pass on the device
     HIPCHECK(launch_psi(s, const_cast<double *>(s.psi), st));
     if ((rc = reset_state(h))) return rc;

@@ -25,6 +25,8 @@ struct TzPlan {
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                            const int *pub2int, int grid_limit, hipStream_t st);
 hipError_t launch_field_tz_prep(const DevState &s, double *Ipub, hipStream_t st);
+// the near kernel values of coil `coil` (rows nr), into s.near_val
+hipError_t launch_near_fill(const DevState &s, int coil, int nr, hipStream_t st);
 hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                                   const int *pub2int, int grid_limit, hipStream_t st);
 

@@ -85,21 +85,6 @@ __device__ __forceinline__ float2 kern32(float dr, float dz, float sr) {
     return make_float2(f * gr, f * gz);
 }
 
-// Mixed precision evaluates g in FP64 where m1 = al2 / be2 < m1_near (k near
-// 1) and in FP32 elsewhere.  For one pair of rows (dr, sr fixed) m1 grows with
-// delta^2, so the near values are those with
-//   delta^2 < (m1_near sr^2 - dr^2) / (1 - m1_near),
-// and the choice is an integer comparison per entry against this bound taken
-// once per row pair (0: no near values).  It depends on delta^2 only, so an
-// entry and its mirror -delta fall on the same side.
-__device__ __forceinline__ int near_bound(double dr, double sr, float m1_near) {
-    const double m = m1_near;
-    if (!(m > 0.0)) return 0;
-    if (!(m < 1.0)) return INT_MAX;
-    const double t = (m * sr * sr - dr * dr) / (1.0 - m);
-    return t <= 0.0 ? 0 : t >= 2147483647.0 ? INT_MAX : (int)ceil(t);
-}
-
 // Table of kernel values g(delta) for delta = dlo + tau, tau in [0, nt),
 // stored at [(tau % W) * Q + tau / W].  g_z is even and g_r odd in delta
 // (g_z depends on delta^2 only, g_r on delta times the same factor, and the
@@ -112,10 +97,14 @@ __device__ __forceinline__ void put(float2 *p, double2 v) { *p = make_float2((fl
 __device__ __forceinline__ void put(double2 *p, float2 v) { *p = make_double2(v.x, v.y); }
 __device__ __forceinline__ void put(float2 *p, float2 v) { *p = v; }
 
+// Mixed precision: g is evaluated in FP32 except near k -> 1, where it is
+// taken from the pair's table of FP64 values made at set-up (np = (first
+// entry, count) for this pair of rows; |delta| < count is near).  The values
+// there are those a direct FP64 evaluation gives, rounded to FP32, and g_r is
+// odd in delta, so the entry for -delta is the stored one with g_r negated.
 template <int MIXED, int W, int Q, bool NEG = false, typename T2>
-__device__ __forceinline__ void fill_table(T2 *gt, int lane, int nt, int dlo, double dr, double sr,
-                                           float m1_near) {
-    const int d2near = MIXED ? near_bound(dr, sr, m1_near) : 0;
+__device__ __forceinline__ void fill_table(T2 *gt, int lane, int nt, int dlo, double dr, double sr, int2 np,
+                                           const float2 *__restrict__ nv) {
     const float drf = (float)dr, srf = (float)sr;
     for (int tau = lane; tau < nt; tau += 64) {
         const int delta = dlo + tau;
@@ -123,10 +112,18 @@ __device__ __forceinline__ void fill_table(T2 *gt, int lane, int nt, int dlo, do
         if (delta >= 0 || mt >= nt) {
             const int dz = NEG ? -delta : delta;
             T2 *p = &gt[(tau % W) * Q + tau / W];
-            if (MIXED && dz * dz >= d2near)  // |dz| < 4096 (rows of at most 2048 elements)
-                put(p, kern32(drf, (float)dz, srf));
-            else
+            if (!MIXED) {
                 put(p, kern64(dr, (double)dz, sr));
+            } else {
+                const int a = dz < 0 ? -dz : dz;
+                if (a < np.y) {
+                    float2 v = nv[np.x + a];
+                    if (dz < 0) v.x = -v.x;
+                    put(p, v);
+                } else {
+                    put(p, kern32(drf, (float)dz, srf));
+                }
+            }
         }
     }
     __syncthreads();
@@ -215,6 +212,7 @@ __device__ __forceinline__ void tz_item(const DevState &s, const RunConst &rc, c
             const int jr = rows[item.roff + k];
             const double dr = (double)(ir - jr);
             const double sr = c.c2d + (double)(ir + jr);
+            const int2 np = MIXED ? s.near_pair[c.near_base + ir * (c.layers * c.ne) + jr] : make_int2(0, 0);
             const double *Irow = Ipub + c.off + (size_t)jr * nz;
             for (int s0 = 0; s0 < nz; s0 += SMAX) {
                 const int sn = min(SMAX, nz - s0);
@@ -223,7 +221,7 @@ __device__ __forceinline__ void tz_item(const DevState &s, const RunConst &rc, c
                 // delta = z_target - z_source = dlo + tau
                 const int dlo = z0 - s0 - se;
                 __syncthreads();
-                fill_table<MIXED, W, Q>(gt, lane, TZ + se, dlo, dr, sr, rc.m1_near);
+                fill_table<MIXED, W, Q>(gt, lane, TZ + se, dlo, dr, sr, np, s.near_val);
                 for (int t = lane; t < se; t += 64) Is[t] = t < sn ? c.kscale * Irow[s0 + t] : 0.0;
                 __syncthreads();
                 double2 ring[W];
@@ -298,6 +296,7 @@ __device__ __forceinline__ void tz_item32(const DevState &s, const RunConst &rc,
         const int jr = rows[item.roff + k];
         const double dr = (double)(ir - jr);
         const double sr = c.c2d + (double)(ir + jr);
+        const int2 np = s.near_pair[c.near_base + ir * (c.layers * c.ne) + jr];
         const double *Irow = Ipub + c.off + (size_t)jr * nz;
         for (int s0 = 0; s0 < nz; s0 += SMAX) {
             const int sn = min(SMAX, nz - s0);
@@ -305,7 +304,7 @@ __device__ __forceinline__ void tz_item32(const DevState &s, const RunConst &rc,
             const int se = nb * W;
             const int dlo = z0 - s0 - se;
             __syncthreads();
-            fill_table<1, W, Q>(gt, lane, TZ + se, dlo, dr, sr, rc.m1_near);
+            fill_table<1, W, Q>(gt, lane, TZ + se, dlo, dr, sr, np, s.near_val);
             for (int t = lane; t < se; t += 64) Is[t] = t < sn ? (float)(c.kscale * Irow[s0 + t]) : 0.0f;
             __syncthreads();
             float2 ring[W];
@@ -456,6 +455,7 @@ __device__ __forceinline__ void tzT_item(const DevState &s, const RunConst &rc, 
             const int ir = rows[item.roff + k];
             const double dr = (double)(ir - jr);
             const double sr = c.c2d + (double)(ir + jr);
+            const int2 np = MIXED ? s.near_pair[c.near_base + ir * (c.layers * c.ne) + jr] : make_int2(0, 0);
             const size_t rowoff = c.off + (size_t)ir * nz;
             for (int s0 = 0; s0 < nz; s0 += SMAX) {
                 const int sn = min(SMAX, nz - s0);
@@ -464,7 +464,7 @@ __device__ __forceinline__ void tzT_item(const DevState &s, const RunConst &rc, 
                 // d = j_z - i_z = dlo + tau; entries hold g(i_r, j_r, -d)
                 const int dlo = z0 - s0 - se;
                 __syncthreads();
-                fill_table<MIXED, W, Q, true>(gt, lane, TZ + se, dlo, dr, sr, rc.m1_near);
+                fill_table<MIXED, W, Q, true>(gt, lane, TZ + se, dlo, dr, sr, np, s.near_val);
                 for (int t = lane; t < se; t += 64)
                     ws[t] = t < sn ? make_double2(wr_pub[rowoff + s0 + t], wz_pub[rowoff + s0 + t])
                                    : make_double2(0.0, 0.0);
@@ -534,6 +534,7 @@ __device__ __forceinline__ void tzT_item32(const DevState &s, const RunConst &rc
         const int ir = rows[item.roff + k];
         const double dr = (double)(ir - jr);
         const double sr = c.c2d + (double)(ir + jr);
+        const int2 np = s.near_pair[c.near_base + ir * (c.layers * c.ne) + jr];
         const size_t rowoff = c.off + (size_t)ir * nz;
         for (int s0 = 0; s0 < nz; s0 += SMAX) {
             const int sn = min(SMAX, nz - s0);
@@ -541,7 +542,7 @@ __device__ __forceinline__ void tzT_item32(const DevState &s, const RunConst &rc
             const int se = nb * W;
             const int dlo = z0 - s0 - se;
             __syncthreads();
-            fill_table<1, W, Q, true>(gt, lane, TZ + se, dlo, dr, sr, rc.m1_near);
+            fill_table<1, W, Q, true>(gt, lane, TZ + se, dlo, dr, sr, np, s.near_val);
             for (int t = lane; t < se; t += 64)
                 ws[t] = t < sn ? make_float2((float)wr_pub[rowoff + s0 + t], (float)wz_pub[rowoff + s0 + t])
                                : make_float2(0.0f, 0.0f);
@@ -646,6 +647,27 @@ __global__ __launch_bounds__(64) void k_fieldT_tz64(DevState s, RunConst rc, con
 __global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) Ipub[perm[i]] = I[i];
+}
+
+// Near kernel values of one coil: one workgroup per pair (a, b) of its rows,
+// g(a - b, delta) for delta = 0 .. count - 1 in FP64, rounded to FP32.
+__global__ __launch_bounds__(64) void k_near_fill(DevState s, int coil, int nr) {
+    const CoilDev c = s.coils[coil];
+    const int pr = blockIdx.x;
+    const int a = pr / nr, b = pr - a * nr;
+    const int2 np = s.near_pair[c.near_base + pr];
+    const double dr = (double)(a - b), sr = c.c2d + (double)(a + b);
+    float2 *out = const_cast<float2 *>(s.near_val) + np.x;
+    for (int d = threadIdx.x; d < np.y; d += 64) {
+        const double2 v = kern64(dr, (double)d, sr);
+        out[d] = make_float2((float)v.x, (float)v.y);
+    }
+}
+
+hipError_t launch_near_fill(const DevState &s, int coil, int nr, hipStream_t st) {
+    if (nr <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_near_fill, dim3(nr * nr), dim3(64), 0, st, s, coil, nr);
+    return hipGetLastError();
 }
 
 hipError_t launch_field_tz_prep(const DevState &s, double *Ipub, hipStream_t st) {

@@ -35,6 +35,7 @@ struct CoilDev {
     int group_off;  // first 64-element bounding-box group
     int nchunk;     // source chunks of the direct field pass (partial-sum slots)
     int nslot_tz;   // source-row groups of the translation-reuse pass (partial-sum slots)
+    int near_base;  // mixed mode: first (target row, source row) entry of near_pair
     float c2f;      // 2 r_inner/d + 1 in grid units (FP32)
     double c2d;     // same, FP64
     double kscale;  // mu0 / (2 pi d): field per ampere in grid units
@@ -93,6 +94,12 @@ struct DevState {
     double *I, *Phi, *Br, *Bz, *E, *Ep, *dI, *q, *Jc;
     double *u[3], *T[3];     // [0] canonical state, [1], [2] heat scratch
     double2 *part;           // field partial sums: [chunk][N]
+    // mixed translation pass: the kernel values near k -> 1 (FP64 evaluations
+    // rounded to FP32), made once at set-up.  Pair (a, b) of a coil's rows
+    // (entry near_base + a nr + b) holds g(a - b, delta) for delta = 0 .. y - 1
+    // at near_val[x ..]; every |delta| < y of the pair is near, all others far.
+    const int2 *near_pair;
+    const float2 *near_val;
     double *Uw, *Qw, *wq, *wmaxx;
     double *hb_max;          // per heat block: max T of the last substep
     long long *hb_arg;       // its public index
