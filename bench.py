@@ -50,8 +50,16 @@ TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_field_tz.h"), "dir
 PLAN_BEGIN, PLAN_END = "// ---- field-pass work plans (begin)", "// ---- field-pass work plans (end)"
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
-    ("translation", "c2_medium_131k", "mixed"): ("3ea8d16ee4845cec6d0968a8200adf2086d3c88d", 133126015),
+    ("translation", "c2_medium_131k", "mixed"): ("5bf119a765470aa1b232ce01d13ed283b82a5a0a", 116442979),
 }
+
+
+def _code_only(text: str) -> str:
+    """The source without its // and /* */ comments and blank lines: what sets the kernel's code."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(ln.rstrip() for ln in text.splitlines() if ln.strip())
 
 
 def _sources_sha(algo: str) -> str:
@@ -59,11 +67,11 @@ def _sources_sha(algo: str) -> str:
     csrc = os.path.join(ROOT, "paper_2403_07666_amd", "csrc")
     h = hashlib.sha1()
     for name in TRAFFIC_SOURCES[algo]:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(csrc, name)) as f:
+            h.update(_code_only(f.read()).encode())
     with open(os.path.join(csrc, "coil_api.hip")) as f:
         api = f.read()
-    h.update(api[api.index(PLAN_BEGIN):api.index(PLAN_END)].encode())
+    h.update(_code_only(api[api.index(PLAN_BEGIN):api.index(PLAN_END)]).encode())
     return h.hexdigest()
 
 

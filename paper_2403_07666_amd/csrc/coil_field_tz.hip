@@ -387,8 +387,8 @@ __device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst
 }
 
 // Mixed precision: 10 KiB of LDS per item and at most 128 VGPRs, so four
-// waves per SIMD; the register limit spills a few values of the FP64
-// near-value evaluation, none of the FMA loop.
+// waves per SIMD; the register limit spills a few addresses, reloaded per
+// row, none in the FMA loop.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_field_tz32(
     DevState s, RunConst rc, const TzItem *__restrict__ items, const int *__restrict__ rows, int nitems,
     const double *__restrict__ Ipub, const int *__restrict__ pub2int) {
