@@ -12,9 +12,10 @@
 // source row and every chunk of up to SMAX source z it
 //   1. evaluates the 64*W + se distinct kernel values g(delta) on the fly
 //      (elliptic integrals as in the direct pass; mixed precision: FP32 where
-//      m1 >= m1_near, FP64 for the near values) into LDS, stored de-interleaved
-//      by delta mod W so that every lane reads a different bank, and copies
-//      the entries whose mirror -delta is already there (g_r odd, g_z even);
+//      m1 >= m1_near, the near values FP64 from a table made once at set-up)
+//      into LDS, stored de-interleaved by delta mod W so that every lane reads
+//      a different bank, and copies the entries whose mirror -delta is
+//      already there (g_r odd, g_z even);
 //   2. streams the source currents through LDS and accumulates
 //      acc[c] += g(delta) * I with a W-register sliding window over delta:
 //      one LDS read of g feeds 2W FMAs.
