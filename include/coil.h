@@ -114,8 +114,11 @@ typedef struct {
     double near_k;          /* mixed mode: pairs with k > near_k run in FP64 (0 -> 0.99) */
     int32_t tile_targets;   /* field-pass tile: targets per workgroup (0 -> 256) */
     int32_t tile_sources;   /* sources per work item (0 -> automatic) */
-    int32_t grid_limit;     /* 0: one workgroup per work item; > 0: persistent grid of at
-                               most this many workgroups striding over the work items */
+    int32_t grid_limit;     /* 0: DIRECT: one workgroup per work item; TRANSLATION: one
+                               workgroup per slot the GPU holds at once, each taking the
+                               next work item in list order when free; > 0: persistent
+                               grid of at most this many workgroups striding over the
+                               work items (both evaluations) */
     int32_t algo;           /* enum coil_algo: how the field pass is evaluated */
 } coil_config;
 

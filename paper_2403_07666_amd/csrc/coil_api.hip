@@ -71,7 +71,7 @@ struct Plan {
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
         perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
-        sc_b, tmp_b, misc_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b;
+        sc_b, tmp_b, misc_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b;
 };
 
 Buf carve(size_t &cur, size_t bytes) {
@@ -493,6 +493,7 @@ size_t layout(Plan &p) {
     p.zphys_b = carve(cur, sizeof(double) * N);
     p.near_pair_b = carve(cur, sizeof(int2) * std::max<size_t>(1, p.near_pair.size()));
     p.near_val_b = carve(cur, sizeof(float2) * std::max<size_t>(1, p.near_total));
+    p.ticket_b = carve(cur, 2 * sizeof(int));
     p.Uw_b = carve(cur, d8 * Nw);
     p.Qw_b = carve(cur, d8 * Nw);
     p.wq_b = carve(cur, d8 * Nw);
@@ -603,7 +604,7 @@ hipError_t launch_fieldT_any(coil_t *h, const double *wr, const double *wz, doub
 }
 
 hipError_t launch_field_any(coil_t *h, const DevState &d, hipStream_t st) {
-    if (d.algo_tz) return launch_field_tz(d, h->rc, h->tz, h->Ipub, h->d_pub2int, 0, st);
+    if (d.algo_tz) return launch_field_tz(d, h->rc, h->tz, h->Ipub, h->d_pub2int, h->grid_limit, st);
     return launch_field(d, h->rc, h->grid_limit, st);
 }
 
@@ -612,10 +613,10 @@ int enqueue_step(coil_t *h) {
     int rc;
     // phase 0 brackets the field kernel alone (its input reordering runs before)
     const DevState &d = h->ds;
-    if (d.algo_tz) HIPCHECK(launch_field_tz_prep(d, h->Ipub, h->stream));
+    if (d.algo_tz) HIPCHECK(launch_field_tz_prep(d, h->tz, h->Ipub, h->stream));
     if ((rc = t_begin(h, &a, 0))) return rc;
     if (d.algo_tz)
-        HIPCHECK(launch_field_tz_kernel(d, h->rc, h->tz, h->Ipub, h->d_pub2int, 0, h->stream));
+        HIPCHECK(launch_field_tz_kernel(d, h->rc, h->tz, h->Ipub, h->d_pub2int, h->grid_limit, h->stream));
     else
         HIPCHECK(launch_field(d, h->rc, h->grid_limit, h->stream));
     if ((rc = t_end(h, 0, a, 1))) return rc;
@@ -907,6 +908,8 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     h->tz.items = at<TzItem>(h, p.tz_b);
     h->tz.rows = at<int>(h, p.tzrows_b);
     h->tz.n = (int)p.tz_items.size();
+    h->tz.ticket = at<int>(h, p.ticket_b);
+    HIPCHECK(tz_resident_grids(h->tz));
     s.coils = at<CoilDev>(h, p.coils_b);
     s.items = at<PairItem>(h, p.items_b);
     s.bbox = at<int4>(h, p.bbox_b);
@@ -985,6 +988,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)h->d_pub2int, pub2int.data(), sizeof(int) * N));
     HIPCHECK(up((void *)at<double>(h, p.zphys_b), zphys.data(), sizeof(double) * N));
     HIPCHECK(up((void *)s.near_pair, p.near_pair.data(), sizeof(int2) * p.near_pair.size()));
+    HIPCHECK(hipMemsetAsync(h->tz.ticket, 0, 2 * sizeof(int), st));
     if (p.prec == COIL_MIXED)
         for (size_t ci = 0; ci < p.coils.size(); ++ci)
             HIPCHECK(launch_near_fill(s, (int)ci, p.coils[ci].layers * p.coils[ci].ne, st));

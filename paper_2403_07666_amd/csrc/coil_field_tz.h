@@ -18,13 +18,20 @@ struct TzPlan {
     const TzItem *items;
     const int *rows;  // source-row lists the items index
     int n;
+    // work queue: ticket[0] forward, ticket[1] transposed pass, reset by the
+    // pass's reordering kernel; grids of as many workgroups as fit at once
+    int *ticket;
+    int grid32, grid64, gridT32, gridT64;
 };
+
+// resident workgroups of each field kernel on the current device (tp.grid*)
+hipError_t tz_resident_grids(TzPlan &tp);
 
 // forward pass: the currents in public order (prep), then the field kernel;
 // launch_field_tz issues both
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                            const int *pub2int, int grid_limit, hipStream_t st);
-hipError_t launch_field_tz_prep(const DevState &s, double *Ipub, hipStream_t st);
+hipError_t launch_field_tz_prep(const DevState &s, const TzPlan &tp, double *Ipub, hipStream_t st);
 // the near kernel values of coil `coil` (rows nr), into s.near_val
 hipError_t launch_near_fill(const DevState &s, int coil, int nr, hipStream_t st);
 hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,

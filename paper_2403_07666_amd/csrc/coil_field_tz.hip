@@ -357,12 +357,27 @@ constexpr bool tz_fits() {
 
 // All widths in one launch: items are ordered widest first, and each
 // workgroup branches (uniformly) on its item's width.
+// Work items of a workgroup.  Workgroup b starts with item b.  With a ticket
+// counter (the default launch, one workgroup per slot of the GPU) it then
+// takes the next item in list order whenever it is free, so the parts of the
+// GPU that run faster take more of them (the counter starts at 0 and hands out
+// items from gridDim.x on); without one it strides by the grid.  Items write
+// disjoint outputs, so the results do not depend on which workgroup takes
+// which item.
+__device__ __forceinline__ int next_item(int *ticket, int it) {
+    if (!ticket) return it + (int)gridDim.x;
+    int t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(ticket, 1);
+    return (int)gridDim.x + __builtin_amdgcn_readfirstlane(t);
+}
+__device__ __forceinline__ int first_item(int *) { return (int)blockIdx.x; }
+
 template <int MIXED>
 __device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst &rc,
                                                const TzItem *__restrict__ items, const int *__restrict__ rows,
                                                int nitems, const double *__restrict__ Ipub,
-                                               const int *__restrict__ pub2int, double2 *lds) {
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+                                               const int *__restrict__ pub2int, double2 *lds, int *ticket) {
+    for (int it = first_item(ticket); it < nitems; it = next_item(ticket, it)) {
         const TzItem item = items[it];
 #define COILQ_TZ_CASE(Wv)                                                                                   \
     case Wv:                                                                                                \
@@ -392,17 +407,17 @@ __device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst
 // row, none in the FMA loop.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_field_tz32(
     DevState s, RunConst rc, const TzItem *__restrict__ items, const int *__restrict__ rows, int nitems,
-    const double *__restrict__ Ipub, const int *__restrict__ pub2int) {
+    const double *__restrict__ Ipub, const int *__restrict__ pub2int, int *ticket) {
     __shared__ double2 lds[kTzLds2 / 2];
-    field_tz_items<1>(s, rc, items, rows, nitems, Ipub, pub2int, lds);
+    field_tz_items<1>(s, rc, items, rows, nitems, Ipub, pub2int, lds, ticket);
 }
 
 __global__ __launch_bounds__(64) void k_field_tz64(DevState s, RunConst rc, const TzItem *__restrict__ items,
                                                    const int *__restrict__ rows, int nitems,
                                                    const double *__restrict__ Ipub,
-                                                   const int *__restrict__ pub2int) {
+                                                   const int *__restrict__ pub2int, int *ticket) {
     __shared__ double2 lds[kTzLds2];
-    field_tz_items<0>(s, rc, items, rows, nitems, Ipub, pub2int, lds);
+    field_tz_items<0>(s, rc, items, rows, nitems, Ipub, pub2int, lds, ticket);
 }
 
 // Transposed pass (adjoint): out(j_r, j_z) = sum over target rows i_r and
@@ -598,8 +613,9 @@ __device__ __forceinline__ void fieldT_tz_items(const DevState &s, const RunCons
                                                 const TzItem *__restrict__ items, const int *__restrict__ rows,
                                                 int nitems, const double *__restrict__ wr_pub,
                                                 const double *__restrict__ wz_pub,
-                                                const int *__restrict__ pub2int, double *partT, double2 *lds) {
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+                                                const int *__restrict__ pub2int, double *partT, double2 *lds,
+                                                int *ticket) {
+    for (int it = first_item(ticket); it < nitems; it = next_item(ticket, it)) {
         const TzItem item = items[it];
 #define COILQ_TZT_CASE(Wv)                                                                                  \
     case Wv:                                                                                                \
@@ -630,24 +646,27 @@ __device__ __forceinline__ void fieldT_tz_items(const DevState &s, const RunCons
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_fieldT_tz32(
     DevState s, RunConst rc, const TzItem *__restrict__ items, const int *__restrict__ rows, int nitems,
     const double *__restrict__ wr_pub, const double *__restrict__ wz_pub, const int *__restrict__ pub2int,
-    double *partT) {
+    double *partT, int *ticket) {
     __shared__ double2 lds[kTzTLds2 / 2];
-    fieldT_tz_items<1>(s, rc, items, rows, nitems, wr_pub, wz_pub, pub2int, partT, lds);
+    fieldT_tz_items<1>(s, rc, items, rows, nitems, wr_pub, wz_pub, pub2int, partT, lds, ticket);
 }
 
 __global__ __launch_bounds__(64) void k_fieldT_tz64(DevState s, RunConst rc, const TzItem *__restrict__ items,
                                                     const int *__restrict__ rows, int nitems,
                                                     const double *__restrict__ wr_pub,
                                                     const double *__restrict__ wz_pub,
-                                                    const int *__restrict__ pub2int, double *partT) {
+                                                    const int *__restrict__ pub2int, double *partT,
+                                                    int *ticket) {
     __shared__ double2 lds[kTzTLds2];
-    fieldT_tz_items<0>(s, rc, items, rows, nitems, wr_pub, wz_pub, pub2int, partT, lds);
+    fieldT_tz_items<0>(s, rc, items, rows, nitems, wr_pub, wz_pub, pub2int, partT, lds, ticket);
 }
 
-// I in public (row-major) order for the convolution pass
-__global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub) {
+// I in public (row-major) order for the convolution pass; also clears the
+// pass's ticket counter (if any) before the pass starts
+__global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub, int *ticket) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) Ipub[perm[i]] = I[i];
+    if (ticket && i == 0) *ticket = 0;
 }
 
 // Near kernel values of one coil: one workgroup per pair (a, b) of its rows,
@@ -671,14 +690,33 @@ hipError_t launch_near_fill(const DevState &s, int coil, int nr, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_field_tz_prep(const DevState &s, double *Ipub, hipStream_t st) {
-    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N, Ipub);
+hipError_t tz_resident_grids(TzPlan &tp) {
+    int dev = 0, cus = 0, b = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_field_tz32, 64, 0)) != hipSuccess) return e;
+    tp.grid32 = b * cus;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_field_tz64, 64, 0)) != hipSuccess) return e;
+    tp.grid64 = b * cus;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fieldT_tz32, 64, 0)) != hipSuccess) return e;
+    tp.gridT32 = b * cus;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fieldT_tz64, 64, 0)) != hipSuccess) return e;
+    tp.gridT64 = b * cus;
+    return hipSuccess;
+}
+
+// one workgroup per resident slot with the ticket counter, or per item without
+static int queue_grid(int slots, int n) { return slots > 0 ? min(slots, n) : n; }
+
+hipError_t launch_field_tz_prep(const DevState &s, const TzPlan &tp, double *Ipub, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N, Ipub, tp.ticket);
     return hipGetLastError();
 }
 
 hipError_t launch_field_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                            const int *pub2int, int grid_limit, hipStream_t st) {
-    hipError_t e = launch_field_tz_prep(s, const_cast<double *>(Ipub), st);
+    hipError_t e = launch_field_tz_prep(s, tp, const_cast<double *>(Ipub), st);
     if (e != hipSuccess) return e;
     return launch_field_tz_kernel(s, rc, tp, Ipub, pub2int, grid_limit, st);
 }
@@ -687,13 +725,18 @@ hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const T
                                   const int *pub2int, int grid_limit, hipStream_t st) {
     const int n = tp.n;
     if (n > 0) {
-        const int grid = grid_limit > 0 ? min(grid_limit, n) : n;
-        if (rc.prec == COIL_MIXED)
+        // grid_limit > 0: a persistent grid of that size striding over the items
+        int *ticket = grid_limit > 0 ? nullptr : tp.ticket;
+        const bool mixed = rc.prec == COIL_MIXED;
+        const int grid = grid_limit > 0 ? min(grid_limit, n)
+                         : ticket       ? queue_grid(mixed ? tp.grid32 : tp.grid64, n)
+                                        : n;
+        if (mixed)
             hipLaunchKernelGGL(k_field_tz32, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
-                               pub2int);
+                               pub2int, ticket);
         else
             hipLaunchKernelGGL(k_field_tz64, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
-                               pub2int);
+                               pub2int, ticket);
     }
     return hipGetLastError();
 }
@@ -701,16 +744,20 @@ hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const T
 hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *wr,
                             const double *wz, double *wr_pub, double *wz_pub, const int *pub2int,
                             double *partT, hipStream_t st) {
-    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wr, s.perm, s.N, wr_pub);
-    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wz, s.perm, s.N, wz_pub);
+    int *ticket = tp.ticket ? tp.ticket + 1 : nullptr;
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wr, s.perm, s.N, wr_pub, ticket);
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wz, s.perm, s.N, wz_pub,
+                       static_cast<int *>(nullptr));
     const int n = tp.n;
     if (n > 0) {
-        if (rc.prec == COIL_MIXED)
-            hipLaunchKernelGGL(k_fieldT_tz32, dim3(n), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
-                               wz_pub, pub2int, partT);
+        const bool mixed = rc.prec == COIL_MIXED;
+        const int grid = ticket ? queue_grid(mixed ? tp.gridT32 : tp.gridT64, n) : n;
+        if (mixed)
+            hipLaunchKernelGGL(k_fieldT_tz32, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
+                               wz_pub, pub2int, partT, ticket);
         else
-            hipLaunchKernelGGL(k_fieldT_tz64, dim3(n), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
-                               wz_pub, pub2int, partT);
+            hipLaunchKernelGGL(k_fieldT_tz64, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, wr_pub,
+                               wz_pub, pub2int, partT, ticket);
     }
     return hipGetLastError();
 }
