@@ -260,7 +260,8 @@ int coil_field_transpose(coil_t *h, const double *bbar_r, const double *bbar_z, 
    chunk) items.  Drops a captured graph.
    coil_autotune: times the candidates over `reps` field passes on the
    handle's current currents and keeps the fastest: TRANSLATION with 4, 8, 16, 32
-   or 64 source-row groups per target row segment, and DIRECT with 3 tile sizes x
+   or 64 source-row groups per target row segment (launched as a work queue,
+   grid_limit 0), and DIRECT with 3 tile sizes x
    5 chunk counts x 3 grid shapes.  A candidate whose first (timed) pass is
    over 3x the best so far is not timed further, nor is the rest of a family
    whose first three candidates all were.  With cache_path it first looks the
@@ -281,9 +282,11 @@ int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, int32_t *chos
 int coil_set_widths(coil_t *h, int32_t w);
 
 /* Work of one field pass as planned: out[0] ordered (target, source) pairs,
-   out[1] Green's-function evaluations (= pairs for DIRECT), out[2] the algorithm
-   (enum coil_algo), out[3] work items, out[4] direct-pass targets per workgroup.
-   Writes min(n, 5) values.  No device work. */
+   out[1] Green's-function evaluations the pass performs (= pairs for DIRECT;
+   TRANSLATION in mixed mode leaves out the near values made at set-up),
+   out[2] the algorithm (enum coil_algo), out[3] work items, out[4] direct-pass
+   targets per workgroup, out[5] workgroups of the launch.  Writes min(n, 6)
+   values.  No device work. */
 int coil_field_stats(coil_t *h, double *out, int32_t n);
 
 void coil_destroy(coil_t *h);  /* does not free the caller's workspace */

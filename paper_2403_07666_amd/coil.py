@@ -368,10 +368,10 @@ class Coil:
 
     def field_stats(self) -> dict:
         """Work of one field pass: pairs, Green's-function evaluations, algorithm, items."""
-        v = np.zeros(5)
-        check(lib().coil_field_stats(self.h, v.ctypes.data_as(_dp), 5))
+        v = np.zeros(6)
+        check(lib().coil_field_stats(self.h, v.ctypes.data_as(_dp), 6))
         return {"pairs": v[0], "kernel_evals": v[1], "algo": "translation" if v[2] == 2 else "direct",
-                "items": int(v[3]), "tile_targets": int(v[4])}
+                "items": int(v[3]), "tile_targets": int(v[4]), "workgroups": int(v[5])}
 
     # -------------------------------------------------------------- probes and snapshots
     def field_at(self, r, z):

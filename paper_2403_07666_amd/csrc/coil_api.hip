@@ -1628,6 +1628,7 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
         if (algo == COIL_ALGO_TRANSLATION) {
             h->ds.algo_tz = 1;
             h->plan.algo = COIL_ALGO_TRANSLATION;
+            h->grid_limit = 0;  // the work-queue launch (a DIRECT candidate may have set a grid)
             return apply_tz(h, a);
         }
         h->ds.algo_tz = 0;
@@ -1727,10 +1728,14 @@ extern "C" int coil_field_stats(coil_t *h, double *out, int32_t n) {
     double pairs = 0.0;
     for (const CoilDev &d : h->plan.coils) pairs += (double)d.n * (double)(d.n - 1);
     const bool tz = h->ds.algo_tz != 0;
-    const double v[5] = {pairs, tz ? h->plan.tz_evals : pairs, tz ? 2.0 : 1.0,
-                         tz ? (double)h->plan.tz_items.size() : (double)h->plan.items.size(),
-                         (double)h->ds.tile_targets};
-    for (int i = 0; i < n && i < 5; ++i) out[i] = v[i];
+    const int nit = tz ? (int)h->plan.tz_items.size() : (int)h->plan.items.size();
+    const int resident = h->rc.prec == COIL_MIXED ? h->tz.grid32 : h->tz.grid64;
+    const int wg = h->grid_limit > 0 ? std::min(h->grid_limit, nit)
+                   : tz && resident > 0 ? std::min(resident, nit)
+                                        : nit;
+    const double v[6] = {pairs, tz ? h->plan.tz_evals : pairs, tz ? 2.0 : 1.0, (double)nit,
+                         (double)h->ds.tile_targets, (double)wg};
+    for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
     return COIL_OK;
 }
 

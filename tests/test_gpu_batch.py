@@ -177,3 +177,29 @@ def test_timing_modes():
     with pytest.raises(pk.CoilError):
         g.timing(3)
     g.close()
+
+
+def test_autotuned_translation_runs_as_work_queue(tmp_path):
+    """A TRANSLATION choice of the autotuner runs the work-queue launch even
+    when a DIRECT tile shape with a persistent grid was set before."""
+    import json
+    pk = _pk()
+    w = _ensemble()
+    inp = cs.generate(w)
+    path = os.path.join(str(tmp_path), "tune.jsonl")
+    g = pk.Coil(w, inp, precision="mixed")
+    g.autotune(reps=1, cache_path=path)
+    rec = json.loads(open(path).read().splitlines()[0])
+    rec.update({"algo": 2, "p1": 8, "p2": 0, "p3": 0})
+    with open(path, "w") as f:
+        f.write(json.dumps(rec) + "\n")
+    g.close()
+    g = pk.Coil(w, inp, precision="mixed")
+    g.set_tiles(64, 2, 7)
+    st = g.field_stats()
+    assert st["algo"] == "direct" and st["workgroups"] == 7
+    assert g.autotune(reps=1, cache_path=path) == (2, 8, 0, 0)
+    st = g.field_stats()
+    assert st["algo"] == "translation" and st["workgroups"] > 7
+    assert st["workgroups"] <= st["items"]
+    g.close()
