@@ -50,7 +50,7 @@ TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_field_tz.h"), "dir
 PLAN_BEGIN, PLAN_END = "// ---- field-pass work plans (begin)", "// ---- field-pass work plans (end)"
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
-    ("translation", "c2_medium_131k", "mixed"): ("5bf119a765470aa1b232ce01d13ed283b82a5a0a", 116442979),
+    ("translation", "c2_medium_131k", "mixed"): ("4344d8c1f79472a946b257bbae2445586c8dd866", 118560589),
 }
 
 
