@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -193,7 +194,7 @@ float m1_near_of(const coil_config *c) {
 // exactly for delta^2 < (m1_near sr^2 - dr^2) / (1 - m1_near) (dr = a - b,
 // sr = c2d + a + b): |delta| < count.  count is capped at the largest |delta|
 // any table of the coil can hold (n_z + 1024).
-void build_near(Plan &p, float m1_near) {
+bool build_near(Plan &p, float m1_near) {
     p.near_pair.clear();
     p.near_total = 0;
     for (CoilDev &d : p.coils) {
@@ -213,10 +214,12 @@ void build_near(Plan &p, float m1_near) {
                     while ((double)((r + 1) * (r + 1)) < t) ++r;
                     cnt = std::min(r, amax) + 1;
                 }
+                if (p.near_total + (size_t)cnt > (size_t)INT_MAX) return false;  // int2 offsets
                 p.near_pair.push_back(make_int2((int)p.near_total, (int)cnt));
                 p.near_total += (size_t)cnt;
             }
     }
+    return true;
 }
 
 std::vector<int> group_sizes(int nr, int ns) {
@@ -382,7 +385,7 @@ int make_plan(const coil_config *c, Plan &p) {
     p.nheat_blocks = (p.N + 255) / 256;
     int tb = c->tile_targets;
     if (tb == 0) tb = p.N <= 8192 ? 64 : 256;
-    build_near(p, m1_near_of(c));
+    if (!build_near(p, m1_near_of(c))) return fail(COIL_E_INVAL, "near-value table exceeds 2^31 entries");
     build_items(p, tb, 0, c->tile_sources);
     // capacity for the autotuner's candidates: targets per item >= 64 and at
     // most kMaxChunks source chunks per coil
