@@ -143,7 +143,8 @@ __device__ __forceinline__ void fill_table(T2 *gt, int lane, int nt, int dlo, do
 // (a whole row of the benchmark coils, so that the mirror halves the table);
 // the table holds TZ + se entries for a chunk of se sources (se = the chunk
 // length rounded up to W), W * Q of them at most.  For W = 8 table and
-// currents take 20 KiB, so eight items fit in the 160 KiB of LDS of a CU.
+// currents take 20 KiB in FP64 (eight items in the 160 KiB of LDS of a CU)
+// and 10 KiB in mixed precision (sixteen).
 template <int W>
 struct TzShape {
     static constexpr int SMAX = W >= 5 ? 512 : 256;
