@@ -224,6 +224,35 @@ __device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, in
 // y(lane) = sum_j A[j n + lane] v_j for a column-major n x n block with v held
 // one element per lane (v_j broadcast from lane j).  The FMAs run in j order;
 // the column loads are issued 16 at a time so that they are in flight together.
+// v of lane j (j uniform) to every lane, by two scalar reads
+__device__ __forceinline__ double lane_value(double v, int j) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), j);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Columns of a column-major n x n matrix (n <= kMaxWireElems), lane i holding
+// row i: loaded all at once, ahead of the product that uses them.
+struct WireCols {
+    double a[kMaxWireElems];
+};
+__device__ __forceinline__ void load_cols(WireCols &c, const double *A, int n, int lane, bool act) {
+#pragma unroll
+    for (int j = 0; j < kMaxWireElems; ++j) c.a[j] = (act && j < n) ? A[(size_t)j * n + lane] : 0.0;
+}
+// y_i = sum_j A_ij v_j, the FMAs in j order as in matvec_cols
+__device__ __forceinline__ double matvec_loaded(const WireCols &c, int n, bool act, double v) {
+    double y = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMaxWireElems; ++j)
+        if (j < n) {
+            const double vj = lane_value(v, j);
+            if (act) y = fma(c.a[j], vj, y);
+        }
+    return y;
+}
+
 __device__ __forceinline__ double matvec_cols(const double *A, int n, int lane, bool act, double v) {
     double y = 0.0;
     for (int j0 = 0; j0 < n; j0 += 16) {

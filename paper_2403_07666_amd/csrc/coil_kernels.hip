@@ -165,6 +165,11 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     const double tk = (double)s.sc->step * dt;
     const double dBa = rc.dBa_dt * dt;
 
+    const size_t lay = (size_t)(c.layer_off + layer);
+    // the fast path's layer inverse, loaded while the field and the local law
+    // are computed
+    WireCols minv;
+    if (FAST) load_cols(minv, s.Minv + lay * n * n, n, lane, act);
     double br, bz;
     if (s.src_Br) {
         br = s.src_Br[e];
@@ -178,7 +183,6 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     unsigned bad = act ? local_law(rc, s.cw[w], s.jcs[e], I0 / d2, s.T[0][e], br, bz, lo) : 0u;
     if (!act) { lo.E = lo.Ep = lo.x = lo.Jc = 0.0; }
     const double re = s.r[e];
-    const size_t lay = (size_t)(c.layer_off + layer);
     const double *M = s.Mlay + lay * n * n;
     const double diag_add = dt * 2.0 * kPi * re * lo.Ep / d2;
     const double b = act ? (-c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * lo.E) : 0.0;
@@ -190,7 +194,7 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
             if (lane == 0) s.wflag[w] = 1;
             return;
         }
-        xv = matvec_cols(s.Minv + lay * n * n, n, lane, act, b);
+        xv = matvec_loaded(minv, n, act, b);
         yv = act ? s.yl[lay * n + lane] : 0.0;
         sy = s.syl[lay];
     } else {
