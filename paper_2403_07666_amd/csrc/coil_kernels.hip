@@ -308,14 +308,26 @@ __global__ __launch_bounds__(256) void k_finalize(DevState s, RunConst rc) {
     __shared__ double a_q[256], a_u[256], a_x[256], a_o[256], a_t[256];
     __shared__ long long a_i[256];
     const int tid = threadIdx.x;
+    // the running scalars are read first, so that their loads overlap the sums
+    Scalars *sc = s.sc;
+    double Q0 = 0.0, Qout0 = 0.0, Tpeak0 = 0.0;
+    long long step0 = 0;
+    if (tid == 0) {
+        Q0 = sc->Q;
+        Qout0 = sc->Qout;
+        Tpeak0 = sc->Tpeak;
+        step0 = sc->step;
+    }
     double q = 0.0, u = 0.0, x = 0.0, o = 0.0, tm = -INFINITY;
     long long ti = LLONG_MAX;
+#pragma unroll 4
     for (int w = tid; w < s.Nw; w += 256) {
         q += s.wq[w];
         u += s.Uw[w];
         x = fmax(x, s.wmaxx[w]);
     }
     const int no = s.nsub * s.nheat_blocks;
+#pragma unroll 4
     for (int i = tid; i < no; i += 256) o += s.hb_out[i];
     for (int b = tid; b < s.nheat_blocks; b += 256) {
         const double v = s.hb_max[b];
@@ -339,18 +351,18 @@ __global__ __launch_bounds__(256) void k_finalize(DevState s, RunConst rc) {
         __syncthreads();
     }
     if (tid == 0) {
-        Scalars *sc = s.sc;
-        sc->Q += a_q[0];
+        const double Q1 = Q0 + a_q[0];
+        sc->Q = Q1;
         sc->sumU = a_u[0];
         sc->maxx = a_x[0];
-        sc->Qout += a_o[0];
-        const long long stepn = sc->step + 1;
-        if (a_t[0] > sc->Tpeak) {
+        sc->Qout = Qout0 + a_o[0];
+        const long long stepn = step0 + 1;
+        if (a_t[0] > Tpeak0) {
             sc->Tpeak = a_t[0];
             sc->Tpeak_pub = a_i[0];
             sc->Tpeak_step = stepn;
         }
-        if (!isfinite(sc->Q)) sc->status |= ST_NONFINITE;
+        if (!isfinite(Q1)) atomicOr(&sc->status, ST_NONFINITE);
         sc->step = stepn;
     }
 }
