@@ -72,7 +72,8 @@ struct Plan {
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
         perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
-        sc_b, tmp_b, misc_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b;
+        sc_b, tmp_b, misc_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b,
+        Ipub32_b;
 };
 
 Buf carve(size_t &cur, size_t bytes) {
@@ -492,6 +493,7 @@ size_t layout(Plan &p) {
     p.tz_b = carve(cur, sizeof(TzItem) * std::max<size_t>(1, std::max(p.tz_items.size(), p.tz_cap)));
     p.tzrows_b = carve(cur, sizeof(int) * std::max<size_t>(1, p.tz_rows.size()));
     p.Ipub_b = carve(cur, sizeof(double) * N);
+    p.Ipub32_b = carve(cur, sizeof(float) * N);
     p.pub2int_b = carve(cur, sizeof(int) * N);
     p.zphys_b = carve(cur, sizeof(double) * N);
     p.near_pair_b = carve(cur, sizeof(int2) * std::max<size_t>(1, p.near_pair.size()));
@@ -912,6 +914,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     h->tz.rows = at<int>(h, p.tzrows_b);
     h->tz.n = (int)p.tz_items.size();
     h->tz.ticket = at<int>(h, p.ticket_b);
+    h->tz.Ipub32 = p.prec == COIL_MIXED ? at<float>(h, p.Ipub32_b) : nullptr;
     HIPCHECK(tz_resident_grids(h->tz));
     s.coils = at<CoilDev>(h, p.coils_b);
     s.items = at<PairItem>(h, p.items_b);

@@ -22,6 +22,9 @@ struct TzPlan {
     // pass's reordering kernel; grids of as many workgroups as fit at once
     int *ticket;
     int grid32, grid64, gridT32, gridT64;
+    // mixed pass input: kscale * I in public order, rounded to FP32 (made
+    // with Ipub by the reordering kernel)
+    float *Ipub32;
 };
 
 // resident workgroups of each field kernel on the current device (tp.grid*)

@@ -282,7 +282,7 @@ __device__ __forceinline__ void tz_block32(const float2 *gt, float2 (&ring)[W], 
 // partial sums are added into FP64 accumulators.
 template <int W>
 __device__ __forceinline__ void tz_item32(const DevState &s, const RunConst &rc, const TzItem &item,
-                                          const int *__restrict__ rows, const double *__restrict__ Ipub,
+                                          const int *__restrict__ rows, const float *__restrict__ Ipub32,
                                           const int *__restrict__ pub2int, float2 *gt, float *Is) {
     using Sh = TzShape<W>;
     constexpr int SMAX = Sh::SMAX, TZ = Sh::TZ, Q = Sh::Q;
@@ -299,7 +299,7 @@ __device__ __forceinline__ void tz_item32(const DevState &s, const RunConst &rc,
         const double dr = (double)(ir - jr);
         const double sr = c.c2d + (double)(ir + jr);
         const int2 np = s.near_pair[c.near_base + ir * (c.layers * c.ne) + jr];
-        const double *Irow = Ipub + c.off + (size_t)jr * nz;
+        const float *Irow = Ipub32 + c.off + (size_t)jr * nz;
         for (int s0 = 0; s0 < nz; s0 += SMAX) {
             const int sn = min(SMAX, nz - s0);
             const int nb = (sn + W - 1) / W;
@@ -307,7 +307,7 @@ __device__ __forceinline__ void tz_item32(const DevState &s, const RunConst &rc,
             const int dlo = z0 - s0 - se;
             __syncthreads();
             fill_table<1, W, Q>(gt, lane, TZ + se, dlo, dr, sr, np, s.near_val);
-            for (int t = lane; t < se; t += 64) Is[t] = t < sn ? (float)(c.kscale * Irow[s0 + t]) : 0.0f;
+            for (int t = lane; t < se; t += 64) Is[t] = t < sn ? Irow[s0 + t] : 0.0f;
             __syncthreads();
             float2 ring[W];
 #pragma unroll
@@ -377,6 +377,7 @@ template <int MIXED>
 __device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst &rc,
                                                const TzItem *__restrict__ items, const int *__restrict__ rows,
                                                int nitems, const double *__restrict__ Ipub,
+                                               const float *__restrict__ Ipub32,
                                                const int *__restrict__ pub2int, double2 *lds, int *ticket) {
     for (int it = first_item(ticket); it < nitems; it = next_item(ticket, it)) {
         const TzItem item = items[it];
@@ -384,7 +385,7 @@ __device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst
     case Wv:                                                                                                \
         static_assert(tz_fits<Wv>(), "LDS");                                                                \
         if (MIXED)                                                                                          \
-            tz_item32<Wv>(s, rc, item, rows, Ipub, pub2int, reinterpret_cast<float2 *>(lds),                \
+            tz_item32<Wv>(s, rc, item, rows, Ipub32, pub2int, reinterpret_cast<float2 *>(lds),              \
                           reinterpret_cast<float *>(reinterpret_cast<float2 *>(lds) + TzShape<Wv>::Q * Wv)); \
         else                                                                                                \
             tz_item<MIXED, Wv>(s, rc, item, rows, Ipub, pub2int, lds,                                       \
@@ -408,9 +409,9 @@ __device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst
 // row, none in the FMA loop.
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_field_tz32(
     DevState s, RunConst rc, const TzItem *__restrict__ items, const int *__restrict__ rows, int nitems,
-    const double *__restrict__ Ipub, const int *__restrict__ pub2int, int *ticket) {
+    const float *__restrict__ Ipub32, const int *__restrict__ pub2int, int *ticket) {
     __shared__ double2 lds[kTzLds2 / 2];
-    field_tz_items<1>(s, rc, items, rows, nitems, Ipub, pub2int, lds, ticket);
+    field_tz_items<1>(s, rc, items, rows, nitems, nullptr, Ipub32, pub2int, lds, ticket);
 }
 
 __global__ __launch_bounds__(64) void k_field_tz64(DevState s, RunConst rc, const TzItem *__restrict__ items,
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(64) void k_field_tz64(DevState s, RunConst rc, cons
                                                    const double *__restrict__ Ipub,
                                                    const int *__restrict__ pub2int, int *ticket) {
     __shared__ double2 lds[kTzLds2];
-    field_tz_items<0>(s, rc, items, rows, nitems, Ipub, pub2int, lds, ticket);
+    field_tz_items<0>(s, rc, items, rows, nitems, Ipub, nullptr, pub2int, lds, ticket);
 }
 
 // Transposed pass (adjoint): out(j_r, j_z) = sum over target rows i_r and
@@ -662,11 +663,18 @@ __global__ __launch_bounds__(64) void k_fieldT_tz64(DevState s, RunConst rc, con
     fieldT_tz_items<0>(s, rc, items, rows, nitems, wr_pub, wz_pub, pub2int, partT, lds, ticket);
 }
 
-// I in public (row-major) order for the convolution pass; also clears the
-// pass's ticket counter (if any) before the pass starts
-__global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub, int *ticket) {
+// I in public (row-major) order for the convolution pass, and (if Ipub32)
+// kscale * I of the element's coil rounded to FP32 for the mixed pass; also
+// clears the pass's ticket counter (if any) before the pass starts
+__global__ void k_to_pub(const double *I, const int *perm, int n, double *Ipub, int *ticket, float *Ipub32,
+                         const int *elem_coil, const CoilDev *coils) {
     const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) Ipub[perm[i]] = I[i];
+    if (i < n) {
+        const double v = I[i];
+        const int pub = perm[i];
+        Ipub[pub] = v;
+        if (Ipub32) Ipub32[pub] = (float)(coils[elem_coil[i]].kscale * v);
+    }
     if (ticket && i == 0) *ticket = 0;
 }
 
@@ -711,7 +719,8 @@ hipError_t tz_resident_grids(TzPlan &tp) {
 static int queue_grid(int slots, int n) { return slots > 0 ? min(slots, n) : n; }
 
 hipError_t launch_field_tz_prep(const DevState &s, const TzPlan &tp, double *Ipub, hipStream_t st) {
-    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N, Ipub, tp.ticket);
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, s.I, s.perm, s.N, Ipub, tp.ticket,
+                       tp.Ipub32, s.elem_coil, s.coils);
     return hipGetLastError();
 }
 
@@ -733,8 +742,8 @@ hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const T
                          : ticket       ? queue_grid(mixed ? tp.grid32 : tp.grid64, n)
                                         : n;
         if (mixed)
-            hipLaunchKernelGGL(k_field_tz32, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
-                               pub2int, ticket);
+            hipLaunchKernelGGL(k_field_tz32, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n,
+                               static_cast<const float *>(tp.Ipub32), pub2int, ticket);
         else
             hipLaunchKernelGGL(k_field_tz64, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
                                pub2int, ticket);
@@ -746,9 +755,10 @@ hipError_t launch_fieldT_tz(const DevState &s, const RunConst &rc, const TzPlan 
                             const double *wz, double *wr_pub, double *wz_pub, const int *pub2int,
                             double *partT, hipStream_t st) {
     int *ticket = tp.ticket ? tp.ticket + 1 : nullptr;
-    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wr, s.perm, s.N, wr_pub, ticket);
+    hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wr, s.perm, s.N, wr_pub, ticket,
+                       static_cast<float *>(nullptr), s.elem_coil, s.coils);
     hipLaunchKernelGGL(k_to_pub, dim3((s.N + 255) / 256), dim3(256), 0, st, wz, s.perm, s.N, wz_pub,
-                       static_cast<int *>(nullptr));
+                       static_cast<int *>(nullptr), static_cast<float *>(nullptr), s.elem_coil, s.coils);
     const int n = tp.n;
     if (n > 0) {
         const bool mixed = rc.prec == COIL_MIXED;
