@@ -148,8 +148,11 @@ int coil_query(const coil_config *cfg, coil_sizes *out);
 
 /* Build a handle: validate, carve `workspace` (device memory, >= workspace_bytes,
    256-byte aligned), precompute geometry, per-layer inductance blocks (host,
-   FP64), the transport-flux pattern (device, FP64 all-pairs pass), heat
-   conductances, and zero the state (I = 0, T = T_bath, Phi = 0, Q = 0).
+   FP64), the transport-flux pattern (device, FP64 all-pairs pass), in mixed
+   precision the near kernel values of the translation pass (device, FP64,
+   stored in FP32), heat conductances, and zero the state (I = 0, T = T_bath,
+   Phi = 0, Q = 0).  COIL_E_INVAL also when the near-value table would exceed
+   2^31 entries.
    `stream` is a hipStream_t (NULL = default stream).  Synchronises once. */
 int coil_init(const coil_config *cfg, const coil_inputs *in, void *workspace,
               size_t workspace_bytes, void *stream, coil_t **out);
