@@ -37,20 +37,5 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
-CALIB = os.path.join(PKG, "calib", "fp32_fma_rate.hip")
-
-
-def build_calib() -> str:
-    """The FP32 FMA issue-rate program (a calibration of the roofline, not part of the library)."""
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    exe = CALIB[:-4]
-    cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           CALIB, "-o", exe]
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    return exe
-
-
 if __name__ == "__main__":
     print(build(verbose=True))
