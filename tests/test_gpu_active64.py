@@ -1,0 +1,99 @@
+"""Active regime at the wire size of the medium and adjoint configurations
+(8 x 8 = 64 elements per wire): flux penetrates, the resistive diagonal
+dt 2 pi r E'/d^2 of the per-wire system is no longer below FP64 resolution,
+and the wire solve factorises (the Cholesky branch of the forward and the
+adjoint wire kernels).  The GPU is compared with the oracle, and the adjoint
+with the oracle's tangent-linear model, at the stated tolerances: 1e-10 in
+FP64 and 1e-5 in mixed precision, normwise on B, I and T (T both literally
+and relative to its rise above the bath)."""
+import sys
+
+import numpy as np
+import pytest
+
+import coil_synth as cs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "mixed": 1e-5}
+
+
+def _pk():
+    import paper_2403_07666_amd as pk
+    return pk
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def nerr(a, b):
+    s = np.abs(b).max()
+    return float(np.abs(a - b).max() / s) if s > 0 else float(np.abs(a).max())
+
+
+def workload():
+    """2 layers x 3 turns of 8x8 elements with the medium configuration's
+    constants (dt 5e-5, 2 % log-normal disorder, seed 2) and a fast ramp
+    (2000 A/s) and Jc0 = 1e8 A/m^2: max |J|/Jc crosses 1 at step 26 and T
+    rises by about 0.02 K over 300 steps."""
+    base = cs.workload("c2_active")
+    return base.replace(name="active64", coils=[cs.Coil(layers=2, turns=3, ne=8, ramp=2000.0)], Jc0=1e8,
+                        weak_spots=0)
+
+
+@pytest.mark.parametrize("algo", ["direct", "translation"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_active_ne64_against_oracle(prec, algo):
+    pk = _pk()
+    w = workload()
+    inp = cs.generate(w)
+    _say("active64", prec, algo)
+    g = pk.Coil(w, inp, precision=prec, algo=algo)
+    o = oracle.Sim(w, inp)
+    tol = TOL[prec]
+    for k in range(3):
+        g.run(100)
+        assert o.run(100) == 0
+        To, Tg = o.get(oracle.T), g.get(pk.F_T)
+        rise = float((To - w.T_bath).max())
+        eb = max(nerr(g.get(pk.F_BR), o.get(oracle.BR)), nerr(g.get(pk.F_BZ), o.get(oracle.BZ)))
+        ei = nerr(g.get(pk.F_I), o.get(oracle.I))
+        ephi = nerr(g.get(pk.F_PHI), o.get(oracle.PHI))
+        et = nerr(Tg, To)
+        er = float(np.abs(Tg - To).max() / rise) if rise > 0 else 0.0
+        sg, so = g.scalars(), o.scalars()
+        eq = abs(sg["Q"] - so["Q"]) / so["Q"] if so["Q"] > 0 else abs(sg["Q"])
+        eqw = nerr(g.get(pk.F_QW), o.get(oracle.QW))
+        _say(f"  step {100 * (k + 1)}: B {eb:.2e} I {ei:.2e} Phi {ephi:.2e} T {et:.2e} dT {er:.2e} "
+             f"Q {eq:.2e} Qw {eqw:.2e} rise {rise:.3e} max_x {so['max_x']:.3f}")
+        assert max(eb, ei, ephi, et, er, eq, eqw) <= tol
+    assert so["max_x"] > 1.0 and rise > 0.01
+    assert abs(sg["T_peak"] - so["T_peak"]) <= tol * (so["T_peak"] - w.T_bath)
+    if prec == "fp64":
+        assert sg["T_peak_elem"] == so["T_peak_elem"] and sg["T_peak_step"] == so["T_peak_step"]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
+def test_active_ne64_adjoint_against_tangent(prec, tol):
+    """The adjoint's Cholesky branch at n_e = 64: gradient of Q and of T_peak
+    along two seeded directions in (c_w, ramp) against the oracle's
+    tangent-linear model over 200 steps."""
+    pk = _pk()
+    w = workload()
+    inp = cs.generate(w)
+    nsteps = 200
+    g = pk.Coil(w, inp, precision=prec)
+    for seed in (3, 4):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        dcw, dramp = rng.standard_normal(w.n_wire), rng.standard_normal(1) * 100.0
+        obj_o, dobj = oracle.tangent(w, inp, dcw, dramp, nsteps)
+        for wQ, wT, k in ((1.0, 0.0, 0), (0.0, 1.0, 1)):
+            gcw, gr, obj = g.adjoint(nsteps, wQ=wQ, wT=wT, ckpt_every=50)
+            dd = float(np.dot(gcw, dcw) + np.dot(gr, dramp))
+            _say(f"{prec} seed {seed} obj {k}: adjoint {dd:.12e} tangent {dobj[k]:.12e} "
+                 f"rel {abs(dd - dobj[k]) / abs(dobj[k]):.2e}")
+            assert abs(obj[0] - obj_o[0]) <= TOL[prec] * abs(obj_o[0])
+            assert abs(dd - dobj[k]) <= tol * abs(dobj[k])

@@ -79,7 +79,7 @@ def _direction(w, seed):
 
 
 @pytest.mark.parametrize("algo", ["direct", "translation"])
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("mixed", 2e-4)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
 def test_adjoint_matches_oracle_tangent(prec, tol, algo):
     pk = _pk()
     w = cs.workload("c1_active")
@@ -152,3 +152,41 @@ def test_adjoint_central_differences_384k():
         _say(f"wire {wi}: adjoint {gcw[wi]:.10e} fd {fd:.10e}")
         assert gcw[wi] == pytest.approx(fd, rel=1e-5)
     g.set_params(inp["c_wire"], None)
+
+
+@pytest.mark.timeout(900)
+def test_c5_active_central_differences_all_seeded_wires():
+    """The adjoint configuration at full size (60 layers x 100 turns x 8x8 =
+    384,000 elements) in its driven variant, FP64, over a 100-step horizon:
+    dQ/dc_w on all 20 seeded wires and dQ/d(ramp) against central differences
+    with h = 1e-4, relative error <= 1e-5."""
+    pk = _pk()
+    w = cs.workload("c5_active")
+    inp = cs.generate(w)
+    nsteps = 100
+    g = pk.Coil(w, inp, precision="fp64")
+    gcw, gr, obj = g.adjoint(nsteps, wQ=1.0, wT=0.0, ckpt_every=50)
+    _say(f"c5_active: Q {obj[0]:.6e}")
+    assert obj[0] > 1e-3
+    h = 1e-4
+    worst = 0.0
+    for wi in cs.fd_wires(w.n_wire, 20, 55):
+        vals = []
+        for sgn in (+1, -1):
+            cw = inp["c_wire"].copy()
+            cw[wi] += sgn * h
+            g.set_params(cw, None)
+            vals.append(g.objectives(nsteps)[0])
+        fd = (vals[0] - vals[1]) / (2 * h)
+        rel = abs(gcw[wi] - fd) / abs(fd)
+        worst = max(worst, rel)
+        _say(f"  wire {wi}: adjoint {gcw[wi]:.10e} fd {fd:.10e} rel {rel:.2e}")
+        assert rel <= 1e-5
+    g.set_params(inp["c_wire"], None)
+    rv = []
+    for sgn in (+1, -1):
+        g.set_params(None, np.array([w.coils[0].ramp + sgn * h]))
+        rv.append(g.objectives(nsteps)[0])
+    fdr = (rv[0] - rv[1]) / (2 * h)
+    _say(f"  ramp: adjoint {gr[0]:.10e} fd {fdr:.10e}; worst wire {worst:.2e}")
+    assert abs(gr[0] - fdr) <= 1e-5 * abs(fdr)

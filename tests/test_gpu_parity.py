@@ -168,9 +168,11 @@ def test_c1_active_run_temperature_and_joule(prec, algo):
     eb = max(nerr(g.get(pk.F_BR), o.get(oracle.BR)), nerr(g.get(pk.F_BZ), o.get(oracle.BZ)))
     ei = nerr(g.get(pk.F_I), o.get(oracle.I))
     _say(f"active {prec}: dT {et:.2e} Q {eq:.2e} Qw {eqw:.2e} B {eb:.2e} I {ei:.2e}")
-    tol = TOL[prec] * (1e2 if prec == "mixed" else 1e3)  # T rise is a small difference
-    assert et <= tol and eq <= tol and eqw <= tol
-    assert eb <= TOL[prec] * 10 and ei <= TOL[prec] * 10
+    etl = nerr(Tg, To)
+    _say(f"  literal T {etl:.2e}")
+    tol = TOL[prec]
+    assert et <= tol and etl <= tol and eq <= tol and eqw <= tol
+    assert eb <= tol and ei <= tol
     assert abs(sg["T_peak"] - so["T_peak"]) <= TOL[prec] * so["T_peak"]
     if prec == "fp64":
         assert sg["T_peak_elem"] == so["T_peak_elem"] and sg["T_peak_step"] == so["T_peak_step"]
