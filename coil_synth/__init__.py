@@ -93,6 +93,11 @@ class Workload:
     h0: float = 500.0
     T_bath: float = 4.2
     dBa_dt: float = 0.0  # background axial field ramp, T/s
+    rho_n: float = 0.0  # normal-state resistivity in parallel with the power law, Ohm m (0 = off)
+    k_exp: float = 0.0  # k = k0 (T/T_ref)^k_exp
+    h_exp: float = 0.0  # h = h0 (T/T_ref)^h_exp
+    coupling: str = "transport"  # inter-wire induction: "transport" or "full"
+    heat_solver: str = "explicit"  # "explicit" (sub-cycled) or "adi"
     heat_substeps: int = 0  # 0 = automatic (stability rule)
     # disorder recipe
     seed: int = 1
@@ -195,6 +200,24 @@ def _c5() -> Workload:
     )
 
 
+def _quench20() -> Workload:
+    """The paper's quench study (Results, quenches propagation in a coil):
+    20 x 20 turns under a 2 A/s transport ramp and a 0.015 T/s background
+    ramp, here with 8x8 elements per wire and the normal-state resistivity
+    of a copper-stabilised wire."""
+    return Workload(
+        name="quench20",
+        coils=[Coil(layers=20, turns=20, ne=8, ramp=2.0)],
+        steps=4000,
+        dt=5.0e-5,
+        seed=20,
+        jc_disorder=("lognormal", 0.02),
+        dBa_dt=0.015,
+        rho_n=3.0e-10,
+        precision="mixed",
+    )
+
+
 def _draw_ensemble(rng: np.random.Generator, rec: dict) -> List[Coil]:
     n = rec["n"]
     layers = rng.choice(np.array(rec["layers"]), n)
@@ -210,8 +233,10 @@ def _draw_ensemble(rng: np.random.Generator, rec: dict) -> List[Coil]:
 # Joule source is non-zero and T rises.  The literal workloads stay deeply
 # sub-critical (|J|/Jc ~ 1e-5): there E ~ Ec (|J|/Jc)^30 is ~1e-150 V/m and T
 # stays at the bath temperature to the last bit.
-# name -> (ramp multiplier, Jc0 in A/m^2)
+# name -> (ramp multiplier, Jc0 in A/m^2); the background field ramp is
+# scaled like the transport ramp
 ACTIVE = {
+    "quench20": (1000.0, 5.0e8),
     "c1": (1000.0, 5.0e8),
     "c3": (1000.0, 5.0e8),
     "c2": (1000.0, 5.0e8),
@@ -226,6 +251,7 @@ WORKLOADS = {
     "c3": _c3,
     "c4": _c4,
     "c5": _c5,
+    "quench20": _quench20,
 }
 
 
@@ -237,7 +263,7 @@ def workload(name: str) -> Workload:
         w = WORKLOADS[base]()
         mult, jc0 = ACTIVE[base]
         coils = [dataclasses.replace(c, ramp=c.ramp * mult) for c in w.coils]
-        return w.replace(name=w.name + "_active", Jc0=jc0, coils=coils)
+        return w.replace(name=w.name + "_active", Jc0=jc0, coils=coils, dBa_dt=w.dBa_dt * mult)
     return WORKLOADS[name]()
 
 

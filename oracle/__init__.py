@@ -22,6 +22,9 @@ MAXC = 64
 
 # field ids (coil_oracle.h)
 I, J, BR, BZ, T, PHI, QW, UW, E, EP, U, Q, PSI, R, Z, V, JC, DI = range(18)
+# per-wire flux-jump / quench diagnostics
+ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH = range(18, 24)
+PER_WIRE = (QW, UW, ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH)
 
 
 def build(force: bool = True) -> str:
@@ -49,6 +52,8 @@ class Cfg(C.Structure):
         ("k0", C.c_double), ("h0", C.c_double), ("T_bath", C.c_double),
         ("dt", C.c_double),
         ("n_sub", C.c_int), ("planar", C.c_int),
+        ("rho_n", C.c_double),
+        ("coupling", C.c_int),
     ]
 
 
@@ -158,6 +163,8 @@ def make_cfg(w, n_sub: int | None = None, planar: bool = False) -> Cfg:
         setattr(c, k, float(getattr(w, k)))
     c.n_sub = int(w.heat_substeps if n_sub is None else n_sub)
     c.planar = 1 if planar else 0
+    c.rho_n = float(getattr(w, "rho_n", 0.0))
+    c.coupling = {"transport": 0, "full": 1}[getattr(w, "coupling", "transport")]
     return c
 
 
@@ -194,7 +201,7 @@ class Sim:
         return lib().orc_run(self.h, int(n))
 
     def get(self, field: int) -> np.ndarray:
-        n = self.Nw if field in (QW, UW) else self.N
+        n = self.Nw if field in PER_WIRE else self.N
         out = np.empty(n, dtype=np.float64)
         rc = lib().orc_get(self.h, field, _p(out), n)
         if rc:

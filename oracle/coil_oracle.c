@@ -30,10 +30,16 @@
  *      distance of a square section, g = 0.4470491559036625 d.
  *   R3 inter-wire coupling in Faraday's law: transport current of the other
  *      wires only (static pattern Psi_u times dI_t); the all-pairs B from
- *      every element current enters through Jc(B).
+ *      every element current enters through Jc(B).  Option coupling = 1: the
+ *      flux of every element current of the coil (the converged form of the
+ *      paper's field iteration), one dense constrained solve per coil.
  *   R4 A-V: 2 pi r_e E_e + U_w = -dPhi_e/dt, sum_{e in w} I_e = I_t.
  *   R5 time integrator: linearised backward Euler per wire.
  *   R6 order: field -> local -> wire solve -> heat; Jc, E from (B^k, T^k).
+ *   R7 normal state: pure power law by default (Jc <= 0 with J != 0 is an
+ *      error); with rho_n > 0 the power-law resistivity acts in parallel with
+ *      the normal-state resistivity rho_n (flux creep, flux flow and normal
+ *      state in one law), and Jc <= 0 is the normal state.
  *   R8 Joule source: q = (E + E' dI/d^2) J^{k+1}.
  *   R9 heat substeps n_sub = max(1, ceil(dt / (0.9 h_max))) (1e-9 relative
  *      tolerance on the quotient), h_max the explicit stability limit at T_bath.
@@ -173,6 +179,66 @@ double orc_self_L(double r, double d) {
 }
 
 /* ------------------------------------------------------------------ */
+/* local E-J law (paper, Methods, E-J paragraph; readings R7)          */
+/* ------------------------------------------------------------------ */
+/* E(J) and dE/dJ at one element for a given Jc.  Power law E = Ec x^n sgn J,
+   x = |J| / Jc.  With rho_n > 0 the power-law resistivity
+   rho_pl = E/J = (Ec/Jc) x^(n-1) is in parallel with rho_n:
+   rho = rho_pl rho_n / (rho_pl + rho_n), E = rho J, so that
+   dE/dJ = rho_n * p/(p + rho_n) * (n rho_n + p)/(rho_n + p) with p = rho_pl;
+   Jc <= 0 (T >= Tc) is then the normal state E = rho_n J.  Returns 1 when the
+   pure power law meets Jc <= 0 with J != 0 (no finite E). */
+static int local_EJ(const orc_cfg *c, double J, double Jc, double *E, double *Ep, double *x) {
+    if (c->rho_n > 0.0 && !(Jc > 0.0)) {
+        *E = c->rho_n * J;
+        *Ep = c->rho_n;
+        *x = (J != 0.0) ? INFINITY : 0.0;
+        return 0;
+    }
+    if (J == 0.0) { *E = 0.0; *Ep = 0.0; *x = 0.0; return 0; }
+    if (!(Jc > 0.0)) { *E = NAN; *Ep = NAN; *x = INFINITY; return 1; }
+    *x = fabs(J) / Jc;
+    if (c->rho_n > 0.0) {
+        const double p = c->Ec / Jc * pow(*x, c->n - 1.0);
+        if (!isfinite(p)) { *E = c->rho_n * J; *Ep = c->rho_n; return 0; }
+        const double sfr = p / (p + c->rho_n);
+        *E = c->rho_n * sfr * J;
+        *Ep = c->rho_n * sfr * ((c->n * c->rho_n + p) / (c->rho_n + p));
+        return 0;
+    }
+    *E = c->Ec * pow(*x, c->n) * (J > 0.0 ? 1.0 : -1.0);
+    *Ep = c->n * c->Ec / Jc * pow(*x, c->n - 1.0);
+    return 0;
+}
+
+/* directional derivatives dE, dE' of the law above for perturbations dJ, dJc */
+static void local_EJ_tangent(const orc_cfg *c, double J, double Jc, double dJ, double dJc,
+                             double *dE, double *dEp) {
+    *dE = 0.0;
+    *dEp = 0.0;
+    if (c->rho_n > 0.0 && !(Jc > 0.0)) { *dE = c->rho_n * dJ; return; }
+    if (J == 0.0 || !(Jc > 0.0)) return;
+    const double x = fabs(J) / Jc;
+    if (c->rho_n > 0.0) {
+        const double rn = c->rho_n, n = c->n;
+        const double p = c->Ec / Jc * pow(x, n - 1.0);
+        if (!isfinite(p)) { *dE = rn * dJ; return; }
+        /* p = Ec |J|^(n-1) / Jc^n */
+        const double dp = p * ((n - 1.0) * dJ / J - n * dJc / Jc);
+        const double sfr = p / (p + rn), tfr = (n * rn + p) / (rn + p);
+        const double dsfr = rn * dp / ((p + rn) * (p + rn));
+        const double dtfr = (1.0 - n) * rn * dp / ((p + rn) * (p + rn));
+        *dE = rn * (sfr * dJ + J * dsfr);
+        *dEp = rn * (dsfr * tfr + sfr * dtfr);
+        return;
+    }
+    const double sg = J > 0.0 ? 1.0 : -1.0;
+    const double dx = x * (dJ / J - dJc / Jc);
+    *dE = c->Ec * c->n * pow(x, c->n - 1.0) * dx * sg;
+    *dEp = c->n * c->Ec * ((c->n - 1.0) * pow(x, c->n - 2.0) * dx / Jc - pow(x, c->n - 1.0) * dJc / (Jc * Jc));
+}
+
+/* ------------------------------------------------------------------ */
 /* simulation state                                                    */
 /* ------------------------------------------------------------------ */
 struct orc_sim {
@@ -191,6 +257,7 @@ struct orc_sim {
     double *cw;                  /* per-wire multiplier */
     /* precompute */
     double **Mww;                /* per wire, wn x wn row-major */
+    double **Mc;                 /* coupling 1: per coil, its full N_c x N_c inductance matrix */
     double *psi;                 /* transport flux pattern per element */
     long *nb;                    /* 4 neighbours per element, -1 = border */
     double *G;                   /* 4 face conductances */
@@ -199,6 +266,8 @@ struct orc_sim {
     double *I, *u, *T, *Phi, *Br, *Bz, *E, *Ep, *Jc, *dI, *q, *Qw, *U;
     double Q, Tpeak, Qout, maxx, sumU;
     long step, Tpeak_e, Tpeak_k;
+    /* per-wire flux-jump / quench diagnostics (see ORC_ONSET .. ORC_P_QUENCH) */
+    double *onset, *quench, *Qon, *Qqu, *Tqu, *Pqu;
     int field_only;  /* geometry only: no inductance blocks, no transport flux */
 };
 
@@ -225,8 +294,12 @@ static int cfg_valid(const orc_cfg *c) {
     if (!(c->dt > 0) || !(c->Ec > 0) || !(c->n >= 1) || !(c->Jc0 > 0)) return 0;
     if (!(c->Tc > 0) || !(c->B0 > 0) || !(c->C0 > 0) || !(c->T_ref > 0)) return 0;
     if (!(c->k0 > 0) || !(c->h0 >= 0) || !(c->T_bath > 0)) return 0;
+    if (!(c->rho_n >= 0) || !isfinite(c->rho_n)) return 0;
+    if (c->coupling != 0 && c->coupling != 1) return 0;
+    for (int i = 0; i < c->n_coils && c->coupling == 1; ++i)
+        if ((long)c->layers[i] * c->turns[i] * c->ne[i] * c->ne[i] > 4096) return 0;
     for (int i = 0; i < c->n_coils; ++i)
-        if (c->I0[i] != 0.0) return 0; /* runs start from zero current */
+        if (!isfinite(c->I0[i])) return 0;
     return 1;
 }
 
@@ -389,6 +462,18 @@ orc_sim *orc_create_ex(const orc_cfg *cfg, const double *jc0_mult, const double 
             }
         s->Mww[w] = M;
     }
+    /* coupling 1: each coil's full inductance matrix (public order inside the coil) */
+    s->Mc = (double **)calloc((size_t)c->n_coils, sizeof(double *));
+    for (int ci = 0; ci < c->n_coils && c->coupling == 1 && !field_only; ++ci) {
+        const long o = s->coil_off[ci], n = s->coil_off[ci + 1] - o;
+        double *M = dalloc(n * n);
+        #pragma omp parallel for schedule(dynamic, 8)
+        for (long i = 0; i < n; ++i)
+            for (long j = 0; j < n; ++j)
+                M[i * n + j] = (i == j) ? orc_self_L(s->r[o + i], s->d[o + i])
+                                        : orc_ring_M(s->r[o + j], s->z[o + j], s->r[o + i], s->z[o + i]);
+        s->Mc[ci] = M;
+    }
     /* transport flux pattern (R3): flux through ring e per ampere of transport
        current carried uniformly by every other wire of the same coil */
     s->psi = dalloc(N);
@@ -412,7 +497,15 @@ orc_sim *orc_create_ex(const orc_cfg *cfg, const double *jc0_mult, const double 
     s->Br = dalloc(N); s->Bz = dalloc(N); s->E = dalloc(N); s->Ep = dalloc(N);
     s->Jc = dalloc(N); s->dI = dalloc(N); s->q = dalloc(N);
     s->Qw = dalloc(Nw); s->U = dalloc(Nw);
+    s->onset = dalloc(Nw); s->quench = dalloc(Nw); s->Qon = dalloc(Nw);
+    s->Qqu = dalloc(Nw); s->Tqu = dalloc(Nw); s->Pqu = dalloc(Nw);
+    for (long w = 0; w < Nw; ++w) { s->onset[w] = -1.0; s->quench[w] = -1.0; }
     for (long e = 0; e < N; ++e) s->T[e] = c->T_bath;
+    /* initial transport current I0 of each coil, spread evenly over the
+       elements of each of its wires */
+    for (long w = 0; w < Nw; ++w)
+        for (int i = 0; i < s->wn[w]; ++i)
+            s->I[s->welem[s->wire_off[w] + i]] = c->I0[s->wcoil[w]] / (double)s->wn[w];
     s->Tpeak = c->T_bath;
     s->Tpeak_e = -1;
     s->Tpeak_k = -1;
@@ -423,9 +516,12 @@ void orc_destroy(orc_sim *s) {
     if (!s) return;
     if (s->Mww) for (long w = 0; w < s->Nw; ++w) free(s->Mww[w]);
     free(s->Mww);
+    if (s->Mc) for (int ci = 0; ci < s->cfg.n_coils; ++ci) free(s->Mc[ci]);
+    free(s->Mc);
     void *p[] = {s->r, s->z, s->d, s->V, s->coil, s->wire, s->coil_off, s->wire_off, s->welem,
                  s->wn, s->wcoil, s->jcs, s->cw, s->psi, s->nb, s->G, s->Gb, s->I, s->u, s->T,
-                 s->Phi, s->Br, s->Bz, s->E, s->Ep, s->Jc, s->dI, s->q, s->Qw, s->U};
+                 s->Phi, s->Br, s->Bz, s->E, s->Ep, s->Jc, s->dI, s->q, s->Qw, s->U,
+                 s->onset, s->quench, s->Qon, s->Qqu, s->Tqu, s->Pqu};
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(s);
 }
@@ -509,6 +605,79 @@ static void chol_solve(const double *L, int n, double *x) { /* L L^T x = b in pl
 }
 
 /* ------------------------------------------------------------------ */
+/* coupled A-V solve (coupling = 1)                                    */
+/* ------------------------------------------------------------------ */
+/* Every ring e of a coil obeys 2 pi r_e E_e + U_w(e) = -dPhi_e/dt with the
+   flux Phi_e = sum_j M_ej I_j + pi r_e^2 B_a of ALL element currents of the
+   coil, and every wire carries the transport current.  Linearised backward
+   Euler (E at I + dI is E + E' dI/d^2):
+     A dI + dt P U = b,   P^T dI = dI_t 1,
+     A = M + dt diag(2 pi r E'/d^2),  b = -pi r^2 dB_a - dt 2 pi r E,
+   with P the element-to-wire incidence.  Solved per coil by a Cholesky
+   factorisation of A: X = A^-1 b, Y = A^-1 P, then the loop voltages from
+   (P^T Y) dt U = P^T X - dI_t 1 (the Schur complement, SPD), dI = X - Y dt U.
+   The flux is updated as Phi += M dI + pi r^2 dB_a. */
+static int coupled_solve(orc_sim *s, double dBa) {
+    const orc_cfg *c = &s->cfg;
+    const double dt = c->dt;
+    int bad = 0;
+    for (int ci = 0; ci < c->n_coils && !bad; ++ci) {
+        const long o = s->coil_off[ci], n = s->coil_off[ci + 1] - o;
+        const double dIt = c->ramp[ci] * dt;
+        /* wires of the coil: the wire index of every element, local numbering */
+        long w0 = -1, nw = 0;
+        for (long w = 0; w < s->Nw; ++w)
+            if (s->wcoil[w] == ci) { if (w0 < 0) w0 = w; ++nw; }
+        double *A = dalloc(n * n), *X = dalloc(n), *Y = dalloc(n * nw), *S = dalloc(nw * nw);
+        double *u = dalloc(nw), *MdI = dalloc(n);
+        memcpy(A, s->Mc[ci], sizeof(double) * (size_t)(n * n));
+        for (long i = 0; i < n; ++i) {
+            const long e = o + i;
+            const double d2 = s->d[e] * s->d[e];
+            A[i * n + i] += dt * 2.0 * ORC_PI * s->r[e] * s->Ep[e] / d2;
+            X[i] = -ORC_PI * s->r[e] * s->r[e] * dBa - dt * 2.0 * ORC_PI * s->r[e] * s->E[e];
+        }
+        if (cholesky(A, (int)n) != 0) { bad = 1; goto done; }
+        chol_solve(A, (int)n, X);
+        #pragma omp parallel for schedule(dynamic, 1)
+        for (long v = 0; v < nw; ++v) {
+            double *col = dalloc(n);
+            for (long i = 0; i < n; ++i) col[i] = (s->wire[o + i] == w0 + v) ? 1.0 : 0.0;
+            chol_solve(A, (int)n, col);
+            for (long i = 0; i < n; ++i) Y[i * nw + v] = col[i];
+            free(col);
+        }
+        for (long i = 0; i < n; ++i) {
+            const long wi = s->wire[o + i] - w0;
+            u[wi] += X[i];
+            for (long v = 0; v < nw; ++v) S[wi * nw + v] += Y[i * nw + v];
+        }
+        for (long v = 0; v < nw; ++v) u[v] -= dIt;
+        if (cholesky(S, (int)nw) != 0) { bad = 1; goto done; }
+        chol_solve(S, (int)nw, u);  /* u = dt U */
+        for (long v = 0; v < nw; ++v) s->U[w0 + v] = u[v] / dt;
+        for (long i = 0; i < n; ++i) {
+            double dI = X[i];
+            for (long v = 0; v < nw; ++v) dI -= Y[i * nw + v] * u[v];
+            s->dI[o + i] = dI;
+        }
+        #pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) {
+            double v = 0.0;
+            for (long j = 0; j < n; ++j) v += s->Mc[ci][i * n + j] * s->dI[o + j];
+            MdI[i] = v;
+        }
+        for (long i = 0; i < n; ++i) {
+            const long e = o + i;
+            s->Phi[e] += MdI[i] + ORC_PI * s->r[e] * s->r[e] * dBa;
+        }
+    done:
+        free(A); free(X); free(Y); free(S); free(u); free(MdI);
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ */
 /* one time step                                                       */
 /* ------------------------------------------------------------------ */
 int orc_step(orc_sim *s) {
@@ -539,21 +708,44 @@ int orc_step(orc_sim *s) {
         const double fT = fmax(0.0, 1.0 - s->T[e] / c->Tc);
         const double Jc = s->cw[s->wire[e]] * s->jcs[e] * fT * c->B0 / (c->B0 + Bm);
         s->Jc[e] = Jc;
-        if (J == 0.0) {
-            s->E[e] = 0.0;
-            s->Ep[e] = 0.0;
-            continue;
-        }
-        if (!(Jc > 0.0)) { bad = 1; s->E[e] = NAN; s->Ep[e] = NAN; continue; }
-        const double x = fabs(J) / Jc;
+        double x;
+        if (local_EJ(c, J, Jc, &s->E[e], &s->Ep[e], &x)) bad = 1;
         if (x > maxx) maxx = x;
-        s->E[e] = c->Ec * pow(x, c->n) * (J > 0.0 ? 1.0 : -1.0);
-        s->Ep[e] = c->n * c->Ec / Jc * pow(x, c->n - 1.0);
     }
 
-    /* 3. per-wire A-V solve, linearised backward Euler */
-    #pragma omp parallel for schedule(dynamic, 4)
+    /* flux-jump onset (|J/Jc| > 1) and quench (rho > 0.95 rho_n) of each wire,
+       from the local law of this step (paper, Results: flux jumps and quenches
+       propagation in a coil) */
     for (long w = 0; w < Nw; ++w) {
+        const long *el = s->welem + s->wire_off[w];
+        double xw = 0.0, sEJ = 0.0, sJJ = 0.0, sV = 0.0, Tw = -INFINITY;
+        for (int i = 0; i < s->wn[w]; ++i) {
+            const long e = el[i];
+            const double d2 = s->d[e] * s->d[e];
+            const double J = s->I[e] / d2;
+            const double x = (J == 0.0) ? 0.0 : (s->Jc[e] > 0.0 ? fabs(J) / s->Jc[e] : INFINITY);
+            if (x > xw) xw = x;
+            sEJ += s->V[e] * s->E[e] * J;
+            sJJ += s->V[e] * J * J;
+            sV += s->V[e];
+            if (s->T[e] > Tw) Tw = s->T[e];
+        }
+        if (s->onset[w] < 0.0 && xw > 1.0) {
+            s->onset[w] = (double)s->step;
+            s->Qon[w] = s->Qw[w];
+        }
+        if (c->rho_n > 0.0 && s->quench[w] < 0.0 && sJJ > 0.0 && sEJ / sJJ > 0.95 * c->rho_n) {
+            s->quench[w] = (double)s->step;
+            s->Qqu[w] = s->Qw[w];
+            s->Tqu[w] = Tw;
+            s->Pqu[w] = sEJ / sV;
+        }
+    }
+
+    /* 3. A-V solve, linearised backward Euler */
+    if (c->coupling == 1 && coupled_solve(s, dBa)) return -4;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (long w = 0; w < (c->coupling == 1 ? 0 : Nw); ++w) {
         const int n = s->wn[w];
         const int ci = s->wcoil[w];
         const double dIt = c->ramp[ci] * dt;
@@ -683,6 +875,12 @@ int orc_get(const orc_sim *s, int field, double *dst, long count) {
         case ORC_V: src = s->V; break;
         case ORC_JC: src = s->Jc; break;
         case ORC_DI: src = s->dI; break;
+        case ORC_ONSET: src = s->onset; n = Nw; break;
+        case ORC_QUENCH: src = s->quench; n = Nw; break;
+        case ORC_Q_ONSET: src = s->Qon; n = Nw; break;
+        case ORC_Q_QUENCH: src = s->Qqu; n = Nw; break;
+        case ORC_T_QUENCH: src = s->Tqu; n = Nw; break;
+        case ORC_P_QUENCH: src = s->Pqu; n = Nw; break;
         case ORC_J:
             if (count < N) return -1;
             for (long e = 0; e < N; ++e) dst[e] = s->I[e] / (s->d[e] * s->d[e]);
@@ -741,6 +939,7 @@ int orc_scalars(const orc_sim *s, double *dst, int n) {
 int orc_tangent(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
                 const double *c_wire, const double *dc_wire, const double *dramp,
                 long nsteps, double *obj, double *dobj) {
+    if (cfg->coupling != 0) return -1;
     orc_sim *s = orc_create(cfg, jc0_mult, strain, c_wire);
     if (!s) return -1;
     const orc_cfg *c = &s->cfg;
@@ -768,7 +967,7 @@ int orc_tangent(const orc_cfg *cfg, const double *jc0_mult, const double *strain
             const double J = Ik[e] / d2;
             dE[e] = 0.0;
             dEp[e] = 0.0;
-            if (J == 0.0) continue;
+            if (J == 0.0 && !(c->rho_n > 0.0)) continue;
             const double Br = s->Br[e], Bz = s->Bz[e];
             const double Bm = sqrt(Br * Br + Bz * Bz);
             const double dBm = Bm > 0.0 ? (Br * dBr[e] + Bz * dBz[e]) / Bm : 0.0;
@@ -782,12 +981,7 @@ int orc_tangent(const orc_cfg *cfg, const double *jc0_mult, const double *strain
             const double Jc = s->Jc[e];
             const double dJc = (dc_wire ? dc_wire[w] : 0.0) * s->jcs[e] * fT * fB
                              + s->cw[w] * s->jcs[e] * (dfT * fB + fT * dfB);
-            const double x = fabs(J) / Jc;
-            const double dx = x * ((dI[e] / d2) / J - dJc / Jc);
-            const double sg = J > 0.0 ? 1.0 : -1.0;
-            dE[e] = c->Ec * c->n * pow(x, c->n - 1.0) * dx * sg;
-            dEp[e] = c->n * c->Ec * ((c->n - 1.0) * pow(x, c->n - 2.0) * dx / Jc
-                                     - pow(x, c->n - 1.0) * dJc / (Jc * Jc));
+            local_EJ_tangent(c, J, Jc, dI[e] / d2, dJc, &dE[e], &dEp[e]);
         }
         /* 3. per-wire KKT tangent */
         #pragma omp parallel for schedule(dynamic, 4)

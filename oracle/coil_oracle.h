@@ -38,6 +38,10 @@ typedef struct {
     double dt;
     int n_sub;   /* heat substeps per step; 0 = automatic stability rule */
     int planar;  /* 1: heat in planar (Cartesian) geometry, test use only */
+    double rho_n;  /* normal-state resistivity in parallel with the power law (0 = off) */
+    int coupling;  /* 0: other wires through their transport current (R3);
+                      1: every element current of the coil (dense solve; coils of
+                      at most 4096 elements) */
 } orc_cfg;
 
 typedef struct orc_sim orc_sim;
@@ -78,7 +82,17 @@ int    orc_run(orc_sim *s, long nsteps);
 /* field names for orc_get / orc_set */
 enum { ORC_I = 0, ORC_J = 1, ORC_BR = 2, ORC_BZ = 3, ORC_T = 4, ORC_PHI = 5,
        ORC_QW = 6, ORC_UW = 7, ORC_E = 8, ORC_EP = 9, ORC_U = 10, ORC_Q = 11,
-       ORC_PSI = 12, ORC_R = 13, ORC_Z = 14, ORC_V = 15, ORC_JC = 16, ORC_DI = 17 };
+       ORC_PSI = 12, ORC_R = 13, ORC_Z = 14, ORC_V = 15, ORC_JC = 16, ORC_DI = 17,
+       /* per-wire flux-jump and quench diagnostics (N_w entries each):
+          ORC_ONSET  first step k with max_e |J_e^k| / Jc_e^k > 1, -1 if none;
+          ORC_QUENCH first step k with rho_w^k > 0.95 rho_n, -1 if none, where
+                     rho_w^k = sum_e V E J / sum_e V J^2 of the step's local law;
+          ORC_Q_ONSET, ORC_Q_QUENCH  the wire's Joule heat accumulated before
+                     those steps; ORC_T_QUENCH the wire's max T^k and
+                     ORC_P_QUENCH its power density sum V E J / sum V at the
+                     quench step */
+       ORC_ONSET = 18, ORC_QUENCH = 19, ORC_Q_ONSET = 20, ORC_Q_QUENCH = 21,
+       ORC_T_QUENCH = 22, ORC_P_QUENCH = 23 };
 int    orc_get(const orc_sim *s, int field, double *dst, long count);
 int    orc_set(orc_sim *s, int field, const double *src, long count);
 /* scalars: [0]=t, [1]=step, [2]=Q, [3]=T_peak, [4]=sum U_w, [5]=max |J|/Jc,
@@ -96,7 +110,8 @@ void   orc_field_points(const orc_sim *s, const double *I, long np, const double
 /* elements of wire w (public indices), returns count */
 int    orc_wire_elems(const orc_sim *s, long w, long *dst);
 
-/* tangent-linear (forward-mode) derivative of the run's objectives
+/* tangent-linear (forward-mode) derivative (coupling 0 only; returns -1 for
+   coupling 1) of the run's objectives
    Q (time-integrated Joule heat) and T_peak along the direction
    (dc_wire[Nw], dramp[n_coils]) for nsteps from the initial state.
    obj[2] = (Q, T_peak), dobj[2] = directional derivatives. */
