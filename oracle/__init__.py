@@ -24,6 +24,7 @@ MAXC = 64
 I, J, BR, BZ, T, PHI, QW, UW, E, EP, U, Q, PSI, R, Z, V, JC, DI = range(18)
 # per-wire flux-jump / quench diagnostics
 ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH = range(18, 24)
+KMULT = 24  # per-element conductivity multiplier of the ADI heat step
 PER_WIRE = (QW, UW, ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH)
 
 
@@ -54,6 +55,8 @@ class Cfg(C.Structure):
         ("n_sub", C.c_int), ("planar", C.c_int),
         ("rho_n", C.c_double),
         ("coupling", C.c_int),
+        ("heat_solver", C.c_int),
+        ("k_exp", C.c_double), ("h_exp", C.c_double), ("ins_R0", C.c_double),
     ]
 
 
@@ -165,6 +168,10 @@ def make_cfg(w, n_sub: int | None = None, planar: bool = False) -> Cfg:
     c.planar = 1 if planar else 0
     c.rho_n = float(getattr(w, "rho_n", 0.0))
     c.coupling = {"transport": 0, "full": 1}[getattr(w, "coupling", "transport")]
+    c.heat_solver = {"explicit": 0, "adi": 1}[getattr(w, "heat_solver", "explicit")]
+    c.k_exp = float(getattr(w, "k_exp", 0.0))
+    c.h_exp = float(getattr(w, "h_exp", 0.0))
+    c.ins_R0 = float(getattr(w, "ins_R0", 0.0))
     return c
 
 

@@ -44,7 +44,10 @@
  *   R9 heat substeps n_sub = max(1, ceil(dt / (0.9 h_max))) (1e-9 relative
  *      tolerance on the quotient), h_max the explicit stability limit at T_bath.
  *   R10 axisymmetric finite volumes, half-cell series resistance at borders.
- *   R11 constant k and h, C = C0 (T/T_ref)^p, enthalpy form.
+ *   R11 constant k and h, C = C0 (T/T_ref)^p, enthalpy form.  Option
+ *      heat_solver = 1: the paper's ADI scheme with k and h proportional to
+ *      (T/T_ref)^k_exp, (T/T_ref)^h_exp, a per-element conductivity map and an
+ *      insulation resistance between wires (composite cross-section).
  * Every reading is listed with its justification in the design notes.
  *
  * Elliptic integrals: Carlson's symmetric forms R_F, R_D by the duplication
@@ -268,6 +271,7 @@ struct orc_sim {
     long step, Tpeak_e, Tpeak_k;
     /* per-wire flux-jump / quench diagnostics (see ORC_ONSET .. ORC_P_QUENCH) */
     double *onset, *quench, *Qon, *Qqu, *Tqu, *Pqu;
+    double *kmult;               /* ADI heat: conductivity multiplier per element */
     int field_only;  /* geometry only: no inductance blocks, no transport flux */
 };
 
@@ -296,6 +300,9 @@ static int cfg_valid(const orc_cfg *c) {
     if (!(c->k0 > 0) || !(c->h0 >= 0) || !(c->T_bath > 0)) return 0;
     if (!(c->rho_n >= 0) || !isfinite(c->rho_n)) return 0;
     if (c->coupling != 0 && c->coupling != 1) return 0;
+    if (c->heat_solver != 0 && c->heat_solver != 1) return 0;
+    if (!isfinite(c->k_exp) || !isfinite(c->h_exp) || !(c->ins_R0 >= 0) || !isfinite(c->ins_R0)) return 0;
+    if (c->heat_solver == 0 && (c->k_exp != 0.0 || c->h_exp != 0.0 || c->ins_R0 != 0.0)) return 0;
     for (int i = 0; i < c->n_coils && c->coupling == 1; ++i)
         if ((long)c->layers[i] * c->turns[i] * c->ne[i] * c->ne[i] > 4096) return 0;
     for (int i = 0; i < c->n_coils; ++i)
@@ -369,7 +376,9 @@ static void build_heat(orc_sim *s) {
             if (h < hmax) hmax = h;
         }
     }
-    if (c->n_sub > 0) {
+    if (c->heat_solver == 1) {
+        s->n_sub = 1;  /* one implicit step */
+    } else if (c->n_sub > 0) {
         s->n_sub = c->n_sub;
     } else {
         const double qt = c->dt / (0.9 * hmax);
@@ -500,6 +509,8 @@ orc_sim *orc_create_ex(const orc_cfg *cfg, const double *jc0_mult, const double 
     s->onset = dalloc(Nw); s->quench = dalloc(Nw); s->Qon = dalloc(Nw);
     s->Qqu = dalloc(Nw); s->Tqu = dalloc(Nw); s->Pqu = dalloc(Nw);
     for (long w = 0; w < Nw; ++w) { s->onset[w] = -1.0; s->quench[w] = -1.0; }
+    s->kmult = dalloc(N);
+    for (long e = 0; e < N; ++e) s->kmult[e] = 1.0;
     for (long e = 0; e < N; ++e) s->T[e] = c->T_bath;
     /* initial transport current I0 of each coil, spread evenly over the
        elements of each of its wires */
@@ -521,7 +532,7 @@ void orc_destroy(orc_sim *s) {
     void *p[] = {s->r, s->z, s->d, s->V, s->coil, s->wire, s->coil_off, s->wire_off, s->welem,
                  s->wn, s->wcoil, s->jcs, s->cw, s->psi, s->nb, s->G, s->Gb, s->I, s->u, s->T,
                  s->Phi, s->Br, s->Bz, s->E, s->Ep, s->Jc, s->dI, s->q, s->Qw, s->U,
-                 s->onset, s->quench, s->Qon, s->Qqu, s->Tqu, s->Pqu};
+                 s->onset, s->quench, s->Qon, s->Qqu, s->Tqu, s->Pqu, s->kmult};
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(s);
 }
@@ -678,6 +689,163 @@ static int coupled_solve(orc_sim *s, double dBa) {
 }
 
 /* ------------------------------------------------------------------ */
+/* ADI heat step (heat_solver = 1)                                     */
+/* ------------------------------------------------------------------ */
+/* Peaceman-Rachford alternating-direction implicit step on the finite
+   volumes (paper, Methods, heat paragraph: ADI on the composite coil, with
+   c, kappa and h proportional to T^3).  Coefficients frozen at T^n:
+   C = dU/dT, k_e = k0 (T_e/T_ref)^k_exp kmult_e, h_e = h0 (T_e/T_ref)^h_exp;
+   face conductance G_ef = A / (d/(2 k_e) + d/(2 k_f) + R_ef), R_ef the
+   insulation resistance ins_R0 (T_ref / T_face)^k_exp, T_face = (T_e + T_f)/2,
+   on faces between different wires; border G^b = A / (1/h_e + d/(2 k_e)).
+   With L_r, L_z the radial and axial parts of the net inflow (borders
+   included) and q held fixed:
+     V C (T* - T^n) / (dt/2)  = L_r(T*)  + L_z(T^n) + V q   (tridiagonal in r)
+     V C (T** - T*) / (dt/2)  = L_r(T*)  + L_z(T**) + V q   (tridiagonal in z)
+   and the enthalpy takes the inflow of those two half steps,
+     u^{n+1} = u^n + (dt/V) [L_r(T*) + (L_z(T^n) + L_z(T**))/2] + dt q,
+   T^{n+1} = T(u^{n+1}), so that interior fluxes cancel and the energy balance
+   is exact.  Tridiagonal systems by the Thomas algorithm. */
+static double k_at(const orc_sim *s, long e, double T) {
+    const orc_cfg *c = &s->cfg;
+    return c->k0 * pow(T / c->T_ref, c->k_exp) * s->kmult[e];
+}
+
+static double face_G(const orc_sim *s, long e, long f, double area, const double *T) {
+    const orc_cfg *c = &s->cfg;
+    const double d = s->d[e];
+    double R = d / (2.0 * k_at(s, e, T[e])) + d / (2.0 * k_at(s, f, T[f]));
+    if (c->ins_R0 > 0.0 && s->wire[e] != s->wire[f])
+        R += c->ins_R0 * pow(c->T_ref / (0.5 * (T[e] + T[f])), c->k_exp);
+    return area / R;
+}
+
+static double border_G(const orc_sim *s, long e, double area, const double *T) {
+    const orc_cfg *c = &s->cfg;
+    if (!(c->h0 > 0.0)) return 0.0;
+    const double h = c->h0 * pow(T[e] / c->T_ref, c->h_exp);
+    return area / (1.0 / h + s->d[e] / (2.0 * k_at(s, e, T[e])));
+}
+
+static void thomas(long n, const double *a, const double *b, const double *cc, const double *r, double *x,
+                   double *cp, double *dp) {
+    /* a_i x_{i-1} + b_i x_i + c_i x_{i+1} = r_i */
+    cp[0] = cc[0] / b[0];
+    dp[0] = r[0] / b[0];
+    for (long i = 1; i < n; ++i) {
+        const double m = b[i] - a[i] * cp[i - 1];
+        cp[i] = cc[i] / m;
+        dp[i] = (r[i] - a[i] * dp[i - 1]) / m;
+    }
+    x[n - 1] = dp[n - 1];
+    for (long i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
+}
+
+static void heat_adi(orc_sim *s) {
+    const orc_cfg *c = &s->cfg;
+    const long N = s->N;
+    const double dt = c->dt;
+    double *Tn = dalloc(N), *Ts = dalloc(N), *Tss = dalloc(N), *Cv = dalloc(N);
+    double *Gf = dalloc(4 * N), *Gbr = dalloc(N), *Gbz = dalloc(N), *Lz0 = dalloc(N), *Lr1 = dalloc(N);
+    memcpy(Tn, s->T, sizeof(double) * (size_t)N);
+    /* coefficients at T^n; faces 0 inner, 1 outer (radial), 2 lower, 3 upper (axial) */
+    for (long e = 0; e < N; ++e) {
+        const int ci = s->coil[e];
+        const double d = s->d[e];
+        const long ir = (long)((s->r[e] - c->r_inner[ci]) / d);
+        const double rin = c->r_inner[ci];
+        double area[4];
+        if (c->planar) {
+            area[0] = area[1] = area[2] = area[3] = d;
+        } else {
+            area[0] = 2.0 * ORC_PI * (rin + (double)ir * d) * d;
+            area[1] = 2.0 * ORC_PI * (rin + (double)(ir + 1) * d) * d;
+            area[2] = area[3] = 2.0 * ORC_PI * s->r[e] * d;
+        }
+        Cv[e] = s->V[e] * c->C0 * pow(Tn[e] / c->T_ref, c->cp_exp);
+        Gbr[e] = Gbz[e] = 0.0;
+        for (int f = 0; f < 4; ++f) {
+            const long nbr = s->nb[4 * e + f];
+            if (nbr >= 0) {
+                Gf[4 * e + f] = face_G(s, e, nbr, area[f], Tn);
+            } else {
+                Gf[4 * e + f] = 0.0;
+                if (f < 2) Gbr[e] += border_G(s, e, area[f], Tn);
+                else       Gbz[e] += border_G(s, e, area[f], Tn);
+            }
+        }
+        double lz = Gbz[e] * (c->T_bath - Tn[e]);
+        for (int f = 2; f < 4; ++f) {
+            const long nbr = s->nb[4 * e + f];
+            if (nbr >= 0) lz += Gf[4 * e + f] * (Tn[nbr] - Tn[e]);
+        }
+        Lz0[e] = lz;
+    }
+    /* half step 1: implicit in r, one system per coil column */
+    for (int ci = 0; ci < c->n_coils; ++ci) {
+        const long o = s->coil_off[ci];
+        const long nr = (long)c->layers[ci] * c->ne[ci], nz = (long)c->turns[ci] * c->ne[ci];
+        double *a = dalloc(nr), *b = dalloc(nr), *cc = dalloc(nr), *rr = dalloc(nr), *x = dalloc(nr);
+        double *cp = dalloc(nr), *dp = dalloc(nr);
+        for (long iz = 0; iz < nz; ++iz) {
+            for (long ir = 0; ir < nr; ++ir) {
+                const long e = o + ir * nz + iz;
+                const double m = 2.0 * Cv[e] / dt;
+                a[ir] = -Gf[4 * e + 0];
+                cc[ir] = -Gf[4 * e + 1];
+                b[ir] = m + Gf[4 * e + 0] + Gf[4 * e + 1] + Gbr[e];
+                rr[ir] = m * Tn[e] + Lz0[e] + s->V[e] * s->q[e] + Gbr[e] * c->T_bath;
+            }
+            thomas(nr, a, b, cc, rr, x, cp, dp);
+            for (long ir = 0; ir < nr; ++ir) Ts[o + ir * nz + iz] = x[ir];
+        }
+        free(a); free(b); free(cc); free(rr); free(x); free(cp); free(dp);
+    }
+    for (long e = 0; e < N; ++e) {
+        double lr = Gbr[e] * (c->T_bath - Ts[e]);
+        for (int f = 0; f < 2; ++f) {
+            const long nbr = s->nb[4 * e + f];
+            if (nbr >= 0) lr += Gf[4 * e + f] * (Ts[nbr] - Ts[e]);
+        }
+        Lr1[e] = lr;
+    }
+    /* half step 2: implicit in z, one system per coil row */
+    for (int ci = 0; ci < c->n_coils; ++ci) {
+        const long o = s->coil_off[ci];
+        const long nr = (long)c->layers[ci] * c->ne[ci], nz = (long)c->turns[ci] * c->ne[ci];
+        double *a = dalloc(nz), *b = dalloc(nz), *cc = dalloc(nz), *rr = dalloc(nz), *x = dalloc(nz);
+        double *cp = dalloc(nz), *dp = dalloc(nz);
+        for (long ir = 0; ir < nr; ++ir) {
+            for (long iz = 0; iz < nz; ++iz) {
+                const long e = o + ir * nz + iz;
+                const double m = 2.0 * Cv[e] / dt;
+                a[iz] = -Gf[4 * e + 2];
+                cc[iz] = -Gf[4 * e + 3];
+                b[iz] = m + Gf[4 * e + 2] + Gf[4 * e + 3] + Gbz[e];
+                rr[iz] = m * Ts[e] + Lr1[e] + s->V[e] * s->q[e] + Gbz[e] * c->T_bath;
+            }
+            thomas(nz, a, b, cc, rr, x, cp, dp);
+            for (long iz = 0; iz < nz; ++iz) Tss[o + ir * nz + iz] = x[iz];
+        }
+        free(a); free(b); free(cc); free(rr); free(x); free(cp); free(dp);
+    }
+    /* enthalpy from the half steps' inflow, border outflow */
+    nsum out = {0.0, 0.0};
+    for (long e = 0; e < N; ++e) {
+        double lz = Gbz[e] * (c->T_bath - Tss[e]);
+        for (int f = 2; f < 4; ++f) {
+            const long nbr = s->nb[4 * e + f];
+            if (nbr >= 0) lz += Gf[4 * e + f] * (Tss[nbr] - Tss[e]);
+        }
+        s->u[e] += dt / s->V[e] * (Lr1[e] + 0.5 * (Lz0[e] + lz)) + dt * s->q[e];
+        s->T[e] = T_of_u(c, s->u[e]);
+        ns_add(&out, dt * (Gbr[e] * (Ts[e] - c->T_bath) + 0.5 * Gbz[e] * ((Tn[e] - c->T_bath) + (Tss[e] - c->T_bath))));
+    }
+    s->Qout += ns_val(&out);
+    free(Tn); free(Ts); free(Tss); free(Cv); free(Gf); free(Gbr); free(Gbz); free(Lz0); free(Lr1);
+}
+
+/* ------------------------------------------------------------------ */
 /* one time step                                                       */
 /* ------------------------------------------------------------------ */
 int orc_step(orc_sim *s) {
@@ -810,10 +978,11 @@ int orc_step(orc_sim *s) {
     }
     s->maxx = maxx;
 
-    /* 4. explicit heat, n_sub substeps with q held fixed */
+    /* 4. heat: ADI, or explicit with n_sub substeps, q held fixed */
+    if (c->heat_solver == 1) heat_adi(s);
     const double hs = dt / (double)s->n_sub;
     double *un = dalloc(N);
-    for (int sub = 0; sub < s->n_sub; ++sub) {
+    for (int sub = 0; sub < (c->heat_solver == 1 ? 0 : s->n_sub); ++sub) {
         nsum out = {0.0, 0.0};
         for (long e = 0; e < N; ++e) {
             double flux = s->Gb[e] * (c->T_bath - s->T[e]);
@@ -881,6 +1050,7 @@ int orc_get(const orc_sim *s, int field, double *dst, long count) {
         case ORC_Q_QUENCH: src = s->Qqu; n = Nw; break;
         case ORC_T_QUENCH: src = s->Tqu; n = Nw; break;
         case ORC_P_QUENCH: src = s->Pqu; n = Nw; break;
+        case ORC_KMULT: src = s->kmult; break;
         case ORC_J:
             if (count < N) return -1;
             for (long e = 0; e < N; ++e) dst[e] = s->I[e] / (s->d[e] * s->d[e]);
@@ -899,6 +1069,10 @@ int orc_set(orc_sim *s, int field, const double *src, long count) {
         case ORC_I: memcpy(s->I, src, sizeof(double) * (size_t)N); return 0;
         case ORC_T:
             for (long e = 0; e < N; ++e) { s->T[e] = src[e]; s->u[e] = u_of_T(&s->cfg, src[e]); }
+            return 0;
+        case ORC_KMULT:
+            for (long e = 0; e < N; ++e) if (!(src[e] > 0.0) || !isfinite(src[e])) return -1;
+            memcpy(s->kmult, src, sizeof(double) * (size_t)N);
             return 0;
         default: return -1;
     }
@@ -939,7 +1113,7 @@ int orc_scalars(const orc_sim *s, double *dst, int n) {
 int orc_tangent(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
                 const double *c_wire, const double *dc_wire, const double *dramp,
                 long nsteps, double *obj, double *dobj) {
-    if (cfg->coupling != 0) return -1;
+    if (cfg->coupling != 0 || cfg->heat_solver != 0) return -1;
     orc_sim *s = orc_create(cfg, jc0_mult, strain, c_wire);
     if (!s) return -1;
     const orc_cfg *c = &s->cfg;
