@@ -9,9 +9,16 @@ precision, with all inputs resident in HBM.  The timed region is K steps
 bracketed by device synchronisation; per-kernel durations come from HIP
 events the library records on its own stream inside that region.
 
-Validity: after the timed run the same number of steps is run in FP64 from
-the same initial state and the normwise relative error of B and T (mixed
-against FP64) is reported; the run is flagged invalid above 1e-5.
+Validity: before the timed run, the configuration's whole run is made in
+mixed precision and in FP64 from the same initial state and the normwise
+relative error of B and T (mixed against FP64) is reported every 100 steps;
+the run is flagged invalid above 1e-5.  The same check covers the driven
+variant, and 200 steps of the 384,000-element adjoint configuration (literal
+and driven).
+
+Other legs after the timed run: the 16-coil ensemble, the adjoint/forward
+ratio at 384,000 elements, the 20 x 20-turn quench workload (onset and quench
+maps, propagation speed), and the CPU oracle baseline.
 
 Prints one JSON line.
 """
@@ -36,7 +43,7 @@ PEAK_HBM_GBS = 8000.0
 # 4, B_r bracket 5 -> 58 flop, plus 3 for the coordinates -> 61.  Direct pass:
 # one evaluation and 2 accumulation FMAs per pair -> 65 flop per pair.
 # Translation pass: each distinct value evaluated once per tile (61 flop) and
-# 2 FP64 FMAs per pair (4 flop).
+# 2 FMAs per pair (4 flop): FP32 FMAs in mixed mode, FP64 FMAs in FP64 mode.
 FLOP_PER_EVAL = 61
 FLOP_PER_PAIR_ACC = 4
 
@@ -144,6 +151,111 @@ def precision_check(pk, cs, name: str, every: int = 100, direct_steps: int = 100
     log(f"[bench] {w.name}: mixed vs FP64 over {nsteps} steps: B {eb:.2e} T {et:.2e} "
         f"(rise-relative {erise}); vs direct FP64 at step {direct_steps}: B {ed:.2e} T {etd:.2e}")
     return res
+
+
+def quench_leg(pk, cs, torch, name: str = "quench20_active", max_steps: int = 6000, every: int = 250) -> dict:
+    """The quench workload (20 x 20 turns, transport and background field
+    ramps, normal-state path): run until every wire has quenched (rho > 0.95
+    rho_n) or max_steps, then per-wire onset and quench steps, the quench
+    propagation speed 1/|grad t_q| over the wire grid (central differences,
+    pitch = wire side), and the Joule heat Q_q of each wire between its onset
+    and its quench."""
+    import numpy as np
+    w = cs.workload(name)
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision="mixed")
+    co = w.coils[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < max_steps:
+        g.run(every)
+        done += every
+        if (g.get(pk.F_QUENCH) >= 0).all():
+            break
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    on, qu = g.get(pk.F_ONSET), g.get(pk.F_QUENCH)
+    Qq = g.get(pk.F_Q_QUENCH) - g.get(pk.F_Q_ONSET)
+    sc = g.scalars()
+    g.close()
+    tq = qu.reshape(co.layers, co.turns) * w.dt
+    speed = None
+    if (qu >= 0).all():
+        gr, gz = np.gradient(tq, co.wire_side)
+        gn = np.hypot(gr, gz)
+        v = 1.0 / gn[gn > 0]
+        speed = {"median_m_per_s": float(np.median(v)), "p90_m_per_s": float(np.percentile(v, 90)),
+                 "max_m_per_s": float(v.max())}
+    out = {"workload": w.name, "n_elem": w.n_elem, "steps": done, "steps_per_s": done / el,
+           "wires": int(w.n_wire), "onset": int((on >= 0).sum()), "quenched": int((qu >= 0).sum()),
+           "first_onset_step": float(on[on >= 0].min()) if (on >= 0).any() else None,
+           "first_quench_step": float(qu[qu >= 0].min()) if (qu >= 0).any() else None,
+           "last_quench_step": float(qu.max()) if (qu >= 0).all() else None,
+           "T_peak": sc["T_peak"], "Q": sc["Q"], "propagation": speed,
+           "Qq_range_J": [float(Qq.min()), float(Qq.max())] if (qu >= 0).all() else None}
+    log(f"[bench] {w.name}: {out['quenched']}/{w.n_wire} wires quenched after {done} steps "
+        f"({out['steps_per_s']:.0f} steps/s), T_peak {sc['T_peak']:.2f} K, speed {speed}")
+    return out
+
+
+def adi_leg(pk, cs, torch, steps: int = 200) -> dict:
+    """The composite thermal model on the medium coil's driven variant: ADI
+    heat step (copper-sheath conductivity 100 W/(m K) with an Nb3Sn core map,
+    k and h proportional to T^3, epoxy between wires).  Reports the step rate,
+    the heat phase per step, the energy balance, and the substeps the explicit
+    step would need at the same conductivity (its stability limit)."""
+    w = cs.composite(cs.workload("c2_active"))
+    inp = cs.generate(w)
+    inp["k_mult"] = cs.composite_map(w)
+    g = pk.Coil(w, inp, precision="mixed")
+    g.run(5)
+    g.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    g.timing(True)
+    g.run(20)
+    ph = g.timing_read()
+    g.timing(False)
+    sc = g.scalars()
+    g.close()
+    explicit = pk.query(w.replace(heat_solver="explicit", k_exp=0.0, h_exp=0.0, ins_R0=0.0)).heat_substeps
+    out = {"workload": w.name, "n_elem": w.n_elem, "steps": steps, "steps_per_s": steps / el,
+           "heat_ms_per_step": ph["heat"]["ms"] / 20, "heat_launches_per_step": ph["heat"]["launches"] / 20,
+           "explicit_substeps_needed": int(explicit), "T_peak": sc["T_peak"],
+           "energy_balance_rel": abs(sc["stored"] - (sc["Q"] - sc["Q_out"])) / max(abs(sc["Q"]), 1e-300)}
+    log(f"[bench] {w.name}: {out['steps_per_s']:.0f} steps/s, ADI heat {out['heat_ms_per_step'] * 1e3:.1f} us/step "
+        f"(explicit would need {explicit} substeps), energy balance {out['energy_balance_rel']:.1e}")
+    return out
+
+
+def coupled_leg(pk, cs, torch, steps: int = 5) -> dict:
+    """The fully coupled inter-wire induction on the medium coil (131,072
+    elements, driven variant, mixed field pass): per-step wall time, CG
+    iterations to a relative residual of 1e-10, and the time of the coupled
+    solve (wire phase) against the field pass."""
+    w = cs.workload("c2_active").replace(coupling="full")
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision="mixed", cg_tol=1e-10, cg_max_iter=200)
+    g.run(2)
+    g.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.run(steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ph = g.timing_read()
+    g.timing(False)
+    sc = g.scalars()
+    g.close()
+    out = {"workload": w.name + "_coupled", "n_elem": w.n_elem, "steps": steps, "ms_per_step": 1e3 * el / steps,
+           "cg_iters_last_step": int(sc["cg_iters"]), "cg_residual_last_step": sc["cg_residual"],
+           "phase_ms_per_step": {k: v["ms"] / steps for k, v in ph.items()}}
+    log(f"[bench] {out['workload']}: {out['ms_per_step']:.1f} ms/step, {out['cg_iters_last_step']} CG iterations")
+    return out
 
 
 def cpu_baseline(w, budget_s: float = 12.0) -> dict:
@@ -332,6 +444,9 @@ def main():
                     help="field-pass evaluation (both compute the same all-pairs sum)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-coil ensemble leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward leg")
+    ap.add_argument("--no-quench", action="store_true", help="skip the 20 x 20-turn quench leg")
+    ap.add_argument("--no-adi", action="store_true", help="skip the composite (ADI heat step) leg")
+    ap.add_argument("--no-coupled", action="store_true", help="skip the fully coupled induction leg")
     ap.add_argument("--adjoint-steps", type=int, default=200,
                     help="horizon of the adjoint/forward timing at 384,000 elements")
     ap.add_argument("--c5-full", action="store_true",
@@ -367,6 +482,21 @@ def main():
     if args.c5_full:
         print(json.dumps(c5_full(pk, cs, torch, args.precision, args.fd_steps)))
         return
+
+    # validity legs first (they also bring the GPU to its sustained clock
+    # before the timed region)
+    check = check_active = check_c5 = check_c5_active = None
+    if not args.no_check and args.precision == "mixed":
+        check = precision_check(pk, cs, args.workload)
+        if args.workload in ("c1", "c2", "c3", "c5"):
+            # the driven variant until shortly before its hot spot passes Tc
+            # (C2: Jc reaches 0 near step 900, which the power law reports)
+            check_active = precision_check(pk, cs, args.workload + "_active",
+                                           steps=600 if args.workload in ("c2", "c5") else 0)
+        if args.workload == "c2":
+            # the adjoint configuration's size: 200 steps, literal and driven
+            check_c5 = precision_check(pk, cs, "c5", steps=200, direct_steps=10)
+            check_c5_active = precision_check(pk, cs, "c5_active", steps=200, direct_steps=10)
 
     w = cs.workload(args.workload)
     inp = cs.generate(w)
@@ -433,14 +563,6 @@ def main():
         }
 
     g.close()
-    check = check_active = None
-    if not args.no_check and args.precision == "mixed":
-        check = precision_check(pk, cs, args.workload)
-        if args.workload in ("c1", "c2", "c3", "c5"):
-            # the driven variant until shortly before its hot spot passes Tc
-            # (C2: Jc reaches 0 near step 900, which the power law reports)
-            check_active = precision_check(pk, cs, args.workload + "_active",
-                                           steps=600 if args.workload in ("c2", "c5") else 0)
 
     batched = None
     if not args.no_batched:
@@ -448,6 +570,15 @@ def main():
     adjoint = None
     if not args.no_adjoint and args.adjoint_steps > 0:
         adjoint = adjoint_leg(pk, cs, torch, args.adjoint_steps)
+    quench = None
+    if not args.no_quench:
+        quench = quench_leg(pk, cs, torch)
+    adi = None
+    if not args.no_adi:
+        adi = adi_leg(pk, cs, torch)
+    coupled = None
+    if not args.no_coupled:
+        coupled = coupled_leg(pk, cs, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -486,10 +617,15 @@ def main():
                          "GeForce RTX 4090 and RTX 3090 cards (FP64 at 1/64 of FP32)",
         "mixed_vs_fp64": check,
         "mixed_vs_fp64_driven": check_active,
+        "mixed_vs_fp64_c5": check_c5,
+        "mixed_vs_fp64_c5_driven": check_c5_active,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "batched": batched,
         "adjoint": adjoint,
+        "quench": quench,
+        "composite_adi": adi,
+        "coupled_induction": coupled,
     }
     print(json.dumps(out))
 

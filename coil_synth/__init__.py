@@ -98,6 +98,7 @@ class Workload:
     h_exp: float = 0.0  # h = h0 (T/T_ref)^h_exp
     coupling: str = "transport"  # inter-wire induction: "transport" or "full"
     heat_solver: str = "explicit"  # "explicit" (sub-cycled) or "adi"
+    ins_R0: float = 0.0  # ADI: insulation resistance between wires, m^2 K/W
     heat_substeps: int = 0  # 0 = automatic (stability rule)
     # disorder recipe
     seed: int = 1
@@ -302,6 +303,28 @@ def generate(w: Workload) -> dict:
         "strain": np.ascontiguousarray(eps, dtype=np.float64),
         "c_wire": np.ones(w.n_wire, dtype=np.float64),
     }
+
+
+def composite_map(w: Workload, core_k: float = 0.02) -> np.ndarray:
+    """Thermal conductivity multipliers of a composite cross-section, public
+    order: inside each wire the (ne-2) x (ne-2) core of elements stands for
+    the Nb3Sn filament bundle (multiplier ``core_k``), the outer ring of
+    elements for the copper sheath (1).  The epoxy between wires is the
+    insulation resistance ``ins_R0`` of the workload, not a map entry."""
+    out = []
+    for c in w.coils:
+        ir, iz = np.divmod(np.arange(c.n_elem), c.n_z)
+        a, b = ir % c.ne, iz % c.ne
+        core = (a > 0) & (a < c.ne - 1) & (b > 0) & (b < c.ne - 1)
+        out.append(np.where(core, core_k, 1.0))
+    return np.ascontiguousarray(np.concatenate(out), dtype=np.float64)
+
+
+def composite(w: Workload) -> Workload:
+    """The composite thermal model of a workload: ADI heat step, a copper-sheath
+    conductivity k0 = 100 W/(m K), k and h proportional to T^3, and 25 um of
+    epoxy (about 0.05 W/(m K) at 4.2 K) between wires, R = 5e-4 m^2 K / W."""
+    return w.replace(name=w.name + "_composite", heat_solver="adi", k0=100.0, k_exp=3.0, h_exp=3.0, ins_R0=5e-4)
 
 
 def random_currents(n: int, seed: int, scale: float = 1.0) -> np.ndarray:

@@ -11,7 +11,9 @@
  *        coaxial-ring Green's function (complete elliptic integrals K, E
  *        evaluated on the fly);
  *     2. local power law E = Ec (|J|/Jc)^n sgn J, Jc = c_w Jc0 mu_e (1 - T/Tc)
- *        B0/(B0 + |B|) (1 - eps_coef |eps|^eps_pow), from the state at step k;
+ *        B0/(B0 + |B|) (1 - eps_coef |eps|^eps_pow), from the state at step k
+ *        (optionally in parallel with a normal-state resistivity rho_n, so that
+ *        the flux-flow and normal states of a quench are covered);
  *     3. per-wire A-V solve: each wire's element currents respond to the flux
  *        of the other wires' transport current and of the background field,
  *        one loop voltage per wire enforces the wire's transport current
@@ -62,18 +64,60 @@ enum coil_status {
 
 enum coil_precision {
     COIL_FP64 = 0,  /* everything in FP64 */
-    COIL_MIXED = 1  /* field pairs in FP32 with compensated sums, pairs with
-                       k > near_k (and their elliptic arguments) in FP64;
-                       all state (I, Phi, u, T, Q) in FP64 */
+    COIL_MIXED = 1  /* field pass in FP32 pair arithmetic: kernel values far from
+                       k -> 1 evaluated in FP32, those with k > near_k evaluated in
+                       FP64 (from FP64 arguments) and rounded to FP32; FP32
+                       products and partial sums, the partial sums of every 16W
+                       sources (TRANSLATION) or 64 sources (DIRECT, with a Kahan
+                       correction across them) added into FP64; all state (I, Phi,
+                       u, T, Q) in FP64 */
 };
 
+/* Geometry of the heat step and of the element volumes (the field and the
+   inductances always treat elements as coaxial rings).  PLANAR replaces the
+   ring volumes 2 pi r d^2 and face areas 2 pi r d by d^2 and d (per metre of
+   depth): a test geometry for the heat step against planar closed forms. */
+enum coil_geometry { COIL_AXISYMMETRIC = 0, COIL_PLANAR = 1 };
+
+/* Inter-wire induction in each wire's circuit equation (paper, Methods,
+   "Numerical Algorithm": a wire is first driven by the field of the transport
+   current of the other wires; later iterations update it from the net currents
+   of all subelements).  TRANSPORT: the other wires enter through the flux of
+   their transport current only (the first iteration, which the paper finds
+   sufficient for large coils).  FULL: the flux of every element current of the
+   coil enters, solved to convergence each step (cg_tol, cg_max_iter). */
+enum coil_coupling { COIL_COUPLE_TRANSPORT = 0, COIL_COUPLE_FULL = 1 };
+/* FULL solves, per step, A dI + dt P U = b with P^T dI = dI_t 1 (A the coil's
+   inductance matrix plus dt diag(2 pi r E'/d^2), P the element-to-wire
+   incidence) by conjugate gradients on the zero-net-current corrections of the
+   transport-only solution, preconditioned by the per-wire constrained solves,
+   with an FP64 all-pairs flux pass as the product (in either precision).
+   Eager stepping synchronises with the host every 8 iterations to stop at
+   convergence; a captured graph holds all cg_max_iter iterations, those after
+   convergence returning at once.  The adjoint is not available for it. */
+
+/* Heat step (paper, Methods, heat paragraph).  EXPLICIT: sub-cycled explicit
+   finite volumes (heat_substeps).  ADI: alternating-direction implicit, one
+   radial and one axial tridiagonal sweep per step. */
+enum coil_heat { COIL_HEAT_EXPLICIT = 0, COIL_HEAT_ADI = 1 };
+/* ADI (Peaceman-Rachford): per step, with the coefficients at T^n and q held,
+   a half step implicit along r (one tridiagonal system per grid column) and
+   one implicit along z (per grid row); the enthalpy takes the two half steps'
+   inflow, so the energy balance is exact.  Face conductances
+   A / (d/(2 k_e) + d/(2 k_f) + R_ins), border A / (1/h + d/(2 k_e)).
+   Unconditionally stable, not monotone for steps far beyond the explicit
+   limit.  Coils of at most 1536 elements per grid side; no adjoint. */
+
 /* Field-pass evaluation.  Both compute the same all-pairs sum (every pair
-   contributes G_B(e,j) I_j once, kernel values evaluated on the fly every step):
-   DIRECT evaluates K, E per pair (tiled N-body sum, any element positions);
+   contributes G_B(e,j) I_j once):
+   DIRECT evaluates K, E per pair on the fly (tiled N-body sum, any element
+   positions);
    TRANSLATION uses that on a coil's regular (r,z) grid G_B depends on
    (i_r, j_r, i_z - j_z) only: per tile each distinct kernel value is evaluated
-   once and reused along z (a per-row-pair 1-D convolution, FP64 accumulation).
-   AUTO = TRANSLATION. */
+   once and reused along z (a per-row-pair 1-D convolution); in mixed
+   precision the values with k > near_k come from a table evaluated once at
+   coil_init, all others are evaluated on the fly every pass.  AUTO =
+   TRANSLATION. */
 enum coil_algo { COIL_ALGO_AUTO = 0, COIL_ALGO_DIRECT = 1, COIL_ALGO_TRANSLATION = 2 };
 
 /* fields for coil_get / coil_set_state */
@@ -94,7 +138,19 @@ enum coil_field {
     COIL_F_R = 13,    /* element radius, m */
     COIL_F_Z = 14,    /* element height, m */
     COIL_F_DI = 15,   /* current increment of the last step, A */
-    COIL_F_JC = 16    /* critical current density of the last step, A/m^2 */
+    COIL_F_JC = 16,   /* critical current density of the last step, A/m^2 */
+    /* per-wire flux-jump and quench diagnostics (N_w entries each; paper,
+       Results: the criterion |J/Jc| > 1 for the nucleation of a flux jump in a
+       wire, and rho > 0.95 rho_n for its quench, Fig. 4 and Fig. 6), from the
+       local law of each step k (J^k, B^k, T^k): */
+    COIL_F_ONSET = 17,    /* first step k with max over the wire |J|/Jc > 1 (Jc <= 0 with
+                             J != 0 counts), -1 if none yet */
+    COIL_F_QUENCH = 18,   /* first step k with rho_w = sum V E J / sum V J^2 > 0.95 rho_n
+                             (rho_n > 0 only), -1 if none yet */
+    COIL_F_Q_ONSET = 19,  /* the wire's Joule heat accumulated before its onset step, J */
+    COIL_F_Q_QUENCH = 20, /* ... before its quench step, J */
+    COIL_F_T_QUENCH = 21, /* the wire's largest T^k at its quench step, K */
+    COIL_F_P_QUENCH = 22  /* its power density sum V E J / sum V at the quench step, W/m^3 */
 };
 
 typedef struct {
@@ -102,7 +158,7 @@ typedef struct {
     int32_t n_coils;
     const int32_t *layers, *turns, *ne;   /* wires radial, axial; elements per wire side */
     const double *r_inner, *z_center, *wire_side; /* m */
-    const double *ramp;                   /* transport current ramp, A/s (I(0) = 0) */
+    const double *ramp;                   /* transport current ramp, A/s (I_t = I0 + ramp t) */
     double dBa_dt;                        /* background axial field ramp, T/s */
     /* E-J law and Jc(B, T, eps) */
     double Ec, n, Jc0, Tc, B0, eps_coef, eps_pow;
@@ -120,6 +176,24 @@ typedef struct {
                                grid of at most this many workgroups striding over the
                                work items (both evaluations) */
     int32_t algo;           /* enum coil_algo: how the field pass is evaluated */
+    /* ---- options of the extended model; zero / NULL everywhere is the model of the
+       benchmark configurations ---- */
+    const double *I0;       /* per coil: transport current at t = 0, A, carried evenly by
+                               the elements of each wire (NULL = 0); I_t = I0 + ramp t */
+    double rho_n;           /* normal-state resistivity, Ohm m, in parallel with the power
+                               law: rho = rho_pl rho_n / (rho_pl + rho_n), rho_pl = E/J of
+                               the power law; Jc <= 0 is then the normal state E = rho_n J.
+                               0 = pure power law (Jc <= 0 with J != 0 is an error) */
+    double k_exp, h_exp;    /* k = k0 (T/T_ref)^k_exp, h = h0 (T/T_ref)^h_exp (paper: both
+                               proportional to T^3); non-zero needs heat_solver = ADI */
+    double ins_R0;          /* insulation between wires (composite cross-section): thermal
+                               resistance per area, m^2 K / W, of every face between two
+                               wires, scaled by (T_ref / T_face)^k_exp; needs ADI (0 = none) */
+    int32_t geometry;       /* enum coil_geometry */
+    int32_t coupling;       /* enum coil_coupling */
+    int32_t heat_solver;    /* enum coil_heat */
+    int32_t cg_max_iter;    /* COIL_COUPLE_FULL: iterations per step at most (0 -> 100) */
+    double cg_tol;          /* COIL_COUPLE_FULL: relative residual to reach (0 -> 1e-12) */
 } coil_config;
 
 typedef struct {
@@ -128,6 +202,8 @@ typedef struct {
     const double *jc0_mult;  /* N: per-element Jc0 multiplier mu_e */
     const double *strain;    /* N: per-element strain eps_e */
     const double *c_wire;    /* N_w: per-wire Jc multiplier c_w */
+    const double *k_mult;    /* N: thermal conductivity multiplier of each element (the
+                                composite map; NULL = all ones; not all ones needs ADI) */
 } coil_inputs;
 
 typedef struct {
@@ -183,7 +259,10 @@ int coil_set_state(coil_t *h, int32_t field, const double *src, int64_t count,
 /* Synchronise and read scalars: 0 t, 1 step, 2 Q, 3 T_peak, 4 sum U_w,
    5 max |J|/Jc, 6 heat out through the borders, 7 stored heat sum V u,
    8 status flags, 9 T_peak element (public index, -1 if none), 10 T_peak step,
-   11 heat substeps, 12 field-pass work items.  Writes min(n, 13) values. */
+   11 heat substeps, 12 field-pass work items, 13 conjugate-gradient iterations
+   of the last step's coupled solve and 14 its final relative residual
+   sqrt(r^T S r / r_0^T S r_0) (both 0 without COIL_COUPLE_FULL).  Writes
+   min(n, 15) values. */
 int coil_scalars(coil_t *h, double *dst, int32_t n);
 
 /* Back to the t = 0 state (keeps the precompute). */
@@ -194,8 +273,9 @@ int coil_reset(coil_t *h);
    background field is not included.  Synchronises. */
 int coil_field_at(coil_t *h, int64_t npts, const double *r, const double *z, double *Br, double *Bz);
 
-/* Host snapshot of the state (I, u, T, Phi, Q_w, step, Q, T_peak and its
-   argmax, heat outflow, status) for checkpoint and resume.  coil_save with
+/* Host snapshot of the state (I, u, T, Phi, Q_w, the per-wire onset and quench
+   diagnostics, step, Q, T_peak and its argmax, heat outflow, status) for
+   checkpoint and resume.  coil_save with
    host_buf = NULL only reports the size in *needed.  coil_load restores a
    snapshot taken from a handle of the same configuration; stepping on from it
    reproduces the uninterrupted run bitwise.  Both synchronise. */
@@ -241,7 +321,8 @@ int coil_set_params(coil_t *h, const double *c_wire, const double *ramp);
    objectives[2] = (Q, T_peak).  `workspace` is caller-owned device memory of
    at least coil_adjoint_query() bytes (256-byte aligned); it is free again on
    return.  The handle is left reset to t = 0.  Synchronises.
-   Returns COIL_E_NONFINITE if the forward pass produced a non-finite value. */
+   Returns COIL_E_NONFINITE if the forward pass produced a non-finite value,
+   COIL_E_INVAL for a handle with coupling COIL_COUPLE_FULL. */
 int coil_adjoint_query(coil_t *h, int64_t nsteps, int32_t ckpt_every, int32_t store_field,
                        size_t *bytes);
 int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak, int32_t ckpt_every,

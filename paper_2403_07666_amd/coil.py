@@ -21,7 +21,11 @@ OK, E_INVAL, E_NOMEM, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
 ALGO_AUTO, ALGO_DIRECT, ALGO_TRANSLATION = 0, 1, 2
 F_I, F_J, F_BR, F_BZ, F_T, F_PHI, F_QW, F_UW, F_E, F_EP, F_U, F_Q, F_PSI, F_R, F_Z, F_DI, F_JC = range(17)
-PER_WIRE = (F_QW, F_UW)
+F_ONSET, F_QUENCH, F_Q_ONSET, F_Q_QUENCH, F_T_QUENCH, F_P_QUENCH = range(17, 23)
+PER_WIRE = (F_QW, F_UW, F_ONSET, F_QUENCH, F_Q_ONSET, F_Q_QUENCH, F_T_QUENCH, F_P_QUENCH)
+AXISYMMETRIC, PLANAR = 0, 1
+COUPLE_TRANSPORT, COUPLE_FULL = 0, 1
+HEAT_EXPLICIT, HEAT_ADI = 0, 1
 
 _i32p = C.POINTER(C.c_int32)
 _dp = C.POINTER(C.c_double)
@@ -48,11 +52,15 @@ class Config(C.Structure):
         ("near_k", C.c_double),
         ("tile_targets", C.c_int32), ("tile_sources", C.c_int32), ("grid_limit", C.c_int32),
         ("algo", C.c_int32),
+        ("I0", _dp), ("rho_n", C.c_double), ("k_exp", C.c_double), ("h_exp", C.c_double),
+        ("ins_R0", C.c_double),
+        ("geometry", C.c_int32), ("coupling", C.c_int32), ("heat_solver", C.c_int32),
+        ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
     ]
 
 
 class Inputs(C.Structure):
-    _fields_ = [("jc0_mult", _dp), ("strain", _dp), ("c_wire", _dp)]
+    _fields_ = [("jc0_mult", _dp), ("strain", _dp), ("c_wire", _dp), ("k_mult", _dp)]
 
 
 class Sizes(C.Structure):
@@ -139,7 +147,8 @@ class _CfgHolder:
     """Keeps the per-coil arrays of a Config alive."""
 
     def __init__(self, w, precision=None, tile_targets=0, tile_sources=0, grid_limit=0,
-                 near_k=0.0, heat_substeps=None, algo=ALGO_AUTO):
+                 near_k=0.0, heat_substeps=None, algo=ALGO_AUTO, geometry=None, coupling=None,
+                 heat_solver=None, cg_max_iter=0, cg_tol=0.0):
         co = w.coils
         self.arr = {
             "layers": np.array([c.layers for c in co], dtype=np.int32),
@@ -149,14 +158,13 @@ class _CfgHolder:
             "z_center": np.array([c.z_center for c in co], dtype=np.float64),
             "wire_side": np.array([c.wire_side for c in co], dtype=np.float64),
             "ramp": np.array([c.ramp for c in co], dtype=np.float64),
+            "I0": np.array([c.I0 for c in co], dtype=np.float64),
         }
-        if any(c.I0 != 0.0 for c in co):
-            raise ValueError("runs start from zero current (I0 must be 0)")
         cfg = Config()
         cfg.n_coils = len(co)
         for k in ("layers", "turns", "ne"):
             setattr(cfg, k, self.arr[k].ctypes.data_as(_i32p))
-        for k in ("r_inner", "z_center", "wire_side", "ramp"):
+        for k in ("r_inner", "z_center", "wire_side", "ramp", "I0"):
             setattr(cfg, k, self.arr[k].ctypes.data_as(_dp))
         for k in ("dBa_dt", "Ec", "n", "Jc0", "Tc", "B0", "eps_coef", "eps_pow", "C0", "T_ref",
                   "cp_exp", "k0", "h0", "T_bath", "dt"):
@@ -168,6 +176,18 @@ class _CfgHolder:
         cfg.tile_sources = int(tile_sources)
         cfg.grid_limit = int(grid_limit)
         cfg.algo = {"auto": ALGO_AUTO, "direct": ALGO_DIRECT, "translation": ALGO_TRANSLATION}.get(algo, algo)
+        cfg.rho_n = float(getattr(w, "rho_n", 0.0))
+        cfg.k_exp = float(getattr(w, "k_exp", 0.0))
+        cfg.h_exp = float(getattr(w, "h_exp", 0.0))
+        geo = getattr(w, "geometry", "axisymmetric") if geometry is None else geometry
+        cfg.geometry = {"axisymmetric": AXISYMMETRIC, "planar": PLANAR}.get(geo, geo)
+        cpl = getattr(w, "coupling", "transport") if coupling is None else coupling
+        cfg.coupling = {"transport": COUPLE_TRANSPORT, "full": COUPLE_FULL}.get(cpl, cpl)
+        hs = getattr(w, "heat_solver", "explicit") if heat_solver is None else heat_solver
+        cfg.heat_solver = {"explicit": HEAT_EXPLICIT, "adi": HEAT_ADI}.get(hs, hs)
+        cfg.cg_max_iter = int(cg_max_iter)
+        cfg.cg_tol = float(cg_tol)
+        cfg.ins_R0 = float(getattr(w, "ins_R0", 0.0))
         self.cfg = cfg
 
 
@@ -204,7 +224,9 @@ class Coil:
             raise RuntimeError("workspace is not 256-byte aligned")
         inputs = inputs or {}
         self._in_arrays = {k: np.ascontiguousarray(inputs[k], dtype=np.float64)
-                           for k in ("jc0_mult", "strain", "c_wire") if inputs.get(k) is not None}
+                           for k in ("jc0_mult", "strain", "c_wire", "k_mult") if inputs.get(k) is not None}
+        if "k_mult" in self._in_arrays and self._in_arrays["k_mult"].size != self.N:
+            raise ValueError("k_mult has the wrong length")
         if "jc0_mult" in self._in_arrays and self._in_arrays["jc0_mult"].size != self.N:
             raise ValueError("jc0_mult has the wrong length")
         if "strain" in self._in_arrays and self._in_arrays["strain"].size != self.N:
@@ -279,10 +301,10 @@ class Coil:
         check(lib().coil_set_state(self.h, int(field), v.ctypes.data_as(C.c_void_p), v.size, 0))
 
     def scalars(self) -> dict:
-        v = np.empty(13, dtype=np.float64)
-        check(lib().coil_scalars(self.h, v.ctypes.data_as(_dp), 13))
+        v = np.empty(15, dtype=np.float64)
+        check(lib().coil_scalars(self.h, v.ctypes.data_as(_dp), 15))
         keys = ["t", "step", "Q", "T_peak", "sumU", "max_x", "Q_out", "stored", "status",
-                "T_peak_elem", "T_peak_step", "n_sub", "n_work_items"]
+                "T_peak_elem", "T_peak_step", "n_sub", "n_work_items", "cg_iters", "cg_residual"]
         return dict(zip(keys, v.tolist()))
 
     # -------------------------------------------------------------- timing

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(64) void k_wire_adj(DevState s, RunConst rc, AdjPtr
     if (act) {
         local_law(rc, cw, s.jcs[e], I0 / d2, T, br, bz, lo);
     } else {
-        lo.Jc = lo.x = lo.E = lo.Ep = lo.fT = lo.fB = lo.Bm = 0.0;
+        lo.Jc = lo.x = lo.E = lo.Ep = lo.fT = lo.fB = lo.Bm = lo.p = 0.0;
     }
     const double re = s.r[e];
     const double kap = 2.0 * kPi * re / d2;
@@ -171,15 +171,9 @@ __global__ __launch_bounds__(64) void k_wire_adj(DevState s, RunConst rc, AdjPtr
     const double Eb = act ? qb * I1 / d2 - dt * 2.0 * kPi * re * nu : 0.0;
     const double Epb = act ? qb * (dI / d2) * (I1 / d2) - nu * dI * dt * kap : 0.0;
     const double dItb = wave_sum(act ? -s.psi[e] * nu : 0.0) + numu;
-    // local law E = Ec x^n sgn J, E' = n Ec x^(n-1) / Jc, x = |J| / Jc
+    // local law (E, E' as functions of J and Jc)
     double Jb = 0.0, Jcb = 0.0;
-    if (act && I0 != 0.0 && lo.Jc > 0.0) {
-        const double x = lo.x, sg = I0 > 0.0 ? 1.0 : -1.0;
-        const double xn2 = pow(x, rc.n - 2.0);
-        const double xb = Eb * rc.Ec * rc.n * xn2 * x * sg + Epb * rc.n * rc.Ec * (rc.n - 1.0) * xn2 / lo.Jc;
-        Jcb = -Epb * lo.Ep / lo.Jc - xb * x / lo.Jc;
-        Jb = xb * sg / lo.Jc;
-    }
+    if (act) local_law_adj(rc, lo, I0 / d2, Eb, Epb, Jb, Jcb);
     if (act) a.Ibar[e] = Ib1 + qb * Elin / d2 + Jb / d2;
     // Jc = c_w jcs fT fB
     const double cwb = wave_sum(act ? Jcb * s.jcs[e] * lo.fT * lo.fB : 0.0);

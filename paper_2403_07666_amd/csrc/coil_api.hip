@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "coil_adjoint.h"
+#include "coil_coupled.h"
 #include "coil_field_tz.h"
 #include "coil_internal.h"
 
@@ -50,7 +51,7 @@ struct Buf {  // one carved region
 };
 
 struct Plan {
-    int N = 0, Nw = 0, nlayers = 0, ngroups = 0, nsub = 1, max_ne2 = 1, nheat_blocks = 0;
+    int N = 0, Nw = 0, nlayers = 0, ngroups = 0, nsub = 1, max_ne2 = 1, nheat_blocks = 0, nrows = 0;
     int tile_targets = 256;
     std::vector<CoilDev> coils;
     std::vector<PairItem> items;
@@ -66,13 +67,16 @@ struct Plan {
     size_t near_total = 0;        // near kernel values over all pairs
     int algo = COIL_ALGO_TRANSLATION;
     int prec = COIL_FP64;  // arithmetic of the field passes (sets the width choice)
+    int coupled = 0;       // COIL_COUPLE_FULL: buffers of the coupled solve
+    int adi = 0;           // COIL_HEAT_ADI: buffers of the ADI heat step
+    int ncols = 0, hb_slots = 1, maxline = 0;
     int nchunk_cap = 1;    // partial-sum capacity in chunks
     size_t total = 0;
     // regions
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
         perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
-        sc_b, tmp_b, misc_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b,
+        sc_b, tmp_b, misc_b, diag_b, hrow_b, Lself_b, cgv_b, cgL_b, cgred_b, cgrw_b, cgsc_b, adi_b, kmult_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b,
         Ipub32_b;
 };
 
@@ -123,6 +127,29 @@ int validate(const coil_config *c) {
         return fail(COIL_E_INVAL, "tile_sources must be a non-negative multiple of %d", kStage);
     if (c->grid_limit < 0) return fail(COIL_E_INVAL, "grid_limit must be >= 0");
     if (c->algo < COIL_ALGO_AUTO || c->algo > COIL_ALGO_TRANSLATION) return fail(COIL_E_INVAL, "unknown algo %d", c->algo);
+    if (c->I0)
+        for (int i = 0; i < c->n_coils; ++i)
+            if (!std::isfinite(c->I0[i])) return fail(COIL_E_INVAL, "coil %d: non-finite I0", i);
+    if (!(std::isfinite(c->rho_n) && c->rho_n >= 0.0)) return fail(COIL_E_INVAL, "rho_n must be finite and >= 0");
+    if (c->geometry != COIL_AXISYMMETRIC && c->geometry != COIL_PLANAR)
+        return fail(COIL_E_INVAL, "unknown geometry %d", c->geometry);
+    if (c->coupling != COIL_COUPLE_TRANSPORT && c->coupling != COIL_COUPLE_FULL)
+        return fail(COIL_E_INVAL, "unknown coupling %d", c->coupling);
+    if (c->heat_solver != COIL_HEAT_EXPLICIT && c->heat_solver != COIL_HEAT_ADI)
+        return fail(COIL_E_INVAL, "unknown heat_solver %d", c->heat_solver);
+    if (c->heat_solver == COIL_HEAT_ADI)
+        for (int i = 0; i < c->n_coils; ++i)
+            if ((long long)c->layers[i] * c->ne[i] > 1536 || (long long)c->turns[i] * c->ne[i] > 1536)
+                return fail(COIL_E_INVAL, "coil %d: the ADI heat step takes at most 1536 elements per grid side", i);
+    if (!(std::isfinite(c->ins_R0) && c->ins_R0 >= 0.0)) return fail(COIL_E_INVAL, "ins_R0 must be finite and >= 0");
+    if (c->ins_R0 != 0.0 && c->heat_solver != COIL_HEAT_ADI)
+        return fail(COIL_E_INVAL, "an insulation resistance (ins_R0) needs heat_solver = COIL_HEAT_ADI");
+    if (!std::isfinite(c->k_exp) || !std::isfinite(c->h_exp))
+        return fail(COIL_E_INVAL, "k_exp and h_exp must be finite");
+    if ((c->k_exp != 0.0 || c->h_exp != 0.0) && c->heat_solver != COIL_HEAT_ADI)
+        return fail(COIL_E_INVAL, "temperature-dependent k or h (k_exp, h_exp) needs heat_solver = COIL_HEAT_ADI");
+    if (c->cg_max_iter < 0 || !(std::isfinite(c->cg_tol) && c->cg_tol >= 0.0))
+        return fail(COIL_E_INVAL, "cg_max_iter must be >= 0 and cg_tol finite and >= 0");
     return COIL_OK;
 }
 
@@ -354,7 +381,9 @@ void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
 int make_plan(const coil_config *c, Plan &p) {
     p = Plan();
     p.prec = c->precision;
-    int off = 0, woff = 0, loff = 0, goff = 0;
+    p.coupled = c->coupling == COIL_COUPLE_FULL ? 1 : 0;
+    p.adi = c->heat_solver == COIL_HEAT_ADI ? 1 : 0;
+    int off = 0, woff = 0, loff = 0, goff = 0, toff = 0, roff = 0;
     for (int i = 0; i < c->n_coils; ++i) {
         CoilDev d{};
         d.ne = c->ne[i];
@@ -372,6 +401,15 @@ int make_plan(const coil_config *c, Plan &p) {
         d.c2f = (float)d.c2d;
         d.kscale = kMu0 / (2.0 * kPi * d.d);
         d.dIt = c->ramp[i] * c->dt;
+        d.I0e = (c->I0 ? c->I0[i] : 0.0) / d.ne2;
+        d.tile_off = toff;
+        d.ntile_z = (d.turns * d.ne + kHT - 1) / kHT;
+        d.row_off = roff;
+        d.col_off = p.ncols;
+        toff += (d.layers * d.ne + kHT - 1) / kHT * d.ntile_z;
+        roff += d.layers * d.ne;
+        p.ncols += d.turns * d.ne;
+        p.maxline = std::max(p.maxline, std::max(d.layers * d.ne, d.turns * d.ne));
         off += d.n;
         woff += d.layers * d.turns;
         loff += d.layers;
@@ -383,7 +421,8 @@ int make_plan(const coil_config *c, Plan &p) {
     p.Nw = woff;
     p.nlayers = loff;
     p.ngroups = goff;
-    p.nheat_blocks = (p.N + 255) / 256;
+    p.nheat_blocks = p.adi ? std::max(p.ncols, roff) : toff;
+    p.nrows = roff;
     int tb = c->tile_targets;
     if (tb == 0) tb = p.N <= 8192 ? 64 : 256;
     if (!build_near(p, m1_near_of(c))) return fail(COIL_E_INVAL, "near-value table exceeds 2^31 entries");
@@ -414,6 +453,7 @@ int make_plan(const coil_config *c, Plan &p) {
 }
 
 int heat_substeps(const coil_config *c, const Plan &p) {
+    if (c->heat_solver == COIL_HEAT_ADI) return 1;  // one implicit step
     if (c->heat_substeps > 0) return c->heat_substeps;
     // explicit stability limit at T_bath: h_max = min_e V_e C(T_bath) / (sum of
     // the element's face and border conductances)
@@ -423,11 +463,13 @@ int heat_substeps(const coil_config *c, const Plan &p) {
         const CoilDev &d = p.coils[ci];
         const int nr = d.layers * d.ne, nz = d.turns * d.ne;
         const double rin = c->r_inner[ci];
+        const bool planar = c->geometry == COIL_PLANAR;
         for (int ir = 0; ir < nr; ++ir) {
             const double re = rin + (ir + 0.5) * d.d;
-            const double V = 2.0 * kPi * re * d.d * d.d;
-            const double faces[4] = {2.0 * kPi * (rin + ir * d.d) * d.d, 2.0 * kPi * (rin + (ir + 1) * d.d) * d.d,
-                                     2.0 * kPi * re * d.d, 2.0 * kPi * re * d.d};
+            const double V = planar ? d.d * d.d : 2.0 * kPi * re * d.d * d.d;
+            double faces[4] = {2.0 * kPi * (rin + ir * d.d) * d.d, 2.0 * kPi * (rin + (ir + 1) * d.d) * d.d,
+                               2.0 * kPi * re * d.d, 2.0 * kPi * re * d.d};
+            if (planar) faces[0] = faces[1] = faces[2] = faces[3] = d.d;
             for (int iz = 0; iz < nz; ++iz) {
                 const bool has[4] = {ir > 0, ir < nr - 1, iz > 0, iz < nz - 1};
                 double g = 0.0;
@@ -503,12 +545,27 @@ size_t layout(Plan &p) {
     p.Qw_b = carve(cur, d8 * Nw);
     p.wq_b = carve(cur, d8 * Nw);
     p.wmaxx_b = carve(cur, d8 * Nw);
+    p.diag_b = carve(cur, d8 * 6 * Nw);
+    p.hrow_b = carve(cur, sizeof(HeatRow) * std::max(1, p.nrows));
     p.hb_max_b = carve(cur, d8 * p.nheat_blocks);
     p.hb_arg_b = carve(cur, sizeof(long long) * p.nheat_blocks);
-    p.hb_out_b = carve(cur, d8 * (size_t)p.nheat_blocks * p.nsub);
+    p.hb_slots = p.adi ? 2 : p.nsub;
+    p.hb_out_b = carve(cur, d8 * (size_t)p.nheat_blocks * p.hb_slots);
     p.sc_b = carve(cur, sizeof(Scalars));
     p.tmp_b = carve(cur, d8 * std::max<size_t>(N, Nw));
     p.misc_b = carve(cur, d8 * 64);
+    if (p.adi) {
+        p.adi_b = carve(cur, d8 * 10 * N);  // Cv, G (4), Gbr, Gbz, Lz0, Lr1, Ts
+        p.kmult_b = carve(cur, d8 * N);
+    }
+    if (p.coupled) {
+        p.Lself_b = carve(cur, d8 * N);
+        p.cgv_b = carve(cur, d8 * 5 * N);
+        p.cgL_b = carve(cur, d8 * Nw * (size_t)p.max_ne2 * (p.max_ne2 + 1));
+        p.cgred_b = carve(cur, d8 * ((N + 255) / 256));
+        p.cgrw_b = carve(cur, d8 * 2 * Nw);
+        p.cgsc_b = carve(cur, sizeof(CgScalars));
+    }
     p.total = (cur + 255) & ~size_t(255);
     return p.total;
 }
@@ -547,6 +604,9 @@ struct coil_s {
     bool capturing = false;
     int tz_split = 0;    // source-row groups of the translation pass (0 = automatic)
     int tz_force_w = 0;  // segment width of the translation pass (0 = automatic)
+    double cg_tol = 1e-12;       // coupled solve: relative residual to reach
+    int cg_maxit = 100;          // coupled solve: iterations per step at most
+    int cg_check = 8;            // eager stepping: iterations between convergence checks
 };
 
 namespace {
@@ -613,6 +673,26 @@ hipError_t launch_field_any(coil_t *h, const DevState &d, hipStream_t st) {
     return launch_field(d, h->rc, h->grid_limit, st);
 }
 
+// The coupled A-V solve after the deferred per-wire kernels.  Eager stepping
+// reads the convergence flag every cg_check iterations (a host
+// synchronisation); under graph capture all cg_maxit iterations are enqueued
+// and those after convergence return at once.
+int coupled_solve(coil_t *h) {
+    const DevState &d = h->ds;
+    HIPCHECK(launch_cg_begin(d, h->rc, h->tz, h->Ipub, h->d_pub2int, h->cg_tol, h->cg_maxit, h->stream));
+    for (int it = 0; it < h->cg_maxit; ++it) {
+        HIPCHECK(launch_cg_iteration(d, h->rc, h->tz, h->Ipub, h->d_pub2int, h->stream));
+        if (!h->capturing && (it + 1) % h->cg_check == 0 && it + 1 < h->cg_maxit) {
+            int done = 0;
+            HIPCHECK(hipMemcpyAsync(&done, &d.cg->done, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+            HIPCHECK(hipStreamSynchronize(h->stream));
+            if (done) break;
+        }
+    }
+    HIPCHECK(launch_cg_finish(d, h->rc, h->stream));
+    return COIL_OK;
+}
+
 int enqueue_step(coil_t *h) {
     hipEvent_t a = nullptr;
     int rc;
@@ -627,10 +707,11 @@ int enqueue_step(coil_t *h) {
     if ((rc = t_end(h, 0, a, 1))) return rc;
     if ((rc = t_begin(h, &a, 1))) return rc;
     HIPCHECK(launch_wire(h->ds, h->rc, h->stream));
+    if (d.cg_defer && (rc = coupled_solve(h))) return rc;
     if ((rc = t_end(h, 1, a, 1))) return rc;
     if ((rc = t_begin(h, &a, 2))) return rc;
-    for (int sub = 0; sub < h->ds.nsub; ++sub) HIPCHECK(launch_heat(h->ds, h->rc, sub, h->stream));
-    if ((rc = t_end(h, 2, a, h->ds.nsub))) return rc;
+    HIPCHECK(launch_heat_step(h->ds, h->rc, h->stream));
+    if ((rc = t_end(h, 2, a, h->rc.adi ? 3 : heat_launches(h->ds.nsub)))) return rc;
     if ((rc = t_begin(h, &a, 3))) return rc;
     HIPCHECK(launch_finalize(h->ds, h->rc, h->stream));
     if ((rc = t_end(h, 3, a, 1))) return rc;
@@ -641,7 +722,7 @@ int enqueue_step(coil_t *h) {
 int reset_state(coil_t *h) {
     const DevState &s = h->ds;
     hipStream_t st = h->stream;
-    HIPCHECK(launch_fill(s.I, 0.0, s.N, st));
+    HIPCHECK(launch_init_current(s, st));
     HIPCHECK(launch_fill(s.Phi, 0.0, s.N, st));
     HIPCHECK(launch_fill(s.Br, 0.0, s.N, st));
     HIPCHECK(launch_fill(s.Bz, 0.0, s.N, st));
@@ -660,6 +741,9 @@ int reset_state(coil_t *h) {
     HIPCHECK(launch_fill(s.Qw, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.wq, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.wmaxx, 0.0, s.Nw, st));
+    HIPCHECK(launch_fill(s.onset, -1.0, 2 * s.Nw, st));  // onset and quench
+    HIPCHECK(launch_fill(s.Qon, 0.0, 4 * s.Nw, st));     // Qon, Qqu, Tqu, Pqu
+    if (s.cg) HIPCHECK(launch_fill(reinterpret_cast<double *>(s.cg), 0.0, sizeof(CgScalars) / sizeof(double), st));
     HIPCHECK(launch_reset_scalars(s.sc, h->T_bath, st));
     return COIL_OK;
 }
@@ -726,6 +810,14 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     r.u_inv = 1.0 / p1;
     r.m1_near = m1_near_of(cfg);
     r.prec = cfg->precision;
+    r.rho_n = cfg->rho_n;
+    r.k0 = cfg->k0;
+    r.h0 = cfg->h0;
+    r.k_exp = cfg->k_exp;
+    r.h_exp = cfg->h_exp;
+    r.ins_R0 = cfg->ins_R0;
+    r.adi = p.adi;
+    const bool planar = cfg->geometry == COIL_PLANAR;
 
     // host precompute, internal (wire-major) order
     std::vector<float2> gpos(N);
@@ -757,7 +849,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
                         gpos[e] = make_float2((float)ir, (float)iz);
                         rho[e] = rin / d.d + ir + 0.5;
                         rr[e] = rin + (ir + 0.5) * d.d;
-                        V[e] = 2.0 * kPi * rr[e] * d.d * d.d;
+                        V[e] = planar ? d.d * d.d : 2.0 * kPi * rr[e] * d.d * d.d;
                         invV[e] = 1.0 / V[e];
                         h->r_pub[pub] = rr[e];
                         h->z_pub[pub] = zbot + (iz + 0.5) * d.d;
@@ -774,6 +866,15 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
         jcs[e] = cfg->Jc0 * mu * (1.0 - cfg->eps_coef * std::pow(std::fabs(ep), cfg->eps_pow));
         if (!std::isfinite(jcs[e])) return fail(COIL_E_INVAL, "non-finite Jc0 multiplier or strain at %d", pub);
     }
+    std::vector<double> kmult(p.adi ? N : 0, 1.0);
+    if (in && in->k_mult) {
+        for (int e = 0; e < N; ++e) {
+            const double v = in->k_mult[perm[e]];
+            if (!(std::isfinite(v) && v > 0.0)) return fail(COIL_E_INVAL, "k_mult must be finite and > 0 (element %d)", perm[e]);
+            if (v != 1.0 && !p.adi) return fail(COIL_E_INVAL, "a conductivity map (k_mult) needs heat_solver = COIL_HEAT_ADI");
+            if (p.adi) kmult[e] = v;
+        }
+    }
     if (in && in->c_wire)
         for (int w = 0; w < Nw; ++w) {
             cw[w] = in->c_wire[w];
@@ -789,8 +890,9 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
                 const int pub = d.off + ir * nz + iz;
                 const int e = pub2int[pub];
                 const double re = rin + (ir + 0.5) * d.d;
-                const double area[4] = {2.0 * kPi * (rin + ir * d.d) * d.d, 2.0 * kPi * (rin + (ir + 1) * d.d) * d.d,
-                                        2.0 * kPi * re * d.d, 2.0 * kPi * re * d.d};
+                double area[4] = {2.0 * kPi * (rin + ir * d.d) * d.d, 2.0 * kPi * (rin + (ir + 1) * d.d) * d.d,
+                                  2.0 * kPi * re * d.d, 2.0 * kPi * re * d.d};
+                if (planar) area[0] = area[1] = area[2] = area[3] = d.d;
                 const int nbp[4] = {ir > 0 ? pub - nz : -1, ir < nr - 1 ? pub + nz : -1, iz > 0 ? pub - 1 : -1,
                                     iz < nz - 1 ? pub + 1 : -1};
                 double gb = 0.0;
@@ -806,6 +908,35 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
                 }
                 Gb[e] = gb;
             }
+    }
+    // the same conductances per grid row, for the tiled heat step (identical
+    // expressions, so the values are bitwise those of G, Gb and invV above)
+    std::vector<HeatRow> hrow(std::max(1, p.nrows));
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        const CoilDev &d = p.coils[ci];
+        const int nr = d.layers * d.ne;
+        const double rin = cfg->r_inner[ci];
+        for (int ir = 0; ir < nr; ++ir) {
+            const double re = rin + (ir + 0.5) * d.d;
+            double area[4] = {2.0 * kPi * (rin + ir * d.d) * d.d, 2.0 * kPi * (rin + (ir + 1) * d.d) * d.d,
+                              2.0 * kPi * re * d.d, 2.0 * kPi * re * d.d};
+            if (planar) area[0] = area[1] = area[2] = area[3] = d.d;
+            const double Ve = planar ? d.d * d.d : 2.0 * kPi * re * d.d * d.d;
+            HeatRow R{};
+            R.ain = area[0];
+            R.aout = area[1];
+            R.aax = area[2];
+            R.gin = cfg->k0 * area[0] / d.d;
+            R.gout = cfg->k0 * area[1] / d.d;
+            R.gax = cfg->k0 * area[2] / d.d;
+            R.invV = 1.0 / Ve;
+            if (cfg->h0 > 0.0) {
+                R.gbin = area[0] / (1.0 / cfg->h0 + d.d / (2.0 * cfg->k0));
+                R.gbout = area[1] / (1.0 / cfg->h0 + d.d / (2.0 * cfg->k0));
+                R.gbax = area[2] / (1.0 / cfg->h0 + d.d / (2.0 * cfg->k0));
+            }
+            hrow[d.row_off + ir] = R;
+        }
     }
     // bounding boxes of 64-element groups (grid indices)
     for (const CoilDev &d : p.coils)
@@ -904,6 +1035,23 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     s.ngroups = p.ngroups;
     s.nitems = (int)p.items.size();
     s.nheat_blocks = p.nheat_blocks;
+    s.ncoils = (int)p.coils.size();
+    s.hrow = at<HeatRow>(h, p.hrow_b);
+    s.hb_slots = p.hb_slots;
+    if (p.adi) {
+        double *a = at<double>(h, p.adi_b);
+        s.adi_Cv = a;
+        s.adi_G = a + N;
+        s.adi_Gbr = a + 5 * (size_t)N;
+        s.adi_Gbz = a + 6 * (size_t)N;
+        s.adi_Lz0 = a + 7 * (size_t)N;
+        s.adi_Lr1 = a + 8 * (size_t)N;
+        s.adi_Ts = a + 9 * (size_t)N;
+        s.kmult = at<double>(h, p.kmult_b);
+        s.adi_ncols = p.ncols;
+        s.adi_nrows = p.nrows;
+        s.adi_maxline = p.maxline;
+    }
     s.nsub = p.nsub;
     s.max_ne2 = p.max_ne2;
     s.tile_targets = p.tile_targets;
@@ -958,10 +1106,36 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     s.Qw = at<double>(h, p.Qw_b);
     s.wq = at<double>(h, p.wq_b);
     s.wmaxx = at<double>(h, p.wmaxx_b);
+    {
+        double *dg = at<double>(h, p.diag_b);
+        s.onset = dg;
+        s.quench = dg + Nw;
+        s.Qon = dg + 2 * (size_t)Nw;
+        s.Qqu = dg + 3 * (size_t)Nw;
+        s.Tqu = dg + 4 * (size_t)Nw;
+        s.Pqu = dg + 5 * (size_t)Nw;
+    }
     s.hb_max = at<double>(h, p.hb_max_b);
     s.hb_arg = at<long long>(h, p.hb_arg_b);
     s.hb_out = at<double>(h, p.hb_out_b);
     s.sc = at<Scalars>(h, p.sc_b);
+    if (p.coupled) {
+        s.cg_defer = 1;
+        s.Lself = at<double>(h, p.Lself_b);
+        double *v = at<double>(h, p.cgv_b);
+        s.cg_x = v;
+        s.cg_r = v + N;
+        s.cg_z = v + 2 * (size_t)N;
+        s.cg_p = v + 3 * (size_t)N;
+        s.cg_q = v + 4 * (size_t)N;
+        s.cg_L = at<double>(h, p.cgL_b);
+        s.cg_red = at<double>(h, p.cgred_b);
+        s.cg_rw = at<double>(h, p.cgrw_b);
+        s.cg_cw = s.cg_rw + Nw;
+        s.cg = at<CgScalars>(h, p.cgsc_b);
+        h->cg_tol = cfg->cg_tol > 0.0 ? cfg->cg_tol : 1e-12;
+        h->cg_maxit = cfg->cg_max_iter > 0 ? cfg->cg_max_iter : 100;
+    }
     s.tmp = at<double>(h, p.tmp_b);
 
     hipStream_t st = h->stream;
@@ -980,6 +1154,8 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)s.jcs, jcs.data(), sizeof(double) * N));
     HIPCHECK(up((void *)s.G, G.data(), sizeof(double) * 4 * N));
     HIPCHECK(up((void *)s.Gb, Gb.data(), sizeof(double) * N));
+    HIPCHECK(up((void *)s.hrow, hrow.data(), sizeof(HeatRow) * p.nrows));
+    if (p.adi) HIPCHECK(up((void *)s.kmult, kmult.data(), sizeof(double) * N));
     HIPCHECK(up((void *)s.nb, nb.data(), sizeof(int) * 4 * N));
     HIPCHECK(up((void *)s.perm, perm.data(), sizeof(int) * N));
     HIPCHECK(up((void *)s.wire_coil, wire_coil.data(), sizeof(int) * Nw));
@@ -988,6 +1164,19 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)s.Minv, Minv.data(), sizeof(double) * Minv.size()));
     HIPCHECK(up((void *)s.yl, yl.data(), sizeof(double) * yl.size()));
     HIPCHECK(up((void *)s.syl, syl.data(), sizeof(double) * syl.size()));
+    std::vector<double> Lself;
+    if (p.coupled) {  // the self inductances, as on the diagonals of the layer blocks
+        Lself.resize(N);
+        size_t base = 0;
+        for (const CoilDev &d : p.coils) {
+            const int n = d.ne2;
+            for (int w = 0; w < d.layers * d.turns; ++w)
+                for (int i = 0; i < n; ++i)
+                    Lself[d.off + (size_t)w * n + i] = Mlay[base + (size_t)(w / d.turns) * n * n + (size_t)i * n + i];
+            base += (size_t)d.layers * n * n;
+        }
+        HIPCHECK(up((void *)s.Lself, Lself.data(), sizeof(double) * N));
+    }
     HIPCHECK(up((void *)s.cw, cw.data(), sizeof(double) * Nw));
     HIPCHECK(up((void *)h->tz.items, p.tz_items.data(), sizeof(TzItem) * p.tz_items.size()));
     HIPCHECK(up((void *)h->tz.rows, p.tz_rows.data(), sizeof(int) * p.tz_rows.size()));
@@ -1058,7 +1247,7 @@ extern "C" int coil_run(coil_t *h, int64_t nsteps, int64_t report_every, coil_re
             double mb = 0.0;
             if ((rc = max_B(h, &mb))) return rc;
             const double t = (double)sc.step * h->rc.dt;
-            const double It0 = h->plan.coils[0].dIt / h->rc.dt * t;
+            const double It0 = h->plan.coils[0].I0e * h->plan.coils[0].ne2 + h->plan.coils[0].dIt / h->rc.dt * t;
             const double diag[8] = {t, (double)sc.step, It0, mb, sc.Tpeak, sc.Q, sc.sumU, sc.maxx};
             cb(diag, 8, user);
             if (sc.status) return fail(COIL_E_NONFINITE, "non-finite state (status 0x%x) at step %lld", sc.status, sc.step);
@@ -1075,6 +1264,8 @@ static int field_len(coil_t *h, int field, int *len, int *per_wire) {
     switch (field) {
         case COIL_F_QW:
         case COIL_F_UW:
+        case COIL_F_ONSET: case COIL_F_QUENCH: case COIL_F_Q_ONSET: case COIL_F_Q_QUENCH:
+        case COIL_F_T_QUENCH: case COIL_F_P_QUENCH:
             *per_wire = 1;
             *len = h->ds.Nw;
             return COIL_OK;
@@ -1104,7 +1295,17 @@ extern "C" int coil_get(coil_t *h, int32_t field, double *dst, int64_t count, in
         return COIL_OK;
     }
     if (pw) {
-        const double *src = field == COIL_F_QW ? s.Qw : s.Uw;
+        const double *src = nullptr;
+        switch (field) {
+            case COIL_F_QW: src = s.Qw; break;
+            case COIL_F_UW: src = s.Uw; break;
+            case COIL_F_ONSET: src = s.onset; break;
+            case COIL_F_QUENCH: src = s.quench; break;
+            case COIL_F_Q_ONSET: src = s.Qon; break;
+            case COIL_F_Q_QUENCH: src = s.Qqu; break;
+            case COIL_F_T_QUENCH: src = s.Tqu; break;
+            default: src = s.Pqu; break;
+        }
         HIPCHECK(hipMemcpyAsync(dst, src, sizeof(double) * len, kind, st));
         if (!dst_on_device) HIPCHECK(hipStreamSynchronize(st));
         return COIL_OK;
@@ -1182,10 +1383,16 @@ extern "C" int coil_scalars(coil_t *h, double *dst, int32_t n) {
     double stored = 0.0;
     HIPCHECK(hipMemcpyAsync(&stored, misc, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(hipStreamSynchronize(h->stream));
-    const double v[13] = {(double)sc.step * h->rc.dt, (double)sc.step, sc.Q, sc.Tpeak, sc.sumU, sc.maxx,
+    CgScalars cg{};
+    if (h->ds.cg) {
+        HIPCHECK(hipMemcpyAsync(&cg, h->ds.cg, sizeof(cg), hipMemcpyDeviceToHost, h->stream));
+        HIPCHECK(hipStreamSynchronize(h->stream));
+    }
+    const double res = cg.rho0 > 0.0 ? std::sqrt(std::max(0.0, cg.rho) / cg.rho0) : 0.0;
+    const double v[15] = {(double)sc.step * h->rc.dt, (double)sc.step, sc.Q, sc.Tpeak, sc.sumU, sc.maxx,
                           sc.Qout, stored, (double)sc.status, (double)sc.Tpeak_pub, (double)sc.Tpeak_step,
-                          (double)h->ds.nsub, (double)h->ds.nitems};
-    for (int i = 0; i < n && i < 13; ++i) dst[i] = v[i];
+                          (double)h->ds.nsub, (double)h->ds.nitems, (double)cg.iters, res};
+    for (int i = 0; i < n && i < 15; ++i) dst[i] = v[i];
     return COIL_OK;
 }
 
@@ -1409,6 +1616,8 @@ extern "C" int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak,
     if (!std::isfinite(wQ) || !std::isfinite(wTpeak)) return fail(COIL_E_INVAL, "non-finite objective weight");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(COIL_E_INVAL, "workspace must be 256-byte aligned");
     if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
+    if (h->ds.cg_defer) return fail(COIL_E_INVAL, "the adjoint covers the transport-only coupling (COIL_COUPLE_TRANSPORT)");
+    if (h->rc.adi) return fail(COIL_E_INVAL, "the adjoint covers the explicit heat step (COIL_HEAT_EXPLICIT)");
     const long long K = nsteps, C = ckpt_every;
     const int sf = store_field != 0;
     const AdjLayout L = adj_layout(h->plan, K, C, sf);
@@ -1427,7 +1636,7 @@ extern "C" int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak,
     auto step_with = [&](const DevState &d, bool field) -> int {
         if (field) HIPCHECK(launch_field_any(h, d, st));
         HIPCHECK(launch_wire(d, rc, st));
-        for (int sub = 0; sub < nsub; ++sub) HIPCHECK(launch_heat(d, rc, sub, st));
+        HIPCHECK(launch_heat_step(d, rc, st));
         HIPCHECK(launch_finalize(d, rc, st));
         return COIL_OK;
     };
@@ -1782,7 +1991,7 @@ struct SnapHeader {
     uint32_t status, nsub;
 };
 size_t snap_bytes(const coil_t *h) {
-    return sizeof(SnapHeader) + sizeof(double) * (4 * (size_t)h->ds.N + (size_t)h->ds.Nw);
+    return sizeof(SnapHeader) + sizeof(double) * (4 * (size_t)h->ds.N + 7 * (size_t)h->ds.Nw);
 }
 }  // namespace
 
@@ -1796,7 +2005,7 @@ extern "C" int coil_save(coil_t *h, void *host_buf, size_t bytes, size_t *needed
     int rc = read_scalars(h, &sc);
     if (rc) return rc;
     SnapHeader hd{};
-    std::memcpy(hd.magic, "COILSNP1", 8);
+    std::memcpy(hd.magic, "COILSNP2", 8);
     hd.N = h->ds.N;
     hd.Nw = h->ds.Nw;
     hd.step = sc.step;
@@ -1818,6 +2027,8 @@ extern "C" int coil_save(coil_t *h, void *host_buf, size_t bytes, size_t *needed
     HIPCHECK(hipMemcpyAsync(d + 2 * N, h->ds.T[0], sizeof(double) * N, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(d + 3 * N, h->ds.Phi, sizeof(double) * N, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(d + 4 * N, h->ds.Qw, sizeof(double) * h->ds.Nw, hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(d + 4 * N + h->ds.Nw, h->ds.onset, sizeof(double) * 6 * h->ds.Nw, hipMemcpyDeviceToHost,
+                            st));
     HIPCHECK(hipStreamSynchronize(st));
     return COIL_OK;
 }
@@ -1828,7 +2039,7 @@ extern "C" int coil_load(coil_t *h, const void *host_buf, size_t bytes) {
     if (bytes < sizeof(SnapHeader)) return fail(COIL_E_INVAL, "snapshot too small");
     SnapHeader hd;
     std::memcpy(&hd, host_buf, sizeof(hd));
-    if (std::memcmp(hd.magic, "COILSNP1", 8) != 0) return fail(COIL_E_INVAL, "not a coil snapshot");
+    if (std::memcmp(hd.magic, "COILSNP2", 8) != 0) return fail(COIL_E_INVAL, "not a coil snapshot");
     if (hd.N != h->ds.N || hd.Nw != h->ds.Nw || (int)hd.nsub != h->ds.nsub)
         return fail(COIL_E_INVAL, "snapshot of a different configuration");
     if (bytes < snap_bytes(h)) return fail(COIL_E_INVAL, "snapshot truncated");
@@ -1842,6 +2053,8 @@ extern "C" int coil_load(coil_t *h, const void *host_buf, size_t bytes) {
     HIPCHECK(hipMemcpyAsync(h->ds.T[0], d + 2 * N, sizeof(double) * N, hipMemcpyHostToDevice, st));
     HIPCHECK(hipMemcpyAsync(h->ds.Phi, d + 3 * N, sizeof(double) * N, hipMemcpyHostToDevice, st));
     HIPCHECK(hipMemcpyAsync(h->ds.Qw, d + 4 * N, sizeof(double) * h->ds.Nw, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipMemcpyAsync(h->ds.onset, d + 4 * N + h->ds.Nw, sizeof(double) * 6 * h->ds.Nw, hipMemcpyHostToDevice,
+                            st));
     Scalars sc{};
     sc.Q = hd.Q;
     sc.Tpeak = hd.Tpeak;

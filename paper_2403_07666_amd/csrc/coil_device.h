@@ -132,10 +132,15 @@ __device__ __forceinline__ double T_of_u(const RunConst &rc, double u) {
     return rc.T_ref * (rc.cp_exp == 3.0 ? sqrt(sqrt(x)) : pow(x, rc.u_inv));
 }
 
-// Local power law at step k: Jc(B, T, eps) and E, dE/dJ.  Returns the status
-// bits (ST_JC when J != 0 and Jc <= 0).
+// Local law at step k: Jc(B, T, eps) and E, dE/dJ.  Power law
+// E = Ec x^n sgn J, x = |J|/Jc.  With rho_n > 0 the power-law resistivity
+// p = E/J = (Ec/Jc) x^(n-1) acts in parallel with rho_n (flux creep, flux flow
+// and normal state in one law): E = rho_n p/(p + rho_n) J and
+// dE/dJ = rho_n p/(p + rho_n) (n rho_n + p)/(rho_n + p); Jc <= 0, or p beyond
+// FP64 range, is the normal state E = rho_n J.  Returns the status bits
+// (ST_JC when the pure power law meets J != 0 with Jc <= 0).
 struct Local {
-    double Jc, x, E, Ep, fT, fB, Bm;
+    double Jc, x, E, Ep, fT, fB, Bm, p;
 };
 __device__ __forceinline__ unsigned local_law(const RunConst &rc, double cw, double jcs, double J,
                                               double T, double br, double bz, Local &o) {
@@ -146,13 +151,67 @@ __device__ __forceinline__ unsigned local_law(const RunConst &rc, double cw, dou
     o.E = 0.0;
     o.Ep = 0.0;
     o.x = 0.0;
+    o.p = 0.0;
+    if (rc.rho_n > 0.0 && !(o.Jc > 0.0)) {  // normal state
+        o.E = rc.rho_n * J;
+        o.Ep = rc.rho_n;
+        o.x = J != 0.0 ? INFINITY : 0.0;
+        o.p = INFINITY;
+        return 0u;
+    }
     if (J == 0.0) return 0u;
     if (!(o.Jc > 0.0)) return ST_JC;
     o.x = fabs(J) / o.Jc;
     const double p = pow(o.x, rc.n - 1.0);
+    if (rc.rho_n > 0.0) {
+        const double rn = rc.rho_n;
+        o.p = rc.Ec / o.Jc * p;
+        if (!isfinite(o.p)) {
+            o.E = rn * J;
+            o.Ep = rn;
+            return 0u;
+        }
+        const double sfr = o.p / (o.p + rn);
+        o.E = rn * sfr * J;
+        o.Ep = rn * sfr * ((rc.n * rn + o.p) / (rn + o.p));
+        return 0u;
+    }
     o.Ep = rc.n * rc.Ec / o.Jc * p;
     o.E = copysign(rc.Ec * p * o.x, J);
     return 0u;
+}
+
+// Adjoint of the local law: given Eb = dObj/dE and Epb = dObj/dE' at current
+// density J, the derivatives with respect to J (Jc held) and to Jc (J held).
+// Zero-measure kinks (J = 0) take the zero branch.
+__device__ __forceinline__ void local_law_adj(const RunConst &rc, const Local &lo, double J, double Eb,
+                                              double Epb, double &Jb, double &Jcb) {
+    Jb = 0.0;
+    Jcb = 0.0;
+    if (rc.rho_n > 0.0 && (!(lo.Jc > 0.0) || !isfinite(lo.p))) {  // normal state: E = rho_n J
+        Jb = Eb * rc.rho_n;
+        return;
+    }
+    if (J == 0.0 || !(lo.Jc > 0.0)) return;
+    if (rc.rho_n > 0.0) {
+        // p = Ec |J|^(n-1) / Jc^n; E = rho_n s J, E' = rho_n s t with
+        // s = p/(p + rho_n), t = (n rho_n + p)/(rho_n + p)
+        const double rn = rc.rho_n, n = rc.n, p = lo.p;
+        const double den = p + rn;
+        const double sfr = p / den, tfr = (n * rn + p) / den;
+        const double ds = rn / (den * den), dtt = (1.0 - n) * rn / (den * den);
+        const double dEp_dp = rn * (ds * tfr + sfr * dtt);
+        const double dp_dJ = (n - 1.0) * p / J, dp_dJc = -n * p / lo.Jc;
+        Jb = Eb * lo.Ep + Epb * dEp_dp * dp_dJ;
+        Jcb = Eb * rn * J * ds * dp_dJc + Epb * dEp_dp * dp_dJc;
+        return;
+    }
+    // E = Ec x^n sgn J, E' = n Ec x^(n-1) / Jc, x = |J| / Jc
+    const double x = lo.x, sg = J > 0.0 ? 1.0 : -1.0;
+    const double xn2 = pow(x, rc.n - 2.0);
+    const double xb = Eb * rc.Ec * rc.n * xn2 * x * sg + Epb * rc.n * rc.Ec * (rc.n - 1.0) * xn2 / lo.Jc;
+    Jcb = -Epb * lo.Ep / lo.Jc - xb * x / lo.Jc;
+    Jb = xb * sg / lo.Jc;
 }
 
 // Cholesky of the n x n matrix in LDS (column-major, leading dimension ld),

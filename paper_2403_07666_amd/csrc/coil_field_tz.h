@@ -21,7 +21,7 @@ struct TzPlan {
     // work queue: ticket[0] forward, ticket[1] transposed pass, reset by the
     // pass's reordering kernel; grids of as many workgroups as fit at once
     int *ticket;
-    int grid32, grid64, gridT32, gridT64;
+    int grid32, grid64, gridT32, gridT64, gridF64;
     // mixed pass input: kscale * I in public order, rounded to FP32 (made
     // with Ipub by the reordering kernel)
     float *Ipub32;
@@ -39,6 +39,12 @@ hipError_t launch_field_tz_prep(const DevState &s, const TzPlan &tp, double *Ipu
 hipError_t launch_near_fill(const DevState &s, int coil, int nr, hipStream_t st);
 hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *Ipub,
                                   const int *pub2int, int grid_limit, hipStream_t st);
+
+// flux pass of the coupled A-V solve: part[slot][e].y = (off-diagonal
+// inductance x v)_e for v in public order (vpub); the work-queue ticket must
+// have been cleared; returns at once in every workgroup when *done != 0
+hipError_t launch_flux_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *vpub,
+                          const int *pub2int, const int *done, hipStream_t st);
 
 // transposed pass: partT[slot][j] for the weights (wr, wz) in internal order;
 // wr_pub / wz_pub are N-element staging buffers

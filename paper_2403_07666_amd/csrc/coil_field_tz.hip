@@ -70,6 +70,23 @@ __device__ __forceinline__ double2 kern64(double dr, double dz, double sr) {
     return make_double2(f * gr, f * gz);
 }
 
+// Flux kernel (unit source strength mu0 d): the mutual inductance of two
+// coaxial rings, Maxwell's M = mu0 be [ (1 + m1)/2 K - E ] with be in grid
+// units times d, as (0, M / (mu0 d)); even in dz.  The element's own ring
+// (al2 = 0) is left out (its self inductance is added by the caller).
+__device__ __forceinline__ double2 kernflux64(double dr, double dz, double sr) {
+    const double dz2 = dz * dz;
+    const double al2 = fma(dr, dr, dz2);
+    const double be2 = fma(sr, sr, dz2);
+    if (!(al2 > 0.0)) return make_double2(0.0, 0.0);
+    const double rb = rsqrt(be2);
+    const double m1 = al2 * (rb * rb);
+    const double L = -log(m1);
+    const double K = fma(horner_sc(ellipk64_Q_c, m1), L, horner_sc(ellipk64_P_c, m1));
+    const double E = fma(horner_sc(ellipe64_Q_c, m1), L, horner_sc(ellipe64_P_c, m1));
+    return make_double2(0.0, sqrt(be2) * fma(0.5 * (1.0 + m1), K, -E));
+}
+
 __device__ __forceinline__ float2 kern32(float dr, float dz, float sr) {
     const float dz2 = dz * dz;
     const float al2 = fmaf(dr, dr, dz2);
@@ -103,7 +120,7 @@ __device__ __forceinline__ void put(float2 *p, float2 v) { *p = v; }
 // entry, count) for this pair of rows; |delta| < count is near).  The values
 // there are those a direct FP64 evaluation gives, rounded to FP32, and g_r is
 // odd in delta, so the entry for -delta is the stored one with g_r negated.
-template <int MIXED, int W, int Q, bool NEG = false, typename T2>
+template <int MIXED, int W, int Q, bool NEG = false, int KIND = 0, typename T2>
 __device__ __forceinline__ void fill_table(T2 *gt, int lane, int nt, int dlo, double dr, double sr, int2 np,
                                            const float2 *__restrict__ nv) {
     const float drf = (float)dr, srf = (float)sr;
@@ -113,7 +130,9 @@ __device__ __forceinline__ void fill_table(T2 *gt, int lane, int nt, int dlo, do
         if (delta >= 0 || mt >= nt) {
             const int dz = NEG ? -delta : delta;
             T2 *p = &gt[(tau % W) * Q + tau / W];
-            if (!MIXED) {
+            if (KIND == 1) {
+                put(p, kernflux64(dr, (double)dz, sr));
+            } else if (!MIXED) {
                 put(p, kern64(dr, (double)dz, sr));
             } else {
                 const int a = dz < 0 ? -dz : dz;
@@ -193,7 +212,7 @@ __device__ __forceinline__ void prio_by_progress(int done, int total) {
         __builtin_amdgcn_s_setprio(0);
 }
 
-template <int MIXED, int W>
+template <int MIXED, int W, int KIND = 0>
 __device__ __forceinline__ void tz_item(const DevState &s, const RunConst &rc, const TzItem &item,
                                         const int *__restrict__ rows, const double *__restrict__ Ipub,
                                         const int *__restrict__ pub2int, double2 *gt, double *Is) {
@@ -223,8 +242,9 @@ __device__ __forceinline__ void tz_item(const DevState &s, const RunConst &rc, c
                 // delta = z_target - z_source = dlo + tau
                 const int dlo = z0 - s0 - se;
                 __syncthreads();
-                fill_table<MIXED, W, Q>(gt, lane, TZ + se, dlo, dr, sr, np, s.near_val);
-                for (int t = lane; t < se; t += 64) Is[t] = t < sn ? c.kscale * Irow[s0 + t] : 0.0;
+                fill_table<MIXED, W, Q, false, KIND>(gt, lane, TZ + se, dlo, dr, sr, np, s.near_val);
+                const double scale = KIND == 1 ? kMu0 * c.d : c.kscale;
+                for (int t = lane; t < se; t += 64) Is[t] = t < sn ? scale * Irow[s0 + t] : 0.0;
                 __syncthreads();
                 double2 ring[W];
 #pragma unroll
@@ -373,7 +393,7 @@ __device__ __forceinline__ int next_item(int *ticket, int it) {
 }
 __device__ __forceinline__ int first_item(int *) { return (int)blockIdx.x; }
 
-template <int MIXED>
+template <int MIXED, int KIND = 0>
 __device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst &rc,
                                                const TzItem *__restrict__ items, const int *__restrict__ rows,
                                                int nitems, const double *__restrict__ Ipub,
@@ -388,7 +408,7 @@ __device__ __forceinline__ void field_tz_items(const DevState &s, const RunConst
             tz_item32<Wv>(s, rc, item, rows, Ipub32, pub2int, reinterpret_cast<float2 *>(lds),              \
                           reinterpret_cast<float *>(reinterpret_cast<float2 *>(lds) + TzShape<Wv>::Q * Wv)); \
         else                                                                                                \
-            tz_item<MIXED, Wv>(s, rc, item, rows, Ipub, pub2int, lds,                                       \
+            tz_item<MIXED, Wv, KIND>(s, rc, item, rows, Ipub, pub2int, lds,                                 \
                                reinterpret_cast<double *>(lds + TzShape<Wv>::Q * Wv));                      \
         break;
         switch (item.w) {
@@ -420,6 +440,19 @@ __global__ __launch_bounds__(64) void k_field_tz64(DevState s, RunConst rc, cons
                                                    const int *__restrict__ pub2int, int *ticket) {
     __shared__ double2 lds[kTzLds2];
     field_tz_items<0>(s, rc, items, rows, nitems, Ipub, nullptr, pub2int, lds, ticket);
+}
+
+// Flux pass of the fully coupled A-V solve: part[slot][e].y = sum over the
+// item's source rows of M(e, j) v_j / (mu0 d) * mu0 d, i.e. the off-diagonal
+// inductance matrix times the vector v (public order in vpub), FP64.  Returns
+// at once when the solve has converged (*done != 0).
+__global__ __launch_bounds__(64) void k_flux_tz64(DevState s, RunConst rc, const TzItem *__restrict__ items,
+                                                  const int *__restrict__ rows, int nitems,
+                                                  const double *__restrict__ vpub, const int *__restrict__ pub2int,
+                                                  int *ticket, const int *__restrict__ done) {
+    if (*done) return;
+    __shared__ double2 lds[kTzLds2];
+    field_tz_items<0, 1>(s, rc, items, rows, nitems, vpub, nullptr, pub2int, lds, ticket);
 }
 
 // Transposed pass (adjoint): out(j_r, j_z) = sum over target rows i_r and
@@ -712,6 +745,8 @@ hipError_t tz_resident_grids(TzPlan &tp) {
     tp.gridT32 = b * cus;
     if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_fieldT_tz64, 64, 0)) != hipSuccess) return e;
     tp.gridT64 = b * cus;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_flux_tz64, 64, 0)) != hipSuccess) return e;
+    tp.gridF64 = b * cus;
     return hipSuccess;
 }
 
@@ -748,6 +783,15 @@ hipError_t launch_field_tz_kernel(const DevState &s, const RunConst &rc, const T
             hipLaunchKernelGGL(k_field_tz64, dim3(grid), dim3(64), 0, st, s, rc, tp.items, tp.rows, n, Ipub,
                                pub2int, ticket);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_flux_tz(const DevState &s, const RunConst &rc, const TzPlan &tp, const double *vpub,
+                          const int *pub2int, const int *done, hipStream_t st) {
+    const int n = tp.n;
+    if (n > 0)
+        hipLaunchKernelGGL(k_flux_tz64, dim3(queue_grid(tp.gridF64, n)), dim3(64), 0, st, s, rc, tp.items, tp.rows,
+                           n, vpub, pub2int, tp.ticket, done);
     return hipGetLastError();
 }
 

@@ -24,6 +24,8 @@ constexpr double kGmdSquare = 0.4470491559036625;
 constexpr int kGroup = 64;       // bounding-box group = one wavefront of targets
 constexpr int kMaxWireElems = 64;  // per-wire solve keeps one element per lane
 constexpr int kStage = 256;      // sources staged in LDS per pass
+constexpr int kHT = 16;          // heat step: tile side (cells owned by a workgroup)
+constexpr int kHMaxHalo = 8;     // heat step: substeps per launch at most (the tile's halo)
 
 struct CoilDev {
     int off;        // first element (internal order)
@@ -41,6 +43,19 @@ struct CoilDev {
     double kscale;  // mu0 / (2 pi d): field per ampere in grid units
     double d;       // element side
     double dIt;     // transport-current increment per step
+    double I0e;     // initial element current: the coil's I0 over the elements of a wire
+    int tile_off;   // heat step: first tile of the coil
+    int ntile_z;    // heat step: tiles along z
+    int row_off;    // heat step: first per-row conductance record of the coil (= first grid row)
+    int col_off;    // ADI heat step: first grid column of the coil
+};
+
+// heat-step conductances of one grid row (all elements of a row share them):
+// faces to the rows inside and outside, axial faces, 1/V, and the border
+// conductances of an inner, outer and axial border face
+struct HeatRow {
+    double gin, gout, gax, invV, gbin, gbout, gbax, pad;
+    double ain, aout, aax;  // the face areas (ADI step: conductances from k(T))
 };
 
 struct PairItem {
@@ -57,6 +72,12 @@ struct Scalars {
 
 enum : unsigned { ST_NONFINITE = 1u, ST_PIVOT = 2u, ST_JC = 4u };
 
+// device scalars of the coupled A-V solve's conjugate-gradient iteration
+struct CgScalars {
+    double rho, rho0, alpha, beta, tol2;
+    int iters, maxit, done, pad;
+};
+
 // global constants of a run
 struct RunConst {
     double Ec, n, Tc, B0, dt, dBa_dt;
@@ -64,13 +85,23 @@ struct RunConst {
     double u_a1;    // (p+1)/(C0 T_ref)
     double u_a0;    // (T_bath/T_ref)^(p+1)
     double u_inv;   // 1/(p+1)
+    double rho_n;   // normal-state resistivity in parallel with the power law (0 = off)
+    double k0, h0, k_exp, h_exp, ins_R0;  // ADI heat step: k(T), h(T), insulation between wires
+    int adi;        // 1: heat step by ADI
     float m1_near;  // mixed mode: pairs with m1 < m1_near run in FP64
     int prec;
 };
 
 // all device pointers of a handle
 struct DevState {
-    int N, Nw, ngroups, nitems, nheat_blocks, nsub;
+    int N, Nw, ngroups, nitems, nheat_blocks, nsub;  // nheat_blocks: heat tiles
+    int ncoils;
+    int hb_slots;            // heat outflow slots per tile/line (substeps, or the ADI half steps)
+    const HeatRow *hrow;     // per coil and grid row
+    // ADI heat step (null otherwise)
+    int adi_ncols, adi_nrows, adi_maxline;
+    const double *kmult;     // thermal conductivity multiplier per element
+    double *adi_Cv, *adi_G, *adi_Gbr, *adi_Gbz, *adi_Lz0, *adi_Lr1, *adi_Ts;
     const CoilDev *coils;
     const PairItem *items;
     const int4 *bbox;        // per group: min ir, max ir, min iz, max iz
@@ -101,11 +132,23 @@ struct DevState {
     const int2 *near_pair;
     const float2 *near_val;
     double *Uw, *Qw, *wq, *wmaxx;
+    // per-wire flux-jump / quench diagnostics: onset and quench step (-1 = not
+    // yet), the wire's Joule heat before each, its max T and power density at
+    // the quench step
+    double *onset, *quench, *Qon, *Qqu, *Tqu, *Pqu;
     double *hb_max;          // per heat block: max T of the last substep
     long long *hb_arg;       // its public index
     double *hb_out;          // [nsub][blocks]: heat out through the borders
     Scalars *sc;
     double *tmp;             // N doubles of staging for get/set
+    // coupled A-V solve (COIL_COUPLE_FULL; null otherwise)
+    int cg_defer;            // 1: the per-wire kernels leave the step's updates to the coupled solve
+    const double *Lself;     // ring self inductance of each element
+    double *cg_x, *cg_r, *cg_z, *cg_p, *cg_q;  // correction, residual, S r, direction, A p
+    double *cg_L;            // per wire: its factorised block (n x (n + 1), column-major)
+    double *cg_red, *cg_rw;  // per-block sums of p.q, per-wire sums of r.z
+    double *cg_cw;           // per wire: the constant part moved out of the residual
+    CgScalars *cg;
     // adjoint support (null in normal stepping)
     const double *src_Br, *src_Bz;    // take B^k from here instead of the field pass
     double *rec_I, *rec_Br, *rec_Bz, *rec_dI;  // record I^k, B^k, dI of the step
@@ -116,19 +159,21 @@ struct DevState {
 hipError_t launch_field(const DevState &s, const RunConst &rc, int grid_limit, hipStream_t st);
 hipError_t launch_field_finalize(const DevState &s, const RunConst &rc, hipStream_t st);
 hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st);
-hipError_t launch_heat(const DevState &s, const RunConst &rc, int sub, hipStream_t st);
+hipError_t launch_heat_step(const DevState &s, const RunConst &rc, hipStream_t st);
+hipError_t launch_adi_step(const DevState &s, const RunConst &rc, hipStream_t st);
+int heat_launches(int nsub);
 hipError_t launch_finalize(const DevState &s, const RunConst &rc, hipStream_t st);
 hipError_t launch_psi(const DevState &s, double *psi_out, hipStream_t st);
 hipError_t launch_gather(const double *src, const int *perm, int n, double *dst, hipStream_t st);
 hipError_t launch_scatter(const double *src, const int *perm, int n, double *dst, hipStream_t st);
 hipError_t launch_u_of_T(const DevState &s, const RunConst &rc, hipStream_t st);
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st);
+hipError_t launch_init_current(const DevState &s, hipStream_t st);
 hipError_t launch_zero_int(int *p, int n, hipStream_t st);
 hipError_t launch_reset_scalars(Scalars *sc, double T_bath, hipStream_t st);
 hipError_t launch_stored(const DevState &s, double *out, hipStream_t st);
 hipError_t launch_probe(const DevState &s, const double *zphys, int np, const double *pr, const double *pz,
                         double *br, double *bz, hipStream_t st);
-void heat_buffers(int nsub, int sub, int *src, int *dst);
 
 // host-side copies of the elliptic approximations (same coefficients)
 void host_ellip_f64(double m1, double *K, double *E);

@@ -23,6 +23,7 @@
 // per wavefront.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -181,7 +182,7 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     const double d2 = c.d * c.d;
     Local lo;
     unsigned bad = act ? local_law(rc, s.cw[w], s.jcs[e], I0 / d2, s.T[0][e], br, bz, lo) : 0u;
-    if (!act) { lo.E = lo.Ep = lo.x = lo.Jc = 0.0; }
+    if (!act) { lo.E = lo.Ep = lo.x = lo.Jc = lo.p = 0.0; }
     const double re = s.r[e];
     const double *M = s.Mlay + lay * n * n;
     const double diag_add = dt * 2.0 * kPi * re * lo.Ep / d2;
@@ -200,6 +201,10 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     } else {
         load_wire_matrix(sm, M, n, ld, lane, act, diag_add);
         bad |= chol_lds(sm, n, ld, lane, act);
+        if (s.cg_defer && act) {  // the factor, for the coupled solve's preconditioner
+            double *L = s.cg_L + (size_t)w * s.max_ne2 * (s.max_ne2 + 1);
+            for (int j = 0; j < n; ++j) L[(size_t)j * ld + lane] = sm[j * ld + lane];
+        }
         xv = b;
         yv = act ? 1.0 : 0.0;
         solve2_lds(sm, n, ld, lane, act, xv, yv);
@@ -209,7 +214,23 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     const double U = (sx - c.dIt) / (dt * sy);
     const double dI = act ? xv - dt * U * yv : 0.0;
     double qv = 0.0;
-    if (act) {
+    if (s.cg_defer) {
+        // coupled solve: dI is its starting point; the step's updates of I, q,
+        // Phi, U_w and Q_w follow once it has converged
+        if (act) {
+            s.dI[e] = dI;
+            s.E[e] = lo.E;
+            s.Ep[e] = lo.Ep;
+            s.Jc[e] = lo.Jc;
+            s.Br[e] = br;
+            s.Bz[e] = bz;
+            if (s.rec_I) s.rec_I[e] = I0;
+            if (s.rec_Br) {
+                s.rec_Br[e] = br;
+                s.rec_Bz[e] = bz;
+            }
+        }
+    } else if (act) {
         const double I1 = I0 + dI;
         const double Elin = lo.E + lo.Ep * dI / d2;
         qv = Elin * (I1 / d2);
@@ -239,67 +260,173 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     const double qw = wave_sum(act ? dt * s.V[e] * qv : 0.0);
     const double mx = wave_max(lo.x);
     bad = wave_or(bad);
+    // quench criterion: the wire's resistivity sum V E J / sum V J^2 of this
+    // step's local law against 0.95 rho_n (uniform branch)
+    double sEJ = 0.0, sJJ = 0.0, sV = 0.0, Tw = 0.0;
+    if (rc.rho_n > 0.0) {
+        const double J0 = I0 / d2, Ve = act ? s.V[e] : 0.0;
+        sEJ = wave_sum(Ve * lo.E * J0);
+        sJJ = wave_sum(Ve * J0 * J0);
+        sV = wave_sum(Ve);
+        Tw = wave_max(act ? s.T[0][e] : -INFINITY);
+    }
     if (lane == 0) {
-        s.Uw[w] = U;
-        s.wq[w] = qw;
-        s.Qw[w] += qw;
+        const double Qold = s.Qw[w];
+        if (!s.cg_defer) {
+            s.Uw[w] = U;
+            s.wq[w] = qw;
+            s.Qw[w] = Qold + qw;
+        }
         s.wmaxx[w] = mx;
         if (!FAST) s.wflag[w] = 0;
         if (bad) atomicOr(&s.sc->status, bad);
+        // flux-jump onset (|J/Jc| > 1) and quench of the wire at step k
+        const double kstep = (double)s.sc->step;
+        if (s.onset[w] < 0.0 && mx > 1.0) {
+            s.onset[w] = kstep;
+            s.Qon[w] = Qold;
+        }
+        if (rc.rho_n > 0.0 && s.quench[w] < 0.0 && sJJ > 0.0 && sEJ / sJJ > 0.95 * rc.rho_n) {
+            s.quench[w] = kstep;
+            s.Qqu[w] = Qold;
+            s.Tqu[w] = Tw;
+            s.Pqu[w] = sEJ / sV;
+        }
     }
 }
 
 // ------------------------------------------------------------------ heat
-// one explicit substep: (u, T)[src] -> (u, T)[dst]
-__global__ __launch_bounds__(256) void k_heat(DevState s, RunConst rc, int src, int dst, int sub,
-                                              int last) {
+// Tiled explicit substeps.  A workgroup owns a kHT x kHT tile of a coil's
+// (r, z) grid and loads it with a halo of H cells (u, T of the source buffer,
+// q) into LDS; substep k (0 <= k < H) updates the cells at least k + 1 cells
+// inside the loaded region, whose neighbours were all updated by substep
+// k - 1, so after H substeps the owned tile is exact.  Neighbours and face
+// conductances follow from the grid indices and a per-row table (the same
+// host-computed values as the per-element conductances, summed in the same
+// face order), so no per-element geometry is read.  Per substep the owned
+// cells' border outflow is summed per tile; the last substep of a step also
+// keeps the tile's largest T and its lowest public index.
+__device__ __forceinline__ int elem_of(const CoilDev &c, int ir, int iz) {
+    return c.off + ((ir / c.ne) * c.turns + iz / c.ne) * c.ne2 + (ir % c.ne) * c.ne + iz % c.ne;
+}
+
+__global__ __launch_bounds__(256) void k_heat_tile(DevState s, RunConst rc, int src, int dst, int sub0, int H,
+                                                   int last) {
+    extern __shared__ double sh[];
     __shared__ double red_o[256];
     __shared__ double red_t[256];
     __shared__ long long red_i[256];
+    const int Wd = kHT + 2 * H, ncell = Wd * Wd;
+    double *Ta = sh, *Tb = sh + ncell, *ul = sh + 2 * ncell, *ql = sh + 3 * ncell;
+    HeatRow *rows = reinterpret_cast<HeatRow *>(sh + 4 * ncell);
     const int tid = threadIdx.x;
-    const int e = blockIdx.x * 256 + tid;
-    const double hs = rc.dt / (double)s.nsub;
-    double outv = 0.0, Tn = -INFINITY;
-    long long pub = LLONG_MAX;
-    if (e < s.N) {
-        const double *Ts = s.T[src];
-        const double Te = Ts[e];
-        if (s.rec_T) s.rec_T[(size_t)sub * s.N + e] = Te;
-        double flux = s.Gb[e] * (rc.T_bath - Te);
-#pragma unroll
-        for (int f = 0; f < 4; ++f) {
-            const int nbr = s.nb[4 * e + f];
-            if (nbr >= 0) flux += s.G[4 * e + f] * (Ts[nbr] - Te);
-        }
-        const double un = s.u[src][e] + hs * s.invV[e] * flux + hs * s.q[e];
-        Tn = T_of_u(rc, un);
-        s.u[dst][e] = un;
-        s.T[dst][e] = Tn;
-        outv = hs * s.Gb[e] * (Te - rc.T_bath);
-        pub = s.perm[e];
-        if (!isfinite(Tn)) atomicOr(&s.sc->status, ST_NONFINITE);
+    // the tile's coil: the last coil whose first tile is <= blockIdx.x
+    int lo = 0, hi = s.ncoils - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (s.coils[mid].tile_off <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
     }
-    red_o[tid] = outv;
-    red_t[tid] = Tn;
-    red_i[tid] = pub;
+    const CoilDev c = s.coils[lo];
+    const int lt = (int)blockIdx.x - c.tile_off;
+    const int nr = c.layers * c.ne, nz = c.turns * c.ne;
+    const int ir0 = (lt / c.ntile_z) * kHT - H, iz0 = (lt % c.ntile_z) * kHT - H;
+    const double *Tsrc = s.T[src], *usrc = s.u[src];
+    for (int k = tid; k < ncell; k += 256) {
+        const int ir = ir0 + k / Wd, iz = iz0 + k % Wd;
+        if (ir >= 0 && ir < nr && iz >= 0 && iz < nz) {
+            const int e = elem_of(c, ir, iz);
+            Ta[k] = Tsrc[e];
+            ul[k] = usrc[e];
+            ql[k] = s.q[e];
+        }
+    }
+    for (int i = tid; i < Wd; i += 256) {
+        const int ir = ir0 + i;
+        if (ir >= 0 && ir < nr) rows[i] = s.hrow[c.row_off + ir];
+    }
+    __syncthreads();
+    const double hs = rc.dt / (double)s.nsub;
+    double *Tc = Ta, *Tn = Tb;
+    for (int k = 0; k < H; ++k) {
+        const int sub = sub0 + k;
+        const int a = k + 1, wr = Wd - 2 * (k + 1);
+        double outv = 0.0;
+        for (int m = tid; m < wr * wr; m += 256) {
+            const int i = a + m / wr, j = a + m % wr;
+            const int ir = ir0 + i, iz = iz0 + j;
+            if (ir < 0 || ir >= nr || iz < 0 || iz >= nz) continue;
+            const int kk = i * Wd + j;
+            const HeatRow R = rows[i];
+            const double Te = Tc[kk];
+            // border faces in the order inner, outer, lower, upper
+            double gb = 0.0;
+            if (ir == 0) gb += R.gbin;
+            if (ir == nr - 1) gb += R.gbout;
+            if (iz == 0) gb += R.gbax;
+            if (iz == nz - 1) gb += R.gbax;
+            double flux = gb * (rc.T_bath - Te);
+            if (ir > 0) flux += R.gin * (Tc[kk - Wd] - Te);
+            if (ir < nr - 1) flux += R.gout * (Tc[kk + Wd] - Te);
+            if (iz > 0) flux += R.gax * (Tc[kk - 1] - Te);
+            if (iz < nz - 1) flux += R.gax * (Tc[kk + 1] - Te);
+            const double un = ul[kk] + hs * R.invV * flux + hs * ql[kk];
+            ul[kk] = un;
+            Tn[kk] = T_of_u(rc, un);
+            if (i >= H && i < H + kHT && j >= H && j < H + kHT) {  // owned cell
+                outv += hs * gb * (Te - rc.T_bath);
+                if (s.rec_T) s.rec_T[(size_t)sub * s.N + elem_of(c, ir, iz)] = Te;
+            }
+        }
+        red_o[tid] = outv;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if (tid < o) red_o[tid] += red_o[tid + o];
+            __syncthreads();
+        }
+        if (tid == 0) s.hb_out[(size_t)sub * s.nheat_blocks + blockIdx.x] = red_o[0];
+        double *t = Tc;
+        Tc = Tn;
+        Tn = t;
+    }
+    // owned cells out, with the tile's largest T (lowest public index on ties)
+    double tm = -INFINITY;
+    long long ti = LLONG_MAX;
+    unsigned bad = 0u;
+    for (int m = tid; m < kHT * kHT; m += 256) {
+        const int i = H + m / kHT, j = H + m % kHT;
+        const int ir = ir0 + i, iz = iz0 + j;
+        if (ir >= nr || iz >= nz) continue;
+        const int kk = i * Wd + j;
+        const int e = elem_of(c, ir, iz);
+        const double Tv = Tc[kk];
+        s.u[dst][e] = ul[kk];
+        s.T[dst][e] = Tv;
+        if (!isfinite(Tv)) bad = ST_NONFINITE;
+        const long long pub = (long long)c.off + (long long)ir * nz + iz;
+        if (Tv > tm || (Tv == tm && pub < ti)) {
+            tm = Tv;
+            ti = pub;
+        }
+    }
+    if (bad) atomicOr(&s.sc->status, bad);
+    if (!last) return;
+    red_t[tid] = tm;
+    red_i[tid] = ti;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (tid < o) {
-            red_o[tid] += red_o[tid + o];
-            const double a = red_t[tid], b = red_t[tid + o];
-            if (b > a || (b == a && red_i[tid + o] < red_i[tid])) {
-                red_t[tid] = b;
+            const double x = red_t[tid], y = red_t[tid + o];
+            if (y > x || (y == x && red_i[tid + o] < red_i[tid])) {
+                red_t[tid] = y;
                 red_i[tid] = red_i[tid + o];
             }
         }
         __syncthreads();
     }
     if (tid == 0) {
-        s.hb_out[(size_t)sub * s.nheat_blocks + blockIdx.x] = red_o[0];
-        if (last) {
-            s.hb_max[blockIdx.x] = red_t[0];
-            s.hb_arg[blockIdx.x] = red_i[0];
-        }
+        s.hb_max[blockIdx.x] = red_t[0];
+        s.hb_arg[blockIdx.x] = red_i[0];
     }
 }
 
@@ -326,7 +453,7 @@ __global__ __launch_bounds__(256) void k_finalize(DevState s, RunConst rc) {
         u += s.Uw[w];
         x = fmax(x, s.wmaxx[w]);
     }
-    const int no = s.nsub * s.nheat_blocks;
+    const int no = s.hb_slots * s.nheat_blocks;
 #pragma unroll 4
     for (int i = tid; i < no; i += 256) o += s.hb_out[i];
     for (int b = tid; b < s.nheat_blocks; b += 256) {
@@ -462,6 +589,11 @@ __global__ void k_fill(double *p, double v, int n) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i < n) p[i] = v;
 }
+// initial element currents: the coil's I0 spread evenly over each wire
+__global__ void k_init_current(DevState s) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e < s.N) s.I[e] = s.coils[s.elem_coil[e]].I0e;
+}
 __global__ void k_u_of_T(DevState s, RunConst rc) {
     const int e = blockIdx.x * 256 + threadIdx.x;
     if (e >= s.N) return;
@@ -530,30 +662,34 @@ hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st) {
     return hipGetLastError();
 }
 
-void heat_buffers(int nsub, int sub, int *src, int *dst) {
-    // substep sub reads buffer src and writes dst; the last substep of a step
-    // lands in buffer 0 (for nsub = 1 the result goes to 1 and is copied back)
-    if (nsub == 1) {
-        *src = 0;
-        *dst = 1;
-    } else {
-        *src = (sub == 0) ? 0 : 1 + ((sub - 1) & 1);
-        *dst = (sub == nsub - 1) ? 0 : 1 + (sub & 1);
-    }
-}
+// The substeps of one time step: L launches of H_l <= kHMaxHalo substeps each
+// (L = 2 for up to 2 kHMaxHalo substeps), through the scratch buffers 1 and 2,
+// the last one writing buffer 0.  A single substep goes to buffer 1 and is
+// copied back.
+int heat_launches(int nsub) { return nsub <= 1 ? 1 : std::max(2, (nsub + kHMaxHalo - 1) / kHMaxHalo); }
 
-hipError_t launch_heat(const DevState &s, const RunConst &rc, int sub, hipStream_t st) {
-    int src, dst;
-    heat_buffers(s.nsub, sub, &src, &dst);
-    hipLaunchKernelGGL(k_heat, dim3(s.nheat_blocks), dim3(256), 0, st, s, rc, src, dst, sub,
-                       sub == s.nsub - 1 ? 1 : 0);
-    hipError_t err = hipGetLastError();
-    if (err == hipSuccess && s.nsub == 1) {
-        hipLaunchKernelGGL(k_copy2, dim3(blocks_for(s.N)), dim3(256), 0, st, s.u[1], s.T[1],
-                           s.u[0], s.T[0], s.N);
-        err = hipGetLastError();
+hipError_t launch_heat_step(const DevState &s, const RunConst &rc, hipStream_t st) {
+    if (rc.adi) return launch_adi_step(s, rc, st);
+    const int L = heat_launches(s.nsub);
+    int sub0 = 0, src = 0;
+    for (int l = 0; l < L; ++l) {
+        const int H = s.nsub / L + (l < s.nsub % L ? 1 : 0);
+        const bool lastl = l == L - 1;
+        const int dst = (lastl && s.nsub > 1) ? 0 : (src == 1 ? 2 : 1);
+        const int Wd = kHT + 2 * H;
+        const size_t lds = sizeof(double) * 4 * (size_t)Wd * Wd + sizeof(HeatRow) * (size_t)Wd;
+        hipLaunchKernelGGL(k_heat_tile, dim3(s.nheat_blocks), dim3(256), lds, st, s, rc, src, dst, sub0, H,
+                           lastl ? 1 : 0);
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+        sub0 += H;
+        src = dst;
     }
-    return err;
+    if (s.nsub == 1) {
+        hipLaunchKernelGGL(k_copy2, dim3(blocks_for(s.N)), dim3(256), 0, st, s.u[1], s.T[1], s.u[0], s.T[0], s.N);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_finalize(const DevState &s, const RunConst &rc, hipStream_t st) {
@@ -584,6 +720,11 @@ hipError_t launch_u_of_T(const DevState &s, const RunConst &rc, hipStream_t st) 
 hipError_t launch_fill(double *p, double v, int n, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_current(const DevState &s, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_current, dim3(blocks_for(s.N)), dim3(256), 0, st, s);
     return hipGetLastError();
 }
 

@@ -68,6 +68,14 @@ def test_validation_errors():
         pk.query(w, tile_targets=100)
     with pytest.raises(pk.CoilError):
         pk.query(w, tile_sources=100)
+    # options of the extended model
+    for kw, wb in [({}, w.replace(rho_n=-1.0)), ({"geometry": 5}, w), ({"coupling": 7}, w),
+                   ({"heat_solver": 9}, w), ({"cg_max_iter": -1}, w), ({}, w.replace(k_exp=float("nan")))]:
+        with pytest.raises(pk.CoilError) as ei:
+            pk.query(wb, **kw)
+        assert ei.value.code == -1
+    pk.query(w.replace(rho_n=3e-10), geometry="planar")
+    pk.query(w.replace(coils=[cs.Coil(**{**w.coils[0].__dict__, "I0": 2.0})]))
 
 
 def test_library_elliptic_approximations():

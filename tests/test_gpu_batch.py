@@ -173,7 +173,9 @@ def test_timing_modes():
     t2 = g.timing_read()
     g.timing(0)
     assert np.array_equal(g.get(pk.F_I), ref)
-    assert [t1[k]["launches"] for k in ("field", "wire", "heat", "reduce")] == [3, 3, 3 * g.n_sub, 3]
+    # the heat substeps of a step run in two tiled launches (one when there is one substep)
+    heat_launches = 1 if g.n_sub <= 1 else max(2, -(-g.n_sub // 8))
+    assert [t1[k]["launches"] for k in ("field", "wire", "heat", "reduce")] == [3, 3, 3 * heat_launches, 3]
     assert all(t1[k]["ms"] > 0 for k in t1)
     assert t2["field"]["launches"] == 2 and t2["field"]["ms"] > 0
     assert all(t2[k]["launches"] == 0 and t2[k]["ms"] == 0 for k in ("wire", "heat", "reduce"))
