@@ -273,6 +273,23 @@ int coil_reset(coil_t *h);
    background field is not included.  Synchronises. */
 int coil_field_at(coil_t *h, int64_t npts, const double *r, const double *z, double *Br, double *Bz);
 
+/* ---- allocation-free probes ----
+   For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the field of
+   coil_field_at (B_r, B_z in T at npts points (r, z) in metres, r >= 0, from
+   the current element currents of every coil, FP64 direct sum, background
+   field excluded, B_r = 0 on the axis), with r, z, Br and Bz DEVICE arrays of
+   npts doubles.  Asynchronous on the handle's stream; calls no hipMalloc,
+   hipFree or allocating library routine.  The sources are split into chunks
+   whose partial sums live in one static device array of
+   COIL_FIELD_AT_SCRATCH_BYTES per GPU (held until the process ends), shared by
+   every handle and call on that GPU: calls that overlap on one GPU race.  Its
+   address is taken once per device at coil_init.  COIL_E_INVAL when npts
+   exceeds COIL_FIELD_AT_SCRATCH_BYTES / 16 (524,288 points).  Results agree
+   with coil_field_at to rounding (the chunks are summed in a fixed order). */
+#define COIL_FIELD_AT_SCRATCH_BYTES (8u << 20)
+int coil_field_at_noalloc(coil_t *h, int64_t npts, const double *r, const double *z, double *Br, double *Bz);
+
 /* Host snapshot of the state (I, u, T, Phi, Q_w, the per-wire onset and quench
    diagnostics, step, Q, T_peak and its argmax, heat outflow, status) for
    checkpoint and resume.  coil_save with

@@ -76,7 +76,9 @@ EXPORTS = [
     "coil_graph", "coil_destroy", "coil_last_error", "coil_host_ellip", "coil_set_params",
     "coil_adjoint_query", "coil_adjoint", "coil_field_transpose", "coil_set_tiles", "coil_autotune",
     "coil_field_stats", "coil_field_at", "coil_save", "coil_load", "coil_set_widths",
+    "coil_field_at_noalloc",
 ]
+FIELD_AT_SCRATCH_BYTES = 8 << 20  # COIL_FIELD_AT_SCRATCH_BYTES
 
 _lib = None
 
@@ -115,6 +117,7 @@ def lib():
         L.coil_autotune.argtypes = [vp, C.c_int32, C.c_char_p, _i32p]
         L.coil_field_stats.argtypes = [vp, _dp, C.c_int32]
         L.coil_field_at.argtypes = [vp, C.c_int64, _dp, _dp, _dp, _dp]
+        L.coil_field_at_noalloc.argtypes = [vp, C.c_int64, vp, vp, vp, vp]
         L.coil_save.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
         L.coil_load.argtypes = [vp, vp, C.c_size_t]
         _lib = L
@@ -405,6 +408,16 @@ class Coil:
         check(lib().coil_field_at(self.h, r.size, r.ctypes.data_as(_dp), z.ctypes.data_as(_dp),
                                   br.ctypes.data_as(_dp), bz.ctypes.data_as(_dp)))
         return br, bz
+
+    def field_at_noalloc(self, r, z, Br, Bz) -> None:
+        """coil_field_at_noalloc: r, z, Br, Bz are float64 device tensors of one
+        length; asynchronous on the handle's stream (synchronize() to wait)."""
+        n = int(r.numel())
+        for t in (r, z, Br, Bz):
+            if t.numel() != n or not t.is_cuda or t.dtype.itemsize != 8 or not t.is_contiguous():
+                raise ValueError("r, z, Br, Bz must be contiguous float64 device tensors of one length")
+        check(lib().coil_field_at_noalloc(self.h, n, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr()),
+                                          C.c_void_p(Br.data_ptr()), C.c_void_p(Bz.data_ptr())))
 
     def save(self) -> bytes:
         need = C.c_size_t()

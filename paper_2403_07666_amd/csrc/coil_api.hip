@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -572,6 +573,10 @@ size_t layout(Plan &p) {
 
 }  // namespace
 
+namespace {
+int scratch_for_current_device(double2 **out);  // defined with the static scratch below
+}  // namespace
+
 // ------------------------------------------------------------------ handle
 struct coil_s {
     Plan plan;
@@ -604,6 +609,7 @@ struct coil_s {
     bool capturing = false;
     int tz_split = 0;    // source-row groups of the translation pass (0 = automatic)
     int tz_force_w = 0;  // segment width of the translation pass (0 = automatic)
+    double2 *scratch = nullptr;  // this device's static scratch (coil_field_at_noalloc)
     double cg_tol = 1e-12;       // coupled solve: relative residual to reach
     int cg_maxit = 100;          // coupled solve: iterations per step at most
     int cg_check = 8;            // eager stepping: iterations between convergence checks
@@ -1064,6 +1070,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     h->tz.ticket = at<int>(h, p.ticket_b);
     h->tz.Ipub32 = p.prec == COIL_MIXED ? at<float>(h, p.Ipub32_b) : nullptr;
     HIPCHECK(tz_resident_grids(h->tz));
+    if ((rc = scratch_for_current_device(&h->scratch))) return rc;
     s.coils = at<CoilDev>(h, p.coils_b);
     s.items = at<PairItem>(h, p.items_b);
     s.bbox = at<int4>(h, p.bbox_b);
@@ -1978,6 +1985,58 @@ extern "C" int coil_field_at(coil_t *h, int64_t npts, const double *r, const dou
         HIPCHECK(hipMemcpyAsync(Bz + p0, oz, sizeof(double) * np, hipMemcpyDeviceToHost, st));
         HIPCHECK(hipStreamSynchronize(st));
     }
+    return COIL_OK;
+}
+
+// ------------------------------------------------------------------ probes without allocation
+// Scratch of coil_field_at_noalloc: the probes' per-chunk partial sums.  Each
+// GPU the library runs on holds its own copy until the process ends; host
+// code uses only the device address found by hipGetSymbolAddress (kept per
+// device), never the array's name.
+static __device__ __align__(256) double2 scratch[COIL_FIELD_AT_SCRATCH_BYTES / sizeof(double2)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2 *g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's scratch address (looked up once per device)
+int scratch_for_current_device(double2 **out) {
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(COIL_E_HIP, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return fail(COIL_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double2 *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return COIL_OK;
+}
+}  // namespace
+
+extern "C" int coil_field_at_noalloc(coil_t *h, int64_t npts, const double *r, const double *z, double *Br,
+                                     double *Bz) {
+    if (!h) return fail(COIL_E_INVAL, "handle is NULL");
+    if (npts < 0) return fail(COIL_E_INVAL, "npts < 0");
+    const int64_t cap = (int64_t)(COIL_FIELD_AT_SCRATCH_BYTES / sizeof(double2));
+    if (npts > cap) return fail(COIL_E_INVAL, "npts %lld exceeds the %lld probes the static scratch holds",
+                                (long long)npts, (long long)cap);
+    if (npts == 0) return COIL_OK;
+    if (!r || !z || !Br || !Bz) return fail(COIL_E_INVAL, "NULL argument");
+    if (!h->scratch) return fail(COIL_E_STATE, "no scratch address for this handle's device");
+    const DevState &s = h->ds;
+    // source chunks: about 2048 workgroups in all, at most one chunk per LDS
+    // stage of sources, and within the scratch
+    const int np = (int)npts;
+    const long long nb = (np + 255) / 256;
+    long long nchunk = std::max<long long>(1, (2048 + nb - 1) / nb);
+    nchunk = std::min<long long>(nchunk, std::max(1, (s.N + kStage - 1) / kStage));
+    nchunk = std::max<long long>(1, std::min<long long>(nchunk, cap / np));
+    HIPCHECK(launch_probe_chunked(s, at<double>(h, h->plan.zphys_b), np, r, z, Br, Bz, h->scratch, (int)nchunk,
+                                  h->stream));
     return COIL_OK;
 }
 

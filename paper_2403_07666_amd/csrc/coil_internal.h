@@ -174,6 +174,9 @@ hipError_t launch_reset_scalars(Scalars *sc, double T_bath, hipStream_t st);
 hipError_t launch_stored(const DevState &s, double *out, hipStream_t st);
 hipError_t launch_probe(const DevState &s, const double *zphys, int np, const double *pr, const double *pz,
                         double *br, double *bz, hipStream_t st);
+// probes with the sources in nchunk chunks, partial sums in part (np * nchunk double2)
+hipError_t launch_probe_chunked(const DevState &s, const double *zphys, int np, const double *pr, const double *pz,
+                                double *br, double *bz, double2 *part, int nchunk, hipStream_t st);
 
 // host-side copies of the elliptic approximations (same coefficients)
 void host_ellip_f64(double m1, double *K, double *E);

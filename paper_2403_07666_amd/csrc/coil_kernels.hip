@@ -572,6 +572,50 @@ __global__ __launch_bounds__(256) void k_probe(DevState s, const double *zphys, 
     }
 }
 
+// Probes with the sources split into chunks (grid.y = chunk): partial sums
+// (B_r r, B_z) of chunk c for probe p at part[c np + p]; k_probe_sum adds the
+// chunks in order.  More workgroups than probes / 256 when there are few probes.
+__global__ __launch_bounds__(256) void k_probe_chunk(DevState s, const double *zphys, int np, const double *pr,
+                                                     const double *pz, int chunk, double2 *part) {
+    __shared__ double2 sp[kStage];  // (r, z)
+    __shared__ double si[kStage];   // mu0 I / (2 pi)
+    const int tid = threadIdx.x;
+    const int p = blockIdx.x * 256 + tid;
+    const bool act = p < np;
+    const double r = act ? pr[p] : 1.0, z = act ? pz[p] : 0.0;
+    double ar = 0.0, az = 0.0;
+    const int j0 = blockIdx.y * chunk, j1 = min(s.N, j0 + chunk);
+    for (int s0 = j0; s0 < j1; s0 += kStage) {
+        const int cnt = min(kStage, j1 - s0);
+        __syncthreads();
+        if (tid < cnt) {
+            sp[tid] = make_double2(s.r[s0 + tid], zphys[s0 + tid]);
+            si[tid] = kMu0 / (2.0 * kPi) * s.I[s0 + tid];
+        }
+        __syncthreads();
+        for (int j = 0; j < cnt; ++j) {
+            const double2 q = sp[j];
+            pair64(r - q.x, z - q.y, r + q.x, si[j], ar, az);
+        }
+    }
+    if (act) part[(size_t)blockIdx.y * np + p] = make_double2(ar, az);
+}
+
+__global__ void k_probe_sum(int np, int nchunk, const double *pr, const double2 *part, double *out_br,
+                            double *out_bz) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= np) return;
+    double ar = 0.0, az = 0.0;
+    for (int c = 0; c < nchunk; ++c) {
+        const double2 v = part[(size_t)c * np + p];
+        ar += v.x;
+        az += v.y;
+    }
+    const double r = pr[p];
+    out_br[p] = r > 0.0 ? ar / r : 0.0;
+    out_bz[p] = az;
+}
+
 // ------------------------------------------------------------------ small kernels
 __global__ void k_gather(const double *src, const int *perm, int n, double *dst) {
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -743,6 +787,18 @@ hipError_t launch_probe(const DevState &s, const double *zphys, int np, const do
                         double *br, double *bz, hipStream_t st) {
     if (np <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_probe, dim3(blocks_for(np)), dim3(256), 0, st, s, zphys, np, pr, pz, br, bz);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_chunked(const DevState &s, const double *zphys, int np, const double *pr, const double *pz,
+                                double *br, double *bz, double2 *part, int nchunk, hipStream_t st) {
+    if (np <= 0) return hipSuccess;
+    const int chunk = (s.N + nchunk - 1) / nchunk;
+    hipLaunchKernelGGL(k_probe_chunk, dim3(blocks_for(np), nchunk), dim3(256), 0, st, s, zphys, np, pr, pz, chunk,
+                       part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_probe_sum, dim3(blocks_for(np)), dim3(256), 0, st, np, nchunk, pr, part, br, bz);
     return hipGetLastError();
 }
 
