@@ -15,6 +15,19 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-10, "mixed": 1e-5}
+EPS = 2.220446049250313e-16
+
+
+def rise_floor(w, T_max, rise):
+    """Rounding floor of T - T_bath relative to its rise: the line systems of
+    the ADI step have condition number kappa = 1 + 4 alpha dt / d^2 (alpha the
+    largest diffusivity), so the two solvers (cyclic reduction on the GPU,
+    Thomas in the oracle) can differ by about kappa eps T; 8 times that,
+    relative to the rise, bounds the comparison from below."""
+    d = min(c.wire_side / c.ne for c in w.coils)
+    alpha = w.k0 * (T_max / w.T_ref) ** w.k_exp / (w.C0 * (w.T_bath / w.T_ref) ** w.cp_exp)
+    kappa = 1 + 4 * alpha * w.dt / d ** 2
+    return 8 * kappa * EPS * T_max / rise
 
 
 def _pk():
@@ -50,8 +63,10 @@ def _compare(w, inp, prec, nsteps, chunks=3, kmult=None):
         ei = nerr(g.get(pk.F_I), o.get(oracle.I))
         sg, so = g.scalars(), o.scalars()
         eq = abs(sg["Q"] - so["Q"]) / so["Q"] if so["Q"] > 0 else 0.0
-        _say(f"  {w.name} {prec} chunk {k}: T {et:.2e} dT {er:.2e} B {eb:.2e} I {ei:.2e} Q {eq:.2e} rise {rise:.3e}")
-        assert max(et, er, eb, ei, eq) <= tol
+        floor = rise_floor(w, float(To.max()), rise) if rise > 0 else 0.0
+        _say(f"  {w.name} {prec} chunk {k}: T {et:.2e} dT {er:.2e} (floor {floor:.1e}) B {eb:.2e} I {ei:.2e} "
+             f"Q {eq:.2e} rise {rise:.3e}")
+        assert max(et, eb, ei, eq) <= tol and er <= max(tol, floor)
     sg = g.scalars()
     assert sg["stored"] == pytest.approx(sg["Q"] - sg["Q_out"], rel=1e-9)
     assert sg["n_sub"] == 1
@@ -93,4 +108,9 @@ def test_adi_far_beyond_explicit_limit():
     for _ in range(10):
         g.run(1)
         assert o.step() == 0
-        assert nerr(g.get(pk.F_T) - 4.2, o.get(oracle.T) - 4.2) <= 1e-10
+        Tg, To = g.get(pk.F_T), o.get(oracle.T)
+        rise = float(np.abs(To - 4.2).max())
+        e = nerr(Tg - 4.2, To - 4.2)
+        _say(f"  far step: T {nerr(Tg, To):.2e} T-T_bath {e:.2e} (floor {rise_floor(w, float(To.max()), rise):.1e})")
+        assert nerr(Tg, To) <= 1e-10
+        assert e <= max(1e-10, rise_floor(w, float(To.max()), rise))
