@@ -99,6 +99,7 @@ class Workload:
     coupling: str = "transport"  # inter-wire induction: "transport" or "full"
     heat_solver: str = "explicit"  # "explicit" (sub-cycled) or "adi"
     ins_R0: float = 0.0  # ADI: insulation resistance between wires, m^2 K/W
+    subelements: int = 0  # 0: the wire model; s >= 1: s x s subelements per wire (I = I_H + I_I)
     heat_substeps: int = 0  # 0 = automatic (stability rule)
     # disorder recipe
     seed: int = 1

@@ -25,6 +25,7 @@ I, J, BR, BZ, T, PHI, QW, UW, E, EP, U, Q, PSI, R, Z, V, JC, DI = range(18)
 # per-wire flux-jump / quench diagnostics
 ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH = range(18, 24)
 KMULT = 24  # per-element conductivity multiplier of the ADI heat step
+IH = 25  # field-driven component of the element current (subelement model)
 PER_WIRE = (QW, UW, ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH)
 
 
@@ -57,6 +58,7 @@ class Cfg(C.Structure):
         ("coupling", C.c_int),
         ("heat_solver", C.c_int),
         ("k_exp", C.c_double), ("h_exp", C.c_double), ("ins_R0", C.c_double),
+        ("subelements", C.c_int),
     ]
 
 
@@ -172,6 +174,7 @@ def make_cfg(w, n_sub: int | None = None, planar: bool = False) -> Cfg:
     c.k_exp = float(getattr(w, "k_exp", 0.0))
     c.h_exp = float(getattr(w, "h_exp", 0.0))
     c.ins_R0 = float(getattr(w, "ins_R0", 0.0))
+    c.subelements = int(getattr(w, "subelements", 0))
     return c
 
 

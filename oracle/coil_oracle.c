@@ -35,6 +35,13 @@
  *      paper's field iteration), one dense constrained solve per coil.
  *   R4 A-V: 2 pi r_e E_e + U_w = -dPhi_e/dt, sum_{e in w} I_e = I_t.
  *   R5 time integrator: linearised backward Euler per wire.
+ *   Subelements (option subelements = s >= 1): a wire's ne x ne elements form
+ *      s x s square subelements.  The element current is I_H + I_I: the
+ *      field-driven part I_H keeps zero net current in every subelement
+ *      (uncoupled subelements), the transport part I_I carries the wire's
+ *      transport current (coupled); both respond through the same wire
+ *      matrix, each driven by the resistivity rho^k = E/J of the total J^k
+ *      times its own current (the paper's J_H and J_I).
  *   R6 order: field -> local -> wire solve -> heat; Jc, E from (B^k, T^k).
  *   R7 normal state: pure power law by default (Jc <= 0 with J != 0 is an
  *      error); with rho_n > 0 the power-law resistivity acts in parallel with
@@ -272,6 +279,7 @@ struct orc_sim {
     /* per-wire flux-jump / quench diagnostics (see ORC_ONSET .. ORC_P_QUENCH) */
     double *onset, *quench, *Qon, *Qqu, *Tqu, *Pqu;
     double *kmult;               /* ADI heat: conductivity multiplier per element */
+    double *IH;                  /* subelement model: field-driven component of I */
     int field_only;  /* geometry only: no inductance blocks, no transport flux */
 };
 
@@ -303,6 +311,10 @@ static int cfg_valid(const orc_cfg *c) {
     if (c->heat_solver != 0 && c->heat_solver != 1) return 0;
     if (!isfinite(c->k_exp) || !isfinite(c->h_exp) || !(c->ins_R0 >= 0) || !isfinite(c->ins_R0)) return 0;
     if (c->heat_solver == 0 && (c->k_exp != 0.0 || c->h_exp != 0.0 || c->ins_R0 != 0.0)) return 0;
+    if (c->subelements < 0) return 0;
+    for (int i = 0; i < c->n_coils && c->subelements >= 1; ++i)
+        if (c->ne[i] % c->subelements != 0) return 0;
+    if (c->subelements >= 1 && c->coupling != 0) return 0;
     for (int i = 0; i < c->n_coils && c->coupling == 1; ++i)
         if ((long)c->layers[i] * c->turns[i] * c->ne[i] * c->ne[i] > 4096) return 0;
     for (int i = 0; i < c->n_coils; ++i)
@@ -511,6 +523,7 @@ orc_sim *orc_create_ex(const orc_cfg *cfg, const double *jc0_mult, const double 
     for (long w = 0; w < Nw; ++w) { s->onset[w] = -1.0; s->quench[w] = -1.0; }
     s->kmult = dalloc(N);
     for (long e = 0; e < N; ++e) s->kmult[e] = 1.0;
+    s->IH = dalloc(N);
     for (long e = 0; e < N; ++e) s->T[e] = c->T_bath;
     /* initial transport current I0 of each coil, spread evenly over the
        elements of each of its wires */
@@ -532,7 +545,7 @@ void orc_destroy(orc_sim *s) {
     void *p[] = {s->r, s->z, s->d, s->V, s->coil, s->wire, s->coil_off, s->wire_off, s->welem,
                  s->wn, s->wcoil, s->jcs, s->cw, s->psi, s->nb, s->G, s->Gb, s->I, s->u, s->T,
                  s->Phi, s->Br, s->Bz, s->E, s->Ep, s->Jc, s->dI, s->q, s->Qw, s->U,
-                 s->onset, s->quench, s->Qon, s->Qqu, s->Tqu, s->Pqu, s->kmult};
+                 s->onset, s->quench, s->Qon, s->Qqu, s->Tqu, s->Pqu, s->kmult, s->IH};
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(s);
 }
@@ -684,6 +697,97 @@ static int coupled_solve(orc_sim *s, double dBa) {
         }
     done:
         free(A); free(X); free(Y); free(S); free(u); free(MdI);
+    }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ */
+/* subelement model (subelements >= 1)                                 */
+/* ------------------------------------------------------------------ */
+/* Per wire, with A = M_ww + dt diag(2 pi r E'/d^2) and rho_e = E_e / J_e
+   (E'_e where J_e = 0):
+     A dI_H = b_H - dt P_s U_s,  P_s^T dI_H = 0   (one loop voltage per subelement)
+     A dI_I = b_I - dt 1 U_w,    1^T dI_I = dI_t  (one loop voltage per wire)
+     b_H = -dI_t Psi_u - pi r^2 dB_a - dt 2 pi r rho J_H,  b_I = -dt 2 pi r rho J_I,
+   P_s the element-to-subelement incidence.  b_H + b_I is the drive of the
+   one-subelement model, so with s = 1 the sum dI_H + dI_I is its solution.
+   dI = dI_H + dI_I; I_H += dI_H; the flux and Joule source as for the
+   wire model.  An element of subelement s sees the loop voltage U_w + U_s;
+   the wire's voltage is their average over its (equal) elements,
+   U_w + mean_s U_s, which is the wire model's U when s = 1. */
+static int subelement_solve(orc_sim *s, double dBa) {
+    const orc_cfg *c = &s->cfg;
+    const double dt = c->dt;
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic, 4)
+    for (long w = 0; w < s->Nw; ++w) {
+        const int n = s->wn[w];
+        const int ci = s->wcoil[w];
+        const int ne = c->ne[ci], sb = ne / c->subelements, ns = c->subelements * c->subelements;
+        const double dIt = c->ramp[ci] * dt;
+        const long *el = s->welem + s->wire_off[w];
+        double *A = dalloc((long)n * n), *xh = dalloc(n), *xi = dalloc(n), *y = dalloc(n);
+        double *Y = dalloc((long)n * ns), *S = dalloc((long)ns * ns), *u = dalloc(ns), *col = dalloc(n);
+        int *sub = (int *)calloc((size_t)n, sizeof(int));
+        memcpy(A, s->Mww[w], sizeof(double) * (size_t)n * n);
+        for (int i = 0; i < n; ++i) {
+            const long e = el[i];
+            const double d2 = s->d[e] * s->d[e];
+            const double J = s->I[e] / d2, JH = s->IH[e] / d2;
+            const double rho = (J != 0.0) ? s->E[e] / J : s->Ep[e];
+            A[i * n + i] += dt * 2.0 * ORC_PI * s->r[e] * s->Ep[e] / d2;
+            xh[i] = -dIt * s->psi[e] - ORC_PI * s->r[e] * s->r[e] * dBa - dt * 2.0 * ORC_PI * s->r[e] * rho * JH;
+            xi[i] = -dt * 2.0 * ORC_PI * s->r[e] * rho * (J - JH);
+            y[i] = 1.0;
+            /* local element order a*ne + b inside the wire: subelement of (a, b) */
+            sub[i] = ((i / ne) / sb) * c->subelements + (i % ne) / sb;
+        }
+        if (cholesky(A, n) != 0) {
+            #pragma omp atomic write
+            bad = 1;
+        } else {
+            chol_solve(A, n, xh);
+            chol_solve(A, n, xi);
+            chol_solve(A, n, y);
+            for (int v = 0; v < ns; ++v) {
+                for (int i = 0; i < n; ++i) col[i] = (sub[i] == v) ? 1.0 : 0.0;
+                chol_solve(A, n, col);
+                for (int i = 0; i < n; ++i) Y[(long)i * ns + v] = col[i];
+            }
+            for (int i = 0; i < n; ++i) {
+                u[sub[i]] += xh[i];
+                for (int v = 0; v < ns; ++v) S[sub[i] * ns + v] += Y[(long)i * ns + v];
+            }
+            if (cholesky(S, ns) != 0) {
+                #pragma omp atomic write
+                bad = 1;
+            } else {
+                chol_solve(S, ns, u);  /* dt U_s */
+                double sx = 0.0, sy = 0.0;
+                for (int i = 0; i < n; ++i) { sx += xi[i]; sy += y[i]; }
+                const double U = (sx - dIt) / (dt * sy);
+                double uh = 0.0;
+                for (int v = 0; v < ns; ++v) uh += u[v];
+                /* wire voltage: the element-averaged loop voltage U_I + mean_s U_s */
+                s->U[w] = U + uh / ((double)ns * dt);
+                for (int i = 0; i < n; ++i) {
+                    double dIH = xh[i];
+                    for (int v = 0; v < ns; ++v) dIH -= Y[(long)i * ns + v] * u[v];
+                    s->dI[el[i]] = dIH + (xi[i] - dt * U * y[i]);
+                    s->IH[el[i]] += dIH;
+                }
+                for (int i = 0; i < n; ++i) {
+                    double v = 0.0;
+                    for (int j = 0; j < n; ++j) v += s->Mww[w][i * n + j] * s->dI[el[j]];
+                    col[i] = v;
+                }
+                for (int i = 0; i < n; ++i) {
+                    const long e = el[i];
+                    s->Phi[e] += col[i] + dIt * s->psi[e] + ORC_PI * s->r[e] * s->r[e] * dBa;
+                }
+            }
+        }
+        free(A); free(xh); free(xi); free(y); free(Y); free(S); free(u); free(col); free(sub);
     }
     return bad;
 }
@@ -912,8 +1016,9 @@ int orc_step(orc_sim *s) {
 
     /* 3. A-V solve, linearised backward Euler */
     if (c->coupling == 1 && coupled_solve(s, dBa)) return -4;
+    if (c->subelements >= 1 && subelement_solve(s, dBa)) return -4;
     #pragma omp parallel for schedule(dynamic, 4)
-    for (long w = 0; w < (c->coupling == 1 ? 0 : Nw); ++w) {
+    for (long w = 0; w < ((c->coupling == 1 || c->subelements >= 1) ? 0 : Nw); ++w) {
         const int n = s->wn[w];
         const int ci = s->wcoil[w];
         const double dIt = c->ramp[ci] * dt;
@@ -1051,6 +1156,7 @@ int orc_get(const orc_sim *s, int field, double *dst, long count) {
         case ORC_T_QUENCH: src = s->Tqu; n = Nw; break;
         case ORC_P_QUENCH: src = s->Pqu; n = Nw; break;
         case ORC_KMULT: src = s->kmult; break;
+        case ORC_IH: src = s->IH; break;
         case ORC_J:
             if (count < N) return -1;
             for (long e = 0; e < N; ++e) dst[e] = s->I[e] / (s->d[e] * s->d[e]);
@@ -1113,7 +1219,7 @@ int orc_scalars(const orc_sim *s, double *dst, int n) {
 int orc_tangent(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
                 const double *c_wire, const double *dc_wire, const double *dramp,
                 long nsteps, double *obj, double *dobj) {
-    if (cfg->coupling != 0 || cfg->heat_solver != 0) return -1;
+    if (cfg->coupling != 0 || cfg->heat_solver != 0 || cfg->subelements >= 1) return -1;
     orc_sim *s = orc_create(cfg, jc0_mult, strain, c_wire);
     if (!s) return -1;
     const orc_cfg *c = &s->cfg;

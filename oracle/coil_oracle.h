@@ -46,6 +46,9 @@ typedef struct {
     double k_exp, h_exp;  /* ADI: k = k0 (T/T_ref)^k_exp k_mult_e, h = h0 (T/T_ref)^h_exp */
     double ins_R0;    /* ADI: thermal resistance per area of the insulation between
                          wires, m^2 K / W, scaled by (T_ref / T_face)^k_exp (0 = none) */
+    int subelements;  /* 0: one current per element (the wire model); s >= 1: the
+                         two-component subelement model with s x s square
+                         subelements of ne/s x ne/s elements per wire */
 } orc_cfg;
 
 typedef struct orc_sim orc_sim;
@@ -99,7 +102,10 @@ enum { ORC_I = 0, ORC_J = 1, ORC_BR = 2, ORC_BZ = 3, ORC_T = 4, ORC_PHI = 5,
        ORC_T_QUENCH = 22, ORC_P_QUENCH = 23,
        /* per-element conductivity multiplier of the ADI heat step (settable,
           default 1): the composite map */
-       ORC_KMULT = 24 };
+       ORC_KMULT = 24,
+       /* the field-driven component I_H of the element current (subelement
+          model; I - I_H is the transport component) */
+       ORC_IH = 25 };
 int    orc_get(const orc_sim *s, int field, double *dst, long count);
 int    orc_set(orc_sim *s, int field, const double *src, long count);
 /* scalars: [0]=t, [1]=step, [2]=Q, [3]=T_peak, [4]=sum U_w, [5]=max |J|/Jc,
@@ -117,8 +123,9 @@ void   orc_field_points(const orc_sim *s, const double *I, long np, const double
 /* elements of wire w (public indices), returns count */
 int    orc_wire_elems(const orc_sim *s, long w, long *dst);
 
-/* tangent-linear (forward-mode) derivative (coupling 0 and the explicit heat
-   step only; returns -1 otherwise) of the run's objectives
+/* tangent-linear (forward-mode) derivative (coupling 0, the explicit heat
+   step and the wire model, subelements 0, only; returns -1 otherwise) of the
+   run's objectives
    Q (time-integrated Joule heat) and T_peak along the direction
    (dc_wire[Nw], dramp[n_coils]) for nsteps from the initial state.
    obj[2] = (Q, T_peak), dobj[2] = directional derivatives. */
