@@ -100,6 +100,8 @@ class Workload:
     heat_solver: str = "explicit"  # "explicit" (sub-cycled) or "adi"
     ins_R0: float = 0.0  # ADI: insulation resistance between wires, m^2 K/W
     subelements: int = 0  # 0: the wire model; s >= 1: s x s subelements per wire (I = I_H + I_I)
+    em_tol: float = 0.0  # > 0: variable-step EM integration within the step (relative tolerance)
+    em_max_level: int = 0  # finest EM substep dt / 2^level (0 -> 10)
     heat_substeps: int = 0  # 0 = automatic (stability rule)
     # disorder recipe
     seed: int = 1

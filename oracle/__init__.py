@@ -26,7 +26,8 @@ I, J, BR, BZ, T, PHI, QW, UW, E, EP, U, Q, PSI, R, Z, V, JC, DI = range(18)
 ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH = range(18, 24)
 KMULT = 24  # per-element conductivity multiplier of the ADI heat step
 IH = 25  # field-driven component of the element current (subelement model)
-PER_WIRE = (QW, UW, ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH)
+EMSUB = 26  # per wire: EM substeps of the last step (variable-step integration)
+PER_WIRE = (QW, UW, ONSET, QUENCH, Q_ONSET, Q_QUENCH, T_QUENCH, P_QUENCH, EMSUB)
 
 
 def build(force: bool = True) -> str:
@@ -59,6 +60,7 @@ class Cfg(C.Structure):
         ("heat_solver", C.c_int),
         ("k_exp", C.c_double), ("h_exp", C.c_double), ("ins_R0", C.c_double),
         ("subelements", C.c_int),
+        ("em_tol", C.c_double), ("em_max_level", C.c_int),
     ]
 
 
@@ -175,6 +177,8 @@ def make_cfg(w, n_sub: int | None = None, planar: bool = False) -> Cfg:
     c.h_exp = float(getattr(w, "h_exp", 0.0))
     c.ins_R0 = float(getattr(w, "ins_R0", 0.0))
     c.subelements = int(getattr(w, "subelements", 0))
+    c.em_tol = float(getattr(w, "em_tol", 0.0))
+    c.em_max_level = int(getattr(w, "em_max_level", 0))
     return c
 
 

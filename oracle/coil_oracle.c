@@ -34,7 +34,9 @@
  *      flux of every element current of the coil (the converged form of the
  *      paper's field iteration), one dense constrained solve per coil.
  *   R4 A-V: 2 pi r_e E_e + U_w = -dPhi_e/dt, sum_{e in w} I_e = I_t.
- *   R5 time integrator: linearised backward Euler per wire.
+ *   R5 time integrator: linearised backward Euler per wire.  Option em_tol > 0:
+ *      variable-step integration of each wire within the step (substeps
+ *      dt / 2^m with step-doubling error control; em_wire).
  *   Subelements (option subelements = s >= 1): a wire's ne x ne elements form
  *      s x s square subelements.  The element current is I_H + I_I: the
  *      field-driven part I_H keeps zero net current in every subelement
@@ -280,6 +282,7 @@ struct orc_sim {
     double *onset, *quench, *Qon, *Qqu, *Tqu, *Pqu;
     double *kmult;               /* ADI heat: conductivity multiplier per element */
     double *IH;                  /* subelement model: field-driven component of I */
+    double *emsub;               /* per wire: EM substeps of the last step */
     int field_only;  /* geometry only: no inductance blocks, no transport flux */
 };
 
@@ -315,6 +318,8 @@ static int cfg_valid(const orc_cfg *c) {
     for (int i = 0; i < c->n_coils && c->subelements >= 1; ++i)
         if (c->ne[i] % c->subelements != 0) return 0;
     if (c->subelements >= 1 && c->coupling != 0) return 0;
+    if (!(c->em_tol >= 0.0) || !isfinite(c->em_tol) || c->em_max_level < 0 || c->em_max_level > 20) return 0;
+    if (c->em_tol > 0.0 && (c->coupling != 0 || c->subelements != 0)) return 0;
     for (int i = 0; i < c->n_coils && c->coupling == 1; ++i)
         if ((long)c->layers[i] * c->turns[i] * c->ne[i] * c->ne[i] > 4096) return 0;
     for (int i = 0; i < c->n_coils; ++i)
@@ -524,6 +529,7 @@ orc_sim *orc_create_ex(const orc_cfg *cfg, const double *jc0_mult, const double 
     s->kmult = dalloc(N);
     for (long e = 0; e < N; ++e) s->kmult[e] = 1.0;
     s->IH = dalloc(N);
+    s->emsub = dalloc(Nw);
     for (long e = 0; e < N; ++e) s->T[e] = c->T_bath;
     /* initial transport current I0 of each coil, spread evenly over the
        elements of each of its wires */
@@ -545,7 +551,7 @@ void orc_destroy(orc_sim *s) {
     void *p[] = {s->r, s->z, s->d, s->V, s->coil, s->wire, s->coil_off, s->wire_off, s->welem,
                  s->wn, s->wcoil, s->jcs, s->cw, s->psi, s->nb, s->G, s->Gb, s->I, s->u, s->T,
                  s->Phi, s->Br, s->Bz, s->E, s->Ep, s->Jc, s->dI, s->q, s->Qw, s->U,
-                 s->onset, s->quench, s->Qon, s->Qqu, s->Tqu, s->Pqu, s->kmult, s->IH};
+                 s->onset, s->quench, s->Qon, s->Qqu, s->Tqu, s->Pqu, s->kmult, s->IH, s->emsub};
     for (size_t i = 0; i < sizeof(p) / sizeof(p[0]); ++i) free(p[i]);
     free(s);
 }
@@ -698,6 +704,129 @@ static int coupled_solve(orc_sim *s, double dBa) {
     done:
         free(A); free(X); free(Y); free(S); free(u); free(MdI);
     }
+    return bad;
+}
+
+/* ------------------------------------------------------------------ */
+/* variable-step EM integration of a wire (em_tol > 0)                 */
+/* ------------------------------------------------------------------ */
+/* One linearised implicit Euler step of length h for wire w from the element
+   currents of the step's state, with E and E' given per element (R5 with dt
+   replaced by h): (M_ww + h diag(2 pi r E'/d^2)) dI + h U 1 = b, 1^T dI = ramp h,
+   b = -ramp h Psi_u - pi r^2 dBa/dt h - h 2 pi r E.  Returns nonzero if the
+   factorisation fails. */
+static int be_step(const orc_sim *s, long w, double h, const double *E, const double *Ep, double *dI,
+                   double *U) {
+    const orc_cfg *c = &s->cfg;
+    const int n = s->wn[w];
+    const double dIt = c->ramp[s->wcoil[w]] * h, dBa = c->dBa_dt * h;
+    const long *el = s->welem + s->wire_off[w];
+    double *A = dalloc((long)n * n), *y = dalloc(n);
+    memcpy(A, s->Mww[w], sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < n; ++i) {
+        const long e = el[i];
+        const double d2 = s->d[e] * s->d[e];
+        A[i * n + i] += h * 2.0 * ORC_PI * s->r[e] * Ep[i] / d2;
+        dI[i] = -dIt * s->psi[e] - ORC_PI * s->r[e] * s->r[e] * dBa - h * 2.0 * ORC_PI * s->r[e] * E[i];
+        y[i] = 1.0;
+    }
+    int bad = cholesky(A, n);
+    if (!bad) {
+        chol_solve(A, n, dI);
+        chol_solve(A, n, y);
+        double sx = 0.0, sy = 0.0;
+        for (int i = 0; i < n; ++i) { sx += dI[i]; sy += y[i]; }
+        *U = (sx - dIt) / (h * sy);
+        for (int i = 0; i < n; ++i) dI[i] -= h * (*U) * y[i];
+    }
+    free(A); free(y);
+    return bad;
+}
+
+/* The wire's currents over [t_k, t_k + dt] with B^k and T^k (so Jc) held, as
+   the paper integrates the electromagnetic equations with a variable time
+   step to follow the stiff power law (Methods, Numerical Algorithm, last
+   sentence).  Substeps h = dt / 2^m.  An attempt takes one step of h and two
+   of h/2 from the same currents I (E, E' re-evaluated at the midpoint
+   currents); with I1 and I2 the two results,
+     err = max_e |I2_e - I1_e| / (em_tol max(|I2_e|, Jc_e d^2)),
+   err <= 1 keeps the extrapolated 2 I2 - I1 (second order; the extrapolated
+   linearly implicit Euler step is L-stable) and advances by h, otherwise m
+   grows by one and the attempt is repeated (at the finest level the attempt
+   is kept whatever err).  After a kept substep with err <= 1/4, at a position
+   that is a multiple of 2h, m falls by one.  Every step starts at m = 0.  Per
+   kept substep the Joule source R8 of each half step, E_lin J^{new}, is
+   accumulated times its length, and the loop voltage as 2 U2 - U1 (U2 the
+   mean of the half steps'); q and U_w are their averages over dt.  dI is the
+   step's total change; the flux update is that of R4 with it. */
+static int em_wire(orc_sim *s, long w) {
+    const orc_cfg *c = &s->cfg;
+    const int n = s->wn[w];
+    const long *el = s->welem + s->wire_off[w];
+    const int L = c->em_max_level > 0 ? c->em_max_level : 10;
+    const long full = 1L << L;
+    double *Iv = dalloc(n), *Im = dalloc(n), *E1 = dalloc(n), *P1 = dalloc(n), *Em = dalloc(n), *Pm = dalloc(n);
+    double *d1 = dalloc(n), *da = dalloc(n), *db = dalloc(n), *qa = dalloc(n);
+    double Uacc = 0.0, x;
+    long pos = 0;
+    int m = 0, nsub = 0, bad = 0;
+    for (int i = 0; i < n; ++i) Iv[i] = s->I[el[i]];
+    while (pos < full && !bad) {
+        const double h = ldexp(c->dt, -m);
+        double U1, Ua, Ub;
+        for (int i = 0; i < n; ++i) {
+            const long e = el[i];
+            bad |= local_EJ(c, Iv[i] / (s->d[e] * s->d[e]), s->Jc[e], &E1[i], &P1[i], &x);
+        }
+        if (bad) break;
+        bad |= be_step(s, w, h, E1, P1, d1, &U1);
+        bad |= be_step(s, w, 0.5 * h, E1, P1, da, &Ua);
+        for (int i = 0; i < n; ++i) {
+            const long e = el[i];
+            Im[i] = Iv[i] + da[i];
+            bad |= local_EJ(c, Im[i] / (s->d[e] * s->d[e]), s->Jc[e], &Em[i], &Pm[i], &x);
+        }
+        if (bad) break;
+        bad |= be_step(s, w, 0.5 * h, Em, Pm, db, &Ub);
+        if (bad) break;
+        double err = 0.0;
+        for (int i = 0; i < n; ++i) {
+            const long e = el[i];
+            const double d2 = s->d[e] * s->d[e];
+            const double I2 = Im[i] + db[i], I1 = Iv[i] + d1[i];
+            const double sc = c->em_tol * fmax(fabs(I2), s->Jc[e] > 0.0 ? s->Jc[e] * d2 : 0.0);
+            const double dif = fabs(I2 - I1);
+            const double ei = (sc > 0.0) ? dif / sc : (dif == 0.0 ? 0.0 : INFINITY);
+            if (ei > err) err = ei;
+        }
+        if (err > 1.0 && m < L) {
+            ++m;
+            continue;
+        }
+        for (int i = 0; i < n; ++i) {
+            const long e = el[i];
+            const double d2 = s->d[e] * s->d[e];
+            const double I2 = Im[i] + db[i];
+            const double Ea = E1[i] + P1[i] * da[i] / d2, Eb = Em[i] + Pm[i] * db[i] / d2;
+            qa[i] += 0.5 * h * (Ea * (Im[i] / d2) + Eb * (I2 / d2));
+            Iv[i] = 2.0 * I2 - (Iv[i] + d1[i]);
+        }
+        Uacc += h * (Ua + Ub - U1);
+        pos += 1L << (L - m);
+        ++nsub;
+        if (err <= 0.25 && m > 0 && pos % (1L << (L - m + 1)) == 0) --m;
+    }
+    if (!bad) {
+        const double dt = c->dt;
+        for (int i = 0; i < n; ++i) {
+            const long e = el[i];
+            s->dI[e] = Iv[i] - s->I[e];
+            s->q[e] = qa[i] / dt;
+        }
+        s->U[w] = Uacc / dt;
+        s->emsub[w] = (double)nsub;
+    }
+    free(Iv); free(Im); free(E1); free(P1); free(Em); free(Pm); free(d1); free(da); free(db); free(qa);
     return bad;
 }
 
@@ -1024,6 +1153,26 @@ int orc_step(orc_sim *s) {
         const double dIt = c->ramp[ci] * dt;
         const long *el = s->welem + s->wire_off[w];
         double *A = dalloc((long)n * n), *x = dalloc(n), *y = dalloc(n), *MdI = dalloc(n);
+        s->emsub[w] = 1.0;
+        if (c->em_tol > 0.0) {
+            /* variable-step integration: dI, q and U_w from the substeps */
+            if (em_wire(s, w)) {
+                #pragma omp atomic write
+                bad = 1;
+            } else {
+                for (int i = 0; i < n; ++i) {
+                    double v = 0.0;
+                    for (int j = 0; j < n; ++j) v += s->Mww[w][i * n + j] * s->dI[el[j]];
+                    MdI[i] = v;
+                }
+                for (int i = 0; i < n; ++i) {
+                    const long e = el[i];
+                    s->Phi[e] += MdI[i] + dIt * s->psi[e] + ORC_PI * s->r[e] * s->r[e] * dBa;
+                }
+            }
+            free(A); free(x); free(y); free(MdI);
+            continue;
+        }
         memcpy(A, s->Mww[w], sizeof(double) * (size_t)n * n);
         for (int i = 0; i < n; ++i) {
             const long e = el[i];
@@ -1068,8 +1217,10 @@ int orc_step(orc_sim *s) {
             const long e = el[i];
             const double d2 = s->d[e] * s->d[e];
             s->I[e] += s->dI[e];
-            const double Elin = s->E[e] + s->Ep[e] * s->dI[e] / d2;
-            s->q[e] = Elin * (s->I[e] / d2);
+            if (c->em_tol <= 0.0) {  /* else q is the substeps' average */
+                const double Elin = s->E[e] + s->Ep[e] * s->dI[e] / d2;
+                s->q[e] = Elin * (s->I[e] / d2);
+            }
             ns_add(&qw, dt * s->V[e] * s->q[e]);
         }
         s->Qw[w] += ns_val(&qw);
@@ -1157,6 +1308,7 @@ int orc_get(const orc_sim *s, int field, double *dst, long count) {
         case ORC_P_QUENCH: src = s->Pqu; n = Nw; break;
         case ORC_KMULT: src = s->kmult; break;
         case ORC_IH: src = s->IH; break;
+        case ORC_EMSUB: src = s->emsub; n = Nw; break;
         case ORC_J:
             if (count < N) return -1;
             for (long e = 0; e < N; ++e) dst[e] = s->I[e] / (s->d[e] * s->d[e]);
@@ -1219,7 +1371,7 @@ int orc_scalars(const orc_sim *s, double *dst, int n) {
 int orc_tangent(const orc_cfg *cfg, const double *jc0_mult, const double *strain,
                 const double *c_wire, const double *dc_wire, const double *dramp,
                 long nsteps, double *obj, double *dobj) {
-    if (cfg->coupling != 0 || cfg->heat_solver != 0 || cfg->subelements >= 1) return -1;
+    if (cfg->coupling != 0 || cfg->heat_solver != 0 || cfg->subelements >= 1 || cfg->em_tol > 0.0) return -1;
     orc_sim *s = orc_create(cfg, jc0_mult, strain, c_wire);
     if (!s) return -1;
     const orc_cfg *c = &s->cfg;

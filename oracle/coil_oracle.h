@@ -49,6 +49,10 @@ typedef struct {
     int subelements;  /* 0: one current per element (the wire model); s >= 1: the
                          two-component subelement model with s x s square
                          subelements of ne/s x ne/s elements per wire */
+    double em_tol;    /* > 0: variable-step integration of each wire's currents within
+                         the step (substeps dt / 2^m, step-doubling error control with
+                         this relative tolerance); 0: one step of dt */
+    int em_max_level; /* finest substep dt / 2^em_max_level (0 -> 10) */
 } orc_cfg;
 
 typedef struct orc_sim orc_sim;
@@ -105,7 +109,9 @@ enum { ORC_I = 0, ORC_J = 1, ORC_BR = 2, ORC_BZ = 3, ORC_T = 4, ORC_PHI = 5,
        ORC_KMULT = 24,
        /* the field-driven component I_H of the element current (subelement
           model; I - I_H is the transport component) */
-       ORC_IH = 25 };
+       ORC_IH = 25,
+       /* per wire: substeps of the last step (variable-step EM integration) */
+       ORC_EMSUB = 26 };
 int    orc_get(const orc_sim *s, int field, double *dst, long count);
 int    orc_set(orc_sim *s, int field, const double *src, long count);
 /* scalars: [0]=t, [1]=step, [2]=Q, [3]=T_peak, [4]=sum U_w, [5]=max |J|/Jc,
