@@ -232,6 +232,34 @@ def adi_leg(pk, cs, torch, steps: int = 200) -> dict:
     return out
 
 
+def subelement_leg(pk, cs, torch, steps: int = 200) -> dict:
+    """The subelement model on the medium coil's driven variant (131,072
+    elements, 8 x 8 per wire as 4 x 4 subelements of 2 x 2 elements, mixed
+    field pass): step rate and wire phase per step against the wire model's."""
+    w = cs.workload("c2_active").replace(subelements=4)
+    inp = cs.generate(w)
+    out = {"workload": w.name + "_sub4x4", "n_elem": w.n_elem, "subelements_per_wire": 16, "steps": steps}
+    for key, wl in (("subelements", w), ("wire_model", w.replace(subelements=0))):
+        g = pk.Coil(wl, inp, precision="mixed")
+        g.run(5)
+        g.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.run(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        g.timing(True)
+        g.run(20)
+        ph = g.timing_read()
+        g.timing(False)
+        g.close()
+        out[key] = {"steps_per_s": steps / el, "wire_ms_per_step": ph["wire"]["ms"] / 20}
+    log(f"[bench] {out['workload']}: {out['subelements']['steps_per_s']:.0f} steps/s, wire phase "
+        f"{out['subelements']['wire_ms_per_step'] * 1e3:.1f} us/step (wire model "
+        f"{out['wire_model']['steps_per_s']:.0f} steps/s, {out['wire_model']['wire_ms_per_step'] * 1e3:.1f} us)")
+    return out
+
+
 def coupled_leg(pk, cs, torch, steps: int = 5) -> dict:
     """The fully coupled inter-wire induction on the medium coil (131,072
     elements, driven variant, mixed field pass): per-step wall time, CG
@@ -447,6 +475,7 @@ def main():
     ap.add_argument("--no-quench", action="store_true", help="skip the 20 x 20-turn quench leg")
     ap.add_argument("--no-adi", action="store_true", help="skip the composite (ADI heat step) leg")
     ap.add_argument("--no-coupled", action="store_true", help="skip the fully coupled induction leg")
+    ap.add_argument("--no-subelements", action="store_true", help="skip the subelement-model leg")
     ap.add_argument("--adjoint-steps", type=int, default=200,
                     help="horizon of the adjoint/forward timing at 384,000 elements")
     ap.add_argument("--c5-full", action="store_true",
@@ -579,6 +608,9 @@ def main():
     coupled = None
     if not args.no_coupled:
         coupled = coupled_leg(pk, cs, torch)
+    subel = None
+    if not args.no_subelements:
+        subel = subelement_leg(pk, cs, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -626,6 +658,7 @@ def main():
         "quench": quench,
         "composite_adi": adi,
         "coupled_induction": coupled,
+        "subelements": subel,
     }
     print(json.dumps(out))
 

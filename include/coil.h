@@ -96,6 +96,35 @@ enum coil_coupling { COIL_COUPLE_TRANSPORT = 0, COIL_COUPLE_FULL = 1 };
    convergence; a captured graph holds all cg_max_iter iterations, those after
    convergence returning at once.  The adjoint is not available for it. */
 
+/* Subelement model (paper, Results, the numerical-algorithm paragraph and the
+   one before it: a wire's subelements, separated by resistive barriers, are
+   uncoupled under an external field, each with zero net current, and coupled
+   under transport current; J = J_H + J_I, both computed from the resistivity of
+   the total J^k).  With subelements = s >= 1 the element current is I_H + I_I:
+   per wire and step, A dI_H = b_H - P (dt U_s) with P^T dI_H = 0 (one loop
+   voltage per subelement, P the element-to-subelement incidence) and
+   A dI_I = b_I - dt U_I 1 with 1^T dI_I = dI_t, A = M_ww + dt diag(2 pi r E'/d^2),
+   b_H = -dI_t Psi_u - pi r^2 dB_a - dt 2 pi r rho J_H, b_I = -dt 2 pi r rho J_I,
+   rho = E/J of the total J^k (E' where J = 0).  s = 1 gives the wire model's
+   currents.  COIL_F_UW is the element mean of the loop voltages,
+   U_I + mean_s U_s.  Setting COIL_F_I leaves I_H as it is.  Transport-only
+   coupling; no adjoint. */
+
+/* Variable-step integration of the wire currents (paper, Methods, Numerical
+   Algorithm, last sentence: Runge-Kutta with a variable time step for the
+   electromagnetic equations, against divergences of the stiff power law).
+   With em_tol > 0 each wire integrates its currents over the step with B^k and
+   T^k (so Jc) held, in substeps h = dt / 2^m of the linearised implicit Euler
+   step: an attempt takes one step of h and two of h/2 (the local law
+   re-evaluated at the midpoint); err = max_e |I2 - I1| / (em_tol max(|I2|,
+   Jc d^2)); err <= 1 keeps the extrapolated 2 I2 - I1 (second order,
+   L-stable), otherwise m grows by one (the finest level is kept whatever err);
+   after a kept substep with err <= 1/4 at a multiple of 2h, m falls by one.
+   Every step starts at m = 0.  q and U_w are the substeps' averages (the half
+   steps' E_lin J^{new}; 2 U2 - U1).  A wire whose resistive diagonal is below
+   FP64 resolution takes its exact one-substep linear step.  Transport-only
+   coupling, wire model; no adjoint. */
+
 /* Heat step (paper, Methods, heat paragraph).  EXPLICIT: sub-cycled explicit
    finite volumes (heat_substeps).  ADI: alternating-direction implicit, one
    radial and one axial tridiagonal sweep per step. */
@@ -150,7 +179,10 @@ enum coil_field {
     COIL_F_Q_ONSET = 19,  /* the wire's Joule heat accumulated before its onset step, J */
     COIL_F_Q_QUENCH = 20, /* ... before its quench step, J */
     COIL_F_T_QUENCH = 21, /* the wire's largest T^k at its quench step, K */
-    COIL_F_P_QUENCH = 22  /* its power density sum V E J / sum V at the quench step, W/m^3 */
+    COIL_F_P_QUENCH = 22, /* its power density sum V E J / sum V at the quench step, W/m^3 */
+    COIL_F_IH = 23,       /* subelement model: the field-driven component I_H of the element
+                             current, A (I - I_H is the transport component) */
+    COIL_F_EM_SUBSTEPS = 24  /* variable step: substeps each wire took in the last step (N_w) */
 };
 
 typedef struct {
@@ -194,6 +226,13 @@ typedef struct {
     int32_t heat_solver;    /* enum coil_heat */
     int32_t cg_max_iter;    /* COIL_COUPLE_FULL: iterations per step at most (0 -> 100) */
     double cg_tol;          /* COIL_COUPLE_FULL: relative residual to reach (0 -> 1e-12) */
+    int32_t subelements;    /* subelement model: s x s square subelements of ne/s x ne/s
+                               elements per wire (1 <= s <= 4, ne a multiple of s for every
+                               coil; 0 = one current per element, the wire model) */
+    double em_tol;          /* > 0: variable-step integration of the wire currents within a
+                               step with this relative tolerance; 0 = one step of dt */
+    int32_t em_max_level;   /* variable step: finest substep dt / 2^em_max_level (0 -> 10;
+                               at most 16) */
 } coil_config;
 
 typedef struct {
@@ -222,7 +261,9 @@ typedef void (*coil_report_fn)(const double *diag, int32_t ndiag, void *user);
 /* Sizes for a configuration.  No device work. */
 int coil_query(const coil_config *cfg, coil_sizes *out);
 
-/* Build a handle: validate, carve `workspace` (device memory, >= workspace_bytes,
+/* Build a handle for the paper's model coil (Methods, Numerical Algorithm and
+   Fig. 2(a): N_x x N_y wires of an axisymmetric solenoid, each split into
+   current elements): validate, carve `workspace` (device memory, >= workspace_bytes,
    256-byte aligned), precompute geometry, per-layer inductance blocks (host,
    FP64), the transport-flux pattern (device, FP64 all-pairs pass), in mixed
    precision the near kernel values of the translation pass (device, FP64,
@@ -233,20 +274,27 @@ int coil_query(const coil_config *cfg, coil_sizes *out);
 int coil_init(const coil_config *cfg, const coil_inputs *in, void *workspace,
               size_t workspace_bytes, void *stream, coil_t **out);
 
-/* Enqueue one time step (field pass, local law + wire solve, heat substeps,
-   reductions).  Asynchronous. */
+/* Enqueue one time step k -> k+1 in the order of the paper's key subroutine
+   (Methods, Numerical Algorithm and the Fig. 2(b) flow chart; the heat
+   paragraph): field pass, local law + wire solve, heat step, reductions.
+   Asynchronous. */
 int coil_step(coil_t *h);
 
-/* nsteps steps.  If report_every > 0 and cb != NULL, synchronise every
+/* nsteps steps of coil_step (the paper's time loop under a ramped transport
+   current and background field).  If report_every > 0 and cb != NULL, synchronise every
    report_every steps and call cb; returns COIL_E_NONFINITE if the status word
    shows a non-finite value at a report point or at the end (state left as is). */
 int coil_run(coil_t *h, int64_t nsteps, int64_t report_every, coil_report_fn cb, void *user);
 
-/* Only the field pass (step 1) on the current currents and time; results in
-   COIL_F_BR / COIL_F_BZ.  Asynchronous. */
+/* Only the field pass (step 1: the field at every element from the currents
+   of all elements plus the background, paper, Methods, Numerical Algorithm)
+   on the current currents and time; results in COIL_F_BR / COIL_F_BZ.
+   Asynchronous. */
 int coil_compute_field(coil_t *h);
 
-/* Copy a field out in public order.  dst is device memory if dst_on_device,
+/* Copy a field of the state (current, field, temperature, flux, the per-wire
+   flux-jump and quench records of the paper's Results) out in public order.
+   dst is device memory if dst_on_device,
    else host memory (then the call synchronises).  count must be >= the
    field's length (N, or N_w for per-wire fields). */
 int coil_get(coil_t *h, int32_t field, double *dst, int64_t count, int32_t dst_on_device);
@@ -269,7 +317,8 @@ int coil_scalars(coil_t *h, double *dst, int32_t n);
 int coil_reset(coil_t *h);
 
 /* Field at npts arbitrary points (host arrays, metres; r >= 0) from the current
-   element currents of every coil, FP64 direct sum; B_r = 0 on the axis.  The
+   element currents of every coil, FP64 direct sum of the coaxial-ring field
+   (the field the paper maps over the coil, Results, Figs. 3 and 5); B_r = 0 on the axis.  The
    background field is not included.  Synchronises. */
 int coil_field_at(coil_t *h, int64_t npts, const double *r, const double *z, double *Br, double *Bz);
 

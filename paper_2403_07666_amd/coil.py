@@ -22,7 +22,9 @@ FP64, MIXED = 0, 1
 ALGO_AUTO, ALGO_DIRECT, ALGO_TRANSLATION = 0, 1, 2
 F_I, F_J, F_BR, F_BZ, F_T, F_PHI, F_QW, F_UW, F_E, F_EP, F_U, F_Q, F_PSI, F_R, F_Z, F_DI, F_JC = range(17)
 F_ONSET, F_QUENCH, F_Q_ONSET, F_Q_QUENCH, F_T_QUENCH, F_P_QUENCH = range(17, 23)
-PER_WIRE = (F_QW, F_UW, F_ONSET, F_QUENCH, F_Q_ONSET, F_Q_QUENCH, F_T_QUENCH, F_P_QUENCH)
+F_IH = 23  # subelement model: field-driven component of the element current
+F_EM_SUBSTEPS = 24  # variable step: substeps per wire in the last step
+PER_WIRE = (F_QW, F_UW, F_ONSET, F_QUENCH, F_Q_ONSET, F_Q_QUENCH, F_T_QUENCH, F_P_QUENCH, F_EM_SUBSTEPS)
 AXISYMMETRIC, PLANAR = 0, 1
 COUPLE_TRANSPORT, COUPLE_FULL = 0, 1
 HEAT_EXPLICIT, HEAT_ADI = 0, 1
@@ -56,6 +58,8 @@ class Config(C.Structure):
         ("ins_R0", C.c_double),
         ("geometry", C.c_int32), ("coupling", C.c_int32), ("heat_solver", C.c_int32),
         ("cg_max_iter", C.c_int32), ("cg_tol", C.c_double),
+        ("subelements", C.c_int32),
+        ("em_tol", C.c_double), ("em_max_level", C.c_int32),
     ]
 
 
@@ -191,6 +195,9 @@ class _CfgHolder:
         cfg.cg_max_iter = int(cg_max_iter)
         cfg.cg_tol = float(cg_tol)
         cfg.ins_R0 = float(getattr(w, "ins_R0", 0.0))
+        cfg.subelements = int(getattr(w, "subelements", 0))
+        cfg.em_tol = float(getattr(w, "em_tol", 0.0))
+        cfg.em_max_level = int(getattr(w, "em_max_level", 0))
         self.cfg = cfg
 
 

@@ -70,6 +70,8 @@ struct Plan {
     int prec = COIL_FP64;  // arithmetic of the field passes (sets the width choice)
     int coupled = 0;       // COIL_COUPLE_FULL: buffers of the coupled solve
     int adi = 0;           // COIL_HEAT_ADI: buffers of the ADI heat step
+    int nsubel = 0;        // subelement model: subelements per wire side (0 = off)
+    int em = 0;            // variable-step EM integration
     int ncols = 0, hb_slots = 1, maxline = 0;
     int nchunk_cap = 1;    // partial-sum capacity in chunks
     size_t total = 0;
@@ -77,7 +79,7 @@ struct Plan {
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
         perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
-        sc_b, tmp_b, misc_b, diag_b, hrow_b, Lself_b, cgv_b, cgL_b, cgred_b, cgrw_b, cgsc_b, adi_b, kmult_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b,
+        sc_b, tmp_b, misc_b, diag_b, hrow_b, Lself_b, cgv_b, cgL_b, cgred_b, cgrw_b, cgsc_b, adi_b, kmult_b, IH_b, emsub_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b,
         Ipub32_b;
 };
 
@@ -151,6 +153,20 @@ int validate(const coil_config *c) {
         return fail(COIL_E_INVAL, "temperature-dependent k or h (k_exp, h_exp) needs heat_solver = COIL_HEAT_ADI");
     if (c->cg_max_iter < 0 || !(std::isfinite(c->cg_tol) && c->cg_tol >= 0.0))
         return fail(COIL_E_INVAL, "cg_max_iter must be >= 0 and cg_tol finite and >= 0");
+    if (!(std::isfinite(c->em_tol) && c->em_tol >= 0.0) || c->em_max_level < 0 || c->em_max_level > 16)
+        return fail(COIL_E_INVAL, "em_tol must be finite and >= 0, em_max_level in 0 .. 16");
+    if (c->em_tol > 0.0 && (c->coupling != COIL_COUPLE_TRANSPORT || c->subelements != 0))
+        return fail(COIL_E_INVAL, "the variable step (em_tol > 0) takes the wire model with transport-only coupling");
+    if (c->subelements < 0 || c->subelements > kMaxSubelements)
+        return fail(COIL_E_INVAL, "subelements must be in 0 .. %d", kMaxSubelements);
+    if (c->subelements > 0) {
+        for (int i = 0; i < c->n_coils; ++i)
+            if (c->ne[i] % c->subelements != 0)
+                return fail(COIL_E_INVAL, "coil %d: ne = %d is not a multiple of subelements = %d", i, c->ne[i],
+                            c->subelements);
+        if (c->coupling == COIL_COUPLE_FULL)
+            return fail(COIL_E_INVAL, "the subelement model takes the transport-only coupling");
+    }
     return COIL_OK;
 }
 
@@ -384,6 +400,8 @@ int make_plan(const coil_config *c, Plan &p) {
     p.prec = c->precision;
     p.coupled = c->coupling == COIL_COUPLE_FULL ? 1 : 0;
     p.adi = c->heat_solver == COIL_HEAT_ADI ? 1 : 0;
+    p.nsubel = c->subelements;
+    p.em = c->em_tol > 0.0 ? 1 : 0;
     int off = 0, woff = 0, loff = 0, goff = 0, toff = 0, roff = 0;
     for (int i = 0; i < c->n_coils; ++i) {
         CoilDev d{};
@@ -559,6 +577,8 @@ size_t layout(Plan &p) {
         p.adi_b = carve(cur, d8 * 10 * N);  // Cv, G (4), Gbr, Gbz, Lz0, Lr1, Ts
         p.kmult_b = carve(cur, d8 * N);
     }
+    if (p.nsubel) p.IH_b = carve(cur, d8 * N);
+    if (p.em) p.emsub_b = carve(cur, d8 * Nw);
     if (p.coupled) {
         p.Lself_b = carve(cur, d8 * N);
         p.cgv_b = carve(cur, d8 * 5 * N);
@@ -749,6 +769,8 @@ int reset_state(coil_t *h) {
     HIPCHECK(launch_fill(s.wmaxx, 0.0, s.Nw, st));
     HIPCHECK(launch_fill(s.onset, -1.0, 2 * s.Nw, st));  // onset and quench
     HIPCHECK(launch_fill(s.Qon, 0.0, 4 * s.Nw, st));     // Qon, Qqu, Tqu, Pqu
+    if (s.IH) HIPCHECK(launch_fill(s.IH, 0.0, s.N, st));
+    if (s.emsub) HIPCHECK(launch_fill(s.emsub, 0.0, s.Nw, st));
     if (s.cg) HIPCHECK(launch_fill(reinterpret_cast<double *>(s.cg), 0.0, sizeof(CgScalars) / sizeof(double), st));
     HIPCHECK(launch_reset_scalars(s.sc, h->T_bath, st));
     return COIL_OK;
@@ -823,6 +845,8 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     r.h_exp = cfg->h_exp;
     r.ins_R0 = cfg->ins_R0;
     r.adi = p.adi;
+    r.em_tol = cfg->em_tol;
+    r.em_levels = cfg->em_max_level > 0 ? cfg->em_max_level : 10;
     const bool planar = cfg->geometry == COIL_PLANAR;
 
     // host precompute, internal (wire-major) order
@@ -1126,6 +1150,11 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     s.hb_arg = at<long long>(h, p.hb_arg_b);
     s.hb_out = at<double>(h, p.hb_out_b);
     s.sc = at<Scalars>(h, p.sc_b);
+    if (p.nsubel) {
+        s.nsubel = p.nsubel;
+        s.IH = at<double>(h, p.IH_b);
+    }
+    if (p.em) s.emsub = at<double>(h, p.emsub_b);
     if (p.coupled) {
         s.cg_defer = 1;
         s.Lself = at<double>(h, p.Lself_b);
@@ -1281,6 +1310,15 @@ static int field_len(coil_t *h, int field, int *len, int *per_wire) {
         case COIL_F_Z: case COIL_F_DI: case COIL_F_JC:
             *len = h->ds.N;
             return COIL_OK;
+        case COIL_F_IH:
+            if (!h->ds.IH) return fail(COIL_E_INVAL, "COIL_F_IH needs the subelement model (subelements > 0)");
+            *len = h->ds.N;
+            return COIL_OK;
+        case COIL_F_EM_SUBSTEPS:
+            if (!h->ds.emsub) return fail(COIL_E_INVAL, "COIL_F_EM_SUBSTEPS needs the variable step (em_tol > 0)");
+            *per_wire = 1;
+            *len = h->ds.Nw;
+            return COIL_OK;
         default:
             return fail(COIL_E_INVAL, "unknown field %d", field);
     }
@@ -1311,6 +1349,7 @@ extern "C" int coil_get(coil_t *h, int32_t field, double *dst, int64_t count, in
             case COIL_F_Q_ONSET: src = s.Qon; break;
             case COIL_F_Q_QUENCH: src = s.Qqu; break;
             case COIL_F_T_QUENCH: src = s.Tqu; break;
+            case COIL_F_EM_SUBSTEPS: src = s.emsub; break;
             default: src = s.Pqu; break;
         }
         HIPCHECK(hipMemcpyAsync(dst, src, sizeof(double) * len, kind, st));
@@ -1332,6 +1371,7 @@ extern "C" int coil_get(coil_t *h, int32_t field, double *dst, int64_t count, in
         case COIL_F_DI: src = s.dI; break;
         case COIL_F_JC: src = s.Jc; break;
         case COIL_F_J: src = s.I; break;
+        case COIL_F_IH: src = s.IH; break;
         default: return fail(COIL_E_INVAL, "field %d not readable", field);
     }
     double *stage = dst_on_device ? dst : s.tmp;
@@ -1624,6 +1664,8 @@ extern "C" int coil_adjoint(coil_t *h, int64_t nsteps, double wQ, double wTpeak,
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(COIL_E_INVAL, "workspace must be 256-byte aligned");
     if (h->capturing) return fail(COIL_E_STATE, "not during graph capture");
     if (h->ds.cg_defer) return fail(COIL_E_INVAL, "the adjoint covers the transport-only coupling (COIL_COUPLE_TRANSPORT)");
+    if (h->ds.nsubel) return fail(COIL_E_INVAL, "the adjoint covers the wire model (subelements = 0)");
+    if (h->ds.emsub) return fail(COIL_E_INVAL, "the adjoint covers the fixed step (em_tol = 0)");
     if (h->rc.adi) return fail(COIL_E_INVAL, "the adjoint covers the explicit heat step (COIL_HEAT_EXPLICIT)");
     const long long K = nsteps, C = ckpt_every;
     const int sf = store_field != 0;
@@ -2048,9 +2090,12 @@ struct SnapHeader {
     double Q, Tpeak, Qout;
     int64_t Tpeak_pub, Tpeak_step;
     uint32_t status, nsub;
+    uint32_t nsubel, pad;
 };
+// I, u, T, Phi, the per-wire Q_w and diagnostics, and I_H in the subelement model
 size_t snap_bytes(const coil_t *h) {
-    return sizeof(SnapHeader) + sizeof(double) * (4 * (size_t)h->ds.N + 7 * (size_t)h->ds.Nw);
+    return sizeof(SnapHeader) +
+           sizeof(double) * ((h->ds.IH ? 5 : 4) * (size_t)h->ds.N + 7 * (size_t)h->ds.Nw);
 }
 }  // namespace
 
@@ -2064,7 +2109,7 @@ extern "C" int coil_save(coil_t *h, void *host_buf, size_t bytes, size_t *needed
     int rc = read_scalars(h, &sc);
     if (rc) return rc;
     SnapHeader hd{};
-    std::memcpy(hd.magic, "COILSNP2", 8);
+    std::memcpy(hd.magic, "COILSNP3", 8);
     hd.N = h->ds.N;
     hd.Nw = h->ds.Nw;
     hd.step = sc.step;
@@ -2075,6 +2120,7 @@ extern "C" int coil_save(coil_t *h, void *host_buf, size_t bytes, size_t *needed
     hd.Tpeak_step = sc.Tpeak_step;
     hd.status = sc.status;
     hd.nsub = (uint32_t)h->ds.nsub;
+    hd.nsubel = (uint32_t)h->ds.nsubel;
     char *b = static_cast<char *>(host_buf);
     std::memcpy(b, &hd, sizeof(hd));
     double *d = reinterpret_cast<double *>(b + sizeof(hd));
@@ -2088,6 +2134,8 @@ extern "C" int coil_save(coil_t *h, void *host_buf, size_t bytes, size_t *needed
     HIPCHECK(hipMemcpyAsync(d + 4 * N, h->ds.Qw, sizeof(double) * h->ds.Nw, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipMemcpyAsync(d + 4 * N + h->ds.Nw, h->ds.onset, sizeof(double) * 6 * h->ds.Nw, hipMemcpyDeviceToHost,
                             st));
+    if (h->ds.IH)
+        HIPCHECK(hipMemcpyAsync(d + 4 * N + 7 * h->ds.Nw, h->ds.IH, sizeof(double) * N, hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     return COIL_OK;
 }
@@ -2098,8 +2146,8 @@ extern "C" int coil_load(coil_t *h, const void *host_buf, size_t bytes) {
     if (bytes < sizeof(SnapHeader)) return fail(COIL_E_INVAL, "snapshot too small");
     SnapHeader hd;
     std::memcpy(&hd, host_buf, sizeof(hd));
-    if (std::memcmp(hd.magic, "COILSNP2", 8) != 0) return fail(COIL_E_INVAL, "not a coil snapshot");
-    if (hd.N != h->ds.N || hd.Nw != h->ds.Nw || (int)hd.nsub != h->ds.nsub)
+    if (std::memcmp(hd.magic, "COILSNP3", 8) != 0) return fail(COIL_E_INVAL, "not a coil snapshot");
+    if (hd.N != h->ds.N || hd.Nw != h->ds.Nw || (int)hd.nsub != h->ds.nsub || (int)hd.nsubel != h->ds.nsubel)
         return fail(COIL_E_INVAL, "snapshot of a different configuration");
     if (bytes < snap_bytes(h)) return fail(COIL_E_INVAL, "snapshot truncated");
     int rc = reset_state(h);  // clears scratch buffers and partial sums
@@ -2114,6 +2162,8 @@ extern "C" int coil_load(coil_t *h, const void *host_buf, size_t bytes) {
     HIPCHECK(hipMemcpyAsync(h->ds.Qw, d + 4 * N, sizeof(double) * h->ds.Nw, hipMemcpyHostToDevice, st));
     HIPCHECK(hipMemcpyAsync(h->ds.onset, d + 4 * N + h->ds.Nw, sizeof(double) * 6 * h->ds.Nw, hipMemcpyHostToDevice,
                             st));
+    if (h->ds.IH)
+        HIPCHECK(hipMemcpyAsync(h->ds.IH, d + 4 * N + 7 * h->ds.Nw, sizeof(double) * N, hipMemcpyHostToDevice, st));
     Scalars sc{};
     sc.Q = hd.Q;
     sc.Tpeak = hd.Tpeak;

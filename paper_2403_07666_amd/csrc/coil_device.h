@@ -264,6 +264,32 @@ __device__ __forceinline__ void solve2_lds(const double *sm, int n, int ld, int 
     }
 }
 
+// Solve L L^T v_q = v_q for K right-hand sides at once (factor in LDS, lane i
+// holding entry i of every v_q).
+template <int K>
+__device__ __forceinline__ void solve_lds(const double *sm, int n, int ld, int lane, bool act, double (&v)[K]) {
+    for (int j = 0; j < n; ++j) {
+        const double ljj = sm[j * ld + j];
+        const double l = (act && lane > j) ? sm[j * ld + lane] : 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const double vj = __shfl(v[q], j) / ljj;
+            if (lane == j) v[q] = vj;
+            if (act && lane > j) v[q] -= l * vj;
+        }
+    }
+    for (int j = n - 1; j >= 0; --j) {
+        const double ljj = sm[j * ld + j];
+        const double l = (act && lane < j) ? sm[lane * ld + j] : 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const double vj = __shfl(v[q], j) / ljj;
+            if (lane == j) v[q] = vj;
+            if (act && lane < j) v[q] -= l * vj;
+        }
+    }
+}
+
 // Load the layer's inductance block into LDS and add dt diag(2 pi r E'/d^2).
 __device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, int n, int ld, int lane,
                                                  bool act, double diag_add) {

@@ -23,6 +23,7 @@ constexpr double kMu0 = 4.0e-7 * kPi;
 constexpr double kGmdSquare = 0.4470491559036625;
 constexpr int kGroup = 64;       // bounding-box group = one wavefront of targets
 constexpr int kMaxWireElems = 64;  // per-wire solve keeps one element per lane
+constexpr int kMaxSubelements = 4;  // subelement model: subelements per wire side at most
 constexpr int kStage = 256;      // sources staged in LDS per pass
 constexpr int kHT = 16;          // heat step: tile side (cells owned by a workgroup)
 constexpr int kHMaxHalo = 8;     // heat step: substeps per launch at most (the tile's halo)
@@ -88,6 +89,8 @@ struct RunConst {
     double rho_n;   // normal-state resistivity in parallel with the power law (0 = off)
     double k0, h0, k_exp, h_exp, ins_R0;  // ADI heat step: k(T), h(T), insulation between wires
     int adi;        // 1: heat step by ADI
+    double em_tol;  // > 0: variable-step integration of the wire currents within a step
+    int em_levels;  // finest substep dt / 2^em_levels
     float m1_near;  // mixed mode: pairs with m1 < m1_near run in FP64
     int prec;
 };
@@ -142,6 +145,11 @@ struct DevState {
     Scalars *sc;
     double *tmp;             // N doubles of staging for get/set
     // coupled A-V solve (COIL_COUPLE_FULL; null otherwise)
+    // subelement model: subelements per wire side (0 = one current per element)
+    // and the field-driven component I_H of the element current
+    int nsubel;
+    double *IH;
+    double *emsub;           // per wire: substeps of the last step (variable step; null otherwise)
     int cg_defer;            // 1: the per-wire kernels leave the step's updates to the coupled solve
     const double *Lself;     // ring self inductance of each element
     double *cg_x, *cg_r, *cg_z, *cg_p, *cg_q;  // correction, residual, S r, direction, A p

@@ -138,6 +138,133 @@ __global__ __launch_bounds__(256) void k_field_finalize(DevState s, RunConst rc,
     s.Bz[e] = bz;
 }
 
+// Per-wire bookkeeping of a step, after its solve: Q_w, U_w, max |J|/Jc, the
+// status bits, the flux-jump onset (|J/Jc| > 1) and the quench criterion (the
+// wire's resistivity sum V E J / sum V J^2 of this step's local law against
+// 0.95 rho_n).  J0 = J^k of the lane's element; lane 0 writes.
+__device__ __forceinline__ void wire_diagnostics(const DevState &s, const RunConst &rc, int w, int e, bool act,
+                                                 double J0, const Local &lo, unsigned bad, double qv, double U,
+                                                 bool clear_flag) {
+    const double qw = wave_sum(act ? rc.dt * s.V[e] * qv : 0.0);
+    const double mx = wave_max(lo.x);
+    bad = wave_or(bad);
+    double sEJ = 0.0, sJJ = 0.0, sV = 0.0, Tw = 0.0;
+    if (rc.rho_n > 0.0) {
+        const double Ve = act ? s.V[e] : 0.0;
+        sEJ = wave_sum(Ve * lo.E * J0);
+        sJJ = wave_sum(Ve * J0 * J0);
+        sV = wave_sum(Ve);
+        Tw = wave_max(act ? s.T[0][e] : -INFINITY);
+    }
+    if (threadIdx.x == 0) {
+        const double Qold = s.Qw[w];
+        if (!s.cg_defer) {
+            s.Uw[w] = U;
+            s.wq[w] = qw;
+            s.Qw[w] = Qold + qw;
+        }
+        s.wmaxx[w] = mx;
+        if (clear_flag) s.wflag[w] = 0;
+        if (bad) atomicOr(&s.sc->status, bad);
+        // flux-jump onset and quench of the wire at step k
+        const double kstep = (double)s.sc->step;
+        if (s.onset[w] < 0.0 && mx > 1.0) {
+            s.onset[w] = kstep;
+            s.Qon[w] = Qold;
+        }
+        if (rc.rho_n > 0.0 && s.quench[w] < 0.0 && sJJ > 0.0 && sEJ / sJJ > 0.95 * rc.rho_n) {
+            s.quench[w] = kstep;
+            s.Qqu[w] = Qold;
+            s.Tqu[w] = Tw;
+            s.Pqu[w] = sEJ / sV;
+        }
+    }
+}
+
+// One linearised implicit Euler step of length h for the wire, from the local
+// law lo of the lane's element (E, E' at the step's currents):
+//   (M_ww + h diag(2 pi r E'/d^2)) dI + h U 1 = b,  1^T dI = ramp h,
+//   b = -ramp h Psi_u - pi r^2 dBa/dt h - h 2 pi r E,
+// A factorised in LDS.  dIt_h = ramp h, dBa_h = dBa/dt h.
+__device__ unsigned be_step_lds(double *sm, const double *M, int n, int ld, int lane, bool act, double h,
+                                const Local &lo, double re, double d2, double psi, double dIt_h, double dBa_h,
+                                double &dI, double &U) {
+    __syncthreads();  // the previous factor's last reads
+    load_wire_matrix(sm, M, n, ld, lane, act, h * 2.0 * kPi * re * lo.Ep / d2);
+    unsigned bad = chol_lds(sm, n, ld, lane, act);
+    double xv = act ? -dIt_h * psi - kPi * re * re * dBa_h - h * 2.0 * kPi * re * lo.E : 0.0;
+    double yv = act ? 1.0 : 0.0;
+    solve2_lds(sm, n, ld, lane, act, xv, yv);
+    const double sx = wave_sum(act ? xv : 0.0);
+    const double sy = wave_sum(act ? yv : 0.0);
+    U = (sx - dIt_h) / (h * sy);
+    dI = act ? xv - h * U * yv : 0.0;
+    return bad;
+}
+
+// Variable-step integration of the wire's currents over the step, with B^k
+// and T^k (so Jc) held: substeps h = dt / 2^m; an attempt takes one step of h
+// and two of h/2 (the local law re-evaluated at the midpoint currents); with
+// I1, I2 their results, err = max_e |I2 - I1| / (em_tol max(|I2|, Jc d^2)).
+// err <= 1 keeps 2 I2 - I1 (local extrapolation) and advances; otherwise m
+// grows by one and the attempt is repeated (kept at the finest level).  After
+// a kept substep with err <= 1/4 at a multiple of 2h, m falls by one.  Every
+// step starts at m = 0.  The Joule source of the half steps, E_lin J^{new},
+// is accumulated times their length; the loop voltage as 2 U2 - U1; the flux
+// as 2 (dPhi_a + dPhi_b) - dPhi_1, each dPhi = -h (2 pi r E_lin + U) from its
+// own circuit equation.  Returns dI, the step's mean q and U, and the flux
+// change; every exit condition is wave-uniform.
+__device__ unsigned em_integrate(double *sm, const DevState &s, const RunConst &rc, const CoilDev &c,
+                                 const double *M, int n, int ld, int lane, bool act, int w, int e, double I0,
+                                 double br, double bz, double &dI, double &qv, double &U, double &dPhi, int &nsub) {
+    const double dt = rc.dt, d2 = c.d * c.d, re = act ? s.r[e] : 0.0, psi = act ? s.psi[e] : 0.0;
+    const double cw = s.cw[w], jcs = act ? s.jcs[e] : 0.0, T = act ? s.T[0][e] : rc.T_bath;
+    const int L = rc.em_levels;
+    const long long full = 1LL << L;
+    long long pos = 0;
+    int m = 0;
+    unsigned bad = 0;
+    double Iv = act ? I0 : 0.0, qa = 0.0, Ua = 0.0, ph = 0.0;
+    nsub = 0;
+    while (pos < full) {
+        const double h = ldexp(dt, -m), hh = 0.5 * h;
+        const double dIt_h = ldexp(c.dIt, -m), dBa_h = ldexp(rc.dBa_dt * dt, -m);
+        Local la, lm;
+        bad |= act ? local_law(rc, cw, jcs, Iv / d2, T, br, bz, la) : 0u;
+        if (!act) la.E = la.Ep = la.Jc = 0.0;
+        double d1, U1, da, Uh1, db, Uh2;
+        bad |= be_step_lds(sm, M, n, ld, lane, act, h, la, re, d2, psi, dIt_h, dBa_h, d1, U1);
+        bad |= be_step_lds(sm, M, n, ld, lane, act, hh, la, re, d2, psi, 0.5 * dIt_h, 0.5 * dBa_h, da, Uh1);
+        const double Im = Iv + da;
+        bad |= act ? local_law(rc, cw, jcs, Im / d2, T, br, bz, lm) : 0u;
+        if (!act) lm.E = lm.Ep = 0.0;
+        bad |= be_step_lds(sm, M, n, ld, lane, act, hh, lm, re, d2, psi, 0.5 * dIt_h, 0.5 * dBa_h, db, Uh2);
+        const double I2 = Im + db, I1 = Iv + d1;
+        const double sc = rc.em_tol * fmax(fabs(I2), la.Jc > 0.0 ? la.Jc * d2 : 0.0);
+        const double dif = fabs(I2 - I1);
+        const double ei = !act ? 0.0 : (sc > 0.0 ? dif / sc : (dif == 0.0 ? 0.0 : INFINITY));
+        const double err = wave_max(ei);
+        if (err > 1.0 && m < L) {
+            ++m;
+            continue;
+        }
+        const double Ea = la.E + la.Ep * da / d2, Eb = lm.E + lm.Ep * db / d2, E1 = la.E + la.Ep * d1 / d2;
+        qa += hh * (Ea * (Im / d2) + Eb * (I2 / d2));
+        ph += 2.0 * (-hh * (2.0 * kPi * re * Ea + Uh1) - hh * (2.0 * kPi * re * Eb + Uh2)) +
+              h * (2.0 * kPi * re * E1 + U1);
+        Ua += h * (Uh1 + Uh2 - U1);
+        Iv = 2.0 * I2 - I1;
+        pos += 1LL << (L - m);
+        ++nsub;
+        if (err <= 0.25 && m > 0 && pos % (1LL << (L - m + 1)) == 0) --m;
+    }
+    dI = act ? Iv - I0 : 0.0;
+    qv = qa / dt;
+    U = Ua / dt;
+    dPhi = ph;
+    return bad;
+}
+
 // ------------------------------------------------------------------ local law + per-wire A-V solve
 // One wavefront per wire, one element per lane (n_e <= 64).  The wire matrix is
 // A = M_ww + dt diag(2 pi r E'/d^2).  Two kernels per step:
@@ -195,6 +322,7 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
             if (lane == 0) s.wflag[w] = 1;
             return;
         }
+        if (s.emsub && lane == 0) s.emsub[w] = 1.0;  // a linear step: one substep is exact
         xv = matvec_loaded(minv, n, act, b);
         yv = act ? s.yl[lay * n + lane] : 0.0;
         sy = s.syl[lay];
@@ -257,42 +385,165 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
         if (s.rec_dI) s.rec_dI[e] = dI;
         if (!isfinite(I1) || !isfinite(qv)) bad |= ST_NONFINITE;
     }
-    const double qw = wave_sum(act ? dt * s.V[e] * qv : 0.0);
-    const double mx = wave_max(lo.x);
-    bad = wave_or(bad);
-    // quench criterion: the wire's resistivity sum V E J / sum V J^2 of this
-    // step's local law against 0.95 rho_n (uniform branch)
-    double sEJ = 0.0, sJJ = 0.0, sV = 0.0, Tw = 0.0;
-    if (rc.rho_n > 0.0) {
-        const double J0 = I0 / d2, Ve = act ? s.V[e] : 0.0;
-        sEJ = wave_sum(Ve * lo.E * J0);
-        sJJ = wave_sum(Ve * J0 * J0);
-        sV = wave_sum(Ve);
-        Tw = wave_max(act ? s.T[0][e] : -INFINITY);
+    wire_diagnostics(s, rc, w, e, act, I0 / (c.d * c.d), lo, bad, qv, U, !FAST);
+}
+
+// Variable-step wires: those the fast path flagged, with em_tol > 0 (in place
+// of k_wire<0>; transport coupling only, so no deferred solve; no adjoint, so
+// no recording).
+__global__ __launch_bounds__(64) void k_wire_em(DevState s, RunConst rc) {
+    extern __shared__ double sm[];
+    const int w = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (s.wflag[w] == 0) return;
+    const CoilDev c = s.coils[s.wire_coil[w]];
+    const int lw = w - c.wire_off;
+    const int n = c.ne2, ld = n + 1;
+    const bool act = lane < n;
+    const int e = c.off + lw * n + (act ? lane : 0);
+    const double tk = (double)s.sc->step * rc.dt;
+    double br, bz;
+    field_at(s, c, e, rc.dBa_dt * tk, br, bz);
+    const double I0 = s.I[e];
+    const double d2 = c.d * c.d;
+    Local lo;
+    unsigned bad = act ? local_law(rc, s.cw[w], s.jcs[e], I0 / d2, s.T[0][e], br, bz, lo) : 0u;
+    if (!act) { lo.E = lo.Ep = lo.x = lo.Jc = lo.p = 0.0; }
+    const double *M = s.Mlay + (size_t)(c.layer_off + lw / c.turns) * n * n;
+    double dI, qv, U, dPhi;
+    int nsub;
+    bad |= em_integrate(sm, s, rc, c, M, n, ld, lane, act, w, e, I0, br, bz, dI, qv, U, dPhi, nsub);
+    if (act) {
+        const double I1 = I0 + dI;
+        s.Phi[e] += dPhi;
+        s.I[e] = I1;
+        s.dI[e] = dI;
+        s.E[e] = lo.E;
+        s.Ep[e] = lo.Ep;
+        s.q[e] = qv;
+        s.Jc[e] = lo.Jc;
+        s.Br[e] = br;
+        s.Bz[e] = bz;
+        if (!isfinite(I1) || !isfinite(qv)) bad |= ST_NONFINITE;
     }
-    if (lane == 0) {
-        const double Qold = s.Qw[w];
-        if (!s.cg_defer) {
-            s.Uw[w] = U;
-            s.wq[w] = qw;
-            s.Qw[w] = Qold + qw;
-        }
-        s.wmaxx[w] = mx;
-        if (!FAST) s.wflag[w] = 0;
-        if (bad) atomicOr(&s.sc->status, bad);
-        // flux-jump onset (|J/Jc| > 1) and quench of the wire at step k
-        const double kstep = (double)s.sc->step;
-        if (s.onset[w] < 0.0 && mx > 1.0) {
-            s.onset[w] = kstep;
-            s.Qon[w] = Qold;
-        }
-        if (rc.rho_n > 0.0 && s.quench[w] < 0.0 && sJJ > 0.0 && sEJ / sJJ > 0.95 * rc.rho_n) {
-            s.quench[w] = kstep;
-            s.Qqu[w] = Qold;
-            s.Tqu[w] = Tw;
-            s.Pqu[w] = sEJ / sV;
-        }
+    if (lane == 0) s.emsub[w] = (double)nsub;
+    wire_diagnostics(s, rc, w, e, act, I0 / d2, lo, bad, act ? qv : 0.0, U, true);
+}
+
+// ------------------------------------------------------------------ subelement model
+// The wire's ne x ne elements form sq x sq square subelements of sb x sb
+// elements (sb = ne / sq); element (a, b) of the wire (lane a ne + b) belongs
+// to subelement (a / sb) sq + b / sb.  Sum over the elements of subelement t of
+// a vector staged in LDS, in ascending element order.
+__device__ __forceinline__ double subelement_sum(const double *v, int t, int sq, int sb, int ne) {
+    const int a0 = (t / sq) * sb, b0 = (t % sq) * sb;
+    double acc = 0.0;
+    for (int a = 0; a < sb; ++a)
+        for (int b = 0; b < sb; ++b) acc += v[(a0 + a) * ne + b0 + b];
+    return acc;
+}
+
+// One wavefront per wire, one element per lane.  The element current is
+// I_H + I_I: the field-driven part keeps zero net current in every subelement,
+// the transport part carries the wire's transport current; both respond
+// through A = M_ww + dt diag(2 pi r E'/d^2), driven by the resistivity
+// rho = E/J of the total J^k (E' where J = 0) times their own current density:
+//   A dI_H = b_H - P (dt U_s),  P^T dI_H = 0     (one voltage per subelement)
+//   A dI_I = b_I - dt U_I 1,    1^T dI_I = dI_t  (one voltage per wire)
+//   b_H = -dI_t Psi_u - pi r^2 dB_a - dt 2 pi r rho J_H,  b_I = -dt 2 pi r rho J_I
+// with P the element-to-subelement incidence.  A is factorised in LDS; the
+// subelement voltages solve S (dt U_s) = P^T A^-1 b_H with S = P^T A^-1 P
+// (ns x ns, built from ns solves, four at a time, and factorised in LDS), and
+// dI_H = A^-1 b_H - A^-1 P (dt U_s).  The wire's voltage is the element mean of
+// the loop voltages, U_I + mean_s U_s.  LDS: A (n (n + 1)), S (ns (ns + 1)) and
+// four staging columns of n.
+__global__ __launch_bounds__(64) void k_wire_sub(DevState s, RunConst rc) {
+    extern __shared__ double sm[];
+    const int w = blockIdx.x;
+    const int lane = threadIdx.x;
+    const CoilDev c = s.coils[s.wire_coil[w]];
+    const int lw = w - c.wire_off;
+    const int layer = lw / c.turns;
+    const int n = c.ne2, ld = n + 1;
+    const int sq = s.nsubel, ns = sq * sq, sb = c.ne / sq, lds = ns + 1;
+    double *S = sm + (size_t)n * ld;
+    double *col = S + (size_t)ns * lds;
+    const bool act = lane < n;
+    const bool sact = lane < ns;
+    const int e = c.off + lw * n + (act ? lane : 0);
+    const int sub = act ? ((lane / c.ne) / sb) * sq + (lane % c.ne) / sb : 0;
+    const double dt = rc.dt;
+    const double tk = (double)s.sc->step * dt;
+    const double dBa = rc.dBa_dt * dt;
+    double br, bz;
+    field_at(s, c, e, rc.dBa_dt * tk, br, bz);
+    const double I0 = s.I[e], IH0 = s.IH[e];
+    const double d2 = c.d * c.d;
+    Local lo;
+    unsigned bad = act ? local_law(rc, s.cw[w], s.jcs[e], I0 / d2, s.T[0][e], br, bz, lo) : 0u;
+    if (!act) { lo.E = lo.Ep = lo.x = lo.Jc = lo.p = 0.0; }
+    const double re = s.r[e];
+    const double J = I0 / d2, JH = IH0 / d2;
+    const double rho = (J != 0.0) ? lo.E / J : lo.Ep;
+    load_wire_matrix(sm, s.Mlay + (size_t)(c.layer_off + layer) * n * n, n, ld, lane, act,
+                     dt * 2.0 * kPi * re * lo.Ep / d2);
+    bad |= chol_lds(sm, n, ld, lane, act);
+    double v3[3];
+    v3[0] = act ? -c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * rho * JH : 0.0;
+    v3[1] = act ? -dt * 2.0 * kPi * re * rho * (J - JH) : 0.0;
+    v3[2] = act ? 1.0 : 0.0;
+    solve_lds<3>(sm, n, ld, lane, act, v3);
+    const double xh = v3[0], xi = v3[1], yv = v3[2];
+    // S = P^T A^-1 P, column v = the subelement sums of A^-1 p_v
+    for (int v0 = 0; v0 < ns; v0 += 4) {
+        double y4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) y4[q] = (act && sub == v0 + q) ? 1.0 : 0.0;
+        solve_lds<4>(sm, n, ld, lane, act, y4);
+        __syncthreads();
+        if (act)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) col[q * n + lane] = y4[q];
+        __syncthreads();
+        if (sact)
+            for (int q = 0; q < 4 && v0 + q < ns; ++q)
+                S[(v0 + q) * lds + lane] = subelement_sum(col + q * n, lane, sq, sb, c.ne);
     }
+    __syncthreads();
+    if (act) col[lane] = xh;
+    __syncthreads();
+    double u1[1] = {sact ? subelement_sum(col, lane, sq, sb, c.ne) : 0.0};
+    bad |= chol_lds(S, ns, lds, lane, sact);
+    solve_lds<1>(S, ns, lds, lane, sact, u1);     // dt U_s of subelement `lane`
+    const double pu = __shfl(u1[0], sub);         // ... of this lane's subelement
+    const double usum = wave_sum(sact ? u1[0] : 0.0);
+    double z1[1] = {act ? pu : 0.0};
+    solve_lds<1>(sm, n, ld, lane, act, z1);
+    const double dIH = act ? xh - z1[0] : 0.0;
+    const double sx = wave_sum(act ? xi : 0.0);
+    const double sy = wave_sum(act ? yv : 0.0);
+    const double UI = (sx - c.dIt) / (dt * sy);
+    const double dI = act ? dIH + (xi - dt * UI * yv) : 0.0;
+    double qv = 0.0;
+    if (act) {
+        const double I1 = I0 + dI;
+        const double Elin = lo.E + lo.Ep * dI / d2;
+        qv = Elin * (I1 / d2);
+        // Phi += M_ww dI + dI_t Psi_u + pi r^2 dB_a, from the circuit equation
+        // of the two solves together (rho J = E)
+        s.Phi[e] += -dt * (2.0 * kPi * re * Elin + UI) - pu;
+        s.I[e] = I1;
+        s.IH[e] = IH0 + dIH;
+        s.dI[e] = dI;
+        s.E[e] = lo.E;
+        s.Ep[e] = lo.Ep;
+        s.q[e] = qv;
+        s.Jc[e] = lo.Jc;
+        s.Br[e] = br;
+        s.Bz[e] = bz;
+        if (!isfinite(I1) || !isfinite(qv)) bad |= ST_NONFINITE;
+    }
+    wire_diagnostics(s, rc, w, e, act, J, lo, bad, qv, UI + usum / ((double)ns * dt), false);
 }
 
 // ------------------------------------------------------------------ heat
@@ -700,9 +951,18 @@ hipError_t launch_field_finalize(const DevState &s, const RunConst &rc, hipStrea
 }
 
 hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st) {
+    if (s.nsubel > 0) {
+        const size_t ns = (size_t)s.nsubel * s.nsubel;
+        const size_t lds = sizeof(double) * ((size_t)(s.max_ne2 + 1) * s.max_ne2 + ns * (ns + 1) + 4 * s.max_ne2);
+        hipLaunchKernelGGL(k_wire_sub, dim3(s.Nw), dim3(64), lds, st, s, rc);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_wire<1>, dim3(s.Nw), dim3(64), 0, st, s, rc);
     const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
-    hipLaunchKernelGGL(k_wire<0>, dim3(s.Nw), dim3(64), lds, st, s, rc);
+    if (rc.em_tol > 0.0)
+        hipLaunchKernelGGL(k_wire_em, dim3(s.Nw), dim3(64), lds, st, s, rc);
+    else
+        hipLaunchKernelGGL(k_wire<0>, dim3(s.Nw), dim3(64), lds, st, s, rc);
     return hipGetLastError();
 }
 

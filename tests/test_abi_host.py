@@ -76,6 +76,20 @@ def test_validation_errors():
         assert ei.value.code == -1
     pk.query(w.replace(rho_n=3e-10), geometry="planar")
     pk.query(w.replace(coils=[cs.Coil(**{**w.coils[0].__dict__, "I0": 2.0})]))
+    # subelement model: ne (4 here) a multiple of s, s <= 4, transport-only coupling
+    for wb in [w.replace(subelements=-1), w.replace(subelements=5), w.replace(subelements=3),
+               w.replace(subelements=2, coupling="full")]:
+        with pytest.raises(pk.CoilError) as ei:
+            pk.query(wb)
+        assert ei.value.code == -1
+    assert pk.query(w.replace(subelements=2)).workspace_bytes > pk.query(w).workspace_bytes
+    # variable step: em_tol >= 0, em_max_level <= 16, wire model with transport coupling
+    for wb in [w.replace(em_tol=-1e-3), w.replace(em_tol=1e-4, em_max_level=17),
+               w.replace(em_tol=1e-4, coupling="full"), w.replace(em_tol=1e-4, subelements=2)]:
+        with pytest.raises(pk.CoilError) as ei:
+            pk.query(wb)
+        assert ei.value.code == -1
+    pk.query(w.replace(em_tol=1e-4, em_max_level=16))
 
 
 def test_library_elliptic_approximations():
