@@ -57,7 +57,7 @@ TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_field_tz.h"), "dir
 PLAN_BEGIN, PLAN_END = "// ---- field-pass work plans (begin)", "// ---- field-pass work plans (end)"
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
-    ("translation", "c2_medium_131k", "mixed"): ("2ddaf695edc3d9f91ffe91283b4b42083343d54e", 108714362),
+    ("translation", "c2_medium_131k", "mixed"): ("758973598b2e10d60faddbfbf3d0fd814ba2daf0", 108620800),
 }
 
 
