@@ -72,12 +72,13 @@ struct Plan {
     int adi = 0;           // COIL_HEAT_ADI: buffers of the ADI heat step
     int nsubel = 0;        // subelement model: subelements per wire side (0 = off)
     int em = 0;            // variable-step EM integration
+    std::vector<int> fast_w0;  // fast wire kernel: first wire of each workgroup (up to kFastWires of one layer)
     int ncols = 0, hb_slots = 1, maxline = 0;
     int nchunk_cap = 1;    // partial-sum capacity in chunks
     size_t total = 0;
     // regions
     Buf coils_b, items_b, bbox_b, gpos_b, rho_b, r_b, V_b, invV_b, jcs_b, psi_b, G_b, Gb_b, nb_b,
-        perm_b, wire_coil_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
+        perm_b, wire_coil_b, fastw_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
         sc_b, tmp_b, misc_b, diag_b, hrow_b, Lself_b, cgv_b, cgL_b, cgred_b, cgrw_b, cgsc_b, adi_b, kmult_b, IH_b, emsub_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b,
         Ipub32_b;
@@ -434,6 +435,8 @@ int make_plan(const coil_config *c, Plan &p) {
         loff += d.layers;
         goff += (d.n + kGroup - 1) / kGroup;
         p.max_ne2 = std::max(p.max_ne2, d.ne2);
+        for (int l = 0; l < d.layers; ++l)
+            for (int t = 0; t < d.turns; t += kFastWires) p.fast_w0.push_back(d.wire_off + l * d.turns + t);
         p.coils.push_back(d);
     }
     p.N = off;
@@ -523,6 +526,7 @@ size_t layout(Plan &p) {
     p.nb_b = carve(cur, sizeof(int) * 4 * N);
     p.perm_b = carve(cur, sizeof(int) * N);
     p.wire_coil_b = carve(cur, sizeof(int) * Nw);
+    p.fastw_b = carve(cur, sizeof(int) * p.fast_w0.size());
     p.elem_coil_b = carve(cur, sizeof(int) * N);
     size_t mlay = 0;
     for (auto &d : p.coils) mlay += (size_t)d.layers * d.ne2 * d.ne2;
@@ -1110,6 +1114,8 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     s.nb = at<int>(h, p.nb_b);
     s.perm = at<int>(h, p.perm_b);
     s.wire_coil = at<int>(h, p.wire_coil_b);
+    s.fast_w0 = at<int>(h, p.fastw_b);
+    s.nfast = (int)p.fast_w0.size();
     s.elem_coil = at<int>(h, p.elem_coil_b);
     s.Mlay = at<double>(h, p.Mlay_b);
     s.Minv = at<double>(h, p.Minv_b);
@@ -1195,6 +1201,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     HIPCHECK(up((void *)s.nb, nb.data(), sizeof(int) * 4 * N));
     HIPCHECK(up((void *)s.perm, perm.data(), sizeof(int) * N));
     HIPCHECK(up((void *)s.wire_coil, wire_coil.data(), sizeof(int) * Nw));
+    HIPCHECK(up((void *)s.fast_w0, p.fast_w0.data(), sizeof(int) * p.fast_w0.size()));
     HIPCHECK(up((void *)s.elem_coil, elem_coil.data(), sizeof(int) * N));
     HIPCHECK(up((void *)s.Mlay, Mlay.data(), sizeof(double) * Mlay.size()));
     HIPCHECK(up((void *)s.Minv, Minv.data(), sizeof(double) * Minv.size()));

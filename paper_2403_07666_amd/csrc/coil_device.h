@@ -214,8 +214,20 @@ __device__ __forceinline__ void local_law_adj(const RunConst &rc, const Local &l
     Jb = xb * sg / lo.Jc;
 }
 
+// v of lane j (j uniform) to every lane, by two scalar reads
+__device__ __forceinline__ double lane_value(double v, int j) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), j);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // Cholesky of the n x n matrix in LDS (column-major, leading dimension ld),
-// one wavefront, one row per lane; lower factor in place.
+// one wavefront, one row per lane; lower factor in place.  The trailing
+// update of column j reads eight columns' entries before it writes any of
+// them back (their loads are in flight together, where one read-modify-write
+// per column would wait out the LDS latency each time); every entry gets the
+// same single FMA as in a column-by-column update.
 __device__ __forceinline__ unsigned chol_lds(double *sm, int n, int ld, int lane, bool act) {
     unsigned bad = 0;
     for (int j = 0; j < n; ++j) {
@@ -228,66 +240,69 @@ __device__ __forceinline__ unsigned chol_lds(double *sm, int n, int ld, int lane
         if (lane == j) sm[j * ld + j] = ljj;
         __syncthreads();
         const double lij = (act && lane > j) ? sm[j * ld + lane] : 0.0;
-        for (int k = j + 1; k < n; ++k) {
-            const double lkj = sm[j * ld + k];
-            if (act && lane >= k) sm[k * ld + lane] -= lij * lkj;
+        for (int k0 = j + 1; k0 < n; k0 += 8) {
+            double lk[8], ak[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = min(k0 + q, n - 1);
+                lk[q] = sm[j * ld + k];
+                ak[q] = act ? sm[k * ld + lane] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = k0 + q;
+                if (act && k < n && lane >= k) sm[k * ld + lane] = ak[q] - lij * lk[q];
+            }
         }
     }
     __syncthreads();
     return bad;
 }
 
-// Solve L L^T [x y] = [x y] with the factor in LDS; lane i holds entry i.
-__device__ __forceinline__ void solve2_lds(const double *sm, int n, int ld, int lane, bool act,
-                                           double &xv, double &yv) {
-    for (int j = 0; j < n; ++j) {
-        const double ljj = sm[j * ld + j];
-        const double xj = __shfl(xv, j) / ljj;
-        const double yj = __shfl(yv, j) / ljj;
-        if (lane == j) { xv = xj; yv = yj; }
-        if (act && lane > j) {
-            const double l = sm[j * ld + lane];
-            xv -= l * xj;
-            yv -= l * yj;
-        }
-    }
-    for (int j = n - 1; j >= 0; --j) {
-        const double ljj = sm[j * ld + j];
-        const double xj = __shfl(xv, j) / ljj;
-        const double yj = __shfl(yv, j) / ljj;
-        if (lane == j) { xv = xj; yv = yj; }
-        if (act && lane < j) {
-            const double l = sm[lane * ld + j];
-            xv -= l * xj;
-            yv -= l * yj;
-        }
-    }
-}
-
 // Solve L L^T v_q = v_q for K right-hand sides at once (factor in LDS, lane i
-// holding entry i of every v_q).
+// holding entry i of every v_q).  v_j comes from lane j by scalar reads; the
+// factor's entries of the next j are read while the current j is applied.
 template <int K>
 __device__ __forceinline__ void solve_lds(const double *sm, int n, int ld, int lane, bool act, double (&v)[K]) {
+    double ljj = sm[0];
+    double l = (act && lane > 0) ? sm[lane] : 0.0;
     for (int j = 0; j < n; ++j) {
-        const double ljj = sm[j * ld + j];
-        const double l = (act && lane > j) ? sm[j * ld + lane] : 0.0;
+        const int jn = j + 1 < n ? j + 1 : j;
+        const double ljj_n = sm[jn * ld + jn];
+        const double l_n = (act && lane > jn) ? sm[jn * ld + lane] : 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            const double vj = __shfl(v[q], j) / ljj;
+            const double vj = lane_value(v[q], j) / ljj;
             if (lane == j) v[q] = vj;
             if (act && lane > j) v[q] -= l * vj;
         }
+        ljj = ljj_n;
+        l = l_n;
     }
+    ljj = sm[(n - 1) * ld + n - 1];
+    l = (act && lane < n - 1) ? sm[lane * ld + n - 1] : 0.0;
     for (int j = n - 1; j >= 0; --j) {
-        const double ljj = sm[j * ld + j];
-        const double l = (act && lane < j) ? sm[lane * ld + j] : 0.0;
+        const int jn = j > 0 ? j - 1 : 0;
+        const double ljj_n = sm[jn * ld + jn];
+        const double l_n = (act && lane < jn) ? sm[lane * ld + jn] : 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            const double vj = __shfl(v[q], j) / ljj;
+            const double vj = lane_value(v[q], j) / ljj;
             if (lane == j) v[q] = vj;
             if (act && lane < j) v[q] -= l * vj;
         }
+        ljj = ljj_n;
+        l = l_n;
     }
+}
+
+// Solve L L^T [x y] = [x y] with the factor in LDS; lane i holds entry i.
+__device__ __forceinline__ void solve2_lds(const double *sm, int n, int ld, int lane, bool act,
+                                           double &xv, double &yv) {
+    double v[2] = {xv, yv};
+    solve_lds<2>(sm, n, ld, lane, act, v);
+    xv = v[0];
+    yv = v[1];
 }
 
 // Load the layer's inductance block into LDS and add dt diag(2 pi r E'/d^2).
@@ -306,35 +321,14 @@ __device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, in
     if (act) sm[lane * ld + lane] += diag_add;
 }
 
-// y(lane) = sum_j A[j n + lane] v_j for a column-major n x n block with v held
-// one element per lane (v_j broadcast from lane j).  The FMAs run in j order;
-// the column loads are issued 16 at a time so that they are in flight together.
-// v of lane j (j uniform) to every lane, by two scalar reads
-__device__ __forceinline__ double lane_value(double v, int j) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), j);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), j);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// Columns of a column-major n x n matrix (n <= kMaxWireElems), lane i holding
-// row i: loaded all at once, ahead of the product that uses them.
-struct WireCols {
-    double a[kMaxWireElems];
-};
-__device__ __forceinline__ void load_cols(WireCols &c, const double *A, int n, int lane, bool act) {
-#pragma unroll
-    for (int j = 0; j < kMaxWireElems; ++j) c.a[j] = (act && j < n) ? A[(size_t)j * n + lane] : 0.0;
-}
-// y_i = sum_j A_ij v_j, the FMAs in j order as in matvec_cols
-__device__ __forceinline__ double matvec_loaded(const WireCols &c, int n, bool act, double v) {
+// y_i = sum_j A_ij v_j with the column-major n x n block in LDS (lane i
+// holding row i), v_j from lane j, the FMAs in j order
+__device__ __forceinline__ double matvec_lds(const double *A, int n, bool act, int lane, double v) {
     double y = 0.0;
-#pragma unroll
-    for (int j = 0; j < kMaxWireElems; ++j)
-        if (j < n) {
-            const double vj = lane_value(v, j);
-            if (act) y = fma(c.a[j], vj, y);
-        }
+    for (int j = 0; j < n; ++j) {
+        const double vj = lane_value(v, j);
+        if (act) y = fma(A[j * n + lane], vj, y);
+    }
     return y;
 }
 

@@ -24,6 +24,7 @@ constexpr double kGmdSquare = 0.4470491559036625;
 constexpr int kGroup = 64;       // bounding-box group = one wavefront of targets
 constexpr int kMaxWireElems = 64;  // per-wire solve keeps one element per lane
 constexpr int kMaxSubelements = 4;  // subelement model: subelements per wire side at most
+constexpr int kFastWires = 4;       // fast wire kernel: wires (one wavefront each) per workgroup
 constexpr int kStage = 256;      // sources staged in LDS per pass
 constexpr int kHT = 16;          // heat step: tile side (cells owned by a workgroup)
 constexpr int kHMaxHalo = 8;     // heat step: substeps per launch at most (the tile's halo)
@@ -115,6 +116,8 @@ struct DevState {
     const int *nb;           // 4 neighbours per element, -1 = border
     const int *perm;         // internal -> public index
     const int *wire_coil;    // coil of each wire
+    const int *fast_w0;      // fast wire kernel: first wire of each workgroup (all of one layer)
+    int nfast;               // its workgroups
     const int *elem_coil;    // coil of each element
     int max_ne2;             // largest elements-per-wire over the coils
     int tile_targets;        // field pass: targets per workgroup (= block size)

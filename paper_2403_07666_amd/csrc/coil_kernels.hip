@@ -141,7 +141,8 @@ __global__ __launch_bounds__(256) void k_field_finalize(DevState s, RunConst rc,
 // Per-wire bookkeeping of a step, after its solve: Q_w, U_w, max |J|/Jc, the
 // status bits, the flux-jump onset (|J/Jc| > 1) and the quench criterion (the
 // wire's resistivity sum V E J / sum V J^2 of this step's local law against
-// 0.95 rho_n).  J0 = J^k of the lane's element; lane 0 writes.
+// 0.95 rho_n).  J0 = J^k of the lane's element; lane 0 of the wire's
+// wavefront writes (a workgroup may hold several wires).
 __device__ __forceinline__ void wire_diagnostics(const DevState &s, const RunConst &rc, int w, int e, bool act,
                                                  double J0, const Local &lo, unsigned bad, double qv, double U,
                                                  bool clear_flag) {
@@ -156,7 +157,7 @@ __device__ __forceinline__ void wire_diagnostics(const DevState &s, const RunCon
         sV = wave_sum(Ve);
         Tw = wave_max(act ? s.T[0][e] : -INFINITY);
     }
-    if (threadIdx.x == 0) {
+    if ((threadIdx.x & 63) == 0) {
         const double Qold = s.Qw[w];
         if (!s.cg_defer) {
             s.Uw[w] = U;
@@ -268,20 +269,36 @@ __device__ unsigned em_integrate(double *sm, const DevState &s, const RunConst &
 // ------------------------------------------------------------------ local law + per-wire A-V solve
 // One wavefront per wire, one element per lane (n_e <= 64).  The wire matrix is
 // A = M_ww + dt diag(2 pi r E'/d^2).  Two kernels per step:
-//   k_wire<1> (no LDS): when every diagonal addition leaves M_ee unchanged in
-//     FP64, A equals the layer's inductance block bitwise and the solution uses
-//     the layer's precomputed inverse (x = M^-1 b, y = M^-1 1); otherwise the
-//     wire is flagged and left untouched;
+//   k_wire<1>: workgroups of kFastWires wavefronts, all wires of one layer,
+//     which share the layer's precomputed inverse staged once in LDS.  When
+//     every diagonal addition leaves M_ee unchanged in FP64, A equals the
+//     layer's inductance block bitwise and the solution uses that inverse
+//     (x = M^-1 b, y = M^-1 1); otherwise the wire is flagged and left
+//     untouched;
 //   k_wire<0>: flagged wires only; A in LDS (column-major, leading dimension
 //     n_e + 1), right-looking Cholesky and two triangular solves.
 // Optional recording (adjoint recompute): I^k, B^k and dI of the step; optional
 // field source (adjoint recompute from a stored field history).
 template <int FAST>
-__global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
+__global__ __launch_bounds__(FAST ? 64 * kFastWires : 64) void k_wire(DevState s, RunConst rc) {
     extern __shared__ double sm[];
-    const int w = blockIdx.x;
-    const int lane = threadIdx.x;
-    if (!FAST && s.wflag[w] == 0) return;
+    const int lane = threadIdx.x & 63;
+    int w;
+    if (FAST) {
+        // the layer inverse of the workgroup's wires, staged once
+        const int w0 = s.fast_w0[blockIdx.x];
+        const CoilDev c0 = s.coils[s.wire_coil[w0]];
+        const int nn = c0.ne2 * c0.ne2;
+        const double *Mi = s.Minv + (size_t)(c0.layer_off + (w0 - c0.wire_off) / c0.turns) * nn;
+        for (int i = threadIdx.x; i < nn; i += 64 * kFastWires) sm[i] = Mi[i];
+        __syncthreads();
+        const int v = threadIdx.x >> 6;
+        if (v >= c0.turns - (w0 - c0.wire_off) % c0.turns) return;  // past the layer's last wire
+        w = w0 + v;
+    } else {
+        w = blockIdx.x;
+        if (s.wflag[w] == 0) return;
+    }
     const CoilDev c = s.coils[s.wire_coil[w]];
     const int lw = w - c.wire_off;
     const int layer = lw / c.turns;
@@ -294,10 +311,6 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
     const double dBa = rc.dBa_dt * dt;
 
     const size_t lay = (size_t)(c.layer_off + layer);
-    // the fast path's layer inverse, loaded while the field and the local law
-    // are computed
-    WireCols minv;
-    if (FAST) load_cols(minv, s.Minv + lay * n * n, n, lane, act);
     double br, bz;
     if (s.src_Br) {
         br = s.src_Br[e];
@@ -323,7 +336,7 @@ __global__ __launch_bounds__(64) void k_wire(DevState s, RunConst rc) {
             return;
         }
         if (s.emsub && lane == 0) s.emsub[w] = 1.0;  // a linear step: one substep is exact
-        xv = matvec_loaded(minv, n, act, b);
+        xv = matvec_lds(sm, n, act, lane, b);
         yv = act ? s.yl[lay * n + lane] : 0.0;
         sy = s.syl[lay];
     } else {
@@ -682,9 +695,11 @@ __global__ __launch_bounds__(256) void k_heat_tile(DevState s, RunConst rc, int 
 }
 
 // ------------------------------------------------------------------ reductions
-__global__ __launch_bounds__(256) void k_finalize(DevState s, RunConst rc) {
-    __shared__ double a_q[256], a_u[256], a_x[256], a_o[256], a_t[256];
-    __shared__ long long a_i[256];
+// One workgroup of kFinThreads threads: strided partial sums, then a tree.
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void k_finalize(DevState s, RunConst rc) {
+    __shared__ double a_q[kFinThreads], a_u[kFinThreads], a_x[kFinThreads], a_o[kFinThreads], a_t[kFinThreads];
+    __shared__ long long a_i[kFinThreads];
     const int tid = threadIdx.x;
     // the running scalars are read first, so that their loads overlap the sums
     Scalars *sc = s.sc;
@@ -699,22 +714,22 @@ __global__ __launch_bounds__(256) void k_finalize(DevState s, RunConst rc) {
     double q = 0.0, u = 0.0, x = 0.0, o = 0.0, tm = -INFINITY;
     long long ti = LLONG_MAX;
 #pragma unroll 4
-    for (int w = tid; w < s.Nw; w += 256) {
+    for (int w = tid; w < s.Nw; w += kFinThreads) {
         q += s.wq[w];
         u += s.Uw[w];
         x = fmax(x, s.wmaxx[w]);
     }
     const int no = s.hb_slots * s.nheat_blocks;
 #pragma unroll 4
-    for (int i = tid; i < no; i += 256) o += s.hb_out[i];
-    for (int b = tid; b < s.nheat_blocks; b += 256) {
+    for (int i = tid; i < no; i += kFinThreads) o += s.hb_out[i];
+    for (int b = tid; b < s.nheat_blocks; b += kFinThreads) {
         const double v = s.hb_max[b];
         const long long iv = s.hb_arg[b];
         if (v > tm || (v == tm && iv < ti)) { tm = v; ti = iv; }
     }
     a_q[tid] = q; a_u[tid] = u; a_x[tid] = x; a_o[tid] = o; a_t[tid] = tm; a_i[tid] = ti;
     __syncthreads();
-    for (int k = 128; k > 0; k >>= 1) {
+    for (int k = kFinThreads / 2; k > 0; k >>= 1) {
         if (tid < k) {
             a_q[tid] += a_q[tid + k];
             a_u[tid] += a_u[tid + k];
@@ -957,7 +972,8 @@ hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st) {
         hipLaunchKernelGGL(k_wire_sub, dim3(s.Nw), dim3(64), lds, st, s, rc);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_wire<1>, dim3(s.Nw), dim3(64), 0, st, s, rc);
+    hipLaunchKernelGGL(k_wire<1>, dim3(s.nfast), dim3(64 * kFastWires), sizeof(double) * (size_t)s.max_ne2 * s.max_ne2,
+                       st, s, rc);
     const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
     if (rc.em_tol > 0.0)
         hipLaunchKernelGGL(k_wire_em, dim3(s.Nw), dim3(64), lds, st, s, rc);
@@ -997,7 +1013,7 @@ hipError_t launch_heat_step(const DevState &s, const RunConst &rc, hipStream_t s
 }
 
 hipError_t launch_finalize(const DevState &s, const RunConst &rc, hipStream_t st) {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, s, rc);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, st, s, rc);
     return hipGetLastError();
 }
 
