@@ -124,7 +124,6 @@ __global__ __launch_bounds__(64) void k_wire_adj(DevState s, RunConst rc, AdjPtr
     const int lw = w - c.wire_off;
     const int layer = lw / c.turns;
     const int n = c.ne2;
-    const int ld = n + 1;
     const bool act = lane < n;
     const int e = c.off + lw * n + (act ? lane : 0);
     const double dt = rc.dt;
@@ -158,10 +157,10 @@ __global__ __launch_bounds__(64) void k_wire_adj(DevState s, RunConst rc, AdjPtr
         yv = act ? s.yl[lay * n + lane] : 0.0;
         sy = s.syl[lay];
     } else {
-        load_wire_matrix(sm, M, n, ld, lane, act, diag_add);
-        chol_lds(sm, n, ld, lane, act);
+        load_wire_matrix(sm, M, n, lane, act, diag_add);
+        chol_lds(sm, n, lane, act, sm + packed_size(n));
         yv = act ? 1.0 : 0.0;
-        solve2_lds(sm, n, ld, lane, act, xv, yv);
+        solve2_lds(sm, n, lane, act, xv, yv);
         sy = wave_sum(act ? yv : 0.0);
     }
     const double sx = wave_sum(act ? xv : 0.0);
@@ -259,7 +258,7 @@ hipError_t launch_field_weights(const DevState &s, double *br, double *bz, hipSt
 }
 
 hipError_t launch_wire_adj(const DevState &s, const RunConst &rc, const AdjPtrs &a, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
+    const size_t lds = sizeof(double) * ((size_t)packed_size(s.max_ne2) + kCholPad);
     hipLaunchKernelGGL(k_wire_adj, dim3(s.Nw), dim3(64), lds, st, s, rc, a);
     return hipGetLastError();
 }

@@ -586,7 +586,7 @@ size_t layout(Plan &p) {
     if (p.coupled) {
         p.Lself_b = carve(cur, d8 * N);
         p.cgv_b = carve(cur, d8 * 5 * N);
-        p.cgL_b = carve(cur, d8 * Nw * (size_t)p.max_ne2 * (p.max_ne2 + 1));
+        p.cgL_b = carve(cur, d8 * Nw * (size_t)packed_size(p.max_ne2));
         p.cgred_b = carve(cur, d8 * ((N + 255) / 256));
         p.cgrw_b = carve(cur, d8 * 2 * Nw);
         p.cgsc_b = carve(cur, sizeof(CgScalars));

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_cg_alpha(DevState s, int nblocks) {
 __device__ __forceinline__ void wire_inverse(const DevState &s, const RunConst &rc, const CoilDev &c, int w,
                                              int lane, bool act, int e, double v, double *sm, double &xv,
                                              double &yv, double &sy) {
-    const int n = c.ne2, ld = n + 1;
+    const int n = c.ne2;
     const int lw = w - c.wire_off;
     const size_t lay = (size_t)(c.layer_off + lw / c.turns);
     const double *M = s.Mlay + lay * n * n;
@@ -121,13 +121,12 @@ __device__ __forceinline__ void wire_inverse(const DevState &s, const RunConst &
         yv = act ? s.yl[lay * n + lane] : 0.0;
         sy = s.syl[lay];
     } else {
-        const double *L = s.cg_L + (size_t)w * s.max_ne2 * (s.max_ne2 + 1);
-        if (act)
-            for (int j = 0; j < n; ++j) sm[j * ld + lane] = L[(size_t)j * ld + lane];
+        const double *L = s.cg_L + (size_t)w * packed_size(s.max_ne2);
+        for (int i = lane; i < packed_size(n); i += 64) sm[i] = L[i];
         __syncthreads();
         xv = v;
         yv = act ? 1.0 : 0.0;
-        solve2_lds(sm, n, ld, lane, act, xv, yv);
+        solve2_lds(sm, n, lane, act, xv, yv);
         sy = wave_sum(act ? yv : 0.0);
     }
 }
@@ -256,7 +255,7 @@ static inline int blocks256(int n) { return (n + 255) / 256; }
 
 hipError_t launch_cg_begin(const DevState &s, const RunConst &rc, const TzPlan &tp, double *vpub, const int *pub2int,
                            double tol, int maxit, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
+    const size_t lds = sizeof(double) * (size_t)packed_size(s.max_ne2);
     hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, st, s.cg, tol * tol, maxit);
     hipLaunchKernelGGL(k_cg_prep, dim3(blocks256(s.N)), dim3(256), 0, st, s, (const double *)s.dI, vpub, tp.ticket, 0);
     hipError_t e = launch_flux_tz(s, rc, tp, vpub, pub2int, &s.cg->done, st);
@@ -269,7 +268,7 @@ hipError_t launch_cg_begin(const DevState &s, const RunConst &rc, const TzPlan &
 
 hipError_t launch_cg_iteration(const DevState &s, const RunConst &rc, const TzPlan &tp, double *vpub,
                                const int *pub2int, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
+    const size_t lds = sizeof(double) * (size_t)packed_size(s.max_ne2);
     hipLaunchKernelGGL(k_cg_prep, dim3(blocks256(s.N)), dim3(256), 0, st, s, (const double *)nullptr, vpub, tp.ticket,
                        1);
     hipError_t e = launch_flux_tz(s, rc, tp, vpub, pub2int, &s.cg->done, st);
@@ -282,7 +281,7 @@ hipError_t launch_cg_iteration(const DevState &s, const RunConst &rc, const TzPl
 }
 
 hipError_t launch_cg_finish(const DevState &s, const RunConst &rc, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
+    const size_t lds = sizeof(double) * (size_t)packed_size(s.max_ne2);
     hipLaunchKernelGGL(k_cg_finish, dim3(s.Nw), dim3(64), lds, st, s, rc);
     return hipGetLastError();
 }

@@ -222,36 +222,58 @@ __device__ __forceinline__ double lane_value(double v, int j) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Cholesky of the n x n matrix in LDS (column-major, leading dimension ld),
-// one wavefront, one row per lane; lower factor in place.  The trailing
-// update of column j reads eight columns' entries before it writes any of
-// them back (their loads are in flight together, where one read-modify-write
-// per column would wait out the LDS latency each time); every entry gets the
-// same single FMA as in a column-by-column update.
-__device__ __forceinline__ unsigned chol_lds(double *sm, int n, int ld, int lane, bool act) {
+// Symmetric n x n matrices in LDS are kept as their lower triangle, packed
+// by columns: entry (i, j), i >= j, at pcol(n, j) + i - j; n (n + 1) / 2
+// doubles (16.25 KiB at n = 64, so that nine wires' workgroups share a CU).
+// Consecutive rows of a column are consecutive in LDS (no bank conflicts when
+// lane i reads row i), a row's entries are at varying strides.
+__device__ __forceinline__ int pcol(int n, int j) { return j * n - ((j * (j - 1)) >> 1); }
+
+// Cholesky of the packed n x n matrix in LDS, one wavefront, one row per lane;
+// lower factor in place.  `dummy` is kCholPad doubles of LDS next to it: lanes
+// with nothing to store write there instead of branching around the store.
+// The trailing update of column j reads eight columns' entries before it
+// writes any of them back (their loads are in flight together, where one
+// read-modify-write per column would wait out the LDS latency each time);
+// every entry gets the same single FMA as in a column-by-column update.
+__device__ __forceinline__ unsigned chol_lds(double *sm, int n, int lane, bool act, double *dummy) {
     unsigned bad = 0;
     for (int j = 0; j < n; ++j) {
+        const int cj = pcol(n, j);
         __syncthreads();
-        const double djj = sm[j * ld + j];
+        const double djj = sm[cj];
         if (!(djj > 0.0)) bad |= ST_PIVOT;
         const double ljj = sqrt(djj);
         __syncthreads();
-        if (act && lane > j) sm[j * ld + lane] /= ljj;
-        if (lane == j) sm[j * ld + j] = ljj;
+        // column j scaled by its pivot (rows j .. n - 1)
+        const bool inj = act && lane >= j;
+        const int aj = inj ? cj + lane - j : 0;
+        const double cv = sm[aj];
+        const double lv = (lane == j) ? ljj : cv / ljj;
+        *(inj ? sm + aj : dummy + lane) = lv;
         __syncthreads();
-        const double lij = (act && lane > j) ? sm[j * ld + lane] : 0.0;
+        const double lij = (act && lane > j) ? lv : 0.0;
         for (int k0 = j + 1; k0 < n; k0 += 8) {
+            // columns k0 .. k0 + nq - 1; lanes above a column's diagonal (and
+            // the padding columns past n) read an in-range entry they do not use
+            const int nq = min(8, n - k0);
+            const int p0 = pcol(n, k0);
             double lk[8], ak[8];
+            int addr[8];
+            int pk = p0;  // pcol(n, k0 + q), advanced column by column
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int k = min(k0 + q, n - 1);
-                lk[q] = sm[j * ld + k];
-                ak[q] = act ? sm[k * ld + lane] : 0.0;
+                const bool valid = q < nq;
+                const int k = valid ? k0 + q : k0;
+                lk[q] = sm[cj + k - j];
+                addr[q] = act ? (valid ? pk : p0) + lane - k : 0;  // at most pcol(n, k + 1) - 1
+                ak[q] = sm[addr[q]];
+                pk += valid ? n - k : 0;
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int k = k0 + q;
-                if (act && k < n && lane >= k) sm[k * ld + lane] = ak[q] - lij * lk[q];
+                const bool st = act && q < nq && lane >= k0 + q;
+                *(st ? sm + addr[q] : dummy + lane) = ak[q] - lij * lk[q];
             }
         }
     }
@@ -259,17 +281,19 @@ __device__ __forceinline__ unsigned chol_lds(double *sm, int n, int ld, int lane
     return bad;
 }
 
-// Solve L L^T v_q = v_q for K right-hand sides at once (factor in LDS, lane i
-// holding entry i of every v_q).  v_j comes from lane j by scalar reads; the
-// factor's entries of the next j are read while the current j is applied.
+// Solve L L^T v_q = v_q for K right-hand sides at once (packed factor in LDS,
+// lane i holding entry i of every v_q).  v_j comes from lane j by scalar
+// reads; the factor's entries of the next j are read while the current j is
+// applied.
 template <int K>
-__device__ __forceinline__ void solve_lds(const double *sm, int n, int ld, int lane, bool act, double (&v)[K]) {
+__device__ __forceinline__ void solve_lds(const double *sm, int n, int lane, bool act, double (&v)[K]) {
     double ljj = sm[0];
     double l = (act && lane > 0) ? sm[lane] : 0.0;
     for (int j = 0; j < n; ++j) {
         const int jn = j + 1 < n ? j + 1 : j;
-        const double ljj_n = sm[jn * ld + jn];
-        const double l_n = (act && lane > jn) ? sm[jn * ld + lane] : 0.0;
+        const int cn = pcol(n, jn);
+        const double ljj_n = sm[cn];
+        const double l_n = (act && lane > jn) ? sm[cn + lane - jn] : 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const double vj = lane_value(v[q], j) / ljj;
@@ -279,12 +303,13 @@ __device__ __forceinline__ void solve_lds(const double *sm, int n, int ld, int l
         ljj = ljj_n;
         l = l_n;
     }
-    ljj = sm[(n - 1) * ld + n - 1];
-    l = (act && lane < n - 1) ? sm[lane * ld + n - 1] : 0.0;
+    // backward: lane i < j needs L(j, i), row j of the factor
+    ljj = sm[pcol(n, n - 1)];
+    l = (act && lane < n - 1) ? sm[pcol(n, lane) + n - 1 - lane] : 0.0;
     for (int j = n - 1; j >= 0; --j) {
         const int jn = j > 0 ? j - 1 : 0;
-        const double ljj_n = sm[jn * ld + jn];
-        const double l_n = (act && lane < jn) ? sm[lane * ld + jn] : 0.0;
+        const double ljj_n = sm[pcol(n, jn)];
+        const double l_n = (act && lane < jn) ? sm[pcol(n, lane) + jn - lane] : 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const double vj = lane_value(v[q], j) / ljj;
@@ -296,29 +321,29 @@ __device__ __forceinline__ void solve_lds(const double *sm, int n, int ld, int l
     }
 }
 
-// Solve L L^T [x y] = [x y] with the factor in LDS; lane i holds entry i.
-__device__ __forceinline__ void solve2_lds(const double *sm, int n, int ld, int lane, bool act,
-                                           double &xv, double &yv) {
+// Solve L L^T [x y] = [x y] with the packed factor in LDS; lane i holds entry i.
+__device__ __forceinline__ void solve2_lds(const double *sm, int n, int lane, bool act, double &xv, double &yv) {
     double v[2] = {xv, yv};
-    solve_lds<2>(sm, n, ld, lane, act, v);
+    solve_lds<2>(sm, n, lane, act, v);
     xv = v[0];
     yv = v[1];
 }
 
-// Load the layer's inductance block into LDS and add dt diag(2 pi r E'/d^2).
-__device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, int n, int ld, int lane,
-                                                 bool act, double diag_add) {
+// Load the lower triangle of the layer's inductance block (column-major
+// n x n in global memory) into packed LDS and add dt diag(2 pi r E'/d^2).
+__device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, int n, int lane, bool act,
+                                                 double diag_add) {
     if (act)
         for (int c0 = 0; c0 < n; c0 += 16) {  // 16 column loads in flight
             double a[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) a[q] = c0 + q < n ? M[(size_t)(c0 + q) * n + lane] : 0.0;
+            for (int q = 0; q < 16; ++q) a[q] = (c0 + q < n && lane >= c0 + q) ? M[(size_t)(c0 + q) * n + lane] : 0.0;
 #pragma unroll
             for (int q = 0; q < 16; ++q)
-                if (c0 + q < n) sm[(c0 + q) * ld + lane] = a[q];
+                if (c0 + q < n && lane >= c0 + q) sm[pcol(n, c0 + q) + lane - (c0 + q)] = a[q];
         }
     __syncthreads();
-    if (act) sm[lane * ld + lane] += diag_add;
+    if (act) sm[pcol(n, lane)] += diag_add;
 }
 
 // y_i = sum_j A_ij v_j with the column-major n x n block in LDS (lane i

@@ -25,6 +25,9 @@ constexpr int kGroup = 64;       // bounding-box group = one wavefront of target
 constexpr int kMaxWireElems = 64;  // per-wire solve keeps one element per lane
 constexpr int kMaxSubelements = 4;  // subelement model: subelements per wire side at most
 constexpr int kFastWires = 4;       // fast wire kernel: wires (one wavefront each) per workgroup
+// doubles of an n x n symmetric matrix kept as its packed lower triangle
+__host__ __device__ constexpr int packed_size(int n) { return n * (n + 1) / 2; }
+constexpr int kCholPad = 64;  // LDS doubles after a factorised matrix: the lanes' store sink
 constexpr int kStage = 256;      // sources staged in LDS per pass
 constexpr int kHT = 16;          // heat step: tile side (cells owned by a workgroup)
 constexpr int kHMaxHalo = 8;     // heat step: substeps per launch at most (the tile's halo)
@@ -156,7 +159,7 @@ struct DevState {
     int cg_defer;            // 1: the per-wire kernels leave the step's updates to the coupled solve
     const double *Lself;     // ring self inductance of each element
     double *cg_x, *cg_r, *cg_z, *cg_p, *cg_q;  // correction, residual, S r, direction, A p
-    double *cg_L;            // per wire: its factorised block (n x (n + 1), column-major)
+    double *cg_L;            // per wire: its Cholesky factor (packed lower triangle, by columns)
     double *cg_red, *cg_rw;  // per-block sums of p.q, per-wire sums of r.z
     double *cg_cw;           // per wire: the constant part moved out of the residual
     CgScalars *cg;

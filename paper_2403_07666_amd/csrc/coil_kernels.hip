@@ -187,15 +187,15 @@ __device__ __forceinline__ void wire_diagnostics(const DevState &s, const RunCon
 //   (M_ww + h diag(2 pi r E'/d^2)) dI + h U 1 = b,  1^T dI = ramp h,
 //   b = -ramp h Psi_u - pi r^2 dBa/dt h - h 2 pi r E,
 // A factorised in LDS.  dIt_h = ramp h, dBa_h = dBa/dt h.
-__device__ unsigned be_step_lds(double *sm, const double *M, int n, int ld, int lane, bool act, double h,
+__device__ unsigned be_step_lds(double *sm, const double *M, int n, int lane, bool act, double h,
                                 const Local &lo, double re, double d2, double psi, double dIt_h, double dBa_h,
                                 double &dI, double &U) {
     __syncthreads();  // the previous factor's last reads
-    load_wire_matrix(sm, M, n, ld, lane, act, h * 2.0 * kPi * re * lo.Ep / d2);
-    unsigned bad = chol_lds(sm, n, ld, lane, act);
+    load_wire_matrix(sm, M, n, lane, act, h * 2.0 * kPi * re * lo.Ep / d2);
+    unsigned bad = chol_lds(sm, n, lane, act, sm + packed_size(n));
     double xv = act ? -dIt_h * psi - kPi * re * re * dBa_h - h * 2.0 * kPi * re * lo.E : 0.0;
     double yv = act ? 1.0 : 0.0;
-    solve2_lds(sm, n, ld, lane, act, xv, yv);
+    solve2_lds(sm, n, lane, act, xv, yv);
     const double sx = wave_sum(act ? xv : 0.0);
     const double sy = wave_sum(act ? yv : 0.0);
     U = (sx - dIt_h) / (h * sy);
@@ -216,7 +216,7 @@ __device__ unsigned be_step_lds(double *sm, const double *M, int n, int ld, int 
 // own circuit equation.  Returns dI, the step's mean q and U, and the flux
 // change; every exit condition is wave-uniform.
 __device__ unsigned em_integrate(double *sm, const DevState &s, const RunConst &rc, const CoilDev &c,
-                                 const double *M, int n, int ld, int lane, bool act, int w, int e, double I0,
+                                 const double *M, int n, int lane, bool act, int w, int e, double I0,
                                  double br, double bz, double &dI, double &qv, double &U, double &dPhi, int &nsub) {
     const double dt = rc.dt, d2 = c.d * c.d, re = act ? s.r[e] : 0.0, psi = act ? s.psi[e] : 0.0;
     const double cw = s.cw[w], jcs = act ? s.jcs[e] : 0.0, T = act ? s.T[0][e] : rc.T_bath;
@@ -234,12 +234,12 @@ __device__ unsigned em_integrate(double *sm, const DevState &s, const RunConst &
         bad |= act ? local_law(rc, cw, jcs, Iv / d2, T, br, bz, la) : 0u;
         if (!act) la.E = la.Ep = la.Jc = 0.0;
         double d1, U1, da, Uh1, db, Uh2;
-        bad |= be_step_lds(sm, M, n, ld, lane, act, h, la, re, d2, psi, dIt_h, dBa_h, d1, U1);
-        bad |= be_step_lds(sm, M, n, ld, lane, act, hh, la, re, d2, psi, 0.5 * dIt_h, 0.5 * dBa_h, da, Uh1);
+        bad |= be_step_lds(sm, M, n, lane, act, h, la, re, d2, psi, dIt_h, dBa_h, d1, U1);
+        bad |= be_step_lds(sm, M, n, lane, act, hh, la, re, d2, psi, 0.5 * dIt_h, 0.5 * dBa_h, da, Uh1);
         const double Im = Iv + da;
         bad |= act ? local_law(rc, cw, jcs, Im / d2, T, br, bz, lm) : 0u;
         if (!act) lm.E = lm.Ep = 0.0;
-        bad |= be_step_lds(sm, M, n, ld, lane, act, hh, lm, re, d2, psi, 0.5 * dIt_h, 0.5 * dBa_h, db, Uh2);
+        bad |= be_step_lds(sm, M, n, lane, act, hh, lm, re, d2, psi, 0.5 * dIt_h, 0.5 * dBa_h, db, Uh2);
         const double I2 = Im + db, I1 = Iv + d1;
         const double sc = rc.em_tol * fmax(fabs(I2), la.Jc > 0.0 ? la.Jc * d2 : 0.0);
         const double dif = fabs(I2 - I1);
@@ -303,7 +303,6 @@ __global__ __launch_bounds__(FAST ? 64 * kFastWires : 64) void k_wire(DevState s
     const int lw = w - c.wire_off;
     const int layer = lw / c.turns;
     const int n = c.ne2;
-    const int ld = n + 1;
     const bool act = lane < n;
     const int e = c.off + lw * n + (act ? lane : 0);
     const double dt = rc.dt;
@@ -340,15 +339,15 @@ __global__ __launch_bounds__(FAST ? 64 * kFastWires : 64) void k_wire(DevState s
         yv = act ? s.yl[lay * n + lane] : 0.0;
         sy = s.syl[lay];
     } else {
-        load_wire_matrix(sm, M, n, ld, lane, act, diag_add);
-        bad |= chol_lds(sm, n, ld, lane, act);
-        if (s.cg_defer && act) {  // the factor, for the coupled solve's preconditioner
-            double *L = s.cg_L + (size_t)w * s.max_ne2 * (s.max_ne2 + 1);
-            for (int j = 0; j < n; ++j) L[(size_t)j * ld + lane] = sm[j * ld + lane];
+        load_wire_matrix(sm, M, n, lane, act, diag_add);
+        bad |= chol_lds(sm, n, lane, act, sm + packed_size(n));
+        if (s.cg_defer) {  // the factor, for the coupled solve's preconditioner (every lane copies)
+            double *L = s.cg_L + (size_t)w * packed_size(s.max_ne2);
+            for (int i = lane; i < packed_size(n); i += 64) L[i] = sm[i];
         }
         xv = b;
         yv = act ? 1.0 : 0.0;
-        solve2_lds(sm, n, ld, lane, act, xv, yv);
+        solve2_lds(sm, n, lane, act, xv, yv);
         sy = wave_sum(act ? yv : 0.0);
     }
     const double sx = wave_sum(act ? xv : 0.0);
@@ -411,7 +410,7 @@ __global__ __launch_bounds__(64) void k_wire_em(DevState s, RunConst rc) {
     if (s.wflag[w] == 0) return;
     const CoilDev c = s.coils[s.wire_coil[w]];
     const int lw = w - c.wire_off;
-    const int n = c.ne2, ld = n + 1;
+    const int n = c.ne2;
     const bool act = lane < n;
     const int e = c.off + lw * n + (act ? lane : 0);
     const double tk = (double)s.sc->step * rc.dt;
@@ -425,7 +424,7 @@ __global__ __launch_bounds__(64) void k_wire_em(DevState s, RunConst rc) {
     const double *M = s.Mlay + (size_t)(c.layer_off + lw / c.turns) * n * n;
     double dI, qv, U, dPhi;
     int nsub;
-    bad |= em_integrate(sm, s, rc, c, M, n, ld, lane, act, w, e, I0, br, bz, dI, qv, U, dPhi, nsub);
+    bad |= em_integrate(sm, s, rc, c, M, n, lane, act, w, e, I0, br, bz, dI, qv, U, dPhi, nsub);
     if (act) {
         const double I1 = I0 + dI;
         s.Phi[e] += dPhi;
@@ -468,8 +467,9 @@ __device__ __forceinline__ double subelement_sum(const double *v, int t, int sq,
 // subelement voltages solve S (dt U_s) = P^T A^-1 b_H with S = P^T A^-1 P
 // (ns x ns, built from ns solves, four at a time, and factorised in LDS), and
 // dI_H = A^-1 b_H - A^-1 P (dt U_s).  The wire's voltage is the element mean of
-// the loop voltages, U_I + mean_s U_s.  LDS: A (n (n + 1)), S (ns (ns + 1)) and
-// four staging columns of n.
+// the loop voltages, U_I + mean_s U_s.  LDS: A and S as packed lower triangles,
+// each followed by its factorisation's store sink, and four staging columns
+// of n.
 __global__ __launch_bounds__(64) void k_wire_sub(DevState s, RunConst rc) {
     extern __shared__ double sm[];
     const int w = blockIdx.x;
@@ -477,10 +477,10 @@ __global__ __launch_bounds__(64) void k_wire_sub(DevState s, RunConst rc) {
     const CoilDev c = s.coils[s.wire_coil[w]];
     const int lw = w - c.wire_off;
     const int layer = lw / c.turns;
-    const int n = c.ne2, ld = n + 1;
-    const int sq = s.nsubel, ns = sq * sq, sb = c.ne / sq, lds = ns + 1;
-    double *S = sm + (size_t)n * ld;
-    double *col = S + (size_t)ns * lds;
+    const int n = c.ne2;
+    const int sq = s.nsubel, ns = sq * sq, sb = c.ne / sq;
+    double *S = sm + packed_size(n) + kCholPad;
+    double *col = S + packed_size(ns) + kCholPad;
     const bool act = lane < n;
     const bool sact = lane < ns;
     const int e = c.off + lw * n + (act ? lane : 0);
@@ -498,40 +498,40 @@ __global__ __launch_bounds__(64) void k_wire_sub(DevState s, RunConst rc) {
     const double re = s.r[e];
     const double J = I0 / d2, JH = IH0 / d2;
     const double rho = (J != 0.0) ? lo.E / J : lo.Ep;
-    load_wire_matrix(sm, s.Mlay + (size_t)(c.layer_off + layer) * n * n, n, ld, lane, act,
+    load_wire_matrix(sm, s.Mlay + (size_t)(c.layer_off + layer) * n * n, n, lane, act,
                      dt * 2.0 * kPi * re * lo.Ep / d2);
-    bad |= chol_lds(sm, n, ld, lane, act);
+    bad |= chol_lds(sm, n, lane, act, sm + packed_size(n));
     double v3[3];
     v3[0] = act ? -c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * rho * JH : 0.0;
     v3[1] = act ? -dt * 2.0 * kPi * re * rho * (J - JH) : 0.0;
     v3[2] = act ? 1.0 : 0.0;
-    solve_lds<3>(sm, n, ld, lane, act, v3);
+    solve_lds<3>(sm, n, lane, act, v3);
     const double xh = v3[0], xi = v3[1], yv = v3[2];
     // S = P^T A^-1 P, column v = the subelement sums of A^-1 p_v
     for (int v0 = 0; v0 < ns; v0 += 4) {
         double y4[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) y4[q] = (act && sub == v0 + q) ? 1.0 : 0.0;
-        solve_lds<4>(sm, n, ld, lane, act, y4);
+        solve_lds<4>(sm, n, lane, act, y4);
         __syncthreads();
         if (act)
 #pragma unroll
             for (int q = 0; q < 4; ++q) col[q * n + lane] = y4[q];
         __syncthreads();
-        if (sact)
+        if (sact)  // the lower triangle of S: rows lane >= column v0 + q
             for (int q = 0; q < 4 && v0 + q < ns; ++q)
-                S[(v0 + q) * lds + lane] = subelement_sum(col + q * n, lane, sq, sb, c.ne);
+                if (lane >= v0 + q) S[pcol(ns, v0 + q) + lane - (v0 + q)] = subelement_sum(col + q * n, lane, sq, sb, c.ne);
     }
     __syncthreads();
     if (act) col[lane] = xh;
     __syncthreads();
     double u1[1] = {sact ? subelement_sum(col, lane, sq, sb, c.ne) : 0.0};
-    bad |= chol_lds(S, ns, lds, lane, sact);
-    solve_lds<1>(S, ns, lds, lane, sact, u1);     // dt U_s of subelement `lane`
+    bad |= chol_lds(S, ns, lane, sact, S + packed_size(ns));
+    solve_lds<1>(S, ns, lane, sact, u1);     // dt U_s of subelement `lane`
     const double pu = __shfl(u1[0], sub);         // ... of this lane's subelement
     const double usum = wave_sum(sact ? u1[0] : 0.0);
     double z1[1] = {act ? pu : 0.0};
-    solve_lds<1>(sm, n, ld, lane, act, z1);
+    solve_lds<1>(sm, n, lane, act, z1);
     const double dIH = act ? xh - z1[0] : 0.0;
     const double sx = wave_sum(act ? xi : 0.0);
     const double sy = wave_sum(act ? yv : 0.0);
@@ -577,9 +577,9 @@ __device__ __forceinline__ int elem_of(const CoilDev &c, int ir, int iz) {
 __global__ __launch_bounds__(256) void k_heat_tile(DevState s, RunConst rc, int src, int dst, int sub0, int H,
                                                    int last) {
     extern __shared__ double sh[];
-    __shared__ double red_o[256];
-    __shared__ double red_t[256];
-    __shared__ long long red_i[256];
+    __shared__ double red_o[2][4];  // per substep parity: written before the next read
+    __shared__ double red_t[4];
+    __shared__ long long red_i[4];
     const int Wd = kHT + 2 * H, ncell = Wd * Wd;
     double *Ta = sh, *Tb = sh + ncell, *ul = sh + 2 * ncell, *ql = sh + 3 * ncell;
     HeatRow *rows = reinterpret_cast<HeatRow *>(sh + 4 * ncell);
@@ -642,13 +642,14 @@ __global__ __launch_bounds__(256) void k_heat_tile(DevState s, RunConst rc, int 
                 if (s.rec_T) s.rec_T[(size_t)sub * s.N + elem_of(c, ir, iz)] = Te;
             }
         }
-        red_o[tid] = outv;
+        // the tile's border outflow: per wavefront by shuffles, then the four
+        // wavefronts' sums in order
+        // (the barrier also orders this substep's T against the next one's reads)
+        outv = wave_sum(outv);
+        double *ro = red_o[k & 1];
+        if ((tid & 63) == 0) ro[tid >> 6] = outv;
         __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if (tid < o) red_o[tid] += red_o[tid + o];
-            __syncthreads();
-        }
-        if (tid == 0) s.hb_out[(size_t)sub * s.nheat_blocks + blockIdx.x] = red_o[0];
+        if (tid == 0) s.hb_out[(size_t)sub * s.nheat_blocks + blockIdx.x] = ((ro[0] + ro[1]) + ro[2]) + ro[3];
         double *t = Tc;
         Tc = Tn;
         Tn = t;
@@ -675,22 +676,30 @@ __global__ __launch_bounds__(256) void k_heat_tile(DevState s, RunConst rc, int 
     }
     if (bad) atomicOr(&s.sc->status, bad);
     if (!last) return;
-    red_t[tid] = tm;
-    red_i[tid] = ti;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) {
-            const double x = red_t[tid], y = red_t[tid + o];
-            if (y > x || (y == x && red_i[tid + o] < red_i[tid])) {
-                red_t[tid] = y;
-                red_i[tid] = red_i[tid + o];
-            }
+    // the tile's largest T, lowest public index on ties: per wavefront by
+    // shuffles, then over the four wavefronts
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double y = __shfl_xor(tm, o);
+        const long long yi = __shfl_xor(ti, o);
+        if (y > tm || (y == tm && yi < ti)) {
+            tm = y;
+            ti = yi;
         }
-        __syncthreads();
     }
+    if ((tid & 63) == 0) {
+        red_t[tid >> 6] = tm;
+        red_i[tid >> 6] = ti;
+    }
+    __syncthreads();
     if (tid == 0) {
-        s.hb_max[blockIdx.x] = red_t[0];
-        s.hb_arg[blockIdx.x] = red_i[0];
+        for (int k = 1; k < 4; ++k)
+            if (red_t[k] > tm || (red_t[k] == tm && red_i[k] < ti)) {
+                tm = red_t[k];
+                ti = red_i[k];
+            }
+        s.hb_max[blockIdx.x] = tm;
+        s.hb_arg[blockIdx.x] = ti;
     }
 }
 
@@ -968,13 +977,14 @@ hipError_t launch_field_finalize(const DevState &s, const RunConst &rc, hipStrea
 hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st) {
     if (s.nsubel > 0) {
         const size_t ns = (size_t)s.nsubel * s.nsubel;
-        const size_t lds = sizeof(double) * ((size_t)(s.max_ne2 + 1) * s.max_ne2 + ns * (ns + 1) + 4 * s.max_ne2);
+        const size_t lds =
+            sizeof(double) * ((size_t)packed_size(s.max_ne2) + kCholPad + packed_size((int)ns) + kCholPad + 4 * s.max_ne2);
         hipLaunchKernelGGL(k_wire_sub, dim3(s.Nw), dim3(64), lds, st, s, rc);
         return hipGetLastError();
     }
     hipLaunchKernelGGL(k_wire<1>, dim3(s.nfast), dim3(64 * kFastWires), sizeof(double) * (size_t)s.max_ne2 * s.max_ne2,
                        st, s, rc);
-    const size_t lds = sizeof(double) * (size_t)(s.max_ne2 + 1) * s.max_ne2;
+    const size_t lds = sizeof(double) * ((size_t)packed_size(s.max_ne2) + kCholPad);
     if (rc.em_tol > 0.0)
         hipLaunchKernelGGL(k_wire_em, dim3(s.Nw), dim3(64), lds, st, s, rc);
     else

@@ -111,12 +111,23 @@ def test_variable_step_stiff_decay_against_oracle():
     assert nerr(g.get(pk.F_PHI), o.get(oracle.PHI)) <= 1e-10
 
 
-def test_variable_step_rejections():
+def test_variable_step_graph_replay_and_rejections():
+    """A captured graph of variable steps replays the eager run bitwise (the
+    substep loop runs inside the kernel, so the graph holds the same kernel
+    nodes as a fixed step); the adjoint and the substep field without the
+    option are refused."""
     pk = _pk()
     w = cs.workload("c1_active").replace(em_tol=1e-5)
     inp = cs.generate(w)
     a = pk.Coil(w, inp)
-    a.run(5)
+    b = pk.Coil(w, inp)
+    a.run(300)
+    b.graph(10)
+    for _ in range(30):
+        b.run(10)
+        b.synchronize()
+    for f in (pk.F_I, pk.F_T, pk.F_PHI, pk.F_UW, pk.F_EM_SUBSTEPS):
+        assert np.array_equal(a.get(f), b.get(f))
     with pytest.raises(pk.CoilError) as ei:
         a.adjoint(5)
     assert ei.value.code == -1
