@@ -283,40 +283,41 @@ __device__ __forceinline__ unsigned chol_lds(double *sm, int n, int lane, bool a
 
 // Solve L L^T v_q = v_q for K right-hand sides at once (packed factor in LDS,
 // lane i holding entry i of every v_q).  v_j comes from lane j by scalar
-// reads; the factor's entries of the next j are read while the current j is
-// applied.
+// reads; the factor's entries of the next j, and the reciprocal of its pivot,
+// are formed while the current j is applied, so that the chain from one j to
+// the next holds a multiplication rather than a division.
 template <int K>
 __device__ __forceinline__ void solve_lds(const double *sm, int n, int lane, bool act, double (&v)[K]) {
-    double ljj = sm[0];
+    double rjj = 1.0 / sm[0];
     double l = (act && lane > 0) ? sm[lane] : 0.0;
     for (int j = 0; j < n; ++j) {
         const int jn = j + 1 < n ? j + 1 : j;
         const int cn = pcol(n, jn);
-        const double ljj_n = sm[cn];
+        const double rjj_n = 1.0 / sm[cn];
         const double l_n = (act && lane > jn) ? sm[cn + lane - jn] : 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            const double vj = lane_value(v[q], j) / ljj;
+            const double vj = lane_value(v[q], j) * rjj;
             if (lane == j) v[q] = vj;
             if (act && lane > j) v[q] -= l * vj;
         }
-        ljj = ljj_n;
+        rjj = rjj_n;
         l = l_n;
     }
     // backward: lane i < j needs L(j, i), row j of the factor
-    ljj = sm[pcol(n, n - 1)];
+    rjj = 1.0 / sm[pcol(n, n - 1)];
     l = (act && lane < n - 1) ? sm[pcol(n, lane) + n - 1 - lane] : 0.0;
     for (int j = n - 1; j >= 0; --j) {
         const int jn = j > 0 ? j - 1 : 0;
-        const double ljj_n = sm[pcol(n, jn)];
+        const double rjj_n = 1.0 / sm[pcol(n, jn)];
         const double l_n = (act && lane < jn) ? sm[pcol(n, lane) + jn - lane] : 0.0;
 #pragma unroll
         for (int q = 0; q < K; ++q) {
-            const double vj = lane_value(v[q], j) / ljj;
+            const double vj = lane_value(v[q], j) * rjj;
             if (lane == j) v[q] = vj;
             if (act && lane < j) v[q] -= l * vj;
         }
-        ljj = ljj_n;
+        rjj = rjj_n;
         l = l_n;
     }
 }
