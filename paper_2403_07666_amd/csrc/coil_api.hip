@@ -219,9 +219,9 @@ void build_items(Plan &p, int tb, int nch_req, int cs_req) {
 // every width runs at the register count of the widest).
 // The source rows of a target segment are split into n_g groups: enough for
 // about 8192 items (four or more per LDS slot of the GPU), and more for large
-// coils, so that an item holds at most about 4e6 pairs (the end of the pass,
-// where SIMDs run out of items at different times, scales with the item);
-// at most kTzMaxSplit.  A group is a run of
+// coils, so that an item of the largest coil holds at most about 4e6 pairs
+// (the end of the pass, where SIMDs run out of items at different times,
+// scales with the item); at most kTzMaxSplit.  A group is a run of
 // the coil's rows in bit-reversed order, so that it samples the whole coil
 // (a like share of near rows), and the group sizes fall linearly from 4 to 1
 // relative units.  All items run in one launch, the most FMA work first, so the
@@ -315,10 +315,14 @@ void build_tz(Plan &p, int nsplit_req, int force_w = 0) {
         }
         segs += (long long)nr * (long long)segw[ci].size();
     }
-    double pairs = 0.0;
-    for (const CoilDev &d : p.coils) pairs += (double)d.n * (double)(d.n - 1);
+    // the split is common to all coils: the largest coil's items set the size bound
+    long long by_size = 1;
+    for (size_t ci = 0; ci < p.coils.size(); ++ci) {
+        const CoilDev &d = p.coils[ci];
+        const double csegs = (double)d.layers * d.ne * (double)segw[ci].size();
+        by_size = std::max(by_size, (long long)std::ceil((double)d.n * (double)(d.n - 1) / (csegs * 4e6)));
+    }
     const long long by_count = (8192 + segs - 1) / segs;
-    const long long by_size = (long long)std::ceil(pairs / ((double)segs * 4e6));
     const int nsplit = nsplit_req > 0 ? std::min(nsplit_req, kTzMaxSplit)
                                       : (int)std::max<long long>(1, std::min<long long>(kTzMaxSplit, std::max(by_count, by_size)));
     p.nslot_tz_max = 1;
