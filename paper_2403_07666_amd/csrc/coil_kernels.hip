@@ -275,8 +275,8 @@ __device__ unsigned em_integrate(double *sm, const DevState &s, const RunConst &
 //     layer's inductance block bitwise and the solution uses that inverse
 //     (x = M^-1 b, y = M^-1 1); otherwise the wire is flagged and left
 //     untouched;
-//   k_wire<0>: flagged wires only; A in LDS (column-major, leading dimension
-//     n_e + 1), right-looking Cholesky and two triangular solves.
+//   k_wire<0>: flagged wires only; A in LDS (packed lower triangle by
+//     columns), right-looking Cholesky and two triangular solves.
 // Optional recording (adjoint recompute): I^k, B^k and dI of the step; optional
 // field source (adjoint recompute from a stored field history).
 template <int FAST>
