@@ -146,8 +146,18 @@ enum coil_heat { COIL_HEAT_EXPLICIT = 0, COIL_HEAT_ADI = 1 };
    once and reused along z (a per-row-pair 1-D convolution); in mixed
    precision the values with k > near_k come from a table evaluated once at
    coil_init, all others are evaluated on the fly every pass.  AUTO =
-   TRANSLATION. */
-enum coil_algo { COIL_ALGO_AUTO = 0, COIL_ALGO_DIRECT = 1, COIL_ALGO_TRANSLATION = 2 };
+   TRANSLATION.
+   FFT uses the same invariance the other way round: each row-pair
+   convolution, zero-padded to a power of two L >= 2 n_z - 1, is a product of
+   DFTs.  coil_init evaluates every kernel value once in FP64, transforms it
+   (FP64) and keeps per coil two real n_r x n_r matrices per bin (L/2 + 1
+   bins: G^_z is real as g_z is even in z, G^_r imaginary as g_r is odd),
+   FP32 in COIL_MIXED, FP64 in COIL_FP64: 2 (L/2+1) n_r^2 reals, about
+   4 n_r^2 n_z for n_z a power of two (1.9 GB for 480 x 800 in FP32).  A pass
+   transforms the source rows, streams the matrices once and transforms the
+   target rows back.  Only selectable at coil_init (the autotuner then also
+   times it); the coupled solve's flux passes stay on TRANSLATION. */
+enum coil_algo { COIL_ALGO_AUTO = 0, COIL_ALGO_DIRECT = 1, COIL_ALGO_TRANSLATION = 2, COIL_ALGO_FFT = 3 };
 
 /* fields for coil_get / coil_set_state */
 enum coil_field {

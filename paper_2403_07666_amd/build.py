@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libcoil.so")
-SOURCES = ["coil_kernels.hip", "coil_adjoint.hip", "coil_field_tz.hip", "coil_coupled.hip", "coil_adi.hip", "coil_api.hip"]
+SOURCES = ["coil_kernels.hip", "coil_adjoint.hip", "coil_field_tz.hip", "coil_field_fft.hip", "coil_coupled.hip", "coil_adi.hip", "coil_api.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

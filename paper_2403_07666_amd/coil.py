@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libcoil.so")
 # enum coil_status / coil_precision / coil_field (include/coil.h)
 OK, E_INVAL, E_NOMEM, E_HIP, E_NONFINITE, E_STATE = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
-ALGO_AUTO, ALGO_DIRECT, ALGO_TRANSLATION = 0, 1, 2
+ALGO_AUTO, ALGO_DIRECT, ALGO_TRANSLATION, ALGO_FFT = 0, 1, 2, 3
 F_I, F_J, F_BR, F_BZ, F_T, F_PHI, F_QW, F_UW, F_E, F_EP, F_U, F_Q, F_PSI, F_R, F_Z, F_DI, F_JC = range(17)
 F_ONSET, F_QUENCH, F_Q_ONSET, F_Q_QUENCH, F_T_QUENCH, F_P_QUENCH = range(17, 23)
 F_IH = 23  # subelement model: field-driven component of the element current
@@ -182,7 +182,8 @@ class _CfgHolder:
         cfg.tile_targets = int(tile_targets)
         cfg.tile_sources = int(tile_sources)
         cfg.grid_limit = int(grid_limit)
-        cfg.algo = {"auto": ALGO_AUTO, "direct": ALGO_DIRECT, "translation": ALGO_TRANSLATION}.get(algo, algo)
+        cfg.algo = {"auto": ALGO_AUTO, "direct": ALGO_DIRECT, "translation": ALGO_TRANSLATION,
+                    "fft": ALGO_FFT}.get(algo, algo)
         cfg.rho_n = float(getattr(w, "rho_n", 0.0))
         cfg.k_exp = float(getattr(w, "k_exp", 0.0))
         cfg.h_exp = float(getattr(w, "h_exp", 0.0))
@@ -392,7 +393,8 @@ class Coil:
     def autotune(self, reps: int = 3, cache_path: Optional[str] = None):
         """Time the field-pass candidates and keep the fastest; returns
         (algo, p1, p2, p3): (2, source-row groups, 0, 0) for the translation
-        evaluation or (1, tile_targets, chunks, grid_limit) for the direct one."""
+        evaluation, (1, tile_targets, chunks, grid_limit) for the direct one or
+        (3, 0, 0, 0) for the fast convolution (a candidate only if set up at init)."""
         ch = np.zeros(4, dtype=np.int32)
         path = cache_path.encode() if cache_path else None
         check(lib().coil_autotune(self.h, int(reps), path, ch.ctypes.data_as(_i32p)))
@@ -402,7 +404,7 @@ class Coil:
         """Work of one field pass: pairs, Green's-function evaluations, algorithm, items."""
         v = np.zeros(6)
         check(lib().coil_field_stats(self.h, v.ctypes.data_as(_dp), 6))
-        return {"pairs": v[0], "kernel_evals": v[1], "algo": "translation" if v[2] == 2 else "direct",
+        return {"pairs": v[0], "kernel_evals": v[1], "algo": {2: "translation", 3: "fft"}.get(int(v[2]), "direct"),
                 "items": int(v[3]), "tile_targets": int(v[4]), "workgroups": int(v[5])}
 
     # -------------------------------------------------------------- probes and snapshots

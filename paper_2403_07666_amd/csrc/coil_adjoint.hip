@@ -92,7 +92,7 @@ __global__ void k_fieldT_sum(DevState s, const double *partT, double *out, int a
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= s.N) return;
     const CoilDev c = s.coils[s.elem_coil[j]];
-    const int nk = s.algo_tz ? c.nslot_tz : c.nchunk;
+    const int nk = field_slots(s, c);
     double v = 0.0;
     int k = 0;
     for (; k + 16 <= nk; k += 16) {  // in order, 16 loads in flight

@@ -18,6 +18,7 @@
 
 #include "coil_adjoint.h"
 #include "coil_coupled.h"
+#include "coil_field_fft.h"
 #include "coil_field_tz.h"
 #include "coil_internal.h"
 
@@ -67,6 +68,8 @@ struct Plan {
     std::vector<int2> near_pair;  // mixed mode: per coil, per (target row, source row): (first, count)
     size_t near_total = 0;        // near kernel values over all pairs
     int algo = COIL_ALGO_TRANSLATION;
+    int fft = 0;            // COIL_ALGO_FFT at init: the spectra and buffers of the fast-convolution pass
+    FftHostPlan fftp;
     int prec = COIL_FP64;  // arithmetic of the field passes (sets the width choice)
     int coupled = 0;       // COIL_COUPLE_FULL: buffers of the coupled solve
     int adi = 0;           // COIL_HEAT_ADI: buffers of the ADI heat step
@@ -81,7 +84,7 @@ struct Plan {
         perm_b, wire_coil_b, fastw_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
         sc_b, tmp_b, misc_b, diag_b, hrow_b, Lself_b, cgv_b, cgL_b, cgred_b, cgrw_b, cgsc_b, adi_b, kmult_b, IH_b, emsub_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b,
-        Ipub32_b;
+        Ipub32_b, fftspec_b, ffthat_b, fftbp_b, fftitems_b, fftcoils_b, ffttw64_b;
 };
 
 Buf carve(size_t &cur, size_t bytes) {
@@ -130,7 +133,7 @@ int validate(const coil_config *c) {
     if (c->tile_sources < 0 || c->tile_sources % kStage != 0)
         return fail(COIL_E_INVAL, "tile_sources must be a non-negative multiple of %d", kStage);
     if (c->grid_limit < 0) return fail(COIL_E_INVAL, "grid_limit must be >= 0");
-    if (c->algo < COIL_ALGO_AUTO || c->algo > COIL_ALGO_TRANSLATION) return fail(COIL_E_INVAL, "unknown algo %d", c->algo);
+    if (c->algo < COIL_ALGO_AUTO || c->algo > COIL_ALGO_FFT) return fail(COIL_E_INVAL, "unknown algo %d", c->algo);
     if (c->I0)
         for (int i = 0; i < c->n_coils; ++i)
             if (!std::isfinite(c->I0[i])) return fail(COIL_E_INVAL, "coil %d: non-finite I0", i);
@@ -475,6 +478,11 @@ int make_plan(const coil_config *c, Plan &p) {
     build_tz(p, 0);
     p.tz_cap = std::max(p.tz_cap, p.tz_items.size());
     p.algo = c->algo == COIL_ALGO_DIRECT ? COIL_ALGO_DIRECT : COIL_ALGO_TRANSLATION;
+    if (c->algo == COIL_ALGO_FFT) {
+        p.algo = COIL_ALGO_FFT;
+        p.fft = 1;
+        fft_plan(p.coils, p.fftp);
+    }
     return COIL_OK;
 }
 
@@ -587,6 +595,15 @@ size_t layout(Plan &p) {
     }
     if (p.nsubel) p.IH_b = carve(cur, d8 * N);
     if (p.em) p.emsub_b = carve(cur, d8 * Nw);
+    if (p.fft) {
+        const size_t rs = p.prec == COIL_MIXED ? sizeof(float) : sizeof(double);
+        p.fftspec_b = carve(cur, rs * p.fftp.spec_reals);
+        p.ffthat_b = carve(cur, d8 * p.fftp.hat_reals);
+        p.fftbp_b = carve(cur, d8 * p.fftp.bpart_reals);
+        p.fftitems_b = carve(cur, sizeof(int4) * p.fftp.items.size());
+        p.fftcoils_b = carve(cur, sizeof(FftCoil) * p.fftp.coils.size());
+        p.ffttw64_b = carve(cur, sizeof(double2) * (p.fftp.Lmax / 2));
+    }
     if (p.coupled) {
         p.Lself_b = carve(cur, d8 * N);
         p.cgv_b = carve(cur, d8 * 5 * N);
@@ -617,6 +634,7 @@ struct coil_s {
     std::vector<double> r_pub, z_pub;  // public order, for COIL_F_R / COIL_F_Z
     std::vector<int> pub2int;          // public -> internal element index
     TzPlan tz{};                       // device items of the translation-reuse pass
+    FftPlan fft{};                     // device plan of the fast-convolution pass (COIL_ALGO_FFT at init)
     double *Ipub = nullptr;            // currents in public order (its input)
     int *d_pub2int = nullptr;
     // timing
@@ -697,12 +715,14 @@ int t_flush(coil_t *h) {
 hipError_t launch_fieldT_any(coil_t *h, const double *wr, const double *wz, double *wpub, double *partT,
                              hipStream_t st) {
     const DevState &d = h->ds;
+    if (d.algo_fft) return launch_fieldT_fft(d, h->fft, wr, wz, h->d_pub2int, partT, st);
     if (d.algo_tz)
         return launch_fieldT_tz(d, h->rc, h->tz, wr, wz, wpub, wpub + d.N, h->d_pub2int, partT, st);
     return launch_fieldT(d, h->rc, h->grid_limit, wr, wz, partT, st);
 }
 
 hipError_t launch_field_any(coil_t *h, const DevState &d, hipStream_t st) {
+    if (d.algo_fft) return launch_field_fft(d, h->fft, h->d_pub2int, st);
     if (d.algo_tz) return launch_field_tz(d, h->rc, h->tz, h->Ipub, h->d_pub2int, h->grid_limit, st);
     return launch_field(d, h->rc, h->grid_limit, st);
 }
@@ -734,7 +754,9 @@ int enqueue_step(coil_t *h) {
     const DevState &d = h->ds;
     if (d.algo_tz) HIPCHECK(launch_field_tz_prep(d, h->tz, h->Ipub, h->stream));
     if ((rc = t_begin(h, &a, 0))) return rc;
-    if (d.algo_tz)
+    if (d.algo_fft)
+        HIPCHECK(launch_field_fft(d, h->fft, h->d_pub2int, h->stream));
+    else if (d.algo_tz)
         HIPCHECK(launch_field_tz_kernel(d, h->rc, h->tz, h->Ipub, h->d_pub2int, h->grid_limit, h->stream));
     else
         HIPCHECK(launch_field(d, h->rc, h->grid_limit, h->stream));
@@ -1094,6 +1116,23 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     s.max_ne2 = p.max_ne2;
     s.tile_targets = p.tile_targets;
     s.algo_tz = p.algo == COIL_ALGO_TRANSLATION ? 1 : 0;
+    s.algo_fft = p.algo == COIL_ALGO_FFT ? 1 : 0;
+    if (p.fft) {
+        FftPlan &f = h->fft;
+        f.coils = at<FftCoil>(h, p.fftcoils_b);
+        f.items = at<int4>(h, p.fftitems_b);
+        f.npairs = p.fftp.npairs;
+        f.nrows = p.fftp.nrows;
+        f.nbins = p.fftp.nbins;
+        f.nbinsT = p.fftp.nbinsT;
+        f.Lmax = p.fftp.Lmax;
+        f.logLmax = p.fftp.logLmax;
+        f.prec = p.prec;
+        f.spec = at<char>(h, p.fftspec_b);
+        f.hat = at<double>(h, p.ffthat_b);
+        f.bpart = at<double>(h, p.fftbp_b);
+        f.tw64 = at<double2>(h, p.ffttw64_b);
+    }
     h->Ipub = at<double>(h, p.Ipub_b);
     h->d_pub2int = at<int>(h, p.pub2int_b);
     h->tz.items = at<TzItem>(h, p.tz_b);
@@ -1234,6 +1273,21 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     if (p.prec == COIL_MIXED)
         for (size_t ci = 0; ci < p.coils.size(); ++ci)
             HIPCHECK(launch_near_fill(s, (int)ci, p.coils[ci].layers * p.coils[ci].ne, st));
+    std::vector<double2> tw64;
+    if (p.fft) {  // twiddles exp(-2 pi i k / Lmax), then the spectra
+        const int Lm = p.fftp.Lmax;
+        tw64.resize(Lm / 2);
+        for (int k = 0; k < Lm / 2; ++k) {
+            const double th = 2.0 * kPi * (double)k / (double)Lm;
+            tw64[k] = make_double2(std::cos(th), -std::sin(th));
+        }
+        HIPCHECK(up((void *)h->fft.tw64, tw64.data(), sizeof(double2) * tw64.size()));
+        HIPCHECK(up((void *)h->fft.coils, p.fftp.coils.data(), sizeof(FftCoil) * p.fftp.coils.size()));
+        HIPCHECK(up((void *)h->fft.items, p.fftp.items.data(), sizeof(int4) * p.fftp.items.size()));
+        // staging: the partial-sum buffer (a slab of source rows at a time)
+        HIPCHECK(launch_fft_setup(s, h->fft, p.fftp.coils.data(), (int)p.fftp.coils.size(), s.part,
+                                  sizeof(double2) * (size_t)N * p.part_slots, st));
+    }
     // transport-flux pattern: FP64 all-pairs pass on the device
     HIPCHECK(launch_psi(s, const_cast<double *>(s.psi), st));
     if ((rc = reset_state(h))) return rc;
@@ -1887,6 +1941,7 @@ extern "C" int coil_set_tiles(coil_t *h, int32_t tile_targets, int32_t chunks, i
     int rc = coil_graph(h, 0);
     if (rc) return rc;
     h->ds.algo_tz = 0;
+    h->ds.algo_fft = 0;
     h->plan.algo = COIL_ALGO_DIRECT;
     return apply_tiles(h, tile_targets, chunks, grid_limit);
 }
@@ -1900,6 +1955,15 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     const std::string key = tune_key(h);
     // choice: algo (1 direct, 2 translation), then (tile_targets, chunks, grid) or (split)
     auto apply = [&](int algo, int a, int b, int c) -> int {
+        h->ds.algo_fft = 0;
+        if (algo == COIL_ALGO_FFT) {  // only where its spectra were made at init
+            if (!h->plan.fft) return fail(COIL_E_INVAL, "the fast-convolution pass was not set up");
+            h->ds.algo_tz = 0;
+            h->ds.algo_fft = 1;
+            h->plan.algo = COIL_ALGO_FFT;
+            h->grid_limit = 0;
+            return COIL_OK;
+        }
         if (algo == COIL_ALGO_TRANSLATION) {
             h->ds.algo_tz = 1;
             h->plan.algo = COIL_ALGO_TRANSLATION;
@@ -1950,6 +2014,7 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     int ba = h->plan.algo, b1 = 0, b2 = 0, b3 = 0;
     struct Cand { int algo, a, b, c; };
     std::vector<Cand> cands;
+    if (h->plan.fft) cands.push_back({COIL_ALGO_FFT, 0, 0, 0});
     for (int sp : {4, 8, 16, 32, 64}) cands.push_back({COIL_ALGO_TRANSLATION, sp, 0, 0});
     for (int tb : {64, 128, 256})
         for (int ch : {1, 2, 4, 8, kMaxChunks})
@@ -1957,8 +2022,8 @@ extern "C" int coil_autotune(coil_t *h, int32_t reps, const char *cache_path, in
     // Every candidate's first launch is timed as a screen: only candidates within
     // 3x of the best so far get the `reps` timed launches, and a family (algorithm)
     // whose first three candidates all stay beyond 3x is not tried further.
-    int fam_tried[3] = {0, 0, 0};
-    double fam_best[3] = {INFINITY, INFINITY, INFINITY};
+    int fam_tried[4] = {0, 0, 0, 0};
+    double fam_best[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
     auto elapsed = [&](float *ms) -> int {
         HIPCHECK(hipEventRecord(eb, h->stream));
         HIPCHECK(hipEventSynchronize(eb));
@@ -2002,13 +2067,14 @@ extern "C" int coil_field_stats(coil_t *h, double *out, int32_t n) {
     if (!h || !out) return fail(COIL_E_INVAL, "NULL argument");
     double pairs = 0.0;
     for (const CoilDev &d : h->plan.coils) pairs += (double)d.n * (double)(d.n - 1);
-    const bool tz = h->ds.algo_tz != 0;
-    const int nit = tz ? (int)h->plan.tz_items.size() : (int)h->plan.items.size();
+    const bool tz = h->ds.algo_tz != 0, ff = h->ds.algo_fft != 0;
+    const int nit = ff ? h->plan.fftp.nbins : tz ? (int)h->plan.tz_items.size() : (int)h->plan.items.size();
     const int resident = h->rc.prec == COIL_MIXED ? h->tz.grid32 : h->tz.grid64;
-    const int wg = h->grid_limit > 0 ? std::min(h->grid_limit, nit)
+    const int wg = ff ? nit
+                   : h->grid_limit > 0 ? std::min(h->grid_limit, nit)
                    : tz && resident > 0 ? std::min(resident, nit)
                                         : nit;
-    const double v[6] = {pairs, tz ? h->plan.tz_evals : pairs, tz ? 2.0 : 1.0, (double)nit,
+    const double v[6] = {pairs, ff ? 0.0 : tz ? h->plan.tz_evals : pairs, ff ? 3.0 : tz ? 2.0 : 1.0, (double)nit,
                          (double)h->ds.tile_targets, (double)wg};
     for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
     return COIL_OK;

@@ -1,0 +1,527 @@
+// coil_field_fft.hip -- field pass by fast convolution along z (the layout,
+// the spectra and the three steps of a pass are described in coil_field_fft.h).
+//
+// Layouts (per coil, rows padded to Rp):
+//   spectra   G^_z[f][j][i], then S[f][j][i]  (j source row, i target row), TS reals:
+//             FP32 in mixed precision (the only data a pass streams from HBM), else FP64
+//   hat       FP64; forward: I^[f][j] (re, im); transposed: W^[f][i] (wr re, wr im, wz re, wz im)
+//   bpart     FP64; forward: [p][f][i] (Bz^ re, Bz^ im, Br^ re, Br^ im), p = source-row part;
+//             transposed: [ib][f][j] (re, im), ib = target block
+// The DFTs run in FP64 (radix-2, decimation in time, in LDS, one row or two
+// real rows packed as one complex row per workgroup), and so do the bin
+// products' sums: in mixed precision only the stored spectra are rounded (to
+// FP32, a relative 2^-24 per value), which keeps the pass's error at about
+// that of the rounded kernel values.  The DFT's own FP32 rounding would be
+// relative to the norm of the whole row instead, and a row packs B_z with the
+// smaller B_r.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "coil_device.h"
+#include "coil_field_fft.h"
+
+namespace coilq {
+
+namespace {
+
+// 4 consecutive reals as doubles (16-byte aligned for float, 32 for double)
+__device__ __forceinline__ void load4(const float *p, double (&v)[4]) {
+    const float4 q = *reinterpret_cast<const float4 *>(p);
+    v[0] = q.x;
+    v[1] = q.y;
+    v[2] = q.z;
+    v[3] = q.w;
+}
+__device__ __forceinline__ void load4(const double *p, double (&v)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0];
+    const double2 b = reinterpret_cast<const double2 *>(p)[1];
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+}
+__device__ __forceinline__ void store4(double *p, double a, double b, double c, double d) {
+    reinterpret_cast<double2 *>(p)[0] = make_double2(a, b);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(c, d);
+}
+
+__device__ __forceinline__ int bitrev(int m, int logL) {
+    return (int)(__builtin_bitreverse32((unsigned)m) >> (32 - logL));
+}
+
+// In-place DFT X[f] = sum_m x[m] exp(-2 pi i f m / L) of the L values in a[]
+// (LDS), stored by the caller in bit-reversed order (then a barrier); the
+// result is in natural order, followed by a barrier.  Stage s combines pairs
+// half = 2^(s-1) apart with the twiddle exp(-2 pi i pos / 2^s), read from the
+// table of exp(-2 pi i k / Lmax) at k = pos Lmax / 2^s.
+__device__ void fft_lds(double2 *a, int L, int logL, const double2 *__restrict__ tw, int logLmax) {
+    const int nb = L >> 1;
+    for (int s = 1; s <= logL; ++s) {
+        const int half = 1 << (s - 1);
+        const int sh = logLmax - s;
+        for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+            const int pos = k & (half - 1);
+            const int i0 = ((k >> (s - 1)) << s) | pos;
+            const int i1 = i0 + half;
+            const double2 w = tw[pos << sh];
+            const double2 u = a[i0], v = a[i1];
+            const double tr = w.x * v.x - w.y * v.y;
+            const double ti = w.x * v.y + w.y * v.x;
+            a[i0] = make_double2(u.x + tr, u.y + ti);
+            a[i1] = make_double2(u.x - tr, u.y - ti);
+        }
+        __syncthreads();
+    }
+}
+
+// Inverse transform of two real rows u, v from their half spectra U, V
+// (bins f = 0 .. L/2; get(f) returns (U re, U im, V re, V im)): the row
+// y = u + i v has the spectrum Y = U + i V, with Y[L - f] = conj(U[f]) +
+// i conj(V[f]); y = conj(DFT(conj Y)) / L.  Leaves DFT(conj Y) in a[].
+template <typename Get>
+__device__ __forceinline__ void inverse_pair(double2 *a, const FftCoil &C, const FftPlan &fp, Get get) {
+    const int L = C.L, logL = C.logL, half = L >> 1;
+    for (int f = threadIdx.x; f < C.bins; f += blockDim.x) {
+        double ur, ui, vr, vi;
+        get(f, ur, ui, vr, vi);
+        a[bitrev(f, logL)] = make_double2(ur - vi, -(ui + vr));
+        if (f > 0 && f < half) a[bitrev(L - f, logL)] = make_double2(ur + vi, ui - vr);
+    }
+    __syncthreads();
+    fft_lds(a, L, logL, fp.tw64, fp.logLmax);
+}
+
+// ------------------------------------------------------------------ set-up
+// One workgroup per (target row a, source row b of the slab): the FP64 kernel
+// values g(a - b, delta) for delta = 0 .. Z-1, placed at m = delta and (their
+// mirrors: g_z even, g_r odd) at m = L - delta as x = g_z + i g_r, the DFT,
+// and per bin G^_z = (X[f] + X[L-f]) / 2, S = (X[L-f] - X[f]) / 2 (real parts).
+__global__ __launch_bounds__(256) void k_fft_spec(FftPlan fp, int coil, int b0, double2 *tmp) {
+    extern __shared__ double2 xs[];
+    const FftCoil C = fp.coils[coil];
+    const int a = blockIdx.x, bl = blockIdx.y, b = b0 + bl;
+    const int L = C.L, logL = C.logL;
+    for (int m = threadIdx.x; m < L; m += blockDim.x) xs[m] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const double dr = (double)(a - b), sr = C.c2d + (double)(a + b);
+    for (int d = threadIdx.x; d < C.Z; d += blockDim.x) {
+        double gr = 0.0, gz = 0.0;
+        pair64(dr, (double)d, sr, 1.0, gr, gz);  // zero for the element's own ring
+        xs[bitrev(d, logL)] = make_double2(gz, gr);
+        if (d > 0) xs[bitrev(L - d, logL)] = make_double2(gz, -gr);
+    }
+    __syncthreads();
+    fft_lds(xs, L, logL, fp.tw64, fp.logLmax);
+    double2 *out = tmp + ((size_t)bl * C.R + a) * C.bins;
+    for (int f = threadIdx.x; f < C.bins; f += blockDim.x) {
+        const double2 X = xs[f], Y = xs[(L - f) & (L - 1)];
+        out[f] = make_double2(0.5 * (X.x + Y.x), 0.5 * (Y.x - X.x));
+    }
+}
+
+// the slab's spectra from [b][a][f] to [f][b][a] (a < Rp; zeros past R), as T
+template <typename T>
+__global__ __launch_bounds__(256) void k_fft_spec_store(FftPlan fp, int coil, int b0, const double2 *tmp) {
+    __shared__ double2 tile[32][33];
+    const FftCoil C = fp.coils[coil];
+    const int f0 = blockIdx.x * 32, a0 = blockIdx.y * 32, bl = blockIdx.z, b = b0 + bl;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int k = 0; k < 32; k += 8) {
+        const int a = a0 + ty + k, f = f0 + tx;
+        tile[ty + k][tx] =
+            (a < C.R && f < C.bins) ? tmp[((size_t)bl * C.R + a) * C.bins + f] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    T *gz = static_cast<T *>(fp.spec) + C.spec;
+    T *gs = gz + (size_t)C.bins * C.R * C.Rp;
+    for (int k = 0; k < 32; k += 8) {
+        const int f = f0 + ty + k, a = a0 + tx;
+        if (f < C.bins && a < C.Rp) {
+            const double2 v = tile[tx][ty + k];
+            const size_t o = ((size_t)f * C.R + b) * C.Rp + a;
+            gz[o] = (T)v.x;
+            gs[o] = (T)v.y;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ forward pass
+// source rows a = 2q, b = 2q + 1 as one complex row kscale (I_a + i I_b),
+// zero-padded to L; I^_a = (X[f] + conj X[L-f]) / 2, I^_b = (X[f] - conj X[L-f]) / 2i
+__global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan fp, const double *__restrict__ I,
+                                                      const int *__restrict__ pub2int) {
+    extern __shared__ double2 xs[];
+    const int4 it = fp.items[blockIdx.x];
+    const FftCoil C = fp.coils[it.x];
+    const int a = 2 * it.y, b = a + 1;
+    const int L = C.L, logL = C.logL, Z = C.Z;
+    const bool hb = b < C.R;
+    const int *pa = pub2int + C.off + (size_t)a * Z;
+    for (int z = threadIdx.x; z < L; z += blockDim.x) {
+        double va = 0.0, vb = 0.0;
+        if (z < Z) {
+            va = C.kscale * I[pa[z]];
+            if (hb) vb = C.kscale * I[pa[Z + z]];
+        }
+        xs[bitrev(z, logL)] = make_double2(va, vb);
+    }
+    __syncthreads();
+    fft_lds(xs, L, logL, fp.tw64, fp.logLmax);
+    double *hat = fp.hat + C.hat;
+    for (int f = threadIdx.x; f < C.bins; f += blockDim.x) {
+        const double2 X = xs[f], Y = xs[(L - f) & (L - 1)];
+        const size_t o = ((size_t)f * C.R + a) * 2;
+        hat[o] = 0.5 * (X.x + Y.x);
+        hat[o + 1] = 0.5 * (X.y - Y.y);
+        if (hb) {
+            hat[o + 2] = 0.5 * (X.y + Y.y);
+            hat[o + 3] = 0.5 * (Y.x - X.x);
+        }
+    }
+}
+
+// Bin products, one workgroup per (coil, bin f, block of kFftI targets, part of
+// kFftJ sources): Bz^_i = sum_j G^_z,ij I^_j, Br^_i = i sum_j S_ij I^_j.  A lane
+// owns 4 consecutive targets (one 16/32-byte load per matrix and source row),
+// the four waves split the part's sources and add in LDS in a fixed order.
+// TS: the stored spectra (the sums are FP64).
+template <typename TS>
+__global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp) {
+    __shared__ double2 sI[kFftJ];
+    __shared__ double red[3][16][65];
+    const int4 it = fp.items[fp.npairs + fp.nrows + blockIdx.x];
+    const FftCoil C = fp.coils[it.x];
+    const int f = it.y, j0 = it.w * kFftJ;
+    const int jn = min(kFftJ, C.R - j0);
+    const double *hat = fp.hat + C.hat;
+    if ((int)threadIdx.x < jn) {
+        const size_t o = ((size_t)f * C.R + j0 + threadIdx.x) * 2;
+        sI[threadIdx.x] = make_double2(hat[o], hat[o + 1]);
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = it.z * kFftI + 4 * lane;
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    constexpr int JW = kFftJ / 4;
+    const int jw0 = w * JW, jw1 = min(jw0 + JW, jn);
+    if (i < C.Rp) {
+        const size_t plane = (size_t)C.bins * C.R * C.Rp;
+        const TS *gz = static_cast<const TS *>(fp.spec) + C.spec + ((size_t)f * C.R + j0) * C.Rp + i;
+#pragma unroll 8
+        for (int j = jw0; j < jw1; ++j) {
+            double g[4], sv[4];
+            load4(gz + (size_t)j * C.Rp, g);
+            load4(gz + plane + (size_t)j * C.Rp, sv);
+            const double2 x = sI[j];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                acc[t] = fma(g[t], x.x, acc[t]);
+                acc[4 + t] = fma(g[t], x.y, acc[4 + t]);
+                acc[8 + t] = fma(-sv[t], x.y, acc[8 + t]);
+                acc[12 + t] = fma(sv[t], x.x, acc[12 + t]);
+            }
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) red[w - 1][q][lane] = acc[q];
+    }
+    __syncthreads();
+    if (w == 0 && i < C.Rp) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = ((acc[q] + red[0][q][lane]) + red[1][q][lane]) + red[2][q][lane];
+        double *out = fp.bpart + C.bpart + (((size_t)it.w * C.bins + f) * C.Rp + i) * 4;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) store4(out + 4 * t, acc[t], acc[4 + t], acc[8 + t], acc[12 + t]);
+    }
+}
+
+// target row i: Y = Bz^ + i Br^ (the parts summed in order), inverse DFT,
+// part[0][e] = (B_r partial, B_z partial) of the row's elements
+__global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan fp, const int *__restrict__ pub2int,
+                                                      double2 *__restrict__ part) {
+    extern __shared__ double2 xs[];
+    const int4 it = fp.items[fp.npairs + blockIdx.x];
+    const FftCoil C = fp.coils[it.x];
+    const int i = it.y;
+    const double *bp = fp.bpart + C.bpart;
+    inverse_pair(xs, C, fp, [&](int f, double &ur, double &ui, double &vr, double &vi) {
+        ur = ui = vr = vi = 0.0;
+        for (int p = 0; p < C.P; ++p) {
+            double v[4];
+            load4(bp + (((size_t)p * C.bins + f) * C.Rp + i) * 4, v);
+            ur += v[0];
+            ui += v[1];
+            vr += v[2];
+            vi += v[3];
+        }
+    });
+    const double invL = 1.0 / (double)C.L;
+    const int *pe = pub2int + C.off + (size_t)i * C.Z;
+    for (int z = threadIdx.x; z < C.Z; z += blockDim.x) {
+        const double2 F = xs[z];
+        part[pe[z]] = make_double2(-F.y * invL, F.x * invL);
+    }
+}
+
+// ------------------------------------------------------------------ transposed pass
+// target row i of the weights as one complex row wr + i wz; W^ per bin
+__global__ __launch_bounds__(256) void k_fft_rows_fwdT(FftPlan fp, const double *__restrict__ wr,
+                                                       const double *__restrict__ wz,
+                                                       const int *__restrict__ pub2int) {
+    extern __shared__ double2 xs[];
+    const int4 it = fp.items[fp.npairs + blockIdx.x];
+    const FftCoil C = fp.coils[it.x];
+    const int i = it.y;
+    const int L = C.L, logL = C.logL, Z = C.Z;
+    const int *pe = pub2int + C.off + (size_t)i * Z;
+    for (int z = threadIdx.x; z < L; z += blockDim.x) {
+        double a = 0.0, b = 0.0;
+        if (z < Z) {
+            const int e = pe[z];
+            a = wr[e];
+            b = wz[e];
+        }
+        xs[bitrev(z, logL)] = make_double2(a, b);
+    }
+    __syncthreads();
+    fft_lds(xs, L, logL, fp.tw64, fp.logLmax);
+    double *hat = fp.hat + C.hat;
+    for (int f = threadIdx.x; f < C.bins; f += blockDim.x) {
+        const double2 X = xs[f], Y = xs[(L - f) & (L - 1)];
+        store4(hat + ((size_t)f * C.Rp + i) * 4, 0.5 * (X.x + Y.x), 0.5 * (X.y - Y.y), 0.5 * (X.y + Y.y),
+               0.5 * (Y.x - X.x));
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Transposed bin products, one workgroup per (coil, bin f, kFftJ sources,
+// block of kFftI targets): out^_j = sum_i [G^_z,ij W^z_i - i S_ij W^r_i] (the
+// transpose takes conj G^).  A lane holds 4 targets' W^; per source row the
+// wave adds its 64 lanes.  TS: the stored spectra (the sums are FP64).
+template <typename TS>
+__global__ __launch_bounds__(256) void k_fft_binsT(FftPlan fp) {
+    const int4 it = fp.items[fp.npairs + fp.nrows + fp.nbins + blockIdx.x];
+    const FftCoil C = fp.coils[it.x];
+    const int f = it.y;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = it.w * kFftI + 4 * lane;
+    const double *hat = fp.hat + C.hat;
+    double wrr[4], wri[4], wzr[4], wzi[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        wrr[t] = wri[t] = wzr[t] = wzi[t] = 0.0;
+        if (i + t < C.R) {
+            double v[4];
+            load4(hat + ((size_t)f * C.Rp + i + t) * 4, v);
+            wrr[t] = v[0];
+            wri[t] = v[1];
+            wzr[t] = v[2];
+            wzi[t] = v[3];
+        }
+    }
+    constexpr int JW = kFftJ / 4;
+    const int jw0 = it.z * kFftJ + w * JW, jw1 = min(jw0 + JW, C.R);
+    const size_t plane = (size_t)C.bins * C.R * C.Rp;
+    const TS *gz = static_cast<const TS *>(fp.spec) + C.spec + (size_t)f * C.R * C.Rp + i;
+    double *out = fp.bpart + C.bpart + ((size_t)it.w * C.bins + f) * C.R * 2;
+    const bool act = i < C.Rp;
+    int j = jw0;
+    for (; j + 4 <= jw1; j += 4) {
+        double re[4], im[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            re[u] = im[u] = 0.0;
+            if (act) {
+                double g[4], sv[4];
+                load4(gz + (size_t)(j + u) * C.Rp, g);
+                load4(gz + plane + (size_t)(j + u) * C.Rp, sv);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    re[u] = fma(g[t], wzr[t], fma(sv[t], wri[t], re[u]));
+                    im[u] = fma(g[t], wzi[t], fma(-sv[t], wrr[t], im[u]));
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            re[u] = wave_sum(re[u]);
+            im[u] = wave_sum(im[u]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                out[(size_t)(j + u) * 2] = re[u];
+                out[(size_t)(j + u) * 2 + 1] = im[u];
+            }
+        }
+    }
+    for (; j < jw1; ++j) {
+        double re = 0.0, im = 0.0;
+        if (act) {
+            double g[4], sv[4];
+            load4(gz + (size_t)j * C.Rp, g);
+            load4(gz + plane + (size_t)j * C.Rp, sv);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                re = fma(g[t], wzr[t], fma(sv[t], wri[t], re));
+                im = fma(g[t], wzi[t], fma(-sv[t], wrr[t], im));
+            }
+        }
+        re = wave_sum(re);
+        im = wave_sum(im);
+        if (lane == 0) {
+            out[(size_t)j * 2] = re;
+            out[(size_t)j * 2 + 1] = im;
+        }
+    }
+}
+
+// source rows a = 2q, b = 2q + 1: Y = out^_a + i out^_b (the target blocks
+// summed in order), inverse DFT, partT[0][e] of both rows' elements
+__global__ __launch_bounds__(256) void k_fft_rows_invT(FftPlan fp, const int *__restrict__ pub2int,
+                                                       double *__restrict__ partT) {
+    extern __shared__ double2 xs[];
+    const int4 it = fp.items[blockIdx.x];
+    const FftCoil C = fp.coils[it.x];
+    const int a = 2 * it.y, b = a + 1;
+    const bool hb = b < C.R;
+    const double *bp = fp.bpart + C.bpart;
+    inverse_pair(xs, C, fp, [&](int f, double &ur, double &ui, double &vr, double &vi) {
+        ur = ui = vr = vi = 0.0;
+        for (int ib = 0; ib < C.IB; ++ib) {
+            const double *q = bp + (((size_t)ib * C.bins + f) * C.R + a) * 2;
+            ur += q[0];
+            ui += q[1];
+            if (hb) {
+                vr += q[2];
+                vi += q[3];
+            }
+        }
+    });
+    const double invL = 1.0 / (double)C.L;
+    const int *pa = pub2int + C.off + (size_t)a * C.Z;
+    for (int z = threadIdx.x; z < C.Z; z += blockDim.x) {
+        const double2 F = xs[z];
+        partT[pa[z]] = F.x * invL;
+        if (hb) partT[pa[C.Z + z]] = -F.y * invL;
+    }
+}
+
+template <typename TS>
+hipError_t field_fft(const DevState &s, const FftPlan &fp, const int *pub2int, hipStream_t st) {
+    const size_t sh = (size_t)fp.Lmax * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_rows_fwd, dim3(fp.npairs), dim3(256), sh, st, fp, s.I, pub2int);
+    hipLaunchKernelGGL(k_fft_bins<TS>, dim3(fp.nbins), dim3(256), 0, st, fp);
+    hipLaunchKernelGGL(k_fft_rows_inv, dim3(fp.nrows), dim3(256), sh, st, fp, pub2int, s.part);
+    return hipGetLastError();
+}
+
+template <typename TS>
+hipError_t fieldT_fft(const FftPlan &fp, const double *wr, const double *wz, const int *pub2int, double *partT,
+                      hipStream_t st) {
+    const size_t sh = (size_t)fp.Lmax * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_rows_fwdT, dim3(fp.nrows), dim3(256), sh, st, fp, wr, wz, pub2int);
+    hipLaunchKernelGGL(k_fft_binsT<TS>, dim3(fp.nbinsT), dim3(256), 0, st, fp);
+    hipLaunchKernelGGL(k_fft_rows_invT, dim3(fp.npairs), dim3(256), sh, st, fp, pub2int, partT);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+void fft_plan(const std::vector<CoilDev> &coils, FftHostPlan &fp) {
+    fp = FftHostPlan();
+    std::vector<int4> pairs, rows, bins, binsT;
+    auto up4 = [](size_t v) { return (v + 3) & ~size_t(3); };
+    for (size_t ci = 0; ci < coils.size(); ++ci) {
+        const CoilDev &d = coils[ci];
+        FftCoil C{};
+        C.R = d.layers * d.ne;
+        C.Z = d.turns * d.ne;
+        C.Rp = (C.R + 3) & ~3;
+        int logL = 1;
+        while ((1 << logL) < 2 * C.Z - 1) ++logL;
+        C.L = 1 << logL;
+        C.logL = logL;
+        C.bins = C.L / 2 + 1;
+        C.P = (C.R + kFftJ - 1) / kFftJ;
+        C.IB = (C.Rp + kFftI - 1) / kFftI;
+        C.off = d.off;
+        C.kscale = d.kscale;
+        C.c2d = d.c2d;
+        C.spec = fp.spec_reals;
+        fp.spec_reals += up4(2 * (size_t)C.bins * C.R * C.Rp);
+        C.hat = fp.hat_reals;
+        fp.hat_reals += up4((size_t)C.bins * C.Rp * 4);
+        C.bpart = fp.bpart_reals;
+        fp.bpart_reals += up4(std::max((size_t)C.P * C.bins * C.Rp * 4, (size_t)C.IB * C.bins * C.R * 2));
+        fp.Lmax = std::max(fp.Lmax, C.L);
+        const int nt = (C.Rp + kFftI - 1) / kFftI;
+        for (int q = 0; q < (C.R + 1) / 2; ++q) pairs.push_back(make_int4((int)ci, q, 0, 0));
+        for (int i = 0; i < C.R; ++i) rows.push_back(make_int4((int)ci, i, 0, 0));
+        for (int f = 0; f < C.bins; ++f) {
+            for (int tb = 0; tb < nt; ++tb)
+                for (int p = 0; p < C.P; ++p) bins.push_back(make_int4((int)ci, f, tb, p));
+            for (int jb = 0; jb < C.P; ++jb)
+                for (int ib = 0; ib < C.IB; ++ib) binsT.push_back(make_int4((int)ci, f, jb, ib));
+        }
+        fp.coils.push_back(C);
+    }
+    fp.logLmax = 1;
+    while ((1 << fp.logLmax) < fp.Lmax) ++fp.logLmax;
+    fp.npairs = (int)pairs.size();
+    fp.nrows = (int)rows.size();
+    fp.nbins = (int)bins.size();
+    fp.nbinsT = (int)binsT.size();
+    fp.items = pairs;
+    fp.items.insert(fp.items.end(), rows.begin(), rows.end());
+    fp.items.insert(fp.items.end(), bins.begin(), bins.end());
+    fp.items.insert(fp.items.end(), binsT.begin(), binsT.end());
+}
+
+hipError_t launch_fft_setup(const DevState &s, const FftPlan &fp, const FftCoil *hc, int ncoils, void *tmp,
+                            size_t tmp_bytes, hipStream_t st) {
+    (void)s;
+    double2 *t = static_cast<double2 *>(tmp);
+    for (int c = 0; c < ncoils; ++c) {
+        const FftCoil &C = hc[c];
+        const size_t per_row = (size_t)C.R * C.bins * sizeof(double2);
+        const int bs = (int)std::min<size_t>((size_t)C.R, tmp_bytes / per_row);
+        if (bs < 1) return hipErrorInvalidValue;
+        for (int b0 = 0; b0 < C.R; b0 += bs) {
+            const int nb = std::min(bs, C.R - b0);
+            hipLaunchKernelGGL(k_fft_spec, dim3(C.R, nb), dim3(256), (size_t)C.L * sizeof(double2), st, fp, c, b0,
+                               t);
+            const dim3 g((C.bins + 31) / 32, (C.Rp + 31) / 32, nb);
+            if (fp.prec == COIL_MIXED)
+                hipLaunchKernelGGL(k_fft_spec_store<float>, g, dim3(256), 0, st, fp, c, b0, t);
+            else
+                hipLaunchKernelGGL(k_fft_spec_store<double>, g, dim3(256), 0, st, fp, c, b0, t);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_field_fft(const DevState &s, const FftPlan &fp, const int *pub2int, hipStream_t st) {
+    return fp.prec == COIL_MIXED ? field_fft<float>(s, fp, pub2int, st) : field_fft<double>(s, fp, pub2int, st);
+}
+
+hipError_t launch_fieldT_fft(const DevState &s, const FftPlan &fp, const double *wr, const double *wz,
+                             const int *pub2int, double *partT, hipStream_t st) {
+    (void)s;
+    return fp.prec == COIL_MIXED ? fieldT_fft<float>(fp, wr, wz, pub2int, partT, st)
+                                 : fieldT_fft<double>(fp, wr, wz, pub2int, partT, st);
+}
+
+}  // namespace coilq

@@ -125,6 +125,7 @@ struct DevState {
     int max_ne2;             // largest elements-per-wire over the coils
     int tile_targets;        // field pass: targets per workgroup (= block size)
     int algo_tz;             // 1: the field partials come from the translation-reuse pass
+    int algo_fft;            // 1: the field comes from the fast-convolution pass (one slot)
     const double *Mlay;      // per layer ne2 x ne2, column-major
     const double *Minv;      // per layer inverse of Mlay, column-major
     const double *yl;        // per layer Minv * 1
@@ -168,6 +169,11 @@ struct DevState {
     double *rec_I, *rec_Br, *rec_Bz, *rec_dI;  // record I^k, B^k, dI of the step
     double *rec_T;                    // record T at the start of each heat substep [sub][N]
 };
+
+// partial-sum slots of the last field pass (and of the transposed pass) per coil
+__host__ __device__ inline int field_slots(const DevState &s, const CoilDev &c) {
+    return s.algo_fft ? 1 : s.algo_tz ? c.nslot_tz : c.nchunk;
+}
 
 // ---- launchers (coil_kernels.hip) ----
 hipError_t launch_field(const DevState &s, const RunConst &rc, int grid_limit, hipStream_t st);

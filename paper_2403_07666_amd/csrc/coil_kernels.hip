@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void k_field(DevState s, RunConst rc) {
 __device__ __forceinline__ void field_at(const DevState &s, const CoilDev &c, int e, double Ba,
                                          double &br, double &bz) {
     double xr = 0.0, xz = 0.0;
-    const int nk = s.algo_tz ? c.nslot_tz : c.nchunk;
+    const int nk = field_slots(s, c);
     // the slots are summed in order; their loads are issued 16 at a time so
     // that they are in flight together
     int k = 0;

@@ -102,3 +102,19 @@ def test_library_elliptic_approximations():
         k32, e32 = pk.host_ellip(m1, pk.MIXED)
         assert abs(k32 / ellipkm1(m1) - 1) < 3e-7
         assert abs(e32 / ellipe(1 - m1) - 1) < 3e-7
+
+
+def test_fft_algorithm_workspace():
+    """COIL_ALGO_FFT keeps per coil 2 (L/2 + 1) n_r^2 spectra reals (L the DFT
+    length, a power of two >= 2 n_z - 1) in the pass's precision, plus small
+    buffers; an unknown algorithm is refused."""
+    pk = _pk()
+    w = cs.workload("c1")  # 4 layers x 8 turns of 4 x 4: n_r = 16, n_z = 32, L = 64
+    nr, bins = 16, 33
+    for prec, rs in (("fp64", 8), ("mixed", 4)):
+        extra = pk.query(w, precision=prec, algo="fft").workspace_bytes - pk.query(w, precision=prec).workspace_bytes
+        spec = 2 * bins * nr * nr * rs
+        assert spec <= extra <= spec + 65536
+    with pytest.raises(pk.CoilError) as ei:
+        pk.query(w, algo=4)
+    assert ei.value.code == -1

@@ -44,7 +44,7 @@ def workload():
                         weak_spots=0)
 
 
-@pytest.mark.parametrize("algo", ["direct", "translation"])
+@pytest.mark.parametrize("algo", ["direct", "translation", "fft"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_active_ne64_against_oracle(prec, algo):
     pk = _pk()

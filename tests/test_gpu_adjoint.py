@@ -22,7 +22,7 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("algo", ["direct", "translation"])
+@pytest.mark.parametrize("algo", ["direct", "translation", "fft"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
 @pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 4), (3, 9, 8), (5, 7, 6), (2, 70, 8)])
 def test_field_transpose_dot_product(prec, tol, shape, algo):
@@ -78,7 +78,7 @@ def _direction(w, seed):
     return rng.standard_normal(w.n_wire), rng.standard_normal(len(w.coils)) * 10.0
 
 
-@pytest.mark.parametrize("algo", ["direct", "translation"])
+@pytest.mark.parametrize("algo", ["direct", "translation", "fft"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
 def test_adjoint_matches_oracle_tangent(prec, tol, algo):
     pk = _pk()

@@ -1,0 +1,134 @@
+"""GPU checks of the fast-convolution field pass (COIL_ALGO_FFT) beyond the
+shared parity cases (the field, run, adjoint and full-size tests are
+parametrised over it): the 16-coil ensemble at full size against the oracle
+at sampled targets, graph replay, the coupled solve on top of it, the
+autotuner's use of it, and switching away from it."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import coil_synth as cs
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _pk():
+    import paper_2403_07666_amd as pk
+    return pk
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def nerr(a, b):
+    s = np.abs(b).max()
+    return float(np.abs(a - b).max() / s) if s > 0 else float(np.abs(a).max())
+
+
+def test_fft_c4_ensemble_full_size():
+    """16 coils of uneven size (every coil its own DFT length) against the
+    oracle at sampled targets of every coil; mixed steps against FP64."""
+    pk = _pk()
+    w = cs.workload("c4")
+    inp = cs.generate(w)
+    _say("c4 fft", w.n_elem)
+    o = oracle.Sim(w, field_only=True)
+    I = cs.random_currents(w.n_elem, seed=44)
+    tg, off = [], 0
+    for i, co in enumerate(w.coils):
+        tg.extend((off + cs.sample_indices(co.n_elem, 8, seed=100 + i)).tolist())
+        off += co.n_elem
+    tg = np.array(tg)
+    obr, obz = o.field_targets(I, tg)
+    scale = max(np.abs(obr).max(), np.abs(obz).max())
+    for prec, tol in (("fp64", 1e-10), ("mixed", 1e-5)):
+        g = pk.Coil(w, inp, precision=prec, algo="fft")
+        assert g.field_stats()["algo"] == "fft"
+        g.set_state(pk.F_I, I)
+        g.compute_field()
+        e = max(np.abs(g.get(pk.F_BR)[tg] - obr).max(), np.abs(g.get(pk.F_BZ)[tg] - obz).max()) / scale
+        _say(f"  c4 fft field {prec}: {e:.2e}")
+        assert e <= tol
+        g.close()
+    runs = {}
+    for prec in ("fp64", "mixed"):
+        g = pk.Coil(w, inp, precision=prec, algo="fft")
+        g.run(3)
+        runs[prec] = (g.get(pk.F_BR), g.get(pk.F_BZ), g.get(pk.F_I))
+        g.close()
+    for a, b in zip(runs["mixed"], runs["fp64"]):
+        assert nerr(a, b) <= 1e-5
+
+
+def test_fft_graph_replay_bitwise():
+    pk = _pk()
+    w = cs.workload("c1_active")
+    inp = cs.generate(w)
+    a = pk.Coil(w, inp, precision="mixed", algo="fft")
+    b = pk.Coil(w, inp, precision="mixed", algo="fft")
+    a.run(200)
+    b.graph(10)
+    for _ in range(20):
+        b.run(10)
+        b.synchronize()
+    for f in (pk.F_I, pk.F_BR, pk.F_BZ, pk.F_T, pk.F_PHI):
+        assert np.array_equal(a.get(f), b.get(f))
+
+
+def test_fft_coupled_solve_against_oracle():
+    """The coupled A-V solve with the field from the fast-convolution pass (its
+    flux passes stay on the translation pass) against the oracle."""
+    pk = _pk()
+    w = cs.workload("c1_active").replace(coupling="full")
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision="fp64", algo="fft")
+    o = oracle.Sim(w, inp)
+    g.run(100)
+    assert o.run(100) == 0
+    e = max(nerr(g.get(pk.F_BR), o.get(oracle.BR)), nerr(g.get(pk.F_BZ), o.get(oracle.BZ)),
+            nerr(g.get(pk.F_I), o.get(oracle.I)), nerr(g.get(pk.F_T), o.get(oracle.T)))
+    _say(f"  coupled fft fp64: {e:.2e}")
+    assert e <= 1e-10
+
+
+def test_fft_autotune_and_switching(tmp_path):
+    """The autotuner times the fast convolution when it was set up at init and
+    its choice reproduces the field; a cached choice of it is refused by a
+    handle without spectra; set_tiles switches to the direct pass."""
+    pk = _pk()
+    w = cs.workload("c1_active")
+    inp = cs.generate(w)
+    I = cs.random_currents(w.n_elem, seed=5)
+    ref = pk.Coil(w, inp, precision="fp64", algo="translation")
+    ref.set_state(pk.F_I, I)
+    ref.compute_field()
+    g = pk.Coil(w, inp, precision="fp64", algo="fft")
+
+    def check(algo):
+        assert g.field_stats()["algo"] == algo
+        g.set_state(pk.F_I, I)
+        g.compute_field()
+        for f in (pk.F_BR, pk.F_BZ):
+            assert nerr(g.get(f), ref.get(f)) <= 1e-12
+
+    check("fft")
+    path = os.path.join(str(tmp_path), "tune.jsonl")
+    ch = g.autotune(reps=1, cache_path=path)
+    assert ch[0] in (1, 2, 3)
+    check({1: "direct", 2: "translation", 3: "fft"}[ch[0]])
+    g.set_tiles(64, 2, 0)
+    check("direct")
+    rec = json.loads(open(path).read().splitlines()[0])
+    rec.update({"algo": 3, "p1": 0, "p2": 0, "p3": 0})
+    with open(path, "w") as fh:
+        fh.write(json.dumps(rec) + "\n")
+    assert g.autotune(reps=1, cache_path=path) == (3, 0, 0, 0)
+    check("fft")
+    with pytest.raises(pk.CoilError):
+        ref.autotune(reps=1, cache_path=path)

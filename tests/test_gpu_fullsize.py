@@ -23,7 +23,7 @@ def _say(*a):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("algo", ["direct", "translation"])
+@pytest.mark.parametrize("algo", ["direct", "translation", "fft"])
 @pytest.mark.parametrize("name", ["c2", "c5"])
 def test_field_pass_sampled_targets(name, algo):
     pk = _pk()

@@ -27,7 +27,7 @@ def _nerr(a, b):
     return float(np.abs(np.asarray(a) - b).max() / s) if s > 0 else float(np.abs(a).max())
 
 
-@pytest.mark.parametrize("algo", ["translation", "direct"])
+@pytest.mark.parametrize("algo", ["translation", "direct", "fft"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("mixed", 1e-5)])
 def test_c2_prefix_against_oracle(prec, tol, algo):
     with open(GOLDEN) as f:

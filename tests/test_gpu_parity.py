@@ -40,7 +40,7 @@ def _coil(layers, turns, ne, **kw):
 SHAPES = [(1, 1, 1), (1, 1, 8), (2, 3, 3), (3, 5, 4), (4, 8, 4), (5, 7, 6), (3, 9, 8)]
 
 
-ALGOS = ["direct", "translation"]
+ALGOS = ["direct", "translation", "fft"]
 
 
 @pytest.mark.parametrize("algo", ALGOS)
