@@ -291,6 +291,82 @@ def coupled_leg(pk, cs, torch, steps: int = 5) -> dict:
     return out
 
 
+def fft_spectra_bytes(w, precision: str) -> int:
+    """Bytes of the fast-convolution pass's spectra (streamed once per pass):
+    per coil 2 (L/2 + 1) n_r n_r4 reals, L the power of two >= 2 n_z - 1 and
+    n_r4 the rows rounded up to 4."""
+    total = 0
+    for c in w.coils:
+        nr, nz = c.layers * c.ne, c.turns * c.ne
+        L = 2
+        while L < 2 * nz - 1:
+            L *= 2
+        total += 2 * (L // 2 + 1) * nr * ((nr + 3) // 4 * 4)
+    return total * (4 if precision == "mixed" else 8)
+
+
+def fft_leg(pk, cs, torch, steps: int = 1000) -> dict:
+    """The fast-convolution field evaluation (COIL_ALGO_FFT) on the medium coil
+    (131,072 elements) and the adjoint coil (384,000): step rate and field
+    pass against the translation-reuse pass, mixed against FP64 and FP64
+    against the FP64 translation pass on the driven variant, and the adjoint
+    over forward ratio with it.  The field pass is HBM-bound on its spectra;
+    the effective rate below counts only their bytes over the whole pass
+    (three kernels), a lower bound of the bin-product kernel's."""
+    out = {}
+    for name, n in (("c2", steps), ("c5", max(1, steps // 4))):
+        w = cs.workload(name)
+        inp = cs.generate(w)
+        rec = {"n_elem": w.n_elem, "steps": n}
+        for algo in ("fft", "translation"):
+            t0 = time.perf_counter()
+            g = pk.Coil(w, inp, precision="mixed", algo=algo)
+            torch.cuda.synchronize()
+            init = time.perf_counter() - t0
+            g.run(5)
+            m = n if algo == "fft" else max(1, n // 10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.run(m)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            g.timing(True)
+            g.run(20)
+            ph = g.timing_read()
+            g.timing(False)
+            g.close()
+            rec[algo] = {"steps_per_s": m / el, "init_s": init,
+                         "phase_ms_per_step": {k: v["ms"] / 20 for k, v in ph.items()}}
+        sb = fft_spectra_bytes(w, "mixed")
+        fms = rec["fft"]["phase_ms_per_step"]["field"]
+        rec["spectra_bytes"] = sb
+        rec["field_pass_effective_GBps"] = sb / (fms * 1e-3) / 1e9
+        rec["speedup_steps_per_s"] = rec["fft"]["steps_per_s"] / rec["translation"]["steps_per_s"]
+        log(f"[bench] fft {name}: {rec['fft']['steps_per_s']:.0f} steps/s (translation "
+            f"{rec['translation']['steps_per_s']:.0f}), field pass {fms * 1e3:.1f} us, spectra {sb / 1e6:.0f} MB "
+            f"-> {rec['field_pass_effective_GBps']:.0f} GB/s over the pass")
+        out[name] = rec
+    # validity on the driven variant: mixed against FP64 (both FFT), FP64 FFT against FP64 translation
+    w = cs.workload("c2_active")
+    inp = cs.generate(w)
+    res = {}
+    for key, prec, algo in (("mixed_fft", "mixed", "fft"), ("fp64_fft", "fp64", "fft"),
+                            ("fp64_translation", "fp64", "translation")):
+        g = pk.Coil(w, inp, precision=prec, algo=algo)
+        g.run(300)
+        res[key] = [g.get(f) for f in (pk.F_BR, pk.F_BZ, pk.F_I, pk.F_T)]
+        g.close()
+    out["driven_300_steps"] = {
+        "mixed_vs_fp64": {k: nerr(a, b) for k, a, b in zip(("Br", "Bz", "I", "T"), res["mixed_fft"], res["fp64_fft"])},
+        "fp64_vs_fp64_translation": {k: nerr(a, b) for k, a, b in zip(("Br", "Bz", "I", "T"), res["fp64_fft"],
+                                                                          res["fp64_translation"])}}
+    log(f"[bench] fft driven c2, 300 steps: mixed vs FP64 {out['driven_300_steps']['mixed_vs_fp64']}, "
+        f"FP64 vs translation {out['driven_300_steps']['fp64_vs_fp64_translation']}")
+    _, adj = _adjoint_ratio(pk, cs, torch, "c5", 200, 50, algo="fft")
+    out["adjoint_c5"] = adj
+    return out
+
+
 def cpu_baseline(w, budget_s: float = 12.0) -> dict:
     """The oracle's field sum (the O(N^2) part of a step) on a bounded sample
     of targets of the same coil, all N sources, on the host cores; scaled to
@@ -360,10 +436,10 @@ def batched_leg(pk, cs, torch, steps: int = 50, warmup: int = 3, graph: int = 10
     return out
 
 
-def _adjoint_ratio(pk, cs, torch, name: str, steps: int, ckpt: int):
+def _adjoint_ratio(pk, cs, torch, name: str, steps: int, ckpt: int, algo: str = "auto"):
     w = cs.workload(name)
     inp = cs.generate(w)
-    g = pk.Coil(w, inp, precision="mixed")
+    g = pk.Coil(w, inp, precision="mixed", algo=algo)
     g.run(2)
     g.reset()
     torch.cuda.synchronize()
@@ -377,8 +453,8 @@ def _adjoint_ratio(pk, cs, torch, name: str, steps: int, ckpt: int):
     torch.cuda.synchronize()
     adj = time.perf_counter() - t0
     g.close()
-    log(f"[bench] adjoint/forward at {w.n_elem} elements ({name}), {steps} steps: {adj:.2f} s / {fwd:.2f} s = "
-        f"{adj / fwd:.2f} (max |J|/Jc {maxx:.2f})")
+    log(f"[bench] adjoint/forward at {w.n_elem} elements ({name}, {algo}), {steps} steps: {adj:.2f} s / "
+        f"{fwd:.2f} s = {adj / fwd:.2f} (max |J|/Jc {maxx:.2f})")
     return w, {"workload": w.name, "steps": steps, "forward_s": fwd, "adjoint_s": adj,
                "adjoint_over_forward": adj / fwd, "max_J_over_Jc_last_step": maxx, "objectives": list(obj)}
 
@@ -492,7 +568,7 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 validity run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--graph", type=int, default=0, help="capture the step loop in HIP graphs of this many steps")
-    ap.add_argument("--algo", default="auto", choices=["auto", "direct", "translation"],
+    ap.add_argument("--algo", default="auto", choices=["auto", "direct", "translation", "fft"],
                     help="field-pass evaluation (both compute the same all-pairs sum)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 16-coil ensemble leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward leg")
@@ -500,6 +576,7 @@ def main():
     ap.add_argument("--no-adi", action="store_true", help="skip the composite (ADI heat step) leg")
     ap.add_argument("--no-coupled", action="store_true", help="skip the fully coupled induction leg")
     ap.add_argument("--no-subelements", action="store_true", help="skip the subelement-model leg")
+    ap.add_argument("--no-fft", action="store_true", help="skip the fast-convolution field-pass leg")
     ap.add_argument("--adjoint-steps", type=int, default=200,
                     help="horizon of the adjoint/forward timing at 384,000 elements")
     ap.add_argument("--c5-full", action="store_true",
@@ -586,7 +663,17 @@ def main():
     pairs = w.pairs_per_pass()
     fs = field_stats
     roofline = None
-    if tm is not None and tm["field"]["launches"] > 0:
+    if tm is not None and tm["field"]["launches"] > 0 and fs["algo"] == "fft":
+        # the fast convolution streams its spectra once per pass: HBM-bound;
+        # the events bracket the whole pass (row DFTs and bin products)
+        avg_ms = tm["field"]["ms"] / tm["field"]["launches"]
+        sb = fft_spectra_bytes(w, args.precision)
+        achieved = sb / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": "k_fft_rows_fwd + k_fft_bins + k_fft_rows_inv (fast-convolution "
+                    "field pass; the bytes are k_fft_bins' spectra)", "achieved": achieved, "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_launch_ms": avg_ms,
+                    "bytes_per_launch": sb, "phase_ms_per_step": phases}
+    elif tm is not None and tm["field"]["launches"] > 0:
         avg_ms = tm["field"]["ms"] / tm["field"]["launches"]
         flop = FLOP_PER_EVAL * fs["kernel_evals"] + FLOP_PER_PAIR_ACC * fs["pairs"]
         achieved = flop / (avg_ms * 1e-3) / 1e12
@@ -635,6 +722,9 @@ def main():
     subel = None
     if not args.no_subelements:
         subel = subelement_leg(pk, cs, torch)
+    fft = None
+    if not args.no_fft:
+        fft = fft_leg(pk, cs, torch)
 
     cpu = None
     if not args.no_cpu:
@@ -683,6 +773,7 @@ def main():
         "composite_adi": adi,
         "coupled_induction": coupled,
         "subelements": subel,
+        "fft_field_pass": fft,
     }
     print(json.dumps(out))
 

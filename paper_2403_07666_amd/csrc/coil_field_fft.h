@@ -27,8 +27,8 @@
 namespace coilq {
 
 constexpr int kFftMaxLog = 12;    // L <= 4096 (n_z <= 2048)
-constexpr int kFftJ = 128;        // bin products: source rows per workgroup (32 per wave)
-constexpr int kFftI = 256;        // bin products: target rows per workgroup (4 per lane)
+constexpr int kFftJ = 256;        // bin products: source rows per workgroup (64 per wave)
+constexpr int kFftI = 256;        // bin products: target rows per workgroup (4 per lane, 64 lanes)
 
 struct FftCoil {
     int R, Rp, Z, L, logL, bins;  // rows, rows padded to 4, row length, DFT length, log2 L, L/2 + 1

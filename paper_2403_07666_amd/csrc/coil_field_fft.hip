@@ -26,17 +26,19 @@ namespace coilq {
 
 namespace {
 
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
 // 4 consecutive reals as doubles (16-byte aligned for float, 32 for double)
 __device__ __forceinline__ void load4(const float *p, double (&v)[4]) {
-    const float4 q = *reinterpret_cast<const float4 *>(p);
+    const f4v q = *reinterpret_cast<const f4v *>(p);
     v[0] = q.x;
     v[1] = q.y;
     v[2] = q.z;
     v[3] = q.w;
 }
 __device__ __forceinline__ void load4(const double *p, double (&v)[4]) {
-    const double2 a = reinterpret_cast<const double2 *>(p)[0];
-    const double2 b = reinterpret_cast<const double2 *>(p)[1];
+    const d2v a = reinterpret_cast<const d2v *>(p)[0];
+    const d2v b = reinterpret_cast<const d2v *>(p)[1];
     v[0] = a.x;
     v[1] = a.y;
     v[2] = b.x;
@@ -53,24 +55,50 @@ __device__ __forceinline__ int bitrev(int m, int logL) {
 
 // In-place DFT X[f] = sum_m x[m] exp(-2 pi i f m / L) of the L values in a[]
 // (LDS), stored by the caller in bit-reversed order (then a barrier); the
-// result is in natural order, followed by a barrier.  Stage s combines pairs
-// half = 2^(s-1) apart with the twiddle exp(-2 pi i pos / 2^s), read from the
-// table of exp(-2 pi i k / Lmax) at k = pos Lmax / 2^s.
+// result is in natural order, followed by a barrier.  Radix-2 stage s
+// combines pairs half = 2^(s-1) apart with the twiddle W_{2 half}^pos =
+// exp(-2 pi i pos / 2^s), read from the table of exp(-2 pi i k / Lmax) at
+// k = pos Lmax / 2^s.  Two stages at a time (radix 2^2): a thread takes the
+// four values pos + {0, 1, 2, 3} half of a group of 4 half, applies stage s to
+// the pairs (0, 1), (2, 3) and stage s + 1 to (0, 2) with W_{4 half}^pos and
+// (1, 3) with W_{4 half}^(pos + half) = -i W_{4 half}^pos, in registers; one
+// LDS round trip and barrier per two stages, a last radix-2 stage if log2 L
+// is odd.
+__device__ __forceinline__ double2 cmul(double2 w, double2 v) {
+    return make_double2(w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x);
+}
+
 __device__ void fft_lds(double2 *a, int L, int logL, const double2 *__restrict__ tw, int logLmax) {
-    const int nb = L >> 1;
-    for (int s = 1; s <= logL; ++s) {
+    int s = 1;
+    for (; s + 1 <= logL; s += 2) {
         const int half = 1 << (s - 1);
-        const int sh = logLmax - s;
-        for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+        for (int k = threadIdx.x; k < (L >> 2); k += blockDim.x) {
+            const int pos = k & (half - 1);
+            const int i0 = ((k >> (s - 1)) << (s + 1)) | pos;
+            const double2 a0 = a[i0], a1 = a[i0 + half], a2 = a[i0 + 2 * half], a3 = a[i0 + 3 * half];
+            const double2 w1 = tw[pos << (logLmax - s)];
+            const double2 w2 = tw[pos << (logLmax - s - 1)];
+            const double2 t1 = cmul(w1, a1), t3 = cmul(w1, a3);
+            const double2 b0 = make_double2(a0.x + t1.x, a0.y + t1.y), b1 = make_double2(a0.x - t1.x, a0.y - t1.y);
+            const double2 b2 = make_double2(a2.x + t3.x, a2.y + t3.y), b3 = make_double2(a2.x - t3.x, a2.y - t3.y);
+            const double2 u = cmul(w2, b2), v0 = cmul(w2, b3);
+            const double2 v = make_double2(v0.y, -v0.x);  // -i w2 b3
+            a[i0] = make_double2(b0.x + u.x, b0.y + u.y);
+            a[i0 + 2 * half] = make_double2(b0.x - u.x, b0.y - u.y);
+            a[i0 + half] = make_double2(b1.x + v.x, b1.y + v.y);
+            a[i0 + 3 * half] = make_double2(b1.x - v.x, b1.y - v.y);
+        }
+        __syncthreads();
+    }
+    if (s == logL) {
+        const int half = 1 << (s - 1);
+        for (int k = threadIdx.x; k < (L >> 1); k += blockDim.x) {
             const int pos = k & (half - 1);
             const int i0 = ((k >> (s - 1)) << s) | pos;
-            const int i1 = i0 + half;
-            const double2 w = tw[pos << sh];
-            const double2 u = a[i0], v = a[i1];
-            const double tr = w.x * v.x - w.y * v.y;
-            const double ti = w.x * v.y + w.y * v.x;
-            a[i0] = make_double2(u.x + tr, u.y + ti);
-            a[i1] = make_double2(u.x - tr, u.y - ti);
+            const double2 t = cmul(tw[pos << (logLmax - s)], a[i0 + half]);
+            const double2 u = a[i0];
+            a[i0] = make_double2(u.x + t.x, u.y + t.y);
+            a[i0 + half] = make_double2(u.x - t.x, u.y - t.y);
         }
         __syncthreads();
     }
