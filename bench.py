@@ -264,30 +264,38 @@ def coupled_leg(pk, cs, torch, steps: int = 5) -> dict:
     """The fully coupled inter-wire induction on the medium coil (131,072
     elements, driven variant, mixed field pass): per-step wall time, CG
     iterations to a relative residual of 1e-10, and the time of the coupled
-    solve (wire phase) against the field pass."""
+    solve (wire phase) against the field pass; with the translation-reuse
+    passes (the default) and with the fast-convolution ones (field and flux)."""
     w = cs.workload("c2_active").replace(coupling="full")
     inp = cs.generate(w)
-    g = pk.Coil(w, inp, precision="mixed", cg_tol=1e-10, cg_max_iter=200)
-    g.run(2)
-    g.timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    g.run(steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ph = g.timing_read()
-    g.timing(False)
-    sc = g.scalars()
-    g.close()
-    out = {"workload": w.name + "_coupled", "n_elem": w.n_elem, "steps": steps, "ms_per_step": 1e3 * el / steps,
-           "cg_iters_last_step": int(sc["cg_iters"]), "cg_residual_last_step": sc["cg_residual"],
-           "phase_ms_per_step": {k: v["ms"] / steps for k, v in ph.items()}}
-    # each CG iteration is one FP64 all-pairs flux pass plus per-wire solves
-    # and two global reductions: its time against the mixed field pass's
-    it = max(1, out["cg_iters_last_step"])
-    out["ms_per_cg_iteration"] = out["phase_ms_per_step"]["wire"] / it
-    log(f"[bench] {out['workload']}: {out['ms_per_step']:.1f} ms/step, {out['cg_iters_last_step']} CG iterations "
-        f"({out['ms_per_cg_iteration']:.2f} ms each, field pass {out['phase_ms_per_step']['field']:.2f} ms)")
+    out = {"workload": w.name + "_coupled", "n_elem": w.n_elem, "steps": steps}
+    for algo in ("auto", "fft"):
+        g = pk.Coil(w, inp, precision="mixed", cg_tol=1e-10, cg_max_iter=200, algo=algo)
+        g.run(2)
+        g.timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.run(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ph = g.timing_read()
+        g.timing(False)
+        sc = g.scalars()
+        g.close()
+        rec = {"ms_per_step": 1e3 * el / steps, "cg_iters_last_step": int(sc["cg_iters"]),
+               "cg_residual_last_step": sc["cg_residual"],
+               "phase_ms_per_step": {k: v["ms"] / steps for k, v in ph.items()}}
+        # each CG iteration is one FP64 all-pairs flux pass plus per-wire solves
+        # and two global reductions: its time against the mixed field pass's
+        it = max(1, rec["cg_iters_last_step"])
+        rec["ms_per_cg_iteration"] = rec["phase_ms_per_step"]["wire"] / it
+        log(f"[bench] {out['workload']} ({algo}): {rec['ms_per_step']:.1f} ms/step, {rec['cg_iters_last_step']} CG "
+            f"iterations ({rec['ms_per_cg_iteration']:.3f} ms each, field pass "
+            f"{rec['phase_ms_per_step']['field']:.3f} ms)")
+        if algo == "auto":
+            out.update(rec)
+        else:
+            out["fft"] = rec
     return out
 
 

@@ -156,7 +156,10 @@ enum coil_heat { COIL_HEAT_EXPLICIT = 0, COIL_HEAT_ADI = 1 };
    4 n_r^2 n_z for n_z a power of two (1.9 GB for 480 x 800 in FP32).  A pass
    transforms the source rows, streams the matrices once and transforms the
    target rows back.  Only selectable at coil_init (the autotuner then also
-   times it); the coupled solve's flux passes stay on TRANSLATION. */
+   times it).  With COIL_COUPLE_FULL the coupled solve's flux passes use the
+   same scheme with the mutual-inductance kernel's spectra (one real matrix
+   per bin, FP64: (L/2 + 1) n_r^2 more reals); otherwise they are
+   TRANSLATION passes. */
 enum coil_algo { COIL_ALGO_AUTO = 0, COIL_ALGO_DIRECT = 1, COIL_ALGO_TRANSLATION = 2, COIL_ALGO_FFT = 3 };
 
 /* fields for coil_get / coil_set_state */

@@ -84,7 +84,7 @@ struct Plan {
         perm_b, wire_coil_b, fastw_b, elem_coil_b, Mlay_b, Minv_b, yl_b, syl_b, wflag_b, cw_b, I_b, Phi_b, Br_b, Bz_b, E_b, Ep_b, dI_b,
         q_b, Jc_b, u_b[3], T_b[3], part_b, Uw_b, Qw_b, wq_b, wmaxx_b, hb_max_b, hb_arg_b, hb_out_b,
         sc_b, tmp_b, misc_b, diag_b, hrow_b, Lself_b, cgv_b, cgL_b, cgred_b, cgrw_b, cgsc_b, adi_b, kmult_b, IH_b, emsub_b, tz_b, tzrows_b, Ipub_b, pub2int_b, zphys_b, near_pair_b, near_val_b, ticket_b,
-        Ipub32_b, fftspec_b, ffthat_b, fftbp_b, fftitems_b, fftcoils_b, ffttw64_b;
+        Ipub32_b, fftspec_b, ffthat_b, fftbp_b, fftitems_b, fftcoils_b, ffttw64_b, fftflux_b;
 };
 
 Buf carve(size_t &cur, size_t bytes) {
@@ -481,7 +481,7 @@ int make_plan(const coil_config *c, Plan &p) {
     if (c->algo == COIL_ALGO_FFT) {
         p.algo = COIL_ALGO_FFT;
         p.fft = 1;
-        fft_plan(p.coils, p.fftp);
+        fft_plan(p.coils, p.coupled, p.fftp);
     }
     return COIL_OK;
 }
@@ -601,6 +601,7 @@ size_t layout(Plan &p) {
         p.ffthat_b = carve(cur, d8 * p.fftp.hat_reals);
         p.fftbp_b = carve(cur, d8 * p.fftp.bpart_reals);
         p.fftitems_b = carve(cur, sizeof(int4) * p.fftp.items.size());
+        p.fftflux_b = carve(cur, d8 * std::max<size_t>(1, p.fftp.flux_reals));
         p.fftcoils_b = carve(cur, sizeof(FftCoil) * p.fftp.coils.size());
         p.ffttw64_b = carve(cur, sizeof(double2) * (p.fftp.Lmax / 2));
     }
@@ -733,9 +734,9 @@ hipError_t launch_field_any(coil_t *h, const DevState &d, hipStream_t st) {
 // and those after convergence return at once.
 int coupled_solve(coil_t *h) {
     const DevState &d = h->ds;
-    HIPCHECK(launch_cg_begin(d, h->rc, h->tz, h->Ipub, h->d_pub2int, h->cg_tol, h->cg_maxit, h->stream));
+    HIPCHECK(launch_cg_begin(d, h->rc, h->tz, h->fft, h->Ipub, h->d_pub2int, h->cg_tol, h->cg_maxit, h->stream));
     for (int it = 0; it < h->cg_maxit; ++it) {
-        HIPCHECK(launch_cg_iteration(d, h->rc, h->tz, h->Ipub, h->d_pub2int, h->stream));
+        HIPCHECK(launch_cg_iteration(d, h->rc, h->tz, h->fft, h->Ipub, h->d_pub2int, h->stream));
         if (!h->capturing && (it + 1) % h->cg_check == 0 && it + 1 < h->cg_maxit) {
             int done = 0;
             HIPCHECK(hipMemcpyAsync(&done, &d.cg->done, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1117,6 +1118,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
     s.tile_targets = p.tile_targets;
     s.algo_tz = p.algo == COIL_ALGO_TRANSLATION ? 1 : 0;
     s.algo_fft = p.algo == COIL_ALGO_FFT ? 1 : 0;
+    s.flux_fft = p.fft && p.fftp.flux ? 1 : 0;
     if (p.fft) {
         FftPlan &f = h->fft;
         f.coils = at<FftCoil>(h, p.fftcoils_b);
@@ -1129,6 +1131,7 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
         f.logLmax = p.fftp.logLmax;
         f.prec = p.prec;
         f.spec = at<char>(h, p.fftspec_b);
+        f.fspec = p.fftp.flux ? at<double>(h, p.fftflux_b) : nullptr;
         f.hat = at<double>(h, p.ffthat_b);
         f.bpart = at<double>(h, p.fftbp_b);
         f.tw64 = at<double2>(h, p.ffttw64_b);

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_cg_av(DevState s, RunConst rc, int mode
     double pq = 0.0;
     if (e < s.N) {
         const CoilDev c = s.coils[s.elem_coil[e]];
-        const int nk = c.nslot_tz;
+        const int nk = s.flux_fft ? 1 : c.nslot_tz;
         double off = 0.0;
         for (int k = 0; k < nk; ++k) off += s.part[(size_t)k * s.N + e].y;
         const double re = s.r[e];
@@ -253,12 +253,13 @@ __global__ void k_cg_reset(CgScalars *g, double tol2, int maxit) {
 
 static inline int blocks256(int n) { return (n + 255) / 256; }
 
-hipError_t launch_cg_begin(const DevState &s, const RunConst &rc, const TzPlan &tp, double *vpub, const int *pub2int,
-                           double tol, int maxit, hipStream_t st) {
+hipError_t launch_cg_begin(const DevState &s, const RunConst &rc, const TzPlan &tp, const FftPlan &fp, double *vpub,
+                           const int *pub2int, double tol, int maxit, hipStream_t st) {
     const size_t lds = sizeof(double) * (size_t)packed_size(s.max_ne2);
     hipLaunchKernelGGL(k_cg_reset, dim3(1), dim3(64), 0, st, s.cg, tol * tol, maxit);
     hipLaunchKernelGGL(k_cg_prep, dim3(blocks256(s.N)), dim3(256), 0, st, s, (const double *)s.dI, vpub, tp.ticket, 0);
-    hipError_t e = launch_flux_tz(s, rc, tp, vpub, pub2int, &s.cg->done, st);
+    hipError_t e = s.flux_fft ? launch_flux_fft(s, fp, s.dI, pub2int, &s.cg->done, st)
+                              : launch_flux_tz(s, rc, tp, vpub, pub2int, &s.cg->done, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cg_av, dim3(blocks256(s.N)), dim3(256), 0, st, s, rc, 0);
     hipLaunchKernelGGL(k_cg_wire, dim3(s.Nw), dim3(64), lds, st, s, rc, 0);
@@ -266,12 +267,14 @@ hipError_t launch_cg_begin(const DevState &s, const RunConst &rc, const TzPlan &
     return hipGetLastError();
 }
 
-hipError_t launch_cg_iteration(const DevState &s, const RunConst &rc, const TzPlan &tp, double *vpub,
-                               const int *pub2int, hipStream_t st) {
+hipError_t launch_cg_iteration(const DevState &s, const RunConst &rc, const TzPlan &tp, const FftPlan &fp,
+                               double *vpub, const int *pub2int, hipStream_t st) {
     const size_t lds = sizeof(double) * (size_t)packed_size(s.max_ne2);
     hipLaunchKernelGGL(k_cg_prep, dim3(blocks256(s.N)), dim3(256), 0, st, s, (const double *)nullptr, vpub, tp.ticket,
                        1);
-    hipError_t e = launch_flux_tz(s, rc, tp, vpub, pub2int, &s.cg->done, st);
+    // the new direction p (k_cg_prep) in internal order for the fast convolution
+    hipError_t e = s.flux_fft ? launch_flux_fft(s, fp, s.cg_p, pub2int, &s.cg->done, st)
+                              : launch_flux_tz(s, rc, tp, vpub, pub2int, &s.cg->done, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_cg_av, dim3(blocks256(s.N)), dim3(256), 0, st, s, rc, 1);
     hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, s, blocks256(s.N));

@@ -37,8 +37,10 @@ struct FftCoil {
     int off;                      // first element of the coil
     int pad;
     double kscale;                // mu0 / (2 pi d)
+    double kflux;                 // mu0 d: the flux kernel's scale
     double c2d;                   // 2 r_inner / d + 1 (grid units)
     size_t spec;   // offset (reals) of the coil's G^_z; S follows after bins R Rp
+    size_t fspec;  // offset (FP64 reals) of its flux spectra M^[f][j][i] (coupled solve)
     size_t hat;    // offset (reals) of its transformed rows: bins Rp 4 reals
     size_t bpart;  // offset (reals) of its partial bin products
 };
@@ -50,6 +52,7 @@ struct FftPlan {
     int Lmax, logLmax;
     int prec;           // COIL_MIXED: spectra stored in FP32; COIL_FP64: in FP64
     void *spec;
+    double *fspec;      // flux spectra (FP64; null unless the coupled solve uses this pass)
     double *hat, *bpart;
     const double2 *tw64;  // exp(-2 pi i k / Lmax), k < Lmax / 2
 };
@@ -60,11 +63,14 @@ struct FftHostPlan {
     std::vector<int4> items;
     int npairs = 0, nrows = 0, nbins = 0, nbinsT = 0;
     int Lmax = 2, logLmax = 1;
+    int flux = 0;  // also the flux kernel's spectra
     size_t spec_reals = 0, hat_reals = 0, bpart_reals = 0;  // spectra in their precision, others FP64
+    size_t flux_reals = 0;
 };
 
-// the plan for coils of (layers * ne) x (turns * ne) grids
-void fft_plan(const std::vector<CoilDev> &coils, FftHostPlan &fp);
+// the plan for coils of (layers * ne) x (turns * ne) grids (flux: also the
+// spectra of the mutual-inductance kernel, for the coupled solve)
+void fft_plan(const std::vector<CoilDev> &coils, int flux, FftHostPlan &fp);
 
 // the spectra of every coil (FP64 DFT of the FP64 kernel values), stored in
 // the pass's precision; tmp: staging of tmp_bytes bytes (a slab of source rows)
@@ -73,6 +79,12 @@ hipError_t launch_fft_setup(const DevState &s, const FftPlan &fp, const FftCoil 
 
 // forward pass: part[0][e] = (sum g_r I, sum g_z I) with I = kscale * s.I
 hipError_t launch_field_fft(const DevState &s, const FftPlan &fp, const int *pub2int, hipStream_t st);
+
+// flux pass of the coupled solve: part[0][e] = (0, sum_j M(e, j) v_j) with M
+// the mutual inductance of the rings of e and j (none for j = e), v in
+// internal order; every kernel returns at once when *done != 0
+hipError_t launch_flux_fft(const DevState &s, const FftPlan &fp, const double *v, const int *pub2int,
+                           const int *done, hipStream_t st);
 
 // transposed pass: partT[0][j] = sum_e [ wr_e g_r(e, j) + wz_e g_z(e, j) ]
 hipError_t launch_fieldT_fft(const DevState &s, const FftPlan &fp, const double *wr, const double *wz,

@@ -122,11 +122,28 @@ __device__ __forceinline__ void inverse_pair(double2 *a, const FftCoil &C, const
 }
 
 // ------------------------------------------------------------------ set-up
+// Mutual inductance of two coaxial rings over mu0 d (Maxwell's formula with
+// the modulus m1 = al^2 / be^2 of the field kernel, grid units), zero for the
+// element's own ring; even in dz.
+__device__ __forceinline__ double flux_kernel(double dr, double dz, double sr) {
+    const double dz2 = dz * dz;
+    const double al2 = fma(dr, dr, dz2);
+    const double be2 = fma(sr, sr, dz2);
+    if (!(al2 > 0.0)) return 0.0;
+    const double rb = rsqrt(be2);
+    const double m1 = al2 * (rb * rb);
+    const double L = -log(m1);
+    const double K = fma(ellipk64_Q(m1), L, ellipk64_P(m1));
+    const double E = fma(ellipe64_Q(m1), L, ellipe64_P(m1));
+    return sqrt(be2) * fma(0.5 * (1.0 + m1), K, -E);
+}
+
 // One workgroup per (target row a, source row b of the slab): the FP64 kernel
 // values g(a - b, delta) for delta = 0 .. Z-1, placed at m = delta and (their
 // mirrors: g_z even, g_r odd) at m = L - delta as x = g_z + i g_r, the DFT,
 // and per bin G^_z = (X[f] + X[L-f]) / 2, S = (X[L-f] - X[f]) / 2 (real parts).
-__global__ __launch_bounds__(256) void k_fft_spec(FftPlan fp, int coil, int b0, double2 *tmp) {
+// kind 1: the flux kernel (even, real spectrum M^ = Re X[f]) in the first place.
+__global__ __launch_bounds__(256) void k_fft_spec(FftPlan fp, int coil, int b0, double2 *tmp, int kind) {
     extern __shared__ double2 xs[];
     const FftCoil C = fp.coils[coil];
     const int a = blockIdx.x, bl = blockIdx.y, b = b0 + bl;
@@ -136,7 +153,10 @@ __global__ __launch_bounds__(256) void k_fft_spec(FftPlan fp, int coil, int b0, 
     const double dr = (double)(a - b), sr = C.c2d + (double)(a + b);
     for (int d = threadIdx.x; d < C.Z; d += blockDim.x) {
         double gr = 0.0, gz = 0.0;
-        pair64(dr, (double)d, sr, 1.0, gr, gz);  // zero for the element's own ring
+        if (kind == 1)
+            gz = flux_kernel(dr, (double)d, sr);
+        else
+            pair64(dr, (double)d, sr, 1.0, gr, gz);  // zero for the element's own ring
         xs[bitrev(d, logL)] = make_double2(gz, gr);
         if (d > 0) xs[bitrev(L - d, logL)] = make_double2(gz, -gr);
     }
@@ -149,9 +169,11 @@ __global__ __launch_bounds__(256) void k_fft_spec(FftPlan fp, int coil, int b0, 
     }
 }
 
-// the slab's spectra from [b][a][f] to [f][b][a] (a < Rp; zeros past R), as T
+// the slab's spectra from [b][a][f] to [f][b][a] (a < Rp; zeros past R), as T,
+// into dst + off: the first place, and the second a plane (bins R Rp) later if planes = 2
 template <typename T>
-__global__ __launch_bounds__(256) void k_fft_spec_store(FftPlan fp, int coil, int b0, const double2 *tmp) {
+__global__ __launch_bounds__(256) void k_fft_spec_store(FftPlan fp, int coil, int b0, const double2 *tmp, T *dst,
+                                                        int planes) {
     __shared__ double2 tile[32][33];
     const FftCoil C = fp.coils[coil];
     const int f0 = blockIdx.x * 32, a0 = blockIdx.y * 32, bl = blockIdx.z, b = b0 + bl;
@@ -162,7 +184,7 @@ __global__ __launch_bounds__(256) void k_fft_spec_store(FftPlan fp, int coil, in
             (a < C.R && f < C.bins) ? tmp[((size_t)bl * C.R + a) * C.bins + f] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    T *gz = static_cast<T *>(fp.spec) + C.spec;
+    T *gz = dst;
     T *gs = gz + (size_t)C.bins * C.R * C.Rp;
     for (int k = 0; k < 32; k += 8) {
         const int f = f0 + ty + k, a = a0 + tx;
@@ -170,19 +192,23 @@ __global__ __launch_bounds__(256) void k_fft_spec_store(FftPlan fp, int coil, in
             const double2 v = tile[tx][ty + k];
             const size_t o = ((size_t)f * C.R + b) * C.Rp + a;
             gz[o] = (T)v.x;
-            gs[o] = (T)v.y;
+            if (planes == 2) gs[o] = (T)v.y;
         }
     }
 }
 
 // ------------------------------------------------------------------ forward pass
-// source rows a = 2q, b = 2q + 1 as one complex row kscale (I_a + i I_b),
-// zero-padded to L; I^_a = (X[f] + conj X[L-f]) / 2, I^_b = (X[f] - conj X[L-f]) / 2i
+// source rows a = 2q, b = 2q + 1 as one complex row k (I_a + i I_b) (k the
+// field's kscale, or the flux kernel's mu0 d), zero-padded to L;
+// I^_a = (X[f] + conj X[L-f]) / 2, I^_b = (X[f] - conj X[L-f]) / 2i
 __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan fp, const double *__restrict__ I,
-                                                      const int *__restrict__ pub2int) {
+                                                      const int *__restrict__ pub2int, int kind,
+                                                      const int *__restrict__ done) {
     extern __shared__ double2 xs[];
+    if (done && *done) return;
     const int4 it = fp.items[blockIdx.x];
     const FftCoil C = fp.coils[it.x];
+    const double k = kind == 1 ? C.kflux : C.kscale;
     const int a = 2 * it.y, b = a + 1;
     const int L = C.L, logL = C.logL, Z = C.Z;
     const bool hb = b < C.R;
@@ -190,8 +216,8 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan fp, const double *
     for (int z = threadIdx.x; z < L; z += blockDim.x) {
         double va = 0.0, vb = 0.0;
         if (z < Z) {
-            va = C.kscale * I[pa[z]];
-            if (hb) vb = C.kscale * I[pa[Z + z]];
+            va = k * I[pa[z]];
+            if (hb) vb = k * I[pa[Z + z]];
         }
         xs[bitrev(z, logL)] = make_double2(va, vb);
     }
@@ -214,11 +240,13 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan fp, const double *
 // kFftJ sources): Bz^_i = sum_j G^_z,ij I^_j, Br^_i = i sum_j S_ij I^_j.  A lane
 // owns 4 consecutive targets (one 16/32-byte load per matrix and source row),
 // the four waves split the part's sources and add in LDS in a fixed order.
-// TS: the stored spectra (the sums are FP64).
-template <typename TS>
-__global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp) {
+// TS: the stored spectra (the sums are FP64).  FLUX: the one real matrix M^ of
+// the flux kernel (FP64) in place of (G^_z, S), its product in the B_z places.
+template <typename TS, int FLUX>
+__global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp, const int *__restrict__ done) {
     __shared__ double2 sI[kFftJ];
     __shared__ double red[3][16][65];
+    if (done && *done) return;
     const int4 it = fp.items[fp.npairs + fp.nrows + blockIdx.x];
     const FftCoil C = fp.coils[it.x];
     const int f = it.y, j0 = it.w * kFftJ;
@@ -236,7 +264,20 @@ __global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp) {
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
     constexpr int JW = kFftJ / 4;
     const int jw0 = w * JW, jw1 = min(jw0 + JW, jn);
-    if (i < C.Rp) {
+    if (i < C.Rp && FLUX) {
+        const double *gm = fp.fspec + C.fspec + ((size_t)f * C.R + j0) * C.Rp + i;
+#pragma unroll 8
+        for (int j = jw0; j < jw1; ++j) {
+            double g[4];
+            load4(gm + (size_t)j * C.Rp, g);
+            const double2 x = sI[j];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                acc[t] = fma(g[t], x.x, acc[t]);
+                acc[4 + t] = fma(g[t], x.y, acc[4 + t]);
+            }
+        }
+    } else if (i < C.Rp) {
         const size_t plane = (size_t)C.bins * C.R * C.Rp;
         const TS *gz = static_cast<const TS *>(fp.spec) + C.spec + ((size_t)f * C.R + j0) * C.Rp + i;
 #pragma unroll 8
@@ -269,10 +310,13 @@ __global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp) {
 }
 
 // target row i: Y = Bz^ + i Br^ (the parts summed in order), inverse DFT,
-// part[0][e] = (B_r partial, B_z partial) of the row's elements
+// part[0][e] = (B_r partial, B_z partial) of the row's elements; kind 1 (the
+// flux pass): (0, flux)
 __global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan fp, const int *__restrict__ pub2int,
-                                                      double2 *__restrict__ part) {
+                                                      double2 *__restrict__ part, int kind,
+                                                      const int *__restrict__ done) {
     extern __shared__ double2 xs[];
+    if (done && *done) return;
     const int4 it = fp.items[fp.npairs + blockIdx.x];
     const FftCoil C = fp.coils[it.x];
     const int i = it.y;
@@ -292,7 +336,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan fp, const int *__r
     const int *pe = pub2int + C.off + (size_t)i * C.Z;
     for (int z = threadIdx.x; z < C.Z; z += blockDim.x) {
         const double2 F = xs[z];
-        part[pe[z]] = make_double2(-F.y * invL, F.x * invL);
+        part[pe[z]] = make_double2(kind == 1 ? 0.0 : -F.y * invL, F.x * invL);
     }
 }
 
@@ -448,9 +492,10 @@ __global__ __launch_bounds__(256) void k_fft_rows_invT(FftPlan fp, const int *__
 template <typename TS>
 hipError_t field_fft(const DevState &s, const FftPlan &fp, const int *pub2int, hipStream_t st) {
     const size_t sh = (size_t)fp.Lmax * sizeof(double2);
-    hipLaunchKernelGGL(k_fft_rows_fwd, dim3(fp.npairs), dim3(256), sh, st, fp, s.I, pub2int);
-    hipLaunchKernelGGL(k_fft_bins<TS>, dim3(fp.nbins), dim3(256), 0, st, fp);
-    hipLaunchKernelGGL(k_fft_rows_inv, dim3(fp.nrows), dim3(256), sh, st, fp, pub2int, s.part);
+    const int *none = nullptr;
+    hipLaunchKernelGGL(k_fft_rows_fwd, dim3(fp.npairs), dim3(256), sh, st, fp, s.I, pub2int, 0, none);
+    hipLaunchKernelGGL((k_fft_bins<TS, 0>), dim3(fp.nbins), dim3(256), 0, st, fp, none);
+    hipLaunchKernelGGL(k_fft_rows_inv, dim3(fp.nrows), dim3(256), sh, st, fp, pub2int, s.part, 0, none);
     return hipGetLastError();
 }
 
@@ -466,8 +511,9 @@ hipError_t fieldT_fft(const FftPlan &fp, const double *wr, const double *wz, con
 
 }  // namespace
 
-void fft_plan(const std::vector<CoilDev> &coils, FftHostPlan &fp) {
+void fft_plan(const std::vector<CoilDev> &coils, int flux, FftHostPlan &fp) {
     fp = FftHostPlan();
+    fp.flux = flux;
     std::vector<int4> pairs, rows, bins, binsT;
     auto up4 = [](size_t v) { return (v + 3) & ~size_t(3); };
     for (size_t ci = 0; ci < coils.size(); ++ci) {
@@ -485,9 +531,12 @@ void fft_plan(const std::vector<CoilDev> &coils, FftHostPlan &fp) {
         C.IB = (C.Rp + kFftI - 1) / kFftI;
         C.off = d.off;
         C.kscale = d.kscale;
+        C.kflux = kMu0 * d.d;
         C.c2d = d.c2d;
         C.spec = fp.spec_reals;
         fp.spec_reals += up4(2 * (size_t)C.bins * C.R * C.Rp);
+        C.fspec = fp.flux_reals;
+        if (flux) fp.flux_reals += up4((size_t)C.bins * C.R * C.Rp);
         C.hat = fp.hat_reals;
         fp.hat_reals += up4((size_t)C.bins * C.Rp * 4);
         C.bpart = fp.bpart_reals;
@@ -525,24 +574,39 @@ hipError_t launch_fft_setup(const DevState &s, const FftPlan &fp, const FftCoil 
         const size_t per_row = (size_t)C.R * C.bins * sizeof(double2);
         const int bs = (int)std::min<size_t>((size_t)C.R, tmp_bytes / per_row);
         if (bs < 1) return hipErrorInvalidValue;
-        for (int b0 = 0; b0 < C.R; b0 += bs) {
-            const int nb = std::min(bs, C.R - b0);
-            hipLaunchKernelGGL(k_fft_spec, dim3(C.R, nb), dim3(256), (size_t)C.L * sizeof(double2), st, fp, c, b0,
-                               t);
-            const dim3 g((C.bins + 31) / 32, (C.Rp + 31) / 32, nb);
-            if (fp.prec == COIL_MIXED)
-                hipLaunchKernelGGL(k_fft_spec_store<float>, g, dim3(256), 0, st, fp, c, b0, t);
-            else
-                hipLaunchKernelGGL(k_fft_spec_store<double>, g, dim3(256), 0, st, fp, c, b0, t);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-        }
+        for (int kind = 0; kind < (fp.fspec ? 2 : 1); ++kind)
+            for (int b0 = 0; b0 < C.R; b0 += bs) {
+                const int nb = std::min(bs, C.R - b0);
+                hipLaunchKernelGGL(k_fft_spec, dim3(C.R, nb), dim3(256), (size_t)C.L * sizeof(double2), st, fp, c,
+                                   b0, t, kind);
+                const dim3 g((C.bins + 31) / 32, (C.Rp + 31) / 32, nb);
+                if (kind == 1)
+                    hipLaunchKernelGGL(k_fft_spec_store<double>, g, dim3(256), 0, st, fp, c, b0, t,
+                                       fp.fspec + C.fspec, 1);
+                else if (fp.prec == COIL_MIXED)
+                    hipLaunchKernelGGL(k_fft_spec_store<float>, g, dim3(256), 0, st, fp, c, b0, t,
+                                       static_cast<float *>(fp.spec) + C.spec, 2);
+                else
+                    hipLaunchKernelGGL(k_fft_spec_store<double>, g, dim3(256), 0, st, fp, c, b0, t,
+                                       static_cast<double *>(fp.spec) + C.spec, 2);
+                hipError_t e = hipGetLastError();
+                if (e != hipSuccess) return e;
+            }
     }
     return hipSuccess;
 }
 
 hipError_t launch_field_fft(const DevState &s, const FftPlan &fp, const int *pub2int, hipStream_t st) {
     return fp.prec == COIL_MIXED ? field_fft<float>(s, fp, pub2int, st) : field_fft<double>(s, fp, pub2int, st);
+}
+
+hipError_t launch_flux_fft(const DevState &s, const FftPlan &fp, const double *v, const int *pub2int,
+                           const int *done, hipStream_t st) {
+    const size_t sh = (size_t)fp.Lmax * sizeof(double2);
+    hipLaunchKernelGGL(k_fft_rows_fwd, dim3(fp.npairs), dim3(256), sh, st, fp, v, pub2int, 1, done);
+    hipLaunchKernelGGL((k_fft_bins<double, 1>), dim3(fp.nbins), dim3(256), 0, st, fp, done);
+    hipLaunchKernelGGL(k_fft_rows_inv, dim3(fp.nrows), dim3(256), sh, st, fp, pub2int, s.part, 1, done);
+    return hipGetLastError();
 }
 
 hipError_t launch_fieldT_fft(const DevState &s, const FftPlan &fp, const double *wr, const double *wz,

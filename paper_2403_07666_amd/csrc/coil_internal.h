@@ -126,6 +126,7 @@ struct DevState {
     int tile_targets;        // field pass: targets per workgroup (= block size)
     int algo_tz;             // 1: the field partials come from the translation-reuse pass
     int algo_fft;            // 1: the field comes from the fast-convolution pass (one slot)
+    int flux_fft;            // 1: the coupled solve's flux passes are fast convolutions (one slot)
     const double *Mlay;      // per layer ne2 x ne2, column-major
     const double *Minv;      // per layer inverse of Mlay, column-major
     const double *yl;        // per layer Minv * 1

@@ -115,6 +115,11 @@ def test_fft_algorithm_workspace():
         extra = pk.query(w, precision=prec, algo="fft").workspace_bytes - pk.query(w, precision=prec).workspace_bytes
         spec = 2 * bins * nr * nr * rs
         assert spec <= extra <= spec + 65536
+        # the coupled solve adds the FP64 spectra of the mutual-inductance kernel
+        wf = w.replace(coupling="full")
+        more = (pk.query(wf, precision=prec, algo="fft").workspace_bytes
+                - pk.query(wf, precision=prec).workspace_bytes - extra)
+        assert abs(more - bins * nr * nr * 8) <= 4096
     with pytest.raises(pk.CoilError) as ei:
         pk.query(w, algo=4)
     assert ei.value.code == -1
