@@ -53,11 +53,13 @@ FLOP_PER_PAIR_ACC = 4
 # holds only while what sets the kernel's traffic is unchanged: the kernel
 # source and the host code that plans its work items (the marked region of
 # coil_api.hip).
-TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_field_tz.h"), "direct": ("coil_kernels.hip",)}
+TRAFFIC_SOURCES = {"translation": ("coil_field_tz.hip", "coil_field_tz.h"), "direct": ("coil_kernels.hip",),
+                   "fft": ("coil_field_fft.hip", "coil_field_fft.h")}
 PLAN_BEGIN, PLAN_END = "// ---- field-pass work plans (begin)", "// ---- field-pass work plans (end)"
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
     ("translation", "c2_medium_131k", "mixed"): ("49bf2f94a8592ed1a99a38e435825fb9ba4b2d98", 108509798),
+    ("fft", "c2_medium_131k", "mixed"): ("01c9fbe205770be42810694fbcdbf3595d12f965", 275410637),
 }
 
 
@@ -679,7 +681,10 @@ def main():
         achieved = sb / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": "k_fft_rows_fwd + k_fft_bins + k_fft_rows_inv (fast-convolution "
                     "field pass; the bytes are k_fft_bins' spectra)", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": None, "avg_launch_ms": avg_ms,
+                    "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                    "traffic": _traffic(w.name, args.precision, "fft"),
+                    "traffic_unit": "bytes per k_fft_bins launch (HBM, rocprofv3 FETCH_SIZE/WRITE_SIZE)",
+                    "avg_launch_ms": avg_ms,
                     "bytes_per_launch": sb, "phase_ms_per_step": phases}
     elif tm is not None and tm["field"]["launches"] > 0:
         avg_ms = tm["field"]["ms"] / tm["field"]["launches"]

@@ -5,8 +5,10 @@
 //   spectra   G^_z[f][j][i], then S[f][j][i]  (j source row, i target row), TS reals:
 //             FP32 in mixed precision (the only data a pass streams from HBM), else FP64
 //   hat       FP64; forward: I^[f][j] (re, im); transposed: W^[f][i] (wr re, wr im, wz re, wz im)
-//   bpart     FP64; forward: [p][f][i] (Bz^ re, Bz^ im, Br^ re, Br^ im), p = source-row part;
-//             transposed: [ib][f][j] (re, im), ib = target block
+//   bpart     FP64; forward: [p][i][f] (Bz^ re, Bz^ im, Br^ re, Br^ im), p = source-row part;
+//             transposed: [ib][j][f] (re, im), ib = target block.  Bin-minor, so that
+//             the inverse DFT of a row reads its bins contiguously; the bin products
+//             write them scattered (a small share of their traffic)
 // The DFTs run in FP64 (radix-2, decimation in time, in LDS, one row or two
 // real rows packed as one complex row per workgroup), and so do the bin
 // products' sums: in mixed precision only the stored spectra are rounded (to
@@ -303,9 +305,10 @@ __global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp, const int *__restr
     if (w == 0 && i < C.Rp) {
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[q] = ((acc[q] + red[0][q][lane]) + red[1][q][lane]) + red[2][q][lane];
-        double *out = fp.bpart + C.bpart + (((size_t)it.w * C.bins + f) * C.Rp + i) * 4;
+        double *out = fp.bpart + C.bpart + (((size_t)it.w * C.Rp + i) * C.bins + f) * 4;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) store4(out + 4 * t, acc[t], acc[4 + t], acc[8 + t], acc[12 + t]);
+        for (int t = 0; t < 4; ++t)
+            store4(out + (size_t)t * C.bins * 4, acc[t], acc[4 + t], acc[8 + t], acc[12 + t]);
     }
 }
 
@@ -325,7 +328,7 @@ __global__ __launch_bounds__(256) void k_fft_rows_inv(FftPlan fp, const int *__r
         ur = ui = vr = vi = 0.0;
         for (int p = 0; p < C.P; ++p) {
             double v[4];
-            load4(bp + (((size_t)p * C.bins + f) * C.Rp + i) * 4, v);
+            load4(bp + (((size_t)p * C.Rp + i) * C.bins + f) * 4, v);
             ur += v[0];
             ui += v[1];
             vr += v[2];
@@ -405,7 +408,7 @@ __global__ __launch_bounds__(256) void k_fft_binsT(FftPlan fp) {
     const int jw0 = it.z * kFftJ + w * JW, jw1 = min(jw0 + JW, C.R);
     const size_t plane = (size_t)C.bins * C.R * C.Rp;
     const TS *gz = static_cast<const TS *>(fp.spec) + C.spec + (size_t)f * C.R * C.Rp + i;
-    double *out = fp.bpart + C.bpart + ((size_t)it.w * C.bins + f) * C.R * 2;
+    double *out = fp.bpart + C.bpart + ((size_t)it.w * C.R * C.bins + f) * 2;
     const bool act = i < C.Rp;
     int j = jw0;
     for (; j + 4 <= jw1; j += 4) {
@@ -432,8 +435,8 @@ __global__ __launch_bounds__(256) void k_fft_binsT(FftPlan fp) {
         if (lane == 0) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                out[(size_t)(j + u) * 2] = re[u];
-                out[(size_t)(j + u) * 2 + 1] = im[u];
+                out[(size_t)(j + u) * C.bins * 2] = re[u];
+                out[(size_t)(j + u) * C.bins * 2 + 1] = im[u];
             }
         }
     }
@@ -452,8 +455,8 @@ __global__ __launch_bounds__(256) void k_fft_binsT(FftPlan fp) {
         re = wave_sum(re);
         im = wave_sum(im);
         if (lane == 0) {
-            out[(size_t)j * 2] = re;
-            out[(size_t)j * 2 + 1] = im;
+            out[(size_t)j * C.bins * 2] = re;
+            out[(size_t)j * C.bins * 2 + 1] = im;
         }
     }
 }
@@ -471,12 +474,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_invT(FftPlan fp, const int *__
     inverse_pair(xs, C, fp, [&](int f, double &ur, double &ui, double &vr, double &vi) {
         ur = ui = vr = vi = 0.0;
         for (int ib = 0; ib < C.IB; ++ib) {
-            const double *q = bp + (((size_t)ib * C.bins + f) * C.R + a) * 2;
+            const double *q = bp + (((size_t)ib * C.R + a) * C.bins + f) * 2;
             ur += q[0];
             ui += q[1];
             if (hb) {
-                vr += q[2];
-                vi += q[3];
+                vr += q[C.bins * 2];
+                vi += q[C.bins * 2 + 1];
             }
         }
     });
