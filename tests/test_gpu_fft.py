@@ -154,3 +154,33 @@ def test_fft_autotune_and_switching(tmp_path):
     check("fft")
     with pytest.raises(pk.CoilError):
         ref.autotune(reps=1, cache_path=path)
+
+
+@pytest.mark.parametrize("algo", ["translation", "fft"])
+def test_overlapped_run_equals_single_steps(algo):
+    """Under the fast convolution coil_run puts the heat step and the
+    reductions of each step on a second stream, overlapping the next field
+    pass; coil_step does not (nor does any step under the translation pass).
+    Both give the same state bitwise: on the active run (T and the per-wire
+    sums move), with report points (joins inside the run), and as a graph
+    capture of overlapped steps."""
+    pk = _pk()
+    w = cs.workload("c1_active")
+    inp = cs.generate(w)
+    a = pk.Coil(w, inp, precision="mixed", algo=algo)
+    for _ in range(150):
+        a.step()
+    b = pk.Coil(w, inp, precision="mixed", algo=algo)
+    seen = []
+    b.run(150, report_every=40, cb=lambda d: seen.append(float(d[1])))
+    c = pk.Coil(w, inp, precision="mixed", algo=algo)
+    c.graph(10)
+    c.run(150)
+    assert seen == [40.0, 80.0, 120.0, 150.0]
+    fields = (pk.F_I, pk.F_BR, pk.F_BZ, pk.F_T, pk.F_PHI, pk.F_QW, pk.F_UW)
+    for g in (b, c):
+        for f in fields:
+            assert np.array_equal(a.get(f), g.get(f))
+        sa, sg = a.scalars(), g.scalars()
+        for k in ("Q", "T_peak", "max_x", "step"):
+            assert sa[k] == sg[k]
