@@ -322,6 +322,56 @@ __device__ __forceinline__ void solve_lds(const double *sm, int n, int lane, boo
     }
 }
 
+// The factor again, packed by rows: entry (i, j), j <= i, at prow(i) + j, so
+// that the backward sweep's reads of row j are consecutive in LDS (by
+// columns they are n - i apart: bank conflicts once per column step).  Worth
+// its LDS where one factor serves many solves.
+__device__ __forceinline__ int prow(int i) { return (i * (i + 1)) >> 1; }
+
+__device__ __forceinline__ void factor_rows_lds(const double *Lc, double *Lr, int n, int lane, bool act) {
+    for (int j = 0; j < n; ++j)
+        if (act && lane >= j) Lr[prow(lane) + j] = Lc[pcol(n, j) + lane - j];
+    __syncthreads();
+}
+
+// solve_lds with the backward sweep on the row copy Lr (same arithmetic)
+template <int K>
+__device__ __forceinline__ void solve_lds_rows(const double *sm, const double *Lr, int n, int lane, bool act,
+                                               double (&v)[K]) {
+    double rjj = 1.0 / sm[0];
+    double l = (act && lane > 0) ? sm[lane] : 0.0;
+    for (int j = 0; j < n; ++j) {
+        const int jn = j + 1 < n ? j + 1 : j;
+        const int cn = pcol(n, jn);
+        const double rjj_n = 1.0 / sm[cn];
+        const double l_n = (act && lane > jn) ? sm[cn + lane - jn] : 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const double vj = lane_value(v[q], j) * rjj;
+            if (lane == j) v[q] = vj;
+            if (act && lane > j) v[q] -= l * vj;
+        }
+        rjj = rjj_n;
+        l = l_n;
+    }
+    rjj = 1.0 / Lr[prow(n - 1) + n - 1];
+    l = (act && lane < n - 1) ? Lr[prow(n - 1) + lane] : 0.0;
+    for (int j = n - 1; j >= 0; --j) {
+        const int jn = j > 0 ? j - 1 : 0;
+        const int rn = prow(jn);
+        const double rjj_n = 1.0 / Lr[rn + jn];
+        const double l_n = (act && lane < jn) ? Lr[rn + lane] : 0.0;
+#pragma unroll
+        for (int q = 0; q < K; ++q) {
+            const double vj = lane_value(v[q], j) * rjj;
+            if (lane == j) v[q] = vj;
+            if (act && lane < j) v[q] -= l * vj;
+        }
+        rjj = rjj_n;
+        l = l_n;
+    }
+}
+
 // Solve L L^T [x y] = [x y] with the packed factor in LDS; lane i holds entry i.
 __device__ __forceinline__ void solve2_lds(const double *sm, int n, int lane, bool act, double &xv, double &yv) {
     double v[2] = {xv, yv};

@@ -479,7 +479,8 @@ __global__ __launch_bounds__(64) void k_wire_sub(DevState s, RunConst rc) {
     const int layer = lw / c.turns;
     const int n = c.ne2;
     const int sq = s.nsubel, ns = sq * sq, sb = c.ne / sq;
-    double *S = sm + packed_size(n) + kCholPad;
+    double *Lr = sm + packed_size(n) + kCholPad;  // the factor by rows (backward sweeps)
+    double *S = Lr + packed_size(n);
     double *col = S + packed_size(ns) + kCholPad;
     const bool act = lane < n;
     const bool sact = lane < ns;
@@ -501,18 +502,19 @@ __global__ __launch_bounds__(64) void k_wire_sub(DevState s, RunConst rc) {
     load_wire_matrix(sm, s.Mlay + (size_t)(c.layer_off + layer) * n * n, n, lane, act,
                      dt * 2.0 * kPi * re * lo.Ep / d2);
     bad |= chol_lds(sm, n, lane, act, sm + packed_size(n));
+    factor_rows_lds(sm, Lr, n, lane, act);
     double v3[3];
     v3[0] = act ? -c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * rho * JH : 0.0;
     v3[1] = act ? -dt * 2.0 * kPi * re * rho * (J - JH) : 0.0;
     v3[2] = act ? 1.0 : 0.0;
-    solve_lds<3>(sm, n, lane, act, v3);
+    solve_lds_rows<3>(sm, Lr, n, lane, act, v3);
     const double xh = v3[0], xi = v3[1], yv = v3[2];
     // S = P^T A^-1 P, column v = the subelement sums of A^-1 p_v
     for (int v0 = 0; v0 < ns; v0 += 4) {
         double y4[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) y4[q] = (act && sub == v0 + q) ? 1.0 : 0.0;
-        solve_lds<4>(sm, n, lane, act, y4);
+        solve_lds_rows<4>(sm, Lr, n, lane, act, y4);
         __syncthreads();
         if (act)
 #pragma unroll
@@ -531,7 +533,7 @@ __global__ __launch_bounds__(64) void k_wire_sub(DevState s, RunConst rc) {
     const double pu = __shfl(u1[0], sub);         // ... of this lane's subelement
     const double usum = wave_sum(sact ? u1[0] : 0.0);
     double z1[1] = {act ? pu : 0.0};
-    solve_lds<1>(sm, n, lane, act, z1);
+    solve_lds_rows<1>(sm, Lr, n, lane, act, z1);
     const double dIH = act ? xh - z1[0] : 0.0;
     const double sx = wave_sum(act ? xi : 0.0);
     const double sy = wave_sum(act ? yv : 0.0);
@@ -978,7 +980,8 @@ hipError_t launch_wire(const DevState &s, const RunConst &rc, hipStream_t st) {
     if (s.nsubel > 0) {
         const size_t ns = (size_t)s.nsubel * s.nsubel;
         const size_t lds =
-            sizeof(double) * ((size_t)packed_size(s.max_ne2) + kCholPad + packed_size((int)ns) + kCholPad + 4 * s.max_ne2);
+            sizeof(double) * (2 * (size_t)packed_size(s.max_ne2) + kCholPad + packed_size((int)ns) + kCholPad +
+                              4 * s.max_ne2);
         hipLaunchKernelGGL(k_wire_sub, dim3(s.Nw), dim3(64), lds, st, s, rc);
         return hipGetLastError();
     }
