@@ -481,7 +481,7 @@ int make_plan(const coil_config *c, Plan &p) {
     if (c->algo == COIL_ALGO_FFT) {
         p.algo = COIL_ALGO_FFT;
         p.fft = 1;
-        fft_plan(p.coils, p.coupled, p.fftp);
+        fft_plan(p.coils, p.coupled, p.prec, p.fftp);
     }
     return COIL_OK;
 }
@@ -1167,6 +1167,8 @@ extern "C" int coil_init(const coil_config *cfg, const coil_inputs *in, void *wo
         f.nrows = p.fftp.nrows;
         f.nbins = p.fftp.nbins;
         f.nbinsT = p.fftp.nbinsT;
+        f.nsym = p.fftp.nsym;
+        f.nflux = p.fftp.nflux;
         f.Lmax = p.fftp.Lmax;
         f.logLmax = p.fftp.logLmax;
         f.prec = p.prec;

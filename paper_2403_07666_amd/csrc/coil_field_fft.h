@@ -35,20 +35,30 @@ struct FftCoil {
     int P;                        // forward bin products: source-row parts (partials) of kFftJ
     int IB;                       // transposed bin products: target blocks (partials) of kFftI
     int off;                      // first element of the coil
-    int pad;
+    int sym;                      // S kept as its packed upper triangle (FP64, one block: n_r <= 256)
     double kscale;                // mu0 / (2 pi d)
     double kflux;                 // mu0 d: the flux kernel's scale
     double c2d;                   // 2 r_inner / d + 1 (grid units)
     size_t spec;   // offset (reals) of the coil's G^_z; S follows after bins R Rp
+    size_t sp;     // sym: reals of one bin's packed S (sym_row(R)); S[f] at spec + bins R Rp + f sp
     size_t fspec;  // offset (FP64 reals) of its flux spectra M^[f][j][i] (coupled solve)
     size_t hat;    // offset (reals) of its transformed rows: bins Rp 4 reals
     size_t bpart;  // offset (reals) of its partial bin products
 };
 
+// Packed upper triangle of a symmetric n x n matrix by rows: row j holds
+// columns 0 .. j, padded with zeros to a multiple of 4 (4 ceil((j + 1) / 4)
+// reals); sym_row(j) is its offset, sym_row(n) the size (about n^2 / 2).
+__host__ __device__ inline size_t sym_row(int j) {
+    const size_t q = (size_t)j >> 2, r = (size_t)j & 3;
+    return 4 * (q + 1) * (2 * q + r);
+}
+
 struct FftPlan {
     const FftCoil *coils;
-    const int4 *items;  // [pairs | rows | bins | binsT]
-    int npairs, nrows, nbins, nbinsT;
+    // [pairs | rows | bins (coils without sym) | binsT (same) | sym bins (coil, f) | bins of every coil (flux)]
+    const int4 *items;
+    int npairs, nrows, nbins, nbinsT, nsym, nflux;
     int Lmax, logLmax;
     int prec;           // COIL_MIXED: spectra stored in FP32; COIL_FP64: in FP64
     void *spec;
@@ -61,7 +71,7 @@ struct FftPlan {
 struct FftHostPlan {
     std::vector<FftCoil> coils;
     std::vector<int4> items;
-    int npairs = 0, nrows = 0, nbins = 0, nbinsT = 0;
+    int npairs = 0, nrows = 0, nbins = 0, nbinsT = 0, nsym = 0, nflux = 0;
     int Lmax = 2, logLmax = 1;
     int flux = 0;  // also the flux kernel's spectra
     size_t spec_reals = 0, hat_reals = 0, bpart_reals = 0;  // spectra in their precision, others FP64
@@ -70,7 +80,7 @@ struct FftHostPlan {
 
 // the plan for coils of (layers * ne) x (turns * ne) grids (flux: also the
 // spectra of the mutual-inductance kernel, for the coupled solve)
-void fft_plan(const std::vector<CoilDev> &coils, int flux, FftHostPlan &fp);
+void fft_plan(const std::vector<CoilDev> &coils, int flux, int prec, FftHostPlan &fp);
 
 // the spectra of every coil (FP64 DFT of the FP64 kernel values), stored in
 // the pass's precision; tmp: staging of tmp_bytes bytes (a slab of source rows)

@@ -3,7 +3,10 @@
 //
 // Layouts (per coil, rows padded to Rp):
 //   spectra   G^_z[f][j][i], then S[f][j][i]  (j source row, i target row), TS reals:
-//             FP32 in mixed precision (the only data a pass streams from HBM), else FP64
+//             FP32 in mixed precision (the only data a pass streams from HBM), else FP64.
+//             S is symmetric (g_r depends on the two rows through (i - j)^2 and i + j
+//             only), so in FP64 a coil of one block (n_r <= 256) keeps per bin only
+//             its upper triangle packed by rows (sym_row): 3/4 of the bytes per pass
 //   hat       FP64; forward: I^[f][j] (re, im); transposed: W^[f][i] (wr re, wr im, wz re, wz im)
 //   bpart     FP64; forward: [p][i][f] (Bz^ re, Bz^ im, Br^ re, Br^ im), p = source-row part;
 //             transposed: [ib][j][f] (re, im), ib = target block.  Bin-minor, so that
@@ -50,6 +53,10 @@ __device__ __forceinline__ void store4(double *p, double a, double b, double c, 
     reinterpret_cast<double2 *>(p)[0] = make_double2(a, b);
     reinterpret_cast<double2 *>(p)[1] = make_double2(c, d);
 }
+
+// waves per bin-product workgroup (they split the workgroup's source rows;
+// eight measured 4-10 % slower than four)
+constexpr int kFftW = 4;
 
 __device__ __forceinline__ int bitrev(int m, int logL) {
     return (int)(__builtin_bitreverse32((unsigned)m) >> (32 - logL));
@@ -172,7 +179,9 @@ __global__ __launch_bounds__(256) void k_fft_spec(FftPlan fp, int coil, int b0, 
 }
 
 // the slab's spectra from [b][a][f] to [f][b][a] (a < Rp; zeros past R), as T,
-// into dst + off: the first place, and the second a plane (bins R Rp) later if planes = 2
+// into dst: the first place, and the second a plane (bins R Rp) later if
+// planes = 2 -- packed by rows (a <= b, zeros up to the row's padded length)
+// for a coil with sym
 template <typename T>
 __global__ __launch_bounds__(256) void k_fft_spec_store(FftPlan fp, int coil, int b0, const double2 *tmp, T *dst,
                                                         int planes) {
@@ -194,7 +203,9 @@ __global__ __launch_bounds__(256) void k_fft_spec_store(FftPlan fp, int coil, in
             const double2 v = tile[tx][ty + k];
             const size_t o = ((size_t)f * C.R + b) * C.Rp + a;
             gz[o] = (T)v.x;
-            if (planes == 2) gs[o] = (T)v.y;
+            if (planes == 2 && !C.sym) gs[o] = (T)v.y;
+            if (planes == 2 && C.sym && a < 4 * ((b >> 2) + 1))
+                gs[(size_t)f * C.sp + sym_row(b) + a] = a <= b ? (T)v.y : (T)0;
         }
     }
 }
@@ -245,11 +256,12 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwd(FftPlan fp, const double *
 // TS: the stored spectra (the sums are FP64).  FLUX: the one real matrix M^ of
 // the flux kernel (FP64) in place of (G^_z, S), its product in the B_z places.
 template <typename TS, int FLUX>
-__global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp, const int *__restrict__ done) {
+__global__ __launch_bounds__(64 * kFftW) void k_fft_bins(FftPlan fp, const int4 *__restrict__ items,
+                                                        const int *__restrict__ done) {
     __shared__ double2 sI[kFftJ];
-    __shared__ double red[3][16][65];
+    __shared__ double red[kFftW - 1][16][65];
     if (done && *done) return;
-    const int4 it = fp.items[fp.npairs + fp.nrows + blockIdx.x];
+    const int4 it = items[blockIdx.x];
     const FftCoil C = fp.coils[it.x];
     const int f = it.y, j0 = it.w * kFftJ;
     const int jn = min(kFftJ, C.R - j0);
@@ -264,7 +276,7 @@ __global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp, const int *__restr
     double acc[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-    constexpr int JW = kFftJ / 4;
+    constexpr int JW = kFftJ / kFftW;
     const int jw0 = w * JW, jw1 = min(jw0 + JW, jn);
     if (i < C.Rp && FLUX) {
         const double *gm = fp.fspec + C.fspec + ((size_t)f * C.R + j0) * C.Rp + i;
@@ -304,7 +316,8 @@ __global__ __launch_bounds__(256) void k_fft_bins(FftPlan fp, const int *__restr
     __syncthreads();
     if (w == 0 && i < C.Rp) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = ((acc[q] + red[0][q][lane]) + red[1][q][lane]) + red[2][q][lane];
+        for (int q = 0; q < 16; ++q)
+            for (int v = 0; v < kFftW - 1; ++v) acc[q] += red[v][q][lane];
         double *out = fp.bpart + C.bpart + (((size_t)it.w * C.Rp + i) * C.bins + f) * 4;
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -373,10 +386,32 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwdT(FftPlan fp, const double 
     }
 }
 
+// One step of the wavefront sum: x + x from the DPP source lane (a 32-bit
+// move per half of the double; lanes whose row the mask leaves out add 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_add(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return x + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes (every lane active), in every lane: pairs and quads
+// by quad permutations, 8 and 16 lanes by the half-row and row mirrors, then
+// row 1 += row 0 and row 3 += row 2 (broadcast of lane 15) and row 3 += rows
+// 0-1 (broadcast of lane 31); lane 63 holds the total.  All in registers,
+// where a butterfly of lane shuffles goes through the LDS crossbar.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
+    v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
+    v = dpp_add<0x140, 0xf>(v);  // row_mirror
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
 // Transposed bin products, one workgroup per (coil, bin f, kFftJ sources,
@@ -384,8 +419,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 // transpose takes conj G^).  A lane holds 4 targets' W^; per source row the
 // wave adds its 64 lanes.  TS: the stored spectra (the sums are FP64).
 template <typename TS>
-__global__ __launch_bounds__(256) void k_fft_binsT(FftPlan fp) {
-    const int4 it = fp.items[fp.npairs + fp.nrows + fp.nbins + blockIdx.x];
+__global__ __launch_bounds__(256) void k_fft_binsT(FftPlan fp, const int4 *__restrict__ items) {
+    const int4 it = items[blockIdx.x];
     const FftCoil C = fp.coils[it.x];
     const int f = it.y;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -461,6 +496,209 @@ __global__ __launch_bounds__(256) void k_fft_binsT(FftPlan fp) {
     }
 }
 
+// Bin products of a coil with sym (n_r <= 256: one workgroup per bin, every
+// source row and target).  G^_z as in k_fft_bins.  S from its packed upper
+// triangle: stored row j holds S_ij for i <= j, and serves twice -- lane i
+// adds S_ij I^_j to its own target i (i <= j; the padding past j holds
+// zeros), and the lanes' S_ij I^_i for i < j, summed over the wave, give
+// target j's share from the rows above the diagonal.  Wave w takes rows
+// 64 w .. 64 w + 63, four at a time.
+template <typename TS>
+__global__ __launch_bounds__(64 * kFftW) void k_fft_bins_sym(FftPlan fp, const int4 *__restrict__ items) {
+    __shared__ double2 sI[kFftI];
+    __shared__ double2 tB[kFftI];  // target j's share from row j's stored entries
+    __shared__ double red[kFftW - 1][16][65];
+    const int4 it = items[blockIdx.x];
+    const FftCoil C = fp.coils[it.x];
+    const int f = it.y, R = C.R;
+    const double *hat = fp.hat + C.hat;
+    if ((int)threadIdx.x < R) {
+        const size_t o = ((size_t)f * R + threadIdx.x) * 2;
+        sI[threadIdx.x] = make_double2(hat[o], hat[o + 1]);
+    }
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = 4 * lane;
+    double2 xi[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) xi[t] = i + t < R ? sI[i + t] : make_double2(0.0, 0.0);
+    double acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+    const bool act = i < C.Rp;
+    const TS *gz = static_cast<const TS *>(fp.spec) + C.spec + (size_t)f * R * C.Rp + i;
+    const TS *sp = static_cast<const TS *>(fp.spec) + C.spec + (size_t)C.bins * R * C.Rp + (size_t)f * C.sp + i;
+    constexpr int JW = kFftI / kFftW;
+    const int jw0 = JW * w, jw1 = min(jw0 + JW, R);
+    for (int j = jw0; j < jw1; j += 4) {
+        double pr[4], pi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pr[u] = pi[u] = 0.0;
+            const int jj = j + u;
+            if (jj >= jw1) continue;  // uniform
+            const double2 x = sI[jj];
+            if (act) {
+                double g[4];
+                load4(gz + (size_t)jj * C.Rp, g);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    acc[t] = fma(g[t], x.x, acc[t]);
+                    acc[4 + t] = fma(g[t], x.y, acc[4 + t]);
+                }
+            }
+            if (lane <= (jj >> 2)) {
+                double sv[4];
+                load4(sp + sym_row(jj), sv);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    acc[8 + t] = fma(-sv[t], x.y, acc[8 + t]);
+                    acc[12 + t] = fma(sv[t], x.x, acc[12 + t]);
+                    const double m = i + t < jj ? sv[t] : 0.0;
+                    pr[u] = fma(m, xi[t].x, pr[u]);
+                    pi[u] = fma(m, xi[t].y, pi[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            pr[u] = wave_sum(pr[u]);
+            pi[u] = wave_sum(pi[u]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j + u < jw1) tB[j + u] = make_double2(pr[u], pi[u]);
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) red[w - 1][q][lane] = acc[q];
+    }
+    __syncthreads();
+    if (w == 0 && act) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            for (int v = 0; v < kFftW - 1; ++v) acc[q] += red[v][q][lane];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (i + t < R) {  // Br^ += i (the rows-above share)
+                acc[8 + t] -= tB[i + t].y;
+                acc[12 + t] += tB[i + t].x;
+            }
+        double *out = fp.bpart + C.bpart + ((size_t)i * C.bins + f) * 4;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            store4(out + (size_t)t * C.bins * 4, acc[t], acc[4 + t], acc[8 + t], acc[12 + t]);
+    }
+}
+
+// Transposed bin products of a coil with sym: out^_j = sum_i [G^_z,ij W^z_i -
+// i S_ij W^r_i].  G^_z and the stored S_ij (i <= j) of row j by a wave sum
+// (out_j); the same stored S_ij for i < j also gives out_i its share
+// -i S_ij W^r_j, kept in the lane's registers and added once at the end.
+template <typename TS>
+__global__ __launch_bounds__(64 * kFftW) void k_fft_binsT_sym(FftPlan fp, const int4 *__restrict__ items) {
+    __shared__ double2 sW[kFftI];  // W^r of every row
+    __shared__ double2 tD[kFftI];  // out^_j from row j's wave sums
+    __shared__ double red[kFftW - 1][8][65];
+    const int4 it = items[blockIdx.x];
+    const FftCoil C = fp.coils[it.x];
+    const int f = it.y, R = C.R;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i = 4 * lane;
+    const double *hat = fp.hat + C.hat;
+    if ((int)threadIdx.x < R) {
+        const double *h4 = hat + ((size_t)f * C.Rp + threadIdx.x) * 4;
+        sW[threadIdx.x] = make_double2(h4[0], h4[1]);
+    }
+    double wrr[4], wri[4], wzr[4], wzi[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        wrr[t] = wri[t] = wzr[t] = wzi[t] = 0.0;
+        if (i + t < R) {
+            double v[4];
+            load4(hat + ((size_t)f * C.Rp + i + t) * 4, v);
+            wrr[t] = v[0];
+            wri[t] = v[1];
+            wzr[t] = v[2];
+            wzi[t] = v[3];
+        }
+    }
+    __syncthreads();
+    double ar[4], ai[4];  // the lane's outputs' shares from rows below
+#pragma unroll
+    for (int t = 0; t < 4; ++t) ar[t] = ai[t] = 0.0;
+    const bool act = i < C.Rp;
+    const TS *gz = static_cast<const TS *>(fp.spec) + C.spec + (size_t)f * R * C.Rp + i;
+    const TS *sp = static_cast<const TS *>(fp.spec) + C.spec + (size_t)C.bins * R * C.Rp + (size_t)f * C.sp + i;
+    constexpr int JW = kFftI / kFftW;
+    const int jw0 = JW * w, jw1 = min(jw0 + JW, R);
+    for (int j = jw0; j < jw1; j += 4) {
+        double re[4], im[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            re[u] = im[u] = 0.0;
+            const int jj = j + u;
+            if (jj >= jw1) continue;  // uniform
+            if (act) {
+                double g[4];
+                load4(gz + (size_t)jj * C.Rp, g);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    re[u] = fma(g[t], wzr[t], re[u]);
+                    im[u] = fma(g[t], wzi[t], im[u]);
+                }
+            }
+            if (lane <= (jj >> 2)) {
+                const double2 wj = sW[jj];
+                double sv[4];
+                load4(sp + sym_row(jj), sv);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    re[u] = fma(sv[t], wri[t], re[u]);
+                    im[u] = fma(-sv[t], wrr[t], im[u]);
+                    const double m = i + t < jj ? sv[t] : 0.0;
+                    ar[t] = fma(m, wj.y, ar[t]);
+                    ai[t] = fma(-m, wj.x, ai[t]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            re[u] = wave_sum(re[u]);
+            im[u] = wave_sum(im[u]);
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (j + u < jw1) tD[j + u] = make_double2(re[u], im[u]);
+        }
+    }
+    if (w > 0) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            red[w - 1][t][lane] = ar[t];
+            red[w - 1][4 + t][lane] = ai[t];
+        }
+    }
+    __syncthreads();
+    if (w == 0) {
+        double *out = fp.bpart + C.bpart + (size_t)f * 2;
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            if (i + t < R) {
+                double sr = ar[t], si = ai[t];
+                for (int v = 0; v < kFftW - 1; ++v) {
+                    sr += red[v][t][lane];
+                    si += red[v][4 + t][lane];
+                }
+                out[(size_t)(i + t) * C.bins * 2] = tD[i + t].x + sr;
+                out[(size_t)(i + t) * C.bins * 2 + 1] = tD[i + t].y + si;
+            }
+    }
+}
+
 // source rows a = 2q, b = 2q + 1: Y = out^_a + i out^_b (the target blocks
 // summed in order), inverse DFT, partT[0][e] of both rows' elements
 __global__ __launch_bounds__(256) void k_fft_rows_invT(FftPlan fp, const int *__restrict__ pub2int,
@@ -497,7 +735,10 @@ hipError_t field_fft(const DevState &s, const FftPlan &fp, const int *pub2int, h
     const size_t sh = (size_t)fp.Lmax * sizeof(double2);
     const int *none = nullptr;
     hipLaunchKernelGGL(k_fft_rows_fwd, dim3(fp.npairs), dim3(256), sh, st, fp, s.I, pub2int, 0, none);
-    hipLaunchKernelGGL((k_fft_bins<TS, 0>), dim3(fp.nbins), dim3(256), 0, st, fp, none);
+    const int4 *bins = fp.items + fp.npairs + fp.nrows;
+    if (fp.nbins) hipLaunchKernelGGL((k_fft_bins<TS, 0>), dim3(fp.nbins), dim3(64 * kFftW), 0, st, fp, bins, none);
+    if (fp.nsym)
+        hipLaunchKernelGGL(k_fft_bins_sym<TS>, dim3(fp.nsym), dim3(64 * kFftW), 0, st, fp, bins + fp.nbins + fp.nbinsT);
     hipLaunchKernelGGL(k_fft_rows_inv, dim3(fp.nrows), dim3(256), sh, st, fp, pub2int, s.part, 0, none);
     return hipGetLastError();
 }
@@ -507,17 +748,19 @@ hipError_t fieldT_fft(const FftPlan &fp, const double *wr, const double *wz, con
                       hipStream_t st) {
     const size_t sh = (size_t)fp.Lmax * sizeof(double2);
     hipLaunchKernelGGL(k_fft_rows_fwdT, dim3(fp.nrows), dim3(256), sh, st, fp, wr, wz, pub2int);
-    hipLaunchKernelGGL(k_fft_binsT<TS>, dim3(fp.nbinsT), dim3(256), 0, st, fp);
+    const int4 *binsT = fp.items + fp.npairs + fp.nrows + fp.nbins;
+    if (fp.nbinsT) hipLaunchKernelGGL(k_fft_binsT<TS>, dim3(fp.nbinsT), dim3(256), 0, st, fp, binsT);
+    if (fp.nsym) hipLaunchKernelGGL(k_fft_binsT_sym<TS>, dim3(fp.nsym), dim3(64 * kFftW), 0, st, fp, binsT + fp.nbinsT);
     hipLaunchKernelGGL(k_fft_rows_invT, dim3(fp.npairs), dim3(256), sh, st, fp, pub2int, partT);
     return hipGetLastError();
 }
 
 }  // namespace
 
-void fft_plan(const std::vector<CoilDev> &coils, int flux, FftHostPlan &fp) {
+void fft_plan(const std::vector<CoilDev> &coils, int flux, int prec, FftHostPlan &fp) {
     fp = FftHostPlan();
     fp.flux = flux;
-    std::vector<int4> pairs, rows, bins, binsT;
+    std::vector<int4> pairs, rows, bins, binsT, sym, all;
     auto up4 = [](size_t v) { return (v + 3) & ~size_t(3); };
     for (size_t ci = 0; ci < coils.size(); ++ci) {
         const CoilDev &d = coils[ci];
@@ -536,8 +779,13 @@ void fft_plan(const std::vector<CoilDev> &coils, int flux, FftHostPlan &fp) {
         C.kscale = d.kscale;
         C.kflux = kMu0 * d.d;
         C.c2d = d.c2d;
+        // packed S where the pass is bound by the spectra's bytes: FP64 spectra
+        // (C2 FP64 145 -> 132 us per pass); with FP32 spectra the wave sums
+        // of the rows-above shares cost more than the bytes saved (67 -> 87 us)
+        C.sym = prec == COIL_FP64 && C.Rp <= kFftI && C.R <= kFftJ ? 1 : 0;
+        C.sp = sym_row(C.R);
         C.spec = fp.spec_reals;
-        fp.spec_reals += up4(2 * (size_t)C.bins * C.R * C.Rp);
+        fp.spec_reals += up4((size_t)C.bins * C.R * C.Rp + (C.sym ? (size_t)C.bins * C.sp : (size_t)C.bins * C.R * C.Rp));
         C.fspec = fp.flux_reals;
         if (flux) fp.flux_reals += up4((size_t)C.bins * C.R * C.Rp);
         C.hat = fp.hat_reals;
@@ -550,7 +798,14 @@ void fft_plan(const std::vector<CoilDev> &coils, int flux, FftHostPlan &fp) {
         for (int i = 0; i < C.R; ++i) rows.push_back(make_int4((int)ci, i, 0, 0));
         for (int f = 0; f < C.bins; ++f) {
             for (int tb = 0; tb < nt; ++tb)
-                for (int p = 0; p < C.P; ++p) bins.push_back(make_int4((int)ci, f, tb, p));
+                for (int p = 0; p < C.P; ++p) {
+                    if (!C.sym) bins.push_back(make_int4((int)ci, f, tb, p));
+                    all.push_back(make_int4((int)ci, f, tb, p));
+                }
+            if (C.sym) {
+                sym.push_back(make_int4((int)ci, f, 0, 0));
+                continue;
+            }
             for (int jb = 0; jb < C.P; ++jb)
                 for (int ib = 0; ib < C.IB; ++ib) binsT.push_back(make_int4((int)ci, f, jb, ib));
         }
@@ -562,10 +817,10 @@ void fft_plan(const std::vector<CoilDev> &coils, int flux, FftHostPlan &fp) {
     fp.nrows = (int)rows.size();
     fp.nbins = (int)bins.size();
     fp.nbinsT = (int)binsT.size();
+    fp.nsym = (int)sym.size();
+    fp.nflux = (int)all.size();
     fp.items = pairs;
-    fp.items.insert(fp.items.end(), rows.begin(), rows.end());
-    fp.items.insert(fp.items.end(), bins.begin(), bins.end());
-    fp.items.insert(fp.items.end(), binsT.begin(), binsT.end());
+    for (const auto *v : {&rows, &bins, &binsT, &sym, &all}) fp.items.insert(fp.items.end(), v->begin(), v->end());
 }
 
 hipError_t launch_fft_setup(const DevState &s, const FftPlan &fp, const FftCoil *hc, int ncoils, void *tmp,
@@ -607,7 +862,8 @@ hipError_t launch_flux_fft(const DevState &s, const FftPlan &fp, const double *v
                            const int *done, hipStream_t st) {
     const size_t sh = (size_t)fp.Lmax * sizeof(double2);
     hipLaunchKernelGGL(k_fft_rows_fwd, dim3(fp.npairs), dim3(256), sh, st, fp, v, pub2int, 1, done);
-    hipLaunchKernelGGL((k_fft_bins<double, 1>), dim3(fp.nbins), dim3(256), 0, st, fp, done);
+    const int4 *all = fp.items + fp.npairs + fp.nrows + fp.nbins + fp.nbinsT + fp.nsym;
+    hipLaunchKernelGGL((k_fft_bins<double, 1>), dim3(fp.nflux), dim3(64 * kFftW), 0, st, fp, all, done);
     hipLaunchKernelGGL(k_fft_rows_inv, dim3(fp.nrows), dim3(256), sh, st, fp, pub2int, s.part, 1, done);
     return hipGetLastError();
 }

@@ -105,15 +105,20 @@ def test_library_elliptic_approximations():
 
 
 def test_fft_algorithm_workspace():
-    """COIL_ALGO_FFT keeps per coil 2 (L/2 + 1) n_r^2 spectra reals (L the DFT
-    length, a power of two >= 2 n_z - 1) in the pass's precision, plus small
-    buffers; an unknown algorithm is refused."""
+    """COIL_ALGO_FFT keeps per coil and bin (L/2 + 1 bins, L the DFT length, a
+    power of two >= 2 n_z - 1) the n_r x n_r matrices of the G_z and G_r
+    spectra in the pass's precision -- in FP64, for a coil of at most 256 rows,
+    only the packed upper triangle of the symmetric G_r spectrum (rows padded
+    to a multiple of 4) -- plus small buffers; an unknown algorithm is refused."""
     pk = _pk()
     w = cs.workload("c1")  # 4 layers x 8 turns of 4 x 4: n_r = 16, n_z = 32, L = 64
     nr, bins = 16, 33
+    q, r = nr // 4, nr % 4
+    tri = 4 * (q + 1) * (2 * q + r)  # rows j = 0 .. 15 of 4 ceil((j + 1) / 4) reals
+    assert tri == sum(4 * (-(-(j + 1) // 4)) for j in range(nr))
     for prec, rs in (("fp64", 8), ("mixed", 4)):
         extra = pk.query(w, precision=prec, algo="fft").workspace_bytes - pk.query(w, precision=prec).workspace_bytes
-        spec = 2 * bins * nr * nr * rs
+        spec = bins * (nr * nr + (tri if prec == "fp64" else nr * nr)) * rs
         assert spec <= extra <= spec + 65536
         # the coupled solve adds the FP64 spectra of the mutual-inductance kernel
         wf = w.replace(coupling="full")

@@ -184,3 +184,26 @@ def test_overlapped_run_equals_single_steps(algo):
         sa, sg = a.scalars(), g.scalars()
         for k in ("Q", "T_peak", "max_x", "step"):
             assert sa[k] == sg[k]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("shape", [(5, 1, 1), (1, 256, 8), (3, 33, 3)])
+def test_fft_extreme_lengths_against_oracle(prec, shape):
+    """DFT lengths at both ends: one element per row (L = 2, odd row count),
+    2048 elements per row (L = 4096, the largest: 64 KiB of FP64 DFT in LDS),
+    and a row of 99 (L = 256, most of it zero padding)."""
+    pk = _pk()
+    layers, turns, ne = shape
+    w = cs.Workload(name="fftlen", coils=[cs.Coil(layers=layers, turns=turns, ne=ne, ramp=1.0)], steps=1, dt=1e-4)
+    g = pk.Coil(w, precision=prec, algo="fft")
+    o = oracle.Sim(w, field_only=True)
+    I = cs.random_currents(w.n_elem, seed=3 + sum(shape))
+    tg = cs.sample_indices(w.n_elem, min(w.n_elem, 256), seed=4)
+    tg = np.unique(np.concatenate([tg, [0, w.n_elem - 1]]))
+    g.set_state(pk.F_I, I)
+    g.compute_field()
+    obr, obz = o.field_targets(I, tg)
+    scale = max(np.abs(obr).max(), np.abs(obz).max())
+    e = max(np.abs(g.get(pk.F_BR)[tg] - obr).max(), np.abs(g.get(pk.F_BZ)[tg] - obz).max()) / scale
+    _say(f"  fft {shape} {prec}: {e:.2e}")
+    assert e <= (1e-10 if prec == "fp64" else 1e-5)
