@@ -284,22 +284,21 @@ __global__ __launch_bounds__(FAST ? 64 * kFastWires : 64) void k_wire(DevState s
     extern __shared__ double sm[];
     const int lane = threadIdx.x & 63;
     int w;
+    bool live = true;
+    CoilDev c;
     if (FAST) {
-        // the layer inverse of the workgroup's wires, staged once
+        // four wires of one layer (so of one coil): every wave of the
+        // workgroup reaches the barrier that stages the layer inverse below
         const int w0 = s.fast_w0[blockIdx.x];
-        const CoilDev c0 = s.coils[s.wire_coil[w0]];
-        const int nn = c0.ne2 * c0.ne2;
-        const double *Mi = s.Minv + (size_t)(c0.layer_off + (w0 - c0.wire_off) / c0.turns) * nn;
-        for (int i = threadIdx.x; i < nn; i += 64 * kFastWires) sm[i] = Mi[i];
-        __syncthreads();
+        c = s.coils[s.wire_coil[w0]];
         const int v = threadIdx.x >> 6;
-        if (v >= c0.turns - (w0 - c0.wire_off) % c0.turns) return;  // past the layer's last wire
-        w = w0 + v;
+        live = v < c.turns - (w0 - c.wire_off) % c.turns;  // past the layer's last wire: no wire
+        w = live ? w0 + v : w0;
     } else {
         w = blockIdx.x;
         if (s.wflag[w] == 0) return;
+        c = s.coils[s.wire_coil[w]];
     }
-    const CoilDev c = s.coils[s.wire_coil[w]];
     const int lw = w - c.wire_off;
     const int layer = lw / c.turns;
     const int n = c.ne2;
@@ -309,6 +308,8 @@ __global__ __launch_bounds__(FAST ? 64 * kFastWires : 64) void k_wire(DevState s
     const double tk = (double)s.sc->step * dt;
     const double dBa = rc.dBa_dt * dt;
 
+    // the element's loads and its local law are issued before the fast
+    // path stages the layer inverse, so that their latencies overlap
     const size_t lay = (size_t)(c.layer_off + layer);
     double br, bz;
     if (s.src_Br) {
@@ -326,9 +327,18 @@ __global__ __launch_bounds__(FAST ? 64 * kFastWires : 64) void k_wire(DevState s
     const double *M = s.Mlay + lay * n * n;
     const double diag_add = dt * 2.0 * kPi * re * lo.Ep / d2;
     const double b = act ? (-c.dIt * s.psi[e] - kPi * re * re * dBa - dt * 2.0 * kPi * re * lo.E) : 0.0;
+    double mee = 1.0, ylv = 0.0, sylv = 0.0;
+    if (FAST) {
+        mee = act ? M[(size_t)lane * n + lane] : 1.0;
+        ylv = act ? s.yl[lay * n + lane] : 0.0;
+        sylv = s.syl[lay];
+        const double *Mi = s.Minv + lay * n * n;
+        for (int i = threadIdx.x; i < n * n; i += 64 * kFastWires) sm[i] = Mi[i];
+        __syncthreads();
+        if (!live) return;
+    }
     double xv, yv, sy;
     if (FAST) {
-        const double mee = act ? M[(size_t)lane * n + lane] : 1.0;
         const int same = act ? (mee + diag_add == mee) : 1;
         if (!__all(same)) {
             if (lane == 0) s.wflag[w] = 1;
@@ -336,8 +346,8 @@ __global__ __launch_bounds__(FAST ? 64 * kFastWires : 64) void k_wire(DevState s
         }
         if (s.emsub && lane == 0) s.emsub[w] = 1.0;  // a linear step: one substep is exact
         xv = matvec_lds(sm, n, act, lane, b);
-        yv = act ? s.yl[lay * n + lane] : 0.0;
-        sy = s.syl[lay];
+        yv = ylv;
+        sy = sylv;
     } else {
         load_wire_matrix(sm, M, n, lane, act, diag_add);
         bad |= chol_lds(sm, n, lane, act, sm + packed_size(n));
