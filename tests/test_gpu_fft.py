@@ -207,3 +207,31 @@ def test_fft_extreme_lengths_against_oracle(prec, shape):
     e = max(np.abs(g.get(pk.F_BR)[tg] - obr).max(), np.abs(g.get(pk.F_BZ)[tg] - obz).max()) / scale
     _say(f"  fft {shape} {prec}: {e:.2e}")
     assert e <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("variant", ["subelements", "em", "adi", "rho_n"])
+def test_fft_with_extended_models_against_oracle(variant):
+    """The fast-convolution field under the other wire and heat kernels (the
+    subelement solve, the variable step, the ADI heat step, the normal-state
+    path): FP64 runs of the active C1 case against the oracle."""
+    pk = _pk()
+    w = cs.workload("c1_active")
+    w = {"subelements": w.replace(subelements=2, dBa_dt=0.5), "em": w.replace(em_tol=1e-5),
+         "adi": w.replace(heat_solver="adi"), "rho_n": w.replace(rho_n=3e-10)}[variant]
+    inp = cs.generate(w)
+    g = pk.Coil(w, inp, precision="fp64", algo="fft")
+    o = oracle.Sim(w, inp)
+    g.run(150)
+    assert o.run(150) == 0
+    e = max(nerr(g.get(pk.F_BR), o.get(oracle.BR)), nerr(g.get(pk.F_BZ), o.get(oracle.BZ)),
+            nerr(g.get(pk.F_I), o.get(oracle.I)), nerr(g.get(pk.F_PHI), o.get(oracle.PHI)))
+    To, Tg = o.get(oracle.T), g.get(pk.F_T)
+    rise = float((To - w.T_bath).max())
+    dT = float(np.abs(Tg - To).max() / rise) if rise > 0 else 0.0
+    floor = 8 * 2.220446049250313e-16 * float(To.max()) / rise if rise > 0 else 0.0
+    if variant == "adi":  # the line solves' condition number, as in the ADI parity tests
+        d = w.coils[0].wire_side / w.coils[0].ne
+        alpha = w.k0 * (float(To.max()) / w.T_ref) ** w.k_exp / (w.C0 * (w.T_bath / w.T_ref) ** w.cp_exp)
+        floor *= 1.0 + 4.0 * alpha * w.dt / d ** 2
+    _say(f"  fft {variant}: {e:.2e} dT {dT:.2e} (floor {floor:.1e})")
+    assert e <= 1e-10 and dT <= max(1e-10, floor)
