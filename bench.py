@@ -317,14 +317,14 @@ def fft_spectra_bytes(w, precision: str) -> int:
 
 def fft_leg(pk, cs, torch, steps: int = 1000) -> dict:
     """The fast-convolution field evaluation (COIL_ALGO_FFT) on the medium coil
-    (131,072 elements) and the adjoint coil (384,000): step rate and field
-    pass against the translation-reuse pass, mixed against FP64 and FP64
-    against the FP64 translation pass on the driven variant, and the adjoint
-    over forward ratio with it.  The field pass is HBM-bound on its spectra;
+    (131,072 elements), the 16-coil ensemble (617,472) and the adjoint coil
+    (384,000): step rate and field pass against the translation-reuse pass,
+    mixed against FP64 and FP64 against the FP64 translation pass on the
+    driven variant, and the adjoint over forward ratio with it.  The field pass is HBM-bound on its spectra;
     the effective rate below counts only their bytes over the whole pass
     (three kernels), a lower bound of the bin-product kernel's."""
     out = {}
-    for name, n in (("c2", steps), ("c5", max(1, steps // 4))):
+    for name, n in (("c2", steps), ("c4", max(1, steps // 2)), ("c5", max(1, steps // 4))):
         w = cs.workload(name)
         inp = cs.generate(w)
         rec = {"n_elem": w.n_elem, "steps": n}
