@@ -15,20 +15,56 @@
 namespace coilq {
 
 // ------------------------------------------------------------------ helpers
+// Wavefront reductions (every lane of the wave active), the result in every
+// lane.  DPP moves in registers: pairs and quads by quad permutations, 8 and
+// 16 lanes by the half-row and row mirrors, then rows 1 and 3 take row 0 and
+// 2 (broadcast of lane 15) and rows 2 and 3 take rows 0-1 (broadcast of lane
+// 31); lane 63 then holds the result, read back as a scalar.  A butterfly of
+// lane shuffles instead goes through the LDS crossbar at each of its six
+// steps.  A 64-bit value moves as two 32-bit halves; lanes a row mask leaves
+// out receive `old` (the operation's identity).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_mov64(double x, double old) {
+    const long long b = __double_as_longlong(x), o = __double_as_longlong(old);
+    const int lo = __builtin_amdgcn_update_dpp((int)(o & 0xffffffffLL), (int)(b & 0xffffffffLL), CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp((int)(o >> 32), (int)(b >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double lane63(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += dpp_mov64<0xb1, 0xf>(v, 0.0);   // quad_perm [1, 0, 3, 2]
+    v += dpp_mov64<0x4e, 0xf>(v, 0.0);   // quad_perm [2, 3, 0, 1]
+    v += dpp_mov64<0x141, 0xf>(v, 0.0);  // row_half_mirror
+    v += dpp_mov64<0x140, 0xf>(v, 0.0);  // row_mirror
+    v += dpp_mov64<0x142, 0xa>(v, 0.0);  // row_bcast:15 into rows 1, 3
+    v += dpp_mov64<0x143, 0xc>(v, 0.0);  // row_bcast:31 into rows 2, 3
+    return lane63(v);
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
+    const double lo = -INFINITY;
+    v = fmax(v, dpp_mov64<0xb1, 0xf>(v, lo));
+    v = fmax(v, dpp_mov64<0x4e, 0xf>(v, lo));
+    v = fmax(v, dpp_mov64<0x141, 0xf>(v, lo));
+    v = fmax(v, dpp_mov64<0x140, 0xf>(v, lo));
+    v = fmax(v, dpp_mov64<0x142, 0xa>(v, lo));
+    v = fmax(v, dpp_mov64<0x143, 0xc>(v, lo));
+    return lane63(v);
 }
 __device__ __forceinline__ unsigned wave_or(unsigned v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
-    return v;
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false);
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xf, 0xf, false);
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x140, 0xf, 0xf, false);
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);
+    v |= (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);
+    return (unsigned)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // FP64 pair: adds the (B_r * rho_t, B_z) contribution of a source of strength

@@ -386,33 +386,6 @@ __global__ __launch_bounds__(256) void k_fft_rows_fwdT(FftPlan fp, const double 
     }
 }
 
-// One step of the wavefront sum: x + x from the DPP source lane (a 32-bit
-// move per half of the double; lanes whose row the mask leaves out add 0).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_add(double x) {
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, ROWS, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, false);
-    return x + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// Sum over the 64 lanes (every lane active), in every lane: pairs and quads
-// by quad permutations, 8 and 16 lanes by the half-row and row mirrors, then
-// row 1 += row 0 and row 3 += row 2 (broadcast of lane 15) and row 3 += rows
-// 0-1 (broadcast of lane 31); lane 63 holds the total.  All in registers,
-// where a butterfly of lane shuffles goes through the LDS crossbar.
-__device__ __forceinline__ double wave_sum(double v) {
-    v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
-    v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2, 3, 0, 1]
-    v = dpp_add<0x141, 0xf>(v);  // row_half_mirror
-    v = dpp_add<0x140, 0xf>(v);  // row_mirror
-    v = dpp_add<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
-    v = dpp_add<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), 63);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
 
 // Transposed bin products, one workgroup per (coil, bin f, kFftJ sources,
 // block of kFftI targets): out^_j = sum_i [G^_z,ij W^z_i - i S_ij W^r_i] (the

@@ -654,7 +654,7 @@ __global__ __launch_bounds__(256) void k_heat_tile(DevState s, RunConst rc, int 
                 if (s.rec_T) s.rec_T[(size_t)sub * s.N + elem_of(c, ir, iz)] = Te;
             }
         }
-        // the tile's border outflow: per wavefront by shuffles, then the four
+        // the tile's border outflow: per wavefront (DPP sum), then the four
         // wavefronts' sums in order
         // (the barrier also orders this substep's T against the next one's reads)
         outv = wave_sum(outv);
