@@ -69,8 +69,10 @@ enum coil_precision {
                        FP64 (from FP64 arguments) and rounded to FP32; FP32
                        products and partial sums, the partial sums of every 16W
                        sources (TRANSLATION) or 64 sources (DIRECT, with a Kahan
-                       correction across them) added into FP64; all state (I, Phi,
-                       u, T, Q) in FP64 */
+                       correction across them) added into FP64; FFT: the kernel
+                       values' spectra stored in FP32, the DFTs and the
+                       products' sums in FP64; all state (I, Phi, u, T, Q) in
+                       FP64 */
 };
 
 /* Geometry of the heat step and of the element volumes (the field and the
@@ -153,9 +155,14 @@ enum coil_heat { COIL_HEAT_EXPLICIT = 0, COIL_HEAT_ADI = 1 };
    (FP64) and keeps per coil two real n_r x n_r matrices per bin (L/2 + 1
    bins: G^_z is real as g_z is even in z, G^_r imaginary as g_r is odd),
    FP32 in COIL_MIXED, FP64 in COIL_FP64: 2 (L/2+1) n_r^2 reals, about
-   4 n_r^2 n_z for n_z a power of two (1.9 GB for 480 x 800 in FP32).  A pass
-   transforms the source rows, streams the matrices once and transforms the
-   target rows back.  Only selectable at coil_init (the autotuner then also
+   4 n_r^2 n_z for n_z a power of two (1.9 GB for 480 x 800 in FP32); in
+   COIL_FP64 a coil of n_r <= 256 keeps G^_r's matrix, symmetric in the two
+   rows, as its packed upper triangle (about 1.5 (L/2+1) n_r^2 reals).  A
+   pass transforms the source rows (FP64 DFTs), streams the matrices once
+   (FP64 sums) and transforms the target rows back.  coil_run then also puts
+   each step's heat step and reductions on a second stream of its own
+   (created at coil_init, default priority), overlapping the next field
+   pass, and joins it before returning.  Only selectable at coil_init (the autotuner then also
    times it).  With COIL_COUPLE_FULL the coupled solve's flux passes use the
    same scheme with the mutual-inductance kernel's spectra (one real matrix
    per bin, FP64: (L/2 + 1) n_r^2 more reals); otherwise they are
