@@ -38,7 +38,9 @@
  *     tensor) of the size coil_query() reports and keeps it alive until
  *     coil_destroy().  The library allocates no device memory of its own
  *     except where a function says so.
- *   - Streams: every call enqueues on the HIP stream given to coil_init.  Only
+ *   - Streams: every call enqueues on the HIP stream given to coil_init
+ *     (coil_run may fork work to a second stream of the handle's own, which
+ *     it joins back into that stream before returning).  Only
  *     coil_run at report points, coil_scalars, host-destination coil_get,
  *     coil_timing and coil_adjoint synchronise with the host.
  *   - A handle is not thread-safe: use one handle per host thread.
