@@ -319,41 +319,40 @@ __device__ __forceinline__ unsigned chol_lds(double *sm, int n, int lane, bool a
 
 // Solve L L^T v_q = v_q for K right-hand sides at once (packed factor in LDS,
 // lane i holding entry i of every v_q).  v_j comes from lane j by scalar
-// reads; the factor's entries of the next j, and the reciprocal of its pivot,
-// are formed while the current j is applied, so that the chain from one j to
-// the next holds a multiplication rather than a division.
+// reads, and so does 1 / L_jj: every lane forms the reciprocal of its own
+// pivot once, in parallel, so that the chain from one j to the next holds a
+// multiplication rather than a division (the same values as a division per
+// step); the factor's entries of the next j are read while the current j is
+// applied.
 template <int K>
 __device__ __forceinline__ void solve_lds(const double *sm, int n, int lane, bool act, double (&v)[K]) {
-    double rjj = 1.0 / sm[0];
+    const double rp = act ? 1.0 / sm[pcol(n, lane)] : 1.0;
     double l = (act && lane > 0) ? sm[lane] : 0.0;
     for (int j = 0; j < n; ++j) {
         const int jn = j + 1 < n ? j + 1 : j;
         const int cn = pcol(n, jn);
-        const double rjj_n = 1.0 / sm[cn];
         const double l_n = (act && lane > jn) ? sm[cn + lane - jn] : 0.0;
+        const double rjj = lane_value(rp, j);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const double vj = lane_value(v[q], j) * rjj;
             if (lane == j) v[q] = vj;
             if (act && lane > j) v[q] -= l * vj;
         }
-        rjj = rjj_n;
         l = l_n;
     }
     // backward: lane i < j needs L(j, i), row j of the factor
-    rjj = 1.0 / sm[pcol(n, n - 1)];
     l = (act && lane < n - 1) ? sm[pcol(n, lane) + n - 1 - lane] : 0.0;
     for (int j = n - 1; j >= 0; --j) {
         const int jn = j > 0 ? j - 1 : 0;
-        const double rjj_n = 1.0 / sm[pcol(n, jn)];
         const double l_n = (act && lane < jn) ? sm[pcol(n, lane) + jn - lane] : 0.0;
+        const double rjj = lane_value(rp, j);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const double vj = lane_value(v[q], j) * rjj;
             if (lane == j) v[q] = vj;
             if (act && lane < j) v[q] -= l * vj;
         }
-        rjj = rjj_n;
         l = l_n;
     }
 }
@@ -374,36 +373,33 @@ __device__ __forceinline__ void factor_rows_lds(const double *Lc, double *Lr, in
 template <int K>
 __device__ __forceinline__ void solve_lds_rows(const double *sm, const double *Lr, int n, int lane, bool act,
                                                double (&v)[K]) {
-    double rjj = 1.0 / sm[0];
+    const double rp = act ? 1.0 / sm[pcol(n, lane)] : 1.0;
     double l = (act && lane > 0) ? sm[lane] : 0.0;
     for (int j = 0; j < n; ++j) {
         const int jn = j + 1 < n ? j + 1 : j;
         const int cn = pcol(n, jn);
-        const double rjj_n = 1.0 / sm[cn];
         const double l_n = (act && lane > jn) ? sm[cn + lane - jn] : 0.0;
+        const double rjj = lane_value(rp, j);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const double vj = lane_value(v[q], j) * rjj;
             if (lane == j) v[q] = vj;
             if (act && lane > j) v[q] -= l * vj;
         }
-        rjj = rjj_n;
         l = l_n;
     }
-    rjj = 1.0 / Lr[prow(n - 1) + n - 1];
     l = (act && lane < n - 1) ? Lr[prow(n - 1) + lane] : 0.0;
     for (int j = n - 1; j >= 0; --j) {
         const int jn = j > 0 ? j - 1 : 0;
         const int rn = prow(jn);
-        const double rjj_n = 1.0 / Lr[rn + jn];
         const double l_n = (act && lane < jn) ? Lr[rn + lane] : 0.0;
+        const double rjj = lane_value(rp, j);
 #pragma unroll
         for (int q = 0; q < K; ++q) {
             const double vj = lane_value(v[q], j) * rjj;
             if (lane == j) v[q] = vj;
             if (act && lane < j) v[q] -= l * vj;
         }
-        rjj = rjj_n;
         l = l_n;
     }
 }
