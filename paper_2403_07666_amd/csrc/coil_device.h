@@ -289,10 +289,32 @@ __device__ __forceinline__ unsigned chol_lds(double *sm, int n, int lane, bool a
         *(inj ? sm + aj : dummy + lane) = lv;
         __syncthreads();
         const double lij = (act && lane > j) ? lv : 0.0;
-        for (int k0 = j + 1; k0 < n; k0 += 8) {
-            // columns k0 .. k0 + nq - 1; lanes above a column's diagonal (and
-            // the padding columns past n) read an in-range entry they do not use
-            const int nq = min(8, n - k0);
+        int k0 = j + 1;
+        for (; k0 + 8 <= n; k0 += 8) {
+            // eight whole columns k0 .. k0 + 7: column k0 + q starts at
+            // pcol(n, k0) + q (n - k0) - q (q - 1) / 2, so the addresses are one
+            // scalar base plus compile-time multiples (the general form below
+            // costs a dozen scalar instructions per column); lanes above a
+            // column's diagonal read an in-range entry they do not use
+            const int base = pcol(n, k0) - k0 + lane, st1 = n - k0 - 1;
+            double lk[8], ak[8];
+            int addr[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                lk[q] = sm[cj + k0 + q - j];
+                addr[q] = act ? base + q * st1 - ((q * (q - 1)) >> 1) : 0;
+                ak[q] = sm[addr[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool st = act && lane >= k0 + q;
+                *(st ? sm + addr[q] : dummy + lane) = ak[q] - lij * lk[q];
+            }
+        }
+        if (k0 < n) {
+            // the last, partial chunk: columns k0 .. k0 + nq - 1; the padding
+            // columns past n read an in-range entry they do not use
+            const int nq = n - k0;
             const int p0 = pcol(n, k0);
             double lk[8], ak[8];
             int addr[8];
