@@ -350,9 +350,10 @@ template <int K>
 __device__ __forceinline__ void solve_lds(const double *sm, int n, int lane, bool act, double (&v)[K]) {
     const double rp = act ? 1.0 / sm[pcol(n, lane)] : 1.0;
     double l = (act && lane > 0) ? sm[lane] : 0.0;
+    int cn = 0;  // pcol(n, j + 1), advanced by n - j per step
     for (int j = 0; j < n; ++j) {
         const int jn = j + 1 < n ? j + 1 : j;
-        const int cn = pcol(n, jn);
+        cn += j + 1 < n ? n - j : 0;
         const double l_n = (act && lane > jn) ? sm[cn + lane - jn] : 0.0;
         const double rjj = lane_value(rp, j);
 #pragma unroll
@@ -397,9 +398,10 @@ __device__ __forceinline__ void solve_lds_rows(const double *sm, const double *L
                                                double (&v)[K]) {
     const double rp = act ? 1.0 / sm[pcol(n, lane)] : 1.0;
     double l = (act && lane > 0) ? sm[lane] : 0.0;
+    int cn = 0;  // pcol(n, j + 1), advanced by n - j per step
     for (int j = 0; j < n; ++j) {
         const int jn = j + 1 < n ? j + 1 : j;
-        const int cn = pcol(n, jn);
+        cn += j + 1 < n ? n - j : 0;
         const double l_n = (act && lane > jn) ? sm[cn + lane - jn] : 0.0;
         const double rjj = lane_value(rp, j);
 #pragma unroll
@@ -438,14 +440,20 @@ __device__ __forceinline__ void solve2_lds(const double *sm, int n, int lane, bo
 // n x n in global memory) into packed LDS and add dt diag(2 pi r E'/d^2).
 __device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, int n, int lane, bool act,
                                                  double diag_add) {
+    // 16 column loads in flight; every active lane loads (the entries above
+    // the diagonal are not kept), and lanes with nothing to keep store to the
+    // sink after the packed matrix, so no load or store sits under a branch
+    double *sink = sm + packed_size(n) + lane;
     if (act)
-        for (int c0 = 0; c0 < n; c0 += 16) {  // 16 column loads in flight
+        for (int c0 = 0; c0 < n; c0 += 16) {
             double a[16];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) a[q] = (c0 + q < n && lane >= c0 + q) ? M[(size_t)(c0 + q) * n + lane] : 0.0;
+            for (int q = 0; q < 16; ++q) a[q] = c0 + q < n ? M[(size_t)(c0 + q) * n + lane] : 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q)
-                if (c0 + q < n && lane >= c0 + q) sm[pcol(n, c0 + q) + lane - (c0 + q)] = a[q];
+            for (int q = 0; q < 16; ++q) {
+                const int c = c0 + q;
+                *(c < n && lane >= c ? sm + pcol(n, c) + lane - c : sink) = a[q];
+            }
         }
     __syncthreads();
     if (act) sm[pcol(n, lane)] += diag_add;
