@@ -312,21 +312,19 @@ __device__ __forceinline__ unsigned chol_lds(double *sm, int n, int lane, bool a
             }
         }
         if (k0 < n) {
-            // the last, partial chunk: columns k0 .. k0 + nq - 1; the padding
-            // columns past n read an in-range entry they do not use
+            // the last, partial chunk: columns k0 .. k0 + nq - 1, the same
+            // addressing with the padding slots q >= nq reading column
+            // k0 + nq - 1 (in range, not stored)
             const int nq = n - k0;
-            const int p0 = pcol(n, k0);
+            const int base = pcol(n, k0) - k0 + lane, st1 = n - k0 - 1;
             double lk[8], ak[8];
             int addr[8];
-            int pk = p0;  // pcol(n, k0 + q), advanced column by column
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const bool valid = q < nq;
-                const int k = valid ? k0 + q : k0;
-                lk[q] = sm[cj + k - j];
-                addr[q] = act ? (valid ? pk : p0) + lane - k : 0;  // at most pcol(n, k + 1) - 1
+                const int qq = q < nq ? q : nq - 1;
+                lk[q] = sm[cj + k0 + qq - j];
+                addr[q] = act ? base + qq * st1 - ((qq * (qq - 1)) >> 1) : 0;
                 ak[q] = sm[addr[q]];
-                pk += valid ? n - k : 0;
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
