@@ -458,14 +458,21 @@ __device__ __forceinline__ void load_wire_matrix(double *sm, const double *M, in
 }
 
 // y_i = sum_j A_ij v_j with the column-major n x n block in LDS (lane i
-// holding row i), v_j from lane j, the FMAs in j order
+// holding row i), v_j from lane j, the FMAs in j order.  Eight LDS reads are
+// issued before their FMAs, and no read sits under a branch (lanes past n
+// read row 0 and return 0).
 __device__ __forceinline__ double matvec_lds(const double *A, int n, bool act, int lane, double v) {
     double y = 0.0;
-    for (int j = 0; j < n; ++j) {
-        const double vj = lane_value(v, j);
-        if (act) y = fma(A[j * n + lane], vj, y);
+    const int li = act ? lane : 0;
+    for (int j0 = 0; j0 < n; j0 += 8) {
+        double a[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q] = j0 + q < n ? A[(j0 + q) * n + li] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (j0 + q < n) y = fma(a[q], lane_value(v, j0 + q), y);
     }
-    return y;
+    return act ? y : 0.0;
 }
 
 __device__ __forceinline__ double matvec_cols(const double *A, int n, int lane, bool act, double v) {
