@@ -59,7 +59,7 @@ PLAN_BEGIN, PLAN_END = "// ---- field-pass work plans (begin)", "// ---- field-p
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
     ("translation", "c2_medium_131k", "mixed"): ("49bf2f94a8592ed1a99a38e435825fb9ba4b2d98", 108509798),
-    ("fft", "c2_medium_131k", "mixed"): ("1465a6012ddcfc9052eeff5750b2aced9ac0ace9", 275403264),
+    ("fft", "c2_medium_131k", "mixed"): ("f2a7aa7ab2d1c37e64d450f405579973d758aac9", 275438080),
 }
 
 

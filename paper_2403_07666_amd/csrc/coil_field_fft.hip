@@ -54,9 +54,34 @@ __device__ __forceinline__ void store4(double *p, double a, double b, double c, 
     reinterpret_cast<double2 *>(p)[1] = make_double2(c, d);
 }
 
+// Four consecutive reals of one source row as loaded (converted to FP64 where
+// they are used), so that a batch of rows can be in flight before the first
+// FMA waits for it.
+template <typename TS>
+struct Row4;
+template <>
+struct Row4<float> {
+    f4v v;
+    __device__ __forceinline__ void ld(const float *p) { v = *reinterpret_cast<const f4v *>(p); }
+    __device__ __forceinline__ double operator[](int t) const { return (double)v[t]; }
+};
+template <>
+struct Row4<double> {
+    d2v a, b;
+    __device__ __forceinline__ void ld(const double *p) {
+        a = reinterpret_cast<const d2v *>(p)[0];
+        b = reinterpret_cast<const d2v *>(p)[1];
+    }
+    __device__ __forceinline__ double operator[](int t) const { return t < 2 ? a[t] : b[t - 2]; }
+};
+
 // waves per bin-product workgroup (they split the workgroup's source rows;
 // eight measured 4-10 % slower than four)
 constexpr int kFftW = 4;
+// source rows per batch of the FP32 bin products (two batches in flight per
+// wave; FP64 spectra: half as many rows).  Eight measured the same, and
+// bounding the kernel to three waves per SIMD (which spills) 1-2 % slower.
+constexpr int kFftNB = 4;
 
 __device__ __forceinline__ int bitrev(int m, int logL) {
     return (int)(__builtin_bitreverse32((unsigned)m) >> (32 - logL));
@@ -278,35 +303,61 @@ __global__ __launch_bounds__(64 * kFftW) void k_fft_bins(FftPlan fp, const int4 
     for (int q = 0; q < 16; ++q) acc[q] = 0.0;
     constexpr int JW = kFftJ / kFftW;
     const int jw0 = w * JW, jw1 = min(jw0 + JW, jn);
-    if (i < C.Rp && FLUX) {
-        const double *gm = fp.fspec + C.fspec + ((size_t)f * C.R + j0) * C.Rp + i;
-#pragma unroll 8
-        for (int j = jw0; j < jw1; ++j) {
-            double g[4];
-            load4(gm + (size_t)j * C.Rp, g);
-            const double2 x = sI[j];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                acc[t] = fma(g[t], x.x, acc[t]);
-                acc[4 + t] = fma(g[t], x.y, acc[4 + t]);
-            }
-        }
-    } else if (i < C.Rp) {
+    // Rows in batches of NB, two batches in registers: the loads of the next
+    // batch are issued before the FMAs of the current one, so that two batches
+    // of each wave stay in flight; the FMAs of each sum in ascending j as in a
+    // plain loop.
+    constexpr int NB = (sizeof(TS) == 4 || FLUX) ? kFftNB : kFftNB / 2;
+    const int nfull = jw1 > jw0 ? (jw1 - jw0) / NB : 0;
+    if (i < C.Rp) {
         const size_t plane = (size_t)C.bins * C.R * C.Rp;
-        const TS *gz = static_cast<const TS *>(fp.spec) + C.spec + ((size_t)f * C.R + j0) * C.Rp + i;
-#pragma unroll 8
-        for (int j = jw0; j < jw1; ++j) {
-            double g[4], sv[4];
-            load4(gz + (size_t)j * C.Rp, g);
-            load4(gz + plane + (size_t)j * C.Rp, sv);
-            const double2 x = sI[j];
+        const TS *gz = FLUX ? reinterpret_cast<const TS *>(fp.fspec + C.fspec)
+                            : static_cast<const TS *>(fp.spec) + C.spec;
+        gz += ((size_t)f * C.R + j0) * C.Rp + i;
+        Row4<TS> ga[NB], sa[NB], gb[NB], sb[NB];
+        auto load = [&](Row4<TS>(&g)[NB], Row4<TS>(&sv)[NB], int j) {
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                g[u].ld(gz + (size_t)(j + u) * C.Rp);
+                if (!FLUX) sv[u].ld(gz + plane + (size_t)(j + u) * C.Rp);
+            }
+        };
+        auto fmas = [&](const Row4<TS> &g, const Row4<TS> &sv, double2 x) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 acc[t] = fma(g[t], x.x, acc[t]);
                 acc[4 + t] = fma(g[t], x.y, acc[4 + t]);
-                acc[8 + t] = fma(-sv[t], x.y, acc[8 + t]);
-                acc[12 + t] = fma(sv[t], x.x, acc[12 + t]);
+                if (!FLUX) {
+                    acc[8 + t] = fma(-sv[t], x.y, acc[8 + t]);
+                    acc[12 + t] = fma(sv[t], x.x, acc[12 + t]);
+                }
             }
+        };
+        auto comp = [&](const Row4<TS>(&g)[NB], const Row4<TS>(&sv)[NB], int j) {
+            // the scheduler would otherwise sink the loads issued just before
+            // below these FMAs (it trades their latency for registers)
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < NB; ++u) fmas(g[u], sv[u], sI[j + u]);
+        };
+        // (the loop body has no branch and the prefetch of its second batch is
+        // clamped -- past the last batch it re-reads it -- so that no load sits
+        // in a branch between its issue and the FMAs of an earlier batch, which
+        // would make those wait for it)
+        if (nfull > 0) {
+            load(ga, sa, jw0);
+            for (int k = 0; k + 1 < nfull; k += 2) {
+                load(gb, sb, jw0 + (k + 1) * NB);
+                comp(ga, sa, jw0 + k * NB);
+                load(ga, sa, jw0 + min(k + 2, nfull - 1) * NB);
+                comp(gb, sb, jw0 + (k + 1) * NB);
+            }
+            if (nfull & 1) comp(ga, sa, jw0 + (nfull - 1) * NB);
+        }
+        for (int j = jw0 + nfull * NB; j < jw1; ++j) {
+            ga[0].ld(gz + (size_t)j * C.Rp);
+            if (!FLUX) sa[0].ld(gz + plane + (size_t)j * C.Rp);
+            fmas(ga[0], sa[0], sI[j]);
         }
     }
     if (w > 0) {
