@@ -82,6 +82,9 @@ constexpr int kFftW = 4;
 // wave; FP64 spectra: half as many rows).  Eight measured the same, and
 // bounding the kernel to three waves per SIMD (which spills) 1-2 % slower.
 constexpr int kFftNB = 4;
+// rows per group of the symmetric kernels' double-buffered loops (four: 320
+// VGPRs, one wave per SIMD, 3 % slower than two)
+constexpr int kFftSG = 2;
 
 __device__ __forceinline__ int bitrev(int m, int logL) {
     return (int)(__builtin_bitreverse32((unsigned)m) >> (32 - logL));
@@ -469,7 +472,55 @@ __global__ __launch_bounds__(256) void k_fft_binsT(FftPlan fp, const int4 *__res
     const TS *gz = static_cast<const TS *>(fp.spec) + C.spec + (size_t)f * C.R * C.Rp + i;
     double *out = fp.bpart + C.bpart + ((size_t)it.w * C.R * C.bins + f) * 2;
     const bool act = i < C.Rp;
-    int j = jw0;
+    // double-buffered groups of SG rows with in-bounds loads in place of the
+    // branch (a lane past the padded rows has zero weights), as in k_fft_bins
+    constexpr int SG = sizeof(TS) == 4 ? kFftNB : kFftNB / 2;
+    const int nfull = jw1 > jw0 ? (jw1 - jw0) / SG : 0;
+    if (nfull > 0) {
+        const TS *gzl = gz + (act ? 0 : C.Rp - 4 - i);
+        Row4<TS> ga[SG], sa[SG], gb[SG], sb[SG];
+        auto load = [&](Row4<TS>(&g)[SG], Row4<TS>(&sv)[SG], int j0) {
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                g[u].ld(gzl + (size_t)(j0 + u) * C.Rp);
+                sv[u].ld(gzl + plane + (size_t)(j0 + u) * C.Rp);
+            }
+        };
+        auto comp = [&](const Row4<TS>(&g)[SG], const Row4<TS>(&sv)[SG], int j0) {
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads above (see k_fft_bins)
+            double re[SG], im[SG];
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                re[u] = im[u] = 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    re[u] = fma(g[u][t], wzr[t], fma(sv[u][t], wri[t], re[u]));
+                    im[u] = fma(g[u][t], wzi[t], fma(-sv[u][t], wrr[t], im[u]));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                re[u] = wave_sum(re[u]);
+                im[u] = wave_sum(im[u]);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int u = 0; u < SG; ++u) {
+                    out[(size_t)(j0 + u) * C.bins * 2] = re[u];
+                    out[(size_t)(j0 + u) * C.bins * 2 + 1] = im[u];
+                }
+            }
+        };
+        load(ga, sa, jw0);
+        for (int k = 0; k + 1 < nfull; k += 2) {
+            load(gb, sb, jw0 + SG * (k + 1));
+            comp(ga, sa, jw0 + SG * k);
+            load(ga, sa, jw0 + SG * min(k + 2, nfull - 1));
+            comp(gb, sb, jw0 + SG * (k + 1));
+        }
+        if (nfull & 1) comp(ga, sa, jw0 + SG * (nfull - 1));
+    }
+    int j = jw0 + SG * nfull;
     for (; j + 4 <= jw1; j += 4) {
         double re[4], im[4];
 #pragma unroll
@@ -554,7 +605,67 @@ __global__ __launch_bounds__(64 * kFftW) void k_fft_bins_sym(FftPlan fp, const i
     const TS *sp = static_cast<const TS *>(fp.spec) + C.spec + (size_t)C.bins * R * C.Rp + (size_t)f * C.sp + i;
     constexpr int JW = kFftI / kFftW;
     const int jw0 = JW * w, jw1 = min(jw0 + JW, R);
-    for (int j = jw0; j < jw1; j += 4) {
+    // Whole groups of SG rows, two groups in registers: the loads of the next
+    // group are issued before the FMAs and wavefront sums of the current one
+    // (as in k_fft_bins); a last partial group as four rows before.  No load sits in a branch: a lane past the padded
+    // rows reads the row's last four columns, and a lane past row j's stored
+    // part (4 lane > j) its last four entries, both in bounds, and uses zeros
+    // in their place -- adding zero products leaves every sum bitwise as if
+    // the lane had skipped them.
+    constexpr int SG = kFftSG;
+    const int nfull = jw1 > jw0 ? (jw1 - jw0) / SG : 0;
+    if (nfull > 0) {
+        const TS *gzl = gz + (act ? 0 : C.Rp - 4 - i);
+        Row4<TS> ga[SG], sa[SG], gb[SG], sb[SG];
+        auto load = [&](Row4<TS>(&g)[SG], Row4<TS>(&sv)[SG], int j) {
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                const int jj = j + u, last = 4 * (jj >> 2);
+                g[u].ld(gzl + (size_t)jj * C.Rp);
+                sv[u].ld(sp - i + sym_row(jj) + min(i, last));
+            }
+        };
+        auto comp = [&](const Row4<TS>(&g)[SG], const Row4<TS>(&sv)[SG], int j) {
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads above (see k_fft_bins)
+            double pr[SG], pi[SG];
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                const int jj = j + u;
+                const double2 x = sI[jj];
+                const bool on = lane <= (jj >> 2);
+                pr[u] = pi[u] = 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    acc[t] = fma(g[u][t], x.x, acc[t]);
+                    acc[4 + t] = fma(g[u][t], x.y, acc[4 + t]);
+                    const double sv_t = on ? sv[u][t] : 0.0;
+                    acc[8 + t] = fma(-sv_t, x.y, acc[8 + t]);
+                    acc[12 + t] = fma(sv_t, x.x, acc[12 + t]);
+                    const double m = i + t < jj ? sv_t : 0.0;
+                    pr[u] = fma(m, xi[t].x, pr[u]);
+                    pi[u] = fma(m, xi[t].y, pi[u]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                pr[u] = wave_sum(pr[u]);
+                pi[u] = wave_sum(pi[u]);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int u = 0; u < SG; ++u) tB[j + u] = make_double2(pr[u], pi[u]);
+            }
+        };
+        load(ga, sa, jw0);
+        for (int k = 0; k + 1 < nfull; k += 2) {
+            load(gb, sb, jw0 + SG * (k + 1));
+            comp(ga, sa, jw0 + SG * k);
+            load(ga, sa, jw0 + SG * min(k + 2, nfull - 1));
+            comp(gb, sb, jw0 + SG * (k + 1));
+        }
+        if (nfull & 1) comp(ga, sa, jw0 + SG * (nfull - 1));
+    }
+    for (int j = jw0 + SG * nfull; j < jw1; j += 4) {
         double pr[4], pi[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -658,7 +769,66 @@ __global__ __launch_bounds__(64 * kFftW) void k_fft_binsT_sym(FftPlan fp, const 
     const TS *sp = static_cast<const TS *>(fp.spec) + C.spec + (size_t)C.bins * R * C.Rp + (size_t)f * C.sp + i;
     constexpr int JW = kFftI / kFftW;
     const int jw0 = JW * w, jw1 = min(jw0 + JW, R);
-    for (int j = jw0; j < jw1; j += 4) {
+    // double-buffered groups of SG rows with in-bounds loads in place of the
+    // branches, as in k_fft_bins_sym (a lane past the padded rows has zero
+    // weights, a lane past row j's stored part uses zeros)
+    constexpr int SG = kFftSG;
+    const int nfull = jw1 > jw0 ? (jw1 - jw0) / SG : 0;
+    if (nfull > 0) {
+        const TS *gzl = gz + (act ? 0 : C.Rp - 4 - i);
+        Row4<TS> ga[SG], sa[SG], gb[SG], sb[SG];
+        auto load = [&](Row4<TS>(&g)[SG], Row4<TS>(&sv)[SG], int j) {
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                const int jj = j + u, last = 4 * (jj >> 2);
+                g[u].ld(gzl + (size_t)jj * C.Rp);
+                sv[u].ld(sp - i + sym_row(jj) + min(i, last));
+            }
+        };
+        auto comp = [&](const Row4<TS>(&g)[SG], const Row4<TS>(&sv)[SG], int j) {
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads above (see k_fft_bins)
+            double re[SG], im[SG];
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                const int jj = j + u;
+                const bool on = lane <= (jj >> 2);
+                const double2 wj = sW[jj];
+                re[u] = im[u] = 0.0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    re[u] = fma(g[u][t], wzr[t], re[u]);
+                    im[u] = fma(g[u][t], wzi[t], im[u]);
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const double sv_t = on ? sv[u][t] : 0.0;
+                    re[u] = fma(sv_t, wri[t], re[u]);
+                    im[u] = fma(-sv_t, wrr[t], im[u]);
+                    const double m = i + t < jj ? sv_t : 0.0;
+                    ar[t] = fma(m, wj.y, ar[t]);
+                    ai[t] = fma(-m, wj.x, ai[t]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < SG; ++u) {
+                re[u] = wave_sum(re[u]);
+                im[u] = wave_sum(im[u]);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int u = 0; u < SG; ++u) tD[j + u] = make_double2(re[u], im[u]);
+            }
+        };
+        load(ga, sa, jw0);
+        for (int k = 0; k + 1 < nfull; k += 2) {
+            load(gb, sb, jw0 + SG * (k + 1));
+            comp(ga, sa, jw0 + SG * k);
+            load(ga, sa, jw0 + SG * min(k + 2, nfull - 1));
+            comp(gb, sb, jw0 + SG * (k + 1));
+        }
+        if (nfull & 1) comp(ga, sa, jw0 + SG * (nfull - 1));
+    }
+    for (int j = jw0 + SG * nfull; j < jw1; j += 4) {
         double re[4], im[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
