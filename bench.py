@@ -59,7 +59,7 @@ PLAN_BEGIN, PLAN_END = "// ---- field-pass work plans (begin)", "// ---- field-p
 MEASURED_TRAFFIC = {
     # (algorithm, workload, precision): (sha1 of the sources, bytes per launch)
     ("translation", "c2_medium_131k", "mixed"): ("49bf2f94a8592ed1a99a38e435825fb9ba4b2d98", 108509798),
-    ("fft", "c2_medium_131k", "mixed"): ("f2a7aa7ab2d1c37e64d450f405579973d758aac9", 275438080),
+    ("fft", "c2_medium_131k", "mixed"): ("eddfdffd22824495e75224e49986c4cc1c6adf01", 275440230),
 }
 
 
