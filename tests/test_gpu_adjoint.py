@@ -24,7 +24,10 @@ def _say(*a):
 
 @pytest.mark.parametrize("algo", ["direct", "translation", "fft"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed", 1e-6)])
-@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 4), (3, 9, 8), (5, 7, 6), (2, 70, 8)])
+# (33, 2, 8) and (87, 1, 3): 264 and 261 element rows, more than one 256-row
+# block of the fast convolution's bin products (two target blocks and two
+# source parts; in FP64 the unpacked spectra)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (2, 3, 4), (3, 9, 8), (5, 7, 6), (2, 70, 8), (33, 2, 8), (87, 1, 3)])
 def test_field_transpose_dot_product(prec, tol, shape, algo):
     pk = _pk()
     w = cs.Workload(name="t", coils=[cs.Coil(*shape)], steps=1, dt=1e-4)

@@ -37,7 +37,9 @@ def _coil(layers, turns, ne, **kw):
                        steps=1, dt=kw.pop("dt", 1e-4), **kw)
 
 
-SHAPES = [(1, 1, 1), (1, 1, 8), (2, 3, 3), (3, 5, 4), (4, 8, 4), (5, 7, 6), (3, 9, 8)]
+# the last two have more than 256 element rows (264, and 261 padded to 264):
+# two row blocks of the fast convolution, in FP64 its unpacked spectra
+SHAPES = [(1, 1, 1), (1, 1, 8), (2, 3, 3), (3, 5, 4), (4, 8, 4), (5, 7, 6), (3, 9, 8), (33, 2, 8), (87, 1, 3)]
 
 
 ALGOS = ["direct", "translation", "fft"]
