@@ -332,8 +332,26 @@ __global__ __launch_bounds__(FAST ? 64 * kFastWires : 64) void k_wire(DevState s
         mee = act ? M[(size_t)lane * n + lane] : 1.0;
         ylv = act ? s.yl[lay * n + lane] : 0.0;
         sylv = s.syl[lay];
+        // the layer inverse into LDS, eight values per thread at a time with
+        // their loads issued at once (a loop that stores each value as it
+        // arrives pays the memory latency once per value: 16 times at n_e = 64);
+        // loads past the end re-read the last.  Issued before the local law
+        // instead, they held registers across it (98-107 VGPRs against 79:
+        // four waves per SIMD instead of six), which slowed the wire phase of
+        // the 17,152-wire ensemble from 60 to 70 us
         const double *Mi = s.Minv + lay * n * n;
-        for (int i = threadIdx.x; i < n * n; i += 64 * kFastWires) sm[i] = Mi[i];
+        constexpr int kStage = 8, kStep = 64 * kFastWires;
+        const int nn = n * n;
+        for (int b = 0; b < nn; b += kStage * kStep) {
+            double mv[kStage];
+#pragma unroll
+            for (int k = 0; k < kStage; ++k) mv[k] = Mi[min(b + (int)threadIdx.x + k * kStep, nn - 1)];
+#pragma unroll
+            for (int k = 0; k < kStage; ++k) {
+                const int i = b + (int)threadIdx.x + k * kStep;
+                if (i < nn) sm[i] = mv[k];
+            }
+        }
         __syncthreads();
         if (!live) return;
     }
