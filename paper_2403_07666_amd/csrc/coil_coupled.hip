@@ -121,8 +121,20 @@ __device__ __forceinline__ void wire_inverse(const DevState &s, const RunConst &
         yv = act ? s.yl[lay * n + lane] : 0.0;
         sy = s.syl[lay];
     } else {
+        // the factor into LDS eight values per lane at a time, their loads
+        // issued together (a loop that stores each value as it arrives pays
+        // the memory latency once per value: 33 times at n_e = 64); loads
+        // past the end re-read the last
         const double *L = s.cg_L + (size_t)w * packed_size(s.max_ne2);
-        for (int i = lane; i < packed_size(n); i += 64) sm[i] = L[i];
+        const int np = packed_size(n);
+        for (int b = 0; b < np; b += 8 * 64) {
+            double f[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) f[k] = L[min(b + lane + 64 * k, np - 1)];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (b + lane + 64 * k < np) sm[b + lane + 64 * k] = f[k];
+        }
         __syncthreads();
         xv = v;
         yv = act ? 1.0 : 0.0;
